@@ -1,0 +1,477 @@
+"""CPU oracle for the adaptive CSR SpMV method (Elafrou, Goumas & Koziris 2017).
+
+TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package. The GPU library never
+calls it, and it shares no code with the GPU library (`paper_1711_05487_amd`).
+
+Two halves:
+
+* ``csr_oracle.c`` (plain C, ``gcc -O2 -ffp-contract=off``), loaded with ctypes:
+  SpMV in storage order, |A||x|, the Dot2 accurate reference, dense matvec,
+  CSR validation, FP32/BF16 rounding, delta codes, merge-path tiles, long-row
+  list and the matrix features.
+* Pure Python/numpy here: the per-class bounds, the profile-guided rule, the
+  class-to-optimization map, the amortization count, the reduced-precision
+  error report, feature normalization and the FP64 MLP with its gradients and
+  Adam.
+
+Every function cites the part of the paper it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "csr_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+GCC_FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11"]
+
+
+def build(force: bool = False) -> str:
+    """Compile csr_oracle.c into liboracle.so with gcc."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", *GCC_FLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32, i64, c_int = ctypes.c_int32, ctypes.c_int64, ctypes.c_int
+        sig = {
+            "or_spmv": (None, [i32, P, P, P, P, P]),
+            "or_absax": (None, [i32, P, P, P, P, P]),
+            "or_spmv_dot2": (None, [i32, P, P, P, P, P]),
+            "or_dense_matvec": (None, [i32, i32, P, P, P]),
+            "or_csr_valid": (c_int, [i32, i32, i64, P, P]),
+            "or_rows_sorted": (c_int, [i32, P, P]),
+            "or_to_f32": (None, [i64, P, P]),
+            "or_to_bf16": (None, [i64, P, P]),
+            "or_bf16_to_f64": (None, [i64, P, P]),
+            "or_delta_eligible": (c_int, [i32, P, P, c_int]),
+            "or_delta_encode": (c_int, [i32, P, P, c_int, P]),
+            "or_delta_decode": (None, [i32, P, P, c_int, P]),
+            "or_merge_tiles": (i64, [i32, P, i64, P, P]),
+            "or_long_rows": (i32, [i32, P, i64, P]),
+            "or_features": (None, [i32, i32, P, P, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _csr(rp, col):
+    return (np.ascontiguousarray(rp, dtype=np.int32), np.ascontiguousarray(col, dtype=np.int32))
+
+
+# ---------------------------------------------------------------------------
+# SpMV and its error scale (Sec. II, Fig. 2)
+# ---------------------------------------------------------------------------
+
+def spmv(rp, col, val, x) -> np.ndarray:
+    """y = A x, each row summed from +0.0 in storage order (Sec. II, Fig. 2)."""
+    rp, col = _csr(rp, col)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(rp.size - 1, dtype=np.float64)
+    lib().or_spmv(rp.size - 1, _p(rp), _p(col), _p(val), _p(x), _p(y))
+    return y
+
+
+def absax(rp, col, val, x) -> np.ndarray:
+    """Per-row sum of |a_ij| |x_j|."""
+    rp, col = _csr(rp, col)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(rp.size - 1, dtype=np.float64)
+    lib().or_absax(rp.size - 1, _p(rp), _p(col), _p(val), _p(x), _p(y))
+    return y
+
+
+def spmv_accurate(rp, col, val, x) -> np.ndarray:
+    """y = A x by compensated dot products (Ogita-Rump-Oishi Dot2)."""
+    rp, col = _csr(rp, col)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(rp.size - 1, dtype=np.float64)
+    lib().or_spmv_dot2(rp.size - 1, _p(rp), _p(col), _p(val), _p(x), _p(y))
+    return y
+
+
+def dense_matvec(a, x) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(a.shape[0], dtype=np.float64)
+    lib().or_dense_matvec(a.shape[0], a.shape[1], _p(a), _p(x), _p(y))
+    return y
+
+
+def csr_valid(n_rows, n_cols, nnz, rp, col) -> bool:
+    rp, col = _csr(rp, col)
+    if rp.size != n_rows + 1:
+        return False
+    if col.size < nnz:
+        return False
+    return bool(lib().or_csr_valid(n_rows, n_cols, nnz, _p(rp), _p(col)))
+
+
+def rows_sorted(rp, col) -> bool:
+    rp, col = _csr(rp, col)
+    return bool(lib().or_rows_sorted(rp.size - 1, _p(rp), _p(col)))
+
+
+# ---------------------------------------------------------------------------
+# Reduced-precision value storage
+# ---------------------------------------------------------------------------
+
+def to_f32(v) -> np.ndarray:
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.empty(v.size, dtype=np.float32)
+    lib().or_to_f32(v.size, _p(v), _p(out))
+    return out
+
+
+def to_bf16_bits(v) -> np.ndarray:
+    """FP64 -> BF16 bit patterns (uint16), one round-to-nearest-even step."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.empty(v.size, dtype=np.uint16)
+    lib().or_to_bf16(v.size, _p(v), _p(out))
+    return out
+
+
+def bf16_bits_to_f64(b) -> np.ndarray:
+    b = np.ascontiguousarray(b, dtype=np.uint16)
+    out = np.empty(b.size, dtype=np.float64)
+    lib().or_bf16_to_f64(b.size, _p(b), _p(out))
+    return out
+
+
+def quantize(v, storage: str) -> np.ndarray:
+    """The FP64 value of each stored element for storage 'f64'|'f32'|'bf16'."""
+    if storage == "f64":
+        return np.asarray(v, dtype=np.float64)
+    if storage == "f32":
+        return to_f32(v).astype(np.float64)
+    if storage == "bf16":
+        return bf16_bits_to_f64(to_bf16_bits(v))
+    raise ValueError(storage)
+
+
+# Unit roundoff of each storage format: 2^-p for p significand bits.
+UNIT_ROUNDOFF = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -8}
+
+
+def reduced_precision_bound(rp, col, val, x, storage: str):
+    """Reference and a-priori error bound for FP32-accumulated SpMV with values
+    and x stored in `storage` (x rounded once to FP32 for f32/bf16 stores).
+
+    Returns (y_q, bound): y_q is the accurate product of the *stored* values
+    and the FP32 x; bound_i = gamma_{n_i+1}(2^-24) * sum |v_q| |x_q| bounds the
+    error of any FP32 summation order of the row's n_i rounded products."""
+    vq = quantize(val, storage)
+    xq = to_f32(x).astype(np.float64)
+    yq = spmv_accurate(rp, col, vq, xq)
+    ab = absax(rp, col, vq, xq)
+    n = np.diff(np.asarray(rp, dtype=np.int64)).astype(np.float64)
+    u = 2.0 ** -24
+    k = n + 1.0
+    gamma = np.where(k * u < 1.0, (k * u) / np.maximum(1.0 - k * u, 1e-300), np.inf)
+    return yq, gamma * ab
+
+
+def rel_error_report(y, y_ref, ab) -> dict:
+    """Per-row relative error |y - y_ref| / (|A||x|), normalized by |A||x| so a
+    cancelled y_ref does not blow up the ratio; rows with |A||x| = 0 must be 0."""
+    y = np.asarray(y, dtype=np.float64)
+    d = np.abs(y - y_ref)
+    nz = ab > 0
+    rel = np.zeros_like(d)
+    rel[nz] = d[nz] / ab[nz]
+    bad_zero = bool((d[~nz] != 0).any())
+    return {"max": float(rel.max(initial=0.0)),
+            "p99": float(np.percentile(rel, 99)) if rel.size else 0.0,
+            "zero_rows_exact": not bad_zero}
+
+
+# ---------------------------------------------------------------------------
+# MB remedy: delta-encoded column indices (Sec. III-E, Table II)
+# ---------------------------------------------------------------------------
+
+def delta_eligible(rp, col, w: int) -> bool:
+    rp, col = _csr(rp, col)
+    return bool(lib().or_delta_eligible(rp.size - 1, _p(rp), _p(col), w))
+
+
+def delta_encode(rp, col, w: int):
+    """w-bit codes (uint8/uint16 array) or None if the matrix is not eligible."""
+    rp, col = _csr(rp, col)
+    out = np.empty(col.size, dtype=np.uint8 if w == 8 else np.uint16)
+    ok = lib().or_delta_encode(rp.size - 1, _p(rp), _p(col), w, _p(out))
+    return out if ok else None
+
+
+def delta_decode(rp, codes, w: int) -> np.ndarray:
+    rp = np.ascontiguousarray(rp, dtype=np.int32)
+    codes = np.ascontiguousarray(codes, dtype=np.uint8 if w == 8 else np.uint16)
+    col = np.empty(codes.size, dtype=np.int32)
+    lib().or_delta_decode(rp.size - 1, _p(rp), _p(codes), w, _p(col))
+    return col
+
+
+def delta_width(rp, col) -> int:
+    """Smallest eligible width (8, then 16), or 32 when neither fits."""
+    for w in (8, 16):
+        if delta_eligible(rp, col, w):
+            return w
+    return 32
+
+
+# ---------------------------------------------------------------------------
+# IMB remedies (Sec. III-E): merge-path tiles and long-row decomposition
+# ---------------------------------------------------------------------------
+
+def merge_tiles(rp, L: int):
+    """(i_t, j_t) for t = 0..T of the merge path of the row ends with the
+    nonzeros, cut every L items."""
+    rp = np.ascontiguousarray(rp, dtype=np.int32)
+    n = rp.size - 1
+    total = n + int(rp[-1])
+    T = (total + L - 1) // L
+    ti = np.empty(T + 1, dtype=np.int32)
+    tj = np.empty(T + 1, dtype=np.int32)
+    lib().or_merge_tiles(n, _p(rp), L, _p(ti), _p(tj))
+    return ti, tj
+
+
+def long_rows(rp, tau: int) -> np.ndarray:
+    rp = np.ascontiguousarray(rp, dtype=np.int32)
+    out = np.empty(max(rp.size - 1, 1), dtype=np.int32)
+    k = lib().or_long_rows(rp.size - 1, _p(rp), tau, _p(out))
+    return out[:k].copy()
+
+
+def long_row_threshold(nnz_avg: float, factor: float = 32.0, floor: int = 4096) -> int:
+    """tau = max(factor * nnz_avg, floor): a row is 'long' when it holds more
+    nonzeros than this (the paper compares nnz_max against nnz_avg but states
+    no number)."""
+    return int(max(factor * nnz_avg, floor))
+
+
+# ---------------------------------------------------------------------------
+# Features (Sec. III-D, Table I)
+# ---------------------------------------------------------------------------
+
+FEATURE_NAMES = ("N", "nnz_min", "nnz_max", "nnz_avg", "nnz_sd", "bw_min", "bw_max",
+                 "bw_avg", "bw_sd", "scatter_avg", "scatter_sd", "clustering_avg",
+                 "misses_avg", "size", "mean_col_gap", "x_reuse")
+FEATURE_INT_NAMES = ("sum_nnz", "sum_nnz2", "sum_bw", "sum_bw2", "sum_misses",
+                     "sum_groups", "reuse_shared", "reuse_distinct")
+
+
+def features(n_rows, n_cols, rp, col):
+    """(16 FP64 features, 8 int64 sums) as defined in csr_oracle.c."""
+    rp, col = _csr(rp, col)
+    out = np.empty(16, dtype=np.float64)
+    iout = np.empty(8, dtype=np.int64)
+    lib().or_features(n_rows, n_cols, _p(rp), _p(col), _p(out), _p(iout))
+    return out, iout
+
+
+# ---------------------------------------------------------------------------
+# Per-class bounds (Sec. III-B) and the profile-guided rule (Sec. III-C, Fig. 4)
+# ---------------------------------------------------------------------------
+
+MALL_BYTES = 256 * 1024 * 1024
+
+
+def format_bytes(n_rows, n_cols, nnz, val_bytes=8, idx_bytes=4, extra=0):
+    """S_format for CSR: values + indices + row pointers (+ any side table)."""
+    return nnz * (val_bytes + idx_bytes) + 4 * (n_rows + 1) + extra
+
+
+def p_mb(nnz, s_format, s_x, s_y, b_max):
+    """P_MB = 2 NNZ / ((S_format + S_x + S_y) / B_max)  [flop/s]."""
+    return 2.0 * nnz / ((s_format + s_x + s_y) / b_max)
+
+
+def p_peak(nnz, s_values, s_x, s_y, b_max):
+    """P_peak = 2 NNZ / ((S_values + S_x + S_y) / B_max): all indexing removed."""
+    return 2.0 * nnz / ((s_values + s_x + s_y) / b_max)
+
+
+def p_imb(nnz, unit_times):
+    """P_IMB = 2 NNZ / t_median over the execution units that ran work; for an
+    even count the median is the mean of the two middle values."""
+    t = np.sort(np.asarray(unit_times, dtype=np.float64))
+    if t.size == 0:
+        return float("inf")
+    m = t.size // 2
+    med = t[m] if t.size % 2 else 0.5 * (t[m - 1] + t[m])
+    return 2.0 * nnz / med
+
+
+def b_for_footprint(bytes_total, b_hbm, b_cache, cache_bytes=MALL_BYTES):
+    """B_max, raised to the cache bandwidth when the working set fits in the
+    last-level cache (the footnote to the P_MB bound)."""
+    return b_cache if bytes_total <= cache_bytes else b_hbm
+
+
+CLS_MB, CLS_ML, CLS_IMB, CLS_CMP = 1, 2, 4, 8
+
+
+def classify(p_csr, p_mb_, p_ml, p_imb_, p_cmp, p_peak_, t_ml=1.25, t_imb=1.24, t_mb=0.8):
+    """Profile-guided rule (Sec. III-C, Fig. 4) -> bit mask of classes.
+
+    IMB  if P_IMB / P_CSR > T_IMB
+    ML   if P_ML  / P_CSR > T_ML
+    MB   if P_CSR ~ P_MB and P_MB < P_CMP < P_peak
+    CMP  if P_MB > P_CMP or P_CMP > P_peak
+    The paper leaves '~' undefined; it is read as P_CSR >= T_MB * P_MB.
+    """
+    c = 0
+    if p_imb_ / p_csr > t_imb:
+        c |= CLS_IMB
+    if p_ml / p_csr > t_ml:
+        c |= CLS_ML
+    if p_csr >= t_mb * p_mb_ and p_mb_ < p_cmp < p_peak_:
+        c |= CLS_MB
+    if p_mb_ > p_cmp or p_cmp > p_peak_:
+        c |= CLS_CMP
+    return c
+
+
+OPT_DELTA, OPT_PREFETCH, OPT_DECOMP, OPT_MERGE, OPT_UNROLL = 1, 2, 4, 8, 16
+OPT_ORDER = (OPT_DELTA, OPT_PREFETCH, OPT_DECOMP, OPT_MERGE, OPT_UNROLL)
+
+
+def remedies(classes: int, has_long_rows: bool) -> int:
+    """Class set -> optimization set (Sec. III-E, Table II), applied jointly.
+
+    MB  -> delta-compressed column indices (+ wide loads)
+    ML  -> prefetched x gathers
+    IMB -> long-row decomposition when long rows exist, else the nnz-balanced
+           merge-path split (the GPU counterpart of the runtime-chosen schedule)
+    CMP -> unrolling with several rows per wavefront (+ wide loads)
+    """
+    o = 0
+    if classes & CLS_MB:
+        o |= OPT_DELTA
+    if classes & CLS_ML:
+        o |= OPT_PREFETCH
+    if classes & CLS_IMB:
+        o |= OPT_DECOMP if has_long_rows else OPT_MERGE
+    if classes & CLS_CMP:
+        o |= OPT_UNROLL
+    return o
+
+
+def catalogue():
+    """The K = 16 optimization sets the trivial optimizers of Sec. IV-D sweep:
+    the baseline, the 5 singles and the 10 pairs (ids in this order)."""
+    sets = [0] + list(OPT_ORDER)
+    for a in range(5):
+        for b in range(a + 1, 5):
+            sets.append(OPT_ORDER[a] | OPT_ORDER[b])
+    return sets
+
+
+def n_iters_min(t_pre, t_base, t_opt):
+    """Solver iterations needed to amortize the optimizer (Sec. IV-D, Eq. (2)):
+    t_pre / (t_base - t_opt), infinite when the optimized SpMV is not faster."""
+    if t_opt >= t_base:
+        return float("inf")
+    return t_pre / (t_base - t_opt)
+
+
+def harmonic_mean(rates):
+    """Run summary of Sec. IV-A: harmonic mean of the per-run rates."""
+    r = np.asarray(rates, dtype=np.float64)
+    return r.size / np.sum(1.0 / r)
+
+
+# ---------------------------------------------------------------------------
+# Learned selector: feature normalization and an FP64 MLP 16-64-64-K
+# (replaces the decision tree of Sec. III-D; labels are timed-best variants)
+# ---------------------------------------------------------------------------
+
+def normalize(f, mu, sigma):
+    """f' = (log2(1 + f) - mu) / sigma, per feature."""
+    return (np.log2(1.0 + np.asarray(f, dtype=np.float64)) - mu) / sigma
+
+
+def mlp_forward(params, X):
+    """Hidden layers ReLU(W h + b), output logits W h + b. X: (B, in)."""
+    h = np.asarray(X, dtype=np.float64)
+    acts = [h]
+    nl = len(params) // 2
+    for l in range(nl):
+        W, b = params[2 * l], params[2 * l + 1]
+        z = h @ W.T + b
+        h = np.maximum(z, 0.0) if l < nl - 1 else z
+        acts.append(h)
+    return h, acts
+
+
+def softmax_xent(logits, labels):
+    """Mean softmax cross-entropy and its gradient w.r.t. the logits."""
+    z = logits - logits.max(axis=1, keepdims=True)
+    e = np.exp(z)
+    p = e / e.sum(axis=1, keepdims=True)
+    B = logits.shape[0]
+    loss = -np.mean(np.log(p[np.arange(B), labels]))
+    g = p.copy()
+    g[np.arange(B), labels] -= 1.0
+    return loss, g / B
+
+
+def mlp_loss_grad(params, X, labels):
+    """Loss and gradients by the chain rule, layer by layer backwards."""
+    logits, acts = mlp_forward(params, X)
+    loss, g = softmax_xent(logits, labels)
+    nl = len(params) // 2
+    grads = [None] * len(params)
+    for l in range(nl - 1, -1, -1):
+        h_in = acts[l]
+        W = params[2 * l]
+        grads[2 * l] = g.T @ h_in
+        grads[2 * l + 1] = g.sum(axis=0)
+        if l > 0:
+            g = (g @ W) * (acts[l] > 0.0)
+    return loss, grads
+
+
+def adam_step(params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba 2015) with bias correction; t counts from 1."""
+    out_p, out_m, out_v = [], [], []
+    for p, g, mm, vv in zip(params, grads, m, v):
+        mm = b1 * mm + (1.0 - b1) * g
+        vv = b2 * vv + (1.0 - b2) * g * g
+        mh = mm / (1.0 - b1 ** t)
+        vh = vv / (1.0 - b2 ** t)
+        out_p.append(p - lr * mh / (np.sqrt(vh) + eps))
+        out_m.append(mm)
+        out_v.append(vv)
+    return out_p, out_m, out_v
+
+
+def regret(t_sel, t_best):
+    """Per-matrix regret t_selected / t_best - 1."""
+    return np.asarray(t_sel, dtype=np.float64) / np.asarray(t_best, dtype=np.float64) - 1.0

@@ -1,0 +1,258 @@
+"""Pins of the oracle's storage transforms: FP32/BF16 rounding, delta-coded
+column indices (Sec. III-E, Table II: MB remedy), merge-path tiles and the
+long-row list (Sec. III-E: IMB remedies)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- precision
+
+def test_f32_matches_numpy_cast():
+    v = np.concatenate([synth.vector(100000, 1) * np.exp2(
+        synth.uindex(2, 0, np.arange(100000, dtype=np.uint64), 300) - 150),
+        [0.0, -0.0, np.inf, -np.inf, 1e-46, 3.4028235677973366e38, 1e39]])
+    with np.errstate(over="ignore"):
+        ref = v.astype(np.float32)
+    assert np.array_equal(oracle.to_f32(v).view(np.uint32), ref.view(np.uint32))
+
+
+def test_bf16_matches_torch_on_f32_representable_values():
+    # For values already exact in FP32 a single rounding to BF16 is what
+    # torch's float32 -> bfloat16 conversion (round to nearest even) does.
+    f = (synth.vector(200000, 3) * np.exp2(
+        synth.uindex(4, 0, np.arange(200000, dtype=np.uint64), 250) - 125)).astype(np.float32)
+    ref = torch.from_numpy(f).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    got = oracle.to_bf16_bits(f.astype(np.float64))
+    assert np.array_equal(got, ref)
+
+
+def _bf16_finite_table():
+    bits = np.arange(1 << 16, dtype=np.uint32)
+    with np.errstate(invalid="ignore"):
+        w = (bits << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    ok = np.isfinite(w) & (w >= 0) & ~((bits == 0x8000))
+    b = bits[ok & (bits < 0x8000)]
+    vals = w[ok & (bits < 0x8000)]
+    order = np.argsort(vals)
+    return vals[order], b[order].astype(np.uint16)
+
+
+def test_bf16_brute_force_nearest_even():
+    # Brute force over the table of all finite non-negative BF16 values: the
+    # nearest one, ties to the even bit pattern, overflow past the halfway
+    # point above the largest finite value to infinity.
+    vals, bits = _bf16_finite_table()
+    n = 20000
+    mag = np.exp2(synth.uindex(6, 0, np.arange(n, dtype=np.uint64), 280) - 140)
+    v = np.abs(synth.vector(n, 5)) * mag
+    # plus exact halfway points and points next to them
+    k = synth.uindex(7, 0, np.arange(2000, dtype=np.uint64), vals.size - 1)
+    mids = 0.5 * (vals[k] + vals[k + 1])
+    v = np.concatenate([v, mids, np.nextafter(mids, 0), np.nextafter(mids, np.inf)])
+    got = oracle.to_bf16_bits(v)
+    hi = np.searchsorted(vals, v, side="left")
+    expect = np.empty(v.size, dtype=np.uint16)
+    top = vals[-1]
+    half_over = top + 0.5 * (top - vals[-2])
+    for q in range(v.size):
+        x = v[q]
+        if x >= half_over:
+            expect[q] = 0x7F80
+            continue
+        h = min(hi[q], vals.size - 1)
+        lo = max(h - 1, 0)
+        cands = [(abs(vals[c] - x), c) for c in {lo, h}]
+        cands.sort(key=lambda t: t[0])
+        if len(cands) == 2 and cands[0][0] == cands[1][0]:
+            c = cands[0][1] if bits[cands[0][1]] % 2 == 0 else cands[1][1]
+        else:
+            c = cands[0][1]
+        expect[q] = bits[c]
+    assert np.array_equal(got, expect)
+    # negative values mirror the sign bit
+    assert np.array_equal(oracle.to_bf16_bits(-v), expect | 0x8000)
+
+
+def test_bf16_edge_table():
+    cases = {
+        1.0: 0x3F80,
+        1.0 + 2.0 ** -8: 0x3F80,                    # halfway, even stays
+        1.0 + 3 * 2.0 ** -8: 0x3F82,                # halfway, odd rounds up
+        1.0 + 2.0 ** -8 + 2.0 ** -40: 0x3F81,       # single rounding (FP32 first would give 0x3F80)
+        (2 - 2.0 ** -7) * 2.0 ** 127: 0x7F7F,       # largest finite
+        (2 - 2.0 ** -8) * 2.0 ** 127: 0x7F80,       # halfway above it: to even = inf
+        np.nextafter((2 - 2.0 ** -8) * 2.0 ** 127, 0): 0x7F7F,
+        2.0 ** -133: 0x0001,                        # smallest subnormal
+        2.0 ** -134: 0x0000,                        # halfway to zero: even
+        1.5 * 2.0 ** -134: 0x0001,
+        2.0 ** -126: 0x0080,                        # smallest normal
+        -0.0: 0x8000,
+        np.inf: 0x7F80,
+        -np.inf: 0xFF80,
+        float("nan"): 0x7FC0,
+    }
+    v = np.array(list(cases.keys()), dtype=np.float64)
+    got = oracle.to_bf16_bits(v)
+    assert [int(g) for g in got] == list(cases.values())
+    back = oracle.bf16_bits_to_f64(np.array([0x3F81, 0x0001, 0xC000], dtype=np.uint16))
+    assert list(back) == [1.0 + 2.0 ** -7, 2.0 ** -133, -2.0]
+
+
+def test_reduced_precision_bound_holds_for_sequential_fp32():
+    # numpy float32 accumulation in storage order is one admissible FP32
+    # summation; it must sit inside the a-priori bound.
+    n, _, rp, col, val = synth.stencil27(12)
+    x = synth.vector(n, 9)
+    for storage in ("f32", "bf16"):
+        vq = oracle.quantize(val, storage).astype(np.float32)
+        xq = x.astype(np.float32)
+        y = np.zeros(n, dtype=np.float32)
+        prods = vq * xq[col]
+        for i in range(n):
+            s = np.float32(0)
+            for p in prods[rp[i]:rp[i + 1]]:
+                s = np.float32(s + p)
+            y[i] = s
+        yq, bound = oracle.reduced_precision_bound(rp, col, val, x, storage)
+        assert np.all(np.abs(y.astype(np.float64) - yq) <= bound)
+
+
+# ---------------------------------------------------------------- delta codes
+
+def test_delta_round_trip_laplacian_w8():
+    n, _, rp, col, _ = synth.laplacian2d(100)
+    assert oracle.delta_width(rp, col) == 8
+    codes = oracle.delta_encode(rp, col, 8)
+    assert codes.dtype == np.uint8
+    assert np.array_equal(oracle.delta_decode(rp, codes, 8), col)
+    # closed form: first offsets in [-100, 0], gaps 1, 99 or 100
+    first = codes[rp[:-1]].view(np.int8)
+    assert first.min() == -100 and first.max() == 0
+    rest = np.delete(codes, rp[:-1])
+    assert set(np.unique(rest).tolist()) == {1, 99, 100}
+
+
+def test_delta_stencil27_w16_closed_form():
+    # 27-point stencil on n^3: the most negative first offset is -(n^2+n+1)
+    # and the largest gap is n^2 - n - 1 (a row on the y=0 or y=n-1 face with
+    # x at a face, jumping from plane z-1 to plane z): 16,513 and 16,255 for
+    # n = 128, so 16-bit codes fit and 8-bit ones do not.
+    gold = json.load(open(os.path.join(GOLDEN, "stencil27_delta.json")))
+    n = gold["n"]
+    N, _, rp, col, _ = synth.stencil27(n)
+    assert not oracle.delta_eligible(rp, col, 8)
+    codes = oracle.delta_encode(rp, col, 16)
+    first = codes[rp[:-1]].view(np.int16)
+    rest = np.delete(codes, rp[:-1])
+    assert int(first.min()) == gold["min_first_offset"]
+    assert int(rest.max()) == gold["max_gap"]
+    assert np.array_equal(oracle.delta_decode(rp, codes, 16), col)
+
+
+@pytest.mark.parametrize("w", [8, 16])
+def test_delta_boundaries(w):
+    lo, umax = -(1 << (w - 1)), (1 << w) - 1
+    ncol = 1 << 20
+    # row 0 at the signed limit, then a gap at the unsigned limit
+    row = 1 << (w - 1)
+    rp = np.array([0] * (row + 1) + [2], dtype=np.int32)
+    ok = np.array([row + lo, row + lo + umax], dtype=np.int32)
+    assert oracle.delta_eligible(rp, ok, w)
+    codes = oracle.delta_encode(rp, ok, w)
+    assert np.array_equal(oracle.delta_decode(rp, codes, w), ok)
+    assert not oracle.delta_eligible(rp, np.array([row + lo - 1, row + lo + umax - 1], dtype=np.int32), w)
+    assert not oracle.delta_eligible(rp, np.array([row + lo, row + lo + umax + 1], dtype=np.int32), w)
+    # positive signed limit
+    assert oracle.delta_eligible(rp, np.array([row + (-lo - 1), row + (-lo - 1) + 1], dtype=np.int32), w)
+    assert not oracle.delta_eligible(rp, np.array([row - lo, row - lo + 1], dtype=np.int32), w)
+    # duplicates and unsorted rows are not encodable
+    assert not oracle.delta_eligible(rp, np.array([row, row], dtype=np.int32), w)
+    assert not oracle.delta_eligible(rp, np.array([row + 1, row], dtype=np.int32), w)
+    assert ncol > 0
+
+
+def test_irregular_matrices_are_not_delta_eligible():
+    _, _, rp, col, _ = synth.uniform_random(1 << 17, 16)
+    assert oracle.delta_width(rp, col) == 32
+
+
+# ---------------------------------------------------------------- merge path
+
+def _merge_path_by_steps(rp):
+    """Walk the merge of row ends and nonzeros one item at a time: a nonzero
+    j is consumed while j < rp[i+1], otherwise the row end i."""
+    n = len(rp) - 1
+    nnz = int(rp[-1])
+    i = j = 0
+    path = [(0, 0)]
+    while i < n or j < nnz:
+        if i < n and j >= rp[i + 1]:
+            i += 1
+        elif j < nnz:
+            j += 1
+        else:
+            i += 1
+        path.append((i, j))
+    return path
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_merge_tiles_match_step_simulation(case):
+    if case == 0:
+        rp = np.array([0], dtype=np.int32)                       # empty matrix
+    elif case == 1:
+        rp = np.array([0, 0, 0, 0], dtype=np.int32)              # only empty rows
+    elif case == 2:
+        rp = np.array([0, 50], dtype=np.int32)                   # one long row
+    elif case == 3:
+        rp = np.array([0, 3, 3, 3, 10, 11, 11], dtype=np.int32)  # mixed
+    else:
+        m, n, rp, _, _ = synth.tiny_random(30 + 7 * case, 40, 0.05 * case, case)
+    path = _merge_path_by_steps(rp)
+    assert path[-1] == (len(rp) - 1, int(rp[-1]))
+    ti, tj = oracle.merge_tiles(rp, 1)
+    assert list(zip(ti.tolist(), tj.tolist())) == path
+    for L in (2, 3, 7, 64):
+        ti, tj = oracle.merge_tiles(rp, L)
+        total = len(path) - 1
+        want = [path[min(t * L, total)] for t in range(len(ti))]
+        assert list(zip(ti.tolist(), tj.tolist())) == want
+        assert len(ti) == (total + L - 1) // L + 1
+
+
+def test_merge_tiles_invariants_on_rmat():
+    n, _, rp, _, _ = synth.rmat(14, 16)
+    L = 256
+    ti, tj = oracle.merge_tiles(rp, L)
+    assert ti[0] == 0 and tj[0] == 0
+    assert ti[-1] == n and tj[-1] == rp[-1]
+    assert np.all(np.diff(ti) >= 0) and np.all(np.diff(tj) >= 0)
+    steps = np.diff(ti.astype(np.int64) + tj)
+    assert np.all(steps[:-1] == L) and 0 < steps[-1] <= L
+    # sampled diagonals against the step rule
+    rp64 = rp.astype(np.int64)
+    for t in range(0, len(ti), 97):
+        i, j = int(ti[t]), int(tj[t])
+        # all row ends before i are consumed: rp[i] <= j; row end i is not: j <= rp[i+1] (when i<n)
+        assert i == n or j <= rp64[i + 1]
+        assert i == 0 or rp64[i] <= j
+
+
+# ---------------------------------------------------------------- long rows
+
+def test_long_rows_hand_built():
+    lens = [1, 5000, 3, 0, 4097, 4096, 9999]
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    assert oracle.long_rows(rp, 4096).tolist() == [1, 4, 6]
+    assert oracle.long_rows(rp, 100000).tolist() == []
+    assert oracle.long_row_threshold(4.0) == 4096
+    assert oracle.long_row_threshold(1000.0) == 32000
