@@ -1,0 +1,219 @@
+/*
+ * csrspmv — matrix-adaptive CSR sparse matrix-vector multiplication y = A x
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Elafrou, Goumas & Koziris, "Performance Analysis and
+ * Optimization of Sparse Matrix-Vector Multiplication on Modern Multi- and
+ * Many-Core Processors" (ICPP 2017): find the bottleneck classes of a matrix
+ * (memory bandwidth MB, memory latency ML, thread imbalance IMB, computation
+ * CMP; Sec. III-A), either by profiling micro-benchmarks against per-class
+ * performance bounds (Sec. III-B/C) or from cheap structural features
+ * (Sec. III-D), then apply the CSR-based remedies of the optimization pool
+ * jointly (Sec. III-E, Table II). The API follows the paper's problem
+ * statement: a square (or rectangular) matrix in CSR (Sec. II), FP64 values
+ * (Sec. IV-A), y overwritten by A x (Sec. II, Fig. 2), the same A reused for
+ * many products so that inspection and selection are paid once
+ * (Sec. IV-D) — an inspector/executor split.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device pointers (hipMalloc'ed or torch CUDA
+ *     tensors); pointers named h_* or out are host pointers.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the legacy default
+ *     stream of the current device.
+ *   - The current HIP device when a handle is created is the device the
+ *     handle lives on; later calls switch to it themselves.
+ *   - Every call returns a csr_status_t; nothing is thrown or aborted across
+ *     this boundary. csr_last_error() returns a message for the most recent
+ *     failure on the calling thread.
+ *   - A handle may be used from one stream at a time; calls on one handle are
+ *     not thread-safe.
+ */
+#ifndef CSRSPMV_H
+#define CSRSPMV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct csr_matrix_s *csr_matrix_t;
+
+typedef enum {
+    CSR_OK = 0,
+    CSR_ERR_INVALID_ARG = 1,     /* bad argument: NULL, negative size, aliasing */
+    CSR_ERR_INVALID_MATRIX = 2,  /* the CSR arrays violate the format */
+    CSR_ERR_OUT_OF_MEMORY = 3,   /* a device or host allocation failed */
+    CSR_ERR_DEVICE = 4,          /* a HIP runtime call failed */
+    CSR_ERR_UNSUPPORTED = 5,     /* e.g. nnz >= 2^31, delta codes on unsorted rows */
+    CSR_ERR_NOT_READY = 6        /* e.g. learned selection without loaded weights */
+} csr_status_t;
+
+/* Precision of the stored values (BASELINE precision sweep). FP64 storage
+ * computes in FP64 with FP64 x and y. FP32 and BF16 storage accumulate in
+ * FP32, with x and y in FP32 (x is rounded once by the caller). */
+typedef enum { CSR_VAL_F64 = 0, CSR_VAL_F32 = 1, CSR_VAL_BF16 = 2 } csr_val_t;
+
+/* Optimizations of the pool (Sec. III-E, Table II), combinable as a mask. */
+enum {
+    CSR_OPT_DELTA = 1,     /* MB:  delta-coded column indices (8 or 16 bit) + wide loads */
+    CSR_OPT_PREFETCH = 2,  /* ML:  streamed val/col with the x gathers issued ahead */
+    CSR_OPT_DECOMP = 4,    /* IMB: long rows split off and computed cooperatively */
+    CSR_OPT_MERGE = 8,     /* IMB: nnz-balanced merge-path split */
+    CSR_OPT_UNROLL = 16    /* CMP: unrolled independent accumulators, several rows per wave */
+};
+
+/* Bottleneck classes (Sec. III-A), as a mask. */
+enum { CSR_CLS_MB = 1, CSR_CLS_ML = 2, CSR_CLS_IMB = 4, CSR_CLS_CMP = 8 };
+
+/* Selection modes for csr_select. */
+typedef enum {
+    CSR_SEL_PLAIN = 0,       /* the baseline row-split kernel, no remedy */
+    CSR_SEL_PROFILE = 1,     /* micro-benchmarks + the rule of Sec. III-C, Fig. 4 */
+    CSR_SEL_LEARNED = 2,     /* features + the loaded MLP (falls back to PROFILE) */
+    CSR_SEL_EXHAUSTIVE = 3,  /* time every catalogue variant, keep the fastest */
+    CSR_SEL_FORCED = 4       /* use cfg->forced_opts / cfg parameters as given */
+} csr_sel_t;
+
+/* Tunables; csr_config_default() fills the defaults. */
+typedef struct {
+    double t_ml;             /* ML threshold on P_ML / P_CSR (paper: 1.25) */
+    double t_imb;            /* IMB threshold on P_IMB / P_CSR (paper: 1.24) */
+    double t_mb;             /* MB: P_CSR >= t_mb * P_MB reads "P_CSR ~ P_MB" */
+    double long_row_factor;  /* a row is long if nnz_i > max(factor*nnz_avg, long_row_floor) */
+    int32_t long_row_floor;
+    int32_t forced_opts;     /* CSR_SEL_FORCED: mask of CSR_OPT_* */
+    int32_t rows_per_group;  /* 0 = auto: lanes per row G in {1,2,4,...,64} */
+    int32_t merge_items;     /* 0 = auto: merge-path items per tile L */
+    int32_t autotune;        /* 1 = time a small parameter grid for the chosen remedies */
+    int32_t timing_calls;    /* SpMV calls per timing run inside selection (default 32) */
+} csr_config_t;
+
+/* What csr_select decided and what it cost. */
+typedef struct {
+    int32_t opts;            /* CSR_OPT_* mask in use */
+    int32_t classes;         /* CSR_CLS_* mask (PROFILE), -1 if not computed */
+    int32_t variant_id;      /* index into the 16-entry catalogue, -1 if outside it */
+    int32_t lanes_per_row;   /* G of the row-split kernels */
+    int32_t merge_items;     /* L of the merge-path kernel */
+    int32_t delta_bits;      /* 8, 16, or 32 (plain int32 indices) */
+    int32_t n_long_rows;     /* rows taken out by the decomposition */
+    int32_t reserved;
+    double p_csr, p_mb, p_ml, p_imb, p_cmp, p_peak;  /* flop/s (PROFILE) */
+    double b_max;            /* B/s used for the bounds */
+    double t_select_ms;      /* features/probes + decision */
+    double t_prep_ms;        /* format conversion for the chosen plan */
+    double format_bytes;     /* algorithmic bytes of one SpMV with this plan */
+} csr_plan_info_t;
+
+/* The 16 features of Sec. III-D, Table I (plus two project-defined ones):
+ * N, nnz_min, nnz_max, nnz_avg, nnz_sd, bw_min, bw_max, bw_avg, bw_sd,
+ * scatter_avg, scatter_sd, clustering_avg, misses_avg, size, mean_col_gap,
+ * x_reuse. isum holds the exact integer sums they come from: sum nnz,
+ * sum nnz^2, sum bw, sum bw^2, sum misses, sum groups, x-reuse shared and
+ * distinct line counts. */
+typedef struct {
+    double f[16];
+    int64_t isum[8];
+    int32_t rows_sorted;     /* 1 if every row is strictly increasing */
+    int32_t reserved;
+} csr_features_t;
+
+/* Fill *cfg with the defaults (t_ml 1.25, t_imb 1.24, t_mb 0.8,
+ * long_row_factor 32, long_row_floor 4096, autotune 1, timing_calls 32). */
+void csr_config_default(csr_config_t *cfg);
+
+/*
+ * Ingest (Sec. II: the CSR format). Copies the caller's CSR arrays into
+ * device memory owned by the new handle, validates them on the device
+ * (row_ptr[0] = 0, row_ptr non-decreasing, row_ptr[n_rows] = nnz,
+ * 0 <= col_idx < n_cols), records whether every row is strictly increasing,
+ * and converts the values to `storage` (FP32: IEEE round-to-nearest-even;
+ * BF16: one round-to-nearest-even step from FP64).
+ *   d_row_ptr  int32[n_rows + 1]   device
+ *   d_col_idx  int32[nnz]          device
+ *   d_val      double[nnz]         device
+ * Synchronizes `stream` before returning, so the caller may free its arrays.
+ * The plan starts as CSR_SEL_PLAIN. Errors: CSR_ERR_INVALID_ARG (NULL out,
+ * negative sizes, NULL arrays with nnz > 0), CSR_ERR_UNSUPPORTED
+ * (nnz >= 2^31), CSR_ERR_INVALID_MATRIX (no handle is created),
+ * CSR_ERR_OUT_OF_MEMORY, CSR_ERR_DEVICE. On error *out is NULL.
+ */
+csr_status_t csr_create(csr_matrix_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz,
+                        const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                        const double *d_val, int32_t storage, void *stream);
+
+/* Frees everything the handle owns. NULL is accepted and ignored. */
+void csr_destroy(csr_matrix_t A);
+
+/*
+ * Feature extraction (Sec. III-D, Table I): one pass over row_ptr and
+ * col_idx on the device; integer sums are exact, the FP64 features are
+ * formed from them on the host. Synchronizes `stream`.
+ */
+csr_status_t csr_inspect(csr_matrix_t A, csr_features_t *out, void *stream);
+
+/*
+ * Variant selection (Sec. III-C to III-E) and preprocessing of the chosen
+ * plan (delta codes, merge-path tiles, long-row list). cfg may be NULL for
+ * the defaults; out may be NULL. Synchronizes `stream`. PROFILE and
+ * EXHAUSTIVE launch SpMV kernels that write into internal scratch vectors.
+ */
+csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg,
+                        csr_plan_info_t *out, void *stream);
+
+/*
+ * y = A x (Sec. II, Fig. 2) with the current plan. Asynchronous on `stream`.
+ *   d_x  n_cols elements, d_y  n_rows elements, device; FP64 for FP64
+ *   storage, FP32 for FP32/BF16 storage. x and y must not overlap
+ *   (CSR_ERR_INVALID_ARG).
+ */
+csr_status_t csr_spmv(csr_matrix_t A, const void *d_x, void *d_y, void *stream);
+
+/*
+ * count independent products y_k = A_k x_k in one persistent launch.
+ * Every handle must live on the current device and share one storage type.
+ * h_A, h_x, h_y are host arrays of count handles / device pointers. The
+ * first call for a given handle list builds a device work queue (cached);
+ * asynchronous on `stream` after that.
+ */
+csr_status_t csr_spmv_batched(int32_t count, const csr_matrix_t *h_A,
+                              const void *const *h_x, void *const *h_y, void *stream);
+
+/* Human-readable name of a status code (static storage). */
+const char *csr_status_str(csr_status_t s);
+
+/* Message describing the most recent failure on the calling thread. */
+const char *csr_last_error(void);
+
+/* Basic facts about a handle. */
+csr_status_t csr_query(csr_matrix_t A, int32_t *n_rows, int32_t *n_cols, int64_t *nnz,
+                       int32_t *storage, int32_t *rows_sorted);
+
+/*
+ * Test support: copies an internal device array of the handle to host
+ * memory so that encodings and partitions can be compared bit for bit.
+ *   what: 0 stored values (nnz elements of the storage type),
+ *         1 delta codes (nnz bytes or uint16), 2 merge tile rows int32[T+1],
+ *         3 merge tile nonzero offsets int32[T+1], 4 long-row list int32[n],
+ *         5 plan info (csr_plan_info_t)
+ * Returns CSR_ERR_INVALID_ARG if `bytes` differs from the array's size
+ * (*needed receives that size when non-NULL) or the array does not exist.
+ * Synchronizes `stream`.
+ */
+csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t bytes,
+                            size_t *needed, void *stream);
+
+/*
+ * B_max probe (Sec. III-B; Sec. IV-A, Table III: STREAM triad). Runs
+ * a[i] = b[i] + s * c[i] over three FP64 arrays of `bytes_per_array` bytes
+ * each (allocated and freed inside) and returns the sustained bandwidth in
+ * bytes/s counting 3 * bytes_per_array per pass (best of `reps` passes).
+ */
+csr_status_t csr_triad(size_t bytes_per_array, int32_t reps, double *gbytes_per_s, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CSRSPMV_H */

@@ -1,0 +1,507 @@
+// C ABI of libcsrspmv: handle life cycle, ingest, the SpMV entry point and the
+// plan machinery shared by the selectors.
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "internal.h"
+
+namespace csr {
+
+namespace {
+thread_local std::string g_err;
+
+// Test hook: CSRSPMV_FAIL_ALLOC_AFTER=n makes the (n+1)-th device allocation
+// of the process fail, to exercise the out-of-memory paths without a GPU
+// actually running out.
+std::atomic<long long> g_alloc_count{0};
+long long fail_alloc_after() {
+    static long long v = [] {
+        const char *e = std::getenv("CSRSPMV_FAIL_ALLOC_AFTER");
+        return e ? std::atoll(e) : -1LL;
+    }();
+    return v;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+}  // namespace
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+csr_status_t fail(csr_status_t s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+csr_status_t hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? CSR_ERR_OUT_OF_MEMORY : CSR_ERR_DEVICE;
+}
+
+csr_status_t DevBuf::alloc(size_t n) {
+    release();
+    if (n == 0) n = 256;  // keep a valid, aligned pointer for empty arrays
+    const long long lim = fail_alloc_after();
+    if (lim >= 0 && g_alloc_count.fetch_add(1) >= lim)
+        return fail(CSR_ERR_OUT_OF_MEMORY, "injected allocation failure");
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return hip_fail(e, "hipMalloc");
+    }
+    bytes = n;
+    return CSR_OK;
+}
+
+XcdGrid xcd_grid(int64_t nblk) {
+    XcdGrid g;
+    g.nblk = nblk;
+    g.per_xcd = (nblk + kNumXcd - 1) / kNumXcd;
+    g.launched = g.per_xcd * kNumXcd;
+    return g;
+}
+
+int default_lanes_per_row(double nnz_avg) {
+    // G0 = clamp(2^round(log2 nnz_avg), 1, 64)
+    if (!(nnz_avg > 1.0)) return 1;
+    int e = (int)std::lround(std::log2(nnz_avg));
+    if (e < 0) e = 0;
+    if (e > 6) e = 6;
+    return 1 << e;
+}
+
+size_t storage_bytes(int storage) {
+    return storage == CSR_VAL_F64 ? 8 : storage == CSR_VAL_F32 ? 4 : 2;
+}
+
+hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void *y,
+                       hipStream_t s) {
+    const void *arr[6] = {A->rp.p, A->col.p, A->codes.p, A->val.p, x, y};
+    const int32_t skip = INT32_MAX;
+    switch (A->storage) {
+    case CSR_VAL_F64:
+        return launch_rowsplit_s0(P.G, P.idx, P.nt != 0, P.U, arr, skip, A->n_rows, P.rows_iter, s);
+    case CSR_VAL_F32:
+        return launch_rowsplit_s1(P.G, P.idx, P.nt != 0, P.U, arr, skip, A->n_rows, P.rows_iter, s);
+    default:
+        return launch_rowsplit_s2(P.G, P.idx, P.nt != 0, P.U, arr, skip, A->n_rows, P.rows_iter, s);
+    }
+}
+
+// Algorithmic bytes of one SpMV under plan P: every array read once, y written
+// once (values + indices or codes + row pointers + x + y + side tables).
+double plan_bytes(const csr_matrix_s *A, const Plan &P) {
+    const double vb = (double)storage_bytes(A->storage);
+    const double xb = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
+    const double ib = P.idx == IDX_D16 ? 2.0 : P.idx == IDX_D8 ? 1.0 : 4.0;
+    double b = (double)A->nnz * (vb + ib) + 4.0 * (A->n_rows + 1) + xb * A->n_cols +
+               xb * A->n_rows;
+    return b;
+}
+
+int catalogue_id(int32_t opts);
+
+// Realize an optimization mask as a concrete plan, building what it needs.
+csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Plan *out,
+                     hipStream_t s) {
+    Plan P;
+    P.opts = opts;
+    const double nnz_avg = A->n_rows ? (double)A->nnz / A->n_rows : 0.0;
+    const int G0 = cfg.rows_per_group > 0 ? cfg.rows_per_group : default_lanes_per_row(nnz_avg);
+    P.G = G0;
+    P.U = 1;
+    P.rows_iter = 1;
+    if (opts & CSR_OPT_UNROLL) {
+        P.G = G0 >= 4 ? G0 / 4 : 1;
+        P.U = 4;
+    }
+    if (opts & CSR_OPT_PREFETCH) {
+        P.nt = 1;
+        P.U = 4;
+    }
+    if (opts & CSR_OPT_DELTA) {
+        if (A->code_bits == 32 && A->rows_sorted) {
+            for (int bits : {8, 16}) {
+                DevBuf flags;
+                csr_status_t st = flags.alloc(sizeof(int32_t));
+                if (st != CSR_OK) return st;
+                CSR_HIP(hipMemsetAsync(flags.p, 0, sizeof(int32_t), s));
+                DevBuf codes;
+                st = codes.alloc((size_t)A->nnz * (bits / 8));
+                if (st != CSR_OK) return st;
+                CSR_HIP(launch_delta_encode(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->n_rows,
+                                            bits, codes.p, flags.as<int32_t>(), s));
+                int32_t h = 0;
+                CSR_HIP(hipMemcpyAsync(&h, flags.p, sizeof(h), hipMemcpyDeviceToHost, s));
+                CSR_HIP(hipStreamSynchronize(s));
+                if (h == 0) {
+                    std::swap(A->codes.p, codes.p);
+                    std::swap(A->codes.bytes, codes.bytes);
+                    A->code_bits = bits;
+                    break;
+                }
+            }
+            if (A->code_bits == 32) A->code_bits = 0;  // tried, not eligible
+        }
+        if (A->code_bits == 8 || A->code_bits == 16) {
+            P.idx = A->code_bits == 8 ? IDX_D8 : IDX_D16;
+            P.U = 1;
+        } else {
+            // Not eligible: only the wide-load half of the remedy applies.
+            P.U = 4;
+        }
+    }
+    P.variant_id = catalogue_id(opts);
+    *out = P;
+    return CSR_OK;
+}
+
+// Scratch vectors for timed selection runs (x = 0, so no value can turn into
+// a subnormal or non-finite operand that changes the timing).
+csr_status_t ensure_scratch(csr_matrix_s *A, hipStream_t s) {
+    const size_t xb = A->storage == CSR_VAL_F64 ? 8 : 4;
+    csr_status_t st;
+    if (!A->scratch_x.p) {
+        if ((st = A->scratch_x.alloc(xb * (size_t)A->n_cols)) != CSR_OK) return st;
+        CSR_HIP(hipMemsetAsync(A->scratch_x.p, 0, A->scratch_x.bytes, s));
+    }
+    if (!A->scratch_y.p) {
+        if ((st = A->scratch_y.alloc(xb * (size_t)A->n_rows)) != CSR_OK) return st;
+    }
+    return CSR_OK;
+}
+
+// Time `calls` back-to-back SpMVs under plan P between two events, `runs`
+// times after one untimed call; returns the run-summary time per call in ms:
+// the reciprocal of the harmonic mean of the per-run rates (Sec. IV-A).
+csr_status_t time_plan(csr_matrix_s *A, const Plan &P, int calls, int runs, hipStream_t s,
+                       double *ms_per_call) {
+    csr_status_t st = ensure_scratch(A, s);
+    if (st != CSR_OK) return st;
+    hipEvent_t e0, e1;
+    CSR_HIP(hipEventCreate(&e0));
+    CSR_HIP(hipEventCreate(&e1));
+    hipError_t e = launch_spmv(A, P, A->scratch_x.p, A->scratch_y.p, s);
+    double inv_rate_sum = 0.0;  // sum over runs of (ms per call) = sum of 1/rate
+    for (int r = 0; r < runs && e == hipSuccess; ++r) {
+        e = hipEventRecord(e0, s);
+        for (int c = 0; c < calls && e == hipSuccess; ++c)
+            e = launch_spmv(A, P, A->scratch_x.p, A->scratch_y.p, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        inv_rate_sum += (double)ms / calls;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "timed SpMV");
+    // harmonic mean of rates r_k = W / t_k is runs / sum(1/r_k) = W * runs / sum t_k
+    *ms_per_call = inv_rate_sum / runs;
+    return CSR_OK;
+}
+
+// Catalogue of optimization sets swept by the exhaustive selector: the
+// baseline, the 5 singles and the 10 pairs (Sec. IV-D, trivial optimizers).
+const int32_t kCatalogue[16] = {0,  1,  2,  4,  8,  16, 1 | 2, 1 | 4, 1 | 8, 1 | 16,
+                                2 | 4, 2 | 8, 2 | 16, 4 | 8, 4 | 16, 8 | 16};
+
+int catalogue_id(int32_t opts) {
+    for (int k = 0; k < 16; ++k)
+        if (kCatalogue[k] == opts) return k;
+    return -1;
+}
+
+bool opts_available(int32_t opts) { return (opts & (CSR_OPT_MERGE | CSR_OPT_DECOMP)) == 0; }
+
+void fill_info(const csr_matrix_s *A, const Plan &P, csr_plan_info_t *info) {
+    info->opts = P.opts;
+    info->lanes_per_row = P.G;
+    info->merge_items = P.L;
+    info->delta_bits = P.idx == IDX_D16 ? 16 : P.idx == IDX_D8 ? 8 : 32;
+    info->n_long_rows = P.long_rows ? A->n_long : 0;
+    info->variant_id = P.variant_id;
+    info->format_bytes = plan_bytes(A, P);
+}
+
+}  // namespace csr
+
+using namespace csr;
+
+extern "C" {
+
+void csr_config_default(csr_config_t *cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->t_ml = 1.25;
+    cfg->t_imb = 1.24;
+    cfg->t_mb = 0.8;
+    cfg->long_row_factor = 32.0;
+    cfg->long_row_floor = 4096;
+    cfg->forced_opts = 0;
+    cfg->rows_per_group = 0;
+    cfg->merge_items = 0;
+    cfg->autotune = 1;
+    cfg->timing_calls = 32;
+}
+
+const char *csr_status_str(csr_status_t s) {
+    switch (s) {
+    case CSR_OK: return "CSR_OK";
+    case CSR_ERR_INVALID_ARG: return "CSR_ERR_INVALID_ARG";
+    case CSR_ERR_INVALID_MATRIX: return "CSR_ERR_INVALID_MATRIX";
+    case CSR_ERR_OUT_OF_MEMORY: return "CSR_ERR_OUT_OF_MEMORY";
+    case CSR_ERR_DEVICE: return "CSR_ERR_DEVICE";
+    case CSR_ERR_UNSUPPORTED: return "CSR_ERR_UNSUPPORTED";
+    case CSR_ERR_NOT_READY: return "CSR_ERR_NOT_READY";
+    }
+    return "CSR_ERR_UNKNOWN";
+}
+
+const char *csr_last_error(void) { return g_err.c_str(); }
+
+csr_status_t csr_create(csr_matrix_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz,
+                        const int32_t *d_row_ptr, const int32_t *d_col_idx, const double *d_val,
+                        int32_t storage, void *stream) {
+    if (!out) return fail(CSR_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_rows < 0 || n_cols < 0 || nnz < 0)
+        return fail(CSR_ERR_INVALID_ARG, "negative size");
+    if (nnz >= (int64_t)INT32_MAX) return fail(CSR_ERR_UNSUPPORTED, "nnz >= 2^31 - 1");
+    if (!d_row_ptr || (nnz > 0 && (!d_col_idx || !d_val)))
+        return fail(CSR_ERR_INVALID_ARG, "NULL array");
+    if (storage < CSR_VAL_F64 || storage > CSR_VAL_BF16)
+        return fail(CSR_ERR_INVALID_ARG, "unknown storage type");
+    hipStream_t s = (hipStream_t)stream;
+    auto *A = new (std::nothrow) csr_matrix_s();
+    if (!A) return fail(CSR_ERR_OUT_OF_MEMORY, "host allocation");
+    auto bail = [&](csr_status_t st) {
+        (void)hipStreamSynchronize(s);
+        delete A;
+        return st;
+    };
+    if (hipGetDevice(&A->device) != hipSuccess) return bail(fail(CSR_ERR_DEVICE, "hipGetDevice"));
+    A->n_rows = n_rows;
+    A->n_cols = n_cols;
+    A->nnz = nnz;
+    A->storage = storage;
+    csr_status_t st;
+    if ((st = A->rp.alloc(sizeof(int32_t) * ((size_t)n_rows + 1))) != CSR_OK) return bail(st);
+    if ((st = A->col.alloc(sizeof(int32_t) * (size_t)nnz)) != CSR_OK) return bail(st);
+    if ((st = A->val.alloc(storage_bytes(storage) * (size_t)nnz)) != CSR_OK) return bail(st);
+    DevBuf flags;
+    if ((st = flags.alloc(sizeof(int32_t))) != CSR_OK) return bail(st);
+    hipError_t e;
+#define STEP(call)                                              \
+    if ((e = (call)) != hipSuccess) return bail(hip_fail(e, #call));
+    STEP(hipMemcpyAsync(A->rp.p, d_row_ptr, sizeof(int32_t) * ((size_t)n_rows + 1),
+                        hipMemcpyDeviceToDevice, s));
+    if (nnz > 0)
+        STEP(hipMemcpyAsync(A->col.p, d_col_idx, sizeof(int32_t) * (size_t)nnz,
+                            hipMemcpyDeviceToDevice, s));
+    STEP(hipMemsetAsync(flags.p, 0, sizeof(int32_t), s));
+    STEP(launch_validate(A->rp.as<int32_t>(), A->col.as<int32_t>(), n_rows, n_cols, nnz,
+                         flags.as<int32_t>(), s));
+    int32_t h = 0;
+    STEP(hipMemcpyAsync(&h, flags.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    STEP(hipStreamSynchronize(s));
+    if (h & 7) {
+        std::string why;
+        if (h & 1) why += " row_ptr[0]!=0 or row_ptr[n]!=nnz;";
+        if (h & 2) why += " row_ptr not monotone within [0,nnz];";
+        if (h & 4) why += " column index out of range;";
+        return bail(fail(CSR_ERR_INVALID_MATRIX, "invalid CSR:" + why));
+    }
+    A->rows_sorted = (h & 8) ? 0 : 1;
+    STEP(launch_convert_values(d_val, A->val.p, nnz, storage, s));
+    STEP(hipStreamSynchronize(s));
+#undef STEP
+    csr_config_t cfg;
+    csr_config_default(&cfg);
+    if ((st = realize(A, 0, cfg, &A->plan, s)) != CSR_OK) return bail(st);
+    A->info.classes = -1;
+    fill_info(A, A->plan, &A->info);
+    *out = A;
+    return CSR_OK;
+}
+
+void csr_destroy(csr_matrix_t A) {
+    if (!A) return;
+    DeviceGuard g(A->device);
+    (void)hipDeviceSynchronize();
+    delete A;
+}
+
+csr_status_t csr_query(csr_matrix_t A, int32_t *n_rows, int32_t *n_cols, int64_t *nnz,
+                       int32_t *storage, int32_t *rows_sorted) {
+    if (!A) return fail(CSR_ERR_INVALID_ARG, "NULL handle");
+    if (n_rows) *n_rows = A->n_rows;
+    if (n_cols) *n_cols = A->n_cols;
+    if (nnz) *nnz = A->nnz;
+    if (storage) *storage = A->storage;
+    if (rows_sorted) *rows_sorted = A->rows_sorted;
+    return CSR_OK;
+}
+
+csr_status_t csr_spmv(csr_matrix_t A, const void *d_x, void *d_y, void *stream) {
+    if (!A) return fail(CSR_ERR_INVALID_ARG, "NULL handle");
+    if ((!d_x && A->n_cols > 0) || (!d_y && A->n_rows > 0))
+        return fail(CSR_ERR_INVALID_ARG, "NULL vector");
+    const size_t xb = A->storage == CSR_VAL_F64 ? 8 : 4;
+    const uintptr_t x0 = (uintptr_t)d_x, x1 = x0 + xb * (size_t)A->n_cols;
+    const uintptr_t y0 = (uintptr_t)d_y, y1 = y0 + xb * (size_t)A->n_rows;
+    if (A->n_rows > 0 && A->n_cols > 0 && x0 < y1 && y0 < x1)
+        return fail(CSR_ERR_INVALID_ARG, "x and y overlap");
+    if (A->n_rows == 0) return CSR_OK;
+    DeviceGuard g(A->device);
+    CSR_HIP(launch_spmv(A, A->plan, d_x, d_y, (hipStream_t)stream));
+    return CSR_OK;
+}
+
+csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in,
+                        csr_plan_info_t *out, void *stream) {
+    if (!A) return fail(CSR_ERR_INVALID_ARG, "NULL handle");
+    csr_config_t cfg;
+    if (cfg_in) cfg = *cfg_in;
+    else csr_config_default(&cfg);
+    DeviceGuard g(A->device);
+    hipStream_t s = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    Plan P;
+    csr_status_t st;
+    switch (mode) {
+    case CSR_SEL_PLAIN:
+        st = realize(A, 0, cfg, &P, s);
+        break;
+    case CSR_SEL_FORCED:
+        if (cfg.forced_opts & ~31) return fail(CSR_ERR_INVALID_ARG, "unknown optimization bits");
+        if (!opts_available(cfg.forced_opts))
+            return fail(CSR_ERR_UNSUPPORTED, "optimization not available");
+        st = realize(A, cfg.forced_opts, cfg, &P, s);
+        break;
+    case CSR_SEL_EXHAUSTIVE: {
+        // Time every available catalogue variant; keep the fastest.
+        double best = 1e300;
+        st = CSR_OK;
+        const int calls = cfg.timing_calls > 0 ? cfg.timing_calls : 32;
+        for (int k = 0; k < 16 && st == CSR_OK; ++k) {
+            if (!opts_available(kCatalogue[k])) continue;
+            Plan Q;
+            if ((st = realize(A, kCatalogue[k], cfg, &Q, s)) != CSR_OK) break;
+            double ms = 0;
+            if ((st = time_plan(A, Q, calls, 3, s, &ms)) != CSR_OK) break;
+            if (ms < best) {
+                best = ms;
+                P = Q;
+            }
+        }
+        break;
+    }
+    default:
+        return fail(CSR_ERR_UNSUPPORTED, "selection mode not available");
+    }
+    if (st != CSR_OK) return st;
+    CSR_HIP(hipStreamSynchronize(s));
+    A->plan = P;
+    A->info = csr_plan_info_t{};
+    A->info.classes = -1;
+    fill_info(A, P, &A->info);
+    A->info.t_select_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (out) *out = A->info;
+    return CSR_OK;
+}
+
+csr_status_t csr_inspect(csr_matrix_t A, csr_features_t *out, void *stream) {
+    (void)stream;
+    if (!A || !out) return fail(CSR_ERR_INVALID_ARG, "NULL argument");
+    return fail(CSR_ERR_UNSUPPORTED, "feature extraction not built");
+}
+
+csr_status_t csr_spmv_batched(int32_t count, const csr_matrix_t *h_A, const void *const *h_x,
+                              void *const *h_y, void *stream) {
+    (void)stream;
+    if (count < 0 || (count > 0 && (!h_A || !h_x || !h_y)))
+        return fail(CSR_ERR_INVALID_ARG, "bad batch arguments");
+    return fail(CSR_ERR_UNSUPPORTED, "batched launch not built");
+}
+
+csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t bytes,
+                            size_t *needed, void *stream) {
+    if (!A) return fail(CSR_ERR_INVALID_ARG, "NULL handle");
+    DeviceGuard g(A->device);
+    const void *src = nullptr;
+    size_t n = 0;
+    switch (what) {
+    case 0: src = A->val.p; n = storage_bytes(A->storage) * (size_t)A->nnz; break;
+    case 1:
+        if (A->code_bits == 8 || A->code_bits == 16) {
+            src = A->codes.p;
+            n = (size_t)A->nnz * (A->code_bits / 8);
+        }
+        break;
+    case 2: if (A->n_tiles > 0) { src = A->tile_i.p; n = sizeof(int32_t) * (A->n_tiles + 1); } break;
+    case 3: if (A->n_tiles > 0) { src = A->tile_j.p; n = sizeof(int32_t) * (A->n_tiles + 1); } break;
+    case 4: if (A->n_long > 0) { src = A->long_list.p; n = sizeof(int32_t) * A->n_long; } break;
+    case 5:
+        if (needed) *needed = sizeof(csr_plan_info_t);
+        if (bytes != sizeof(csr_plan_info_t) || !h_dst) return fail(CSR_ERR_INVALID_ARG, "size");
+        std::memcpy(h_dst, &A->info, sizeof(csr_plan_info_t));
+        return CSR_OK;
+    default: return fail(CSR_ERR_INVALID_ARG, "unknown array id");
+    }
+    if (needed) *needed = n;
+    if (!src) return fail(CSR_ERR_INVALID_ARG, "array not present");
+    if (bytes != n || !h_dst) return fail(CSR_ERR_INVALID_ARG, "size mismatch");
+    if (n == 0) return CSR_OK;
+    CSR_HIP(hipMemcpyAsync(h_dst, src, n, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    CSR_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return CSR_OK;
+}
+
+csr_status_t csr_triad(size_t bytes_per_array, int32_t reps, double *gbytes_per_s, void *stream) {
+    if (!gbytes_per_s || reps < 1 || bytes_per_array < 4096)
+        return fail(CSR_ERR_INVALID_ARG, "bad triad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = (int64_t)(bytes_per_array / 16) * 2;
+    DevBuf a, b, c;
+    csr_status_t st;
+    if ((st = a.alloc(n * 8)) != CSR_OK || (st = b.alloc(n * 8)) != CSR_OK ||
+        (st = c.alloc(n * 8)) != CSR_OK)
+        return st;
+    CSR_HIP(hipMemsetAsync(b.p, 0, n * 8, s));
+    CSR_HIP(hipMemsetAsync(c.p, 0, n * 8, s));
+    hipEvent_t e0, e1;
+    CSR_HIP(hipEventCreate(&e0));
+    CSR_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    CSR_HIP(launch_triad(a.as<double>(), b.as<double>(), c.as<double>(), 3.0, n, s));
+    for (int r = 0; r < reps; ++r) {
+        CSR_HIP(hipEventRecord(e0, s));
+        CSR_HIP(launch_triad(a.as<double>(), b.as<double>(), c.as<double>(), 3.0, n, s));
+        CSR_HIP(hipEventRecord(e1, s));
+        CSR_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        CSR_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) best = ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *gbytes_per_s = 3.0 * 8.0 * (double)n / (best * 1e-3);
+    return CSR_OK;
+}
+
+}  // extern "C"

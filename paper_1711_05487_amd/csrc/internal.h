@@ -1,0 +1,137 @@
+// Internal declarations shared by the HIP sources of libcsrspmv.
+// Not installed; the public interface is include/csrspmv.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "csrspmv.h"
+
+namespace csr {
+
+constexpr int kBlock = 256;       // threads per workgroup (4 wave64s)
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies
+
+enum IdxMode { IDX_I32 = 0, IDX_D16 = 1, IDX_D8 = 2 };
+
+// Error plumbing -------------------------------------------------------------
+void set_error(const std::string &msg);
+csr_status_t fail(csr_status_t s, const std::string &msg);
+csr_status_t hip_fail(hipError_t e, const char *what);
+
+#define CSR_HIP(call)                                                  \
+    do {                                                               \
+        hipError_t _e = (call);                                        \
+        if (_e != hipSuccess) return ::csr::hip_fail(_e, #call);       \
+    } while (0)
+
+// Device memory owned by a handle (freed in the destructor).
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    csr_status_t alloc(size_t n);
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Grid shape of a static-partition launch: `nblk` logical workgroups, padded to
+// a multiple of 8 so that logical block l = (b % 8) * per_xcd + b / 8 gives
+// every XCD one contiguous range of logical blocks (workgroups are dispatched
+// to the XCDs round-robin).
+struct XcdGrid {
+    int64_t nblk = 0;     // logical blocks that carry work
+    int64_t per_xcd = 0;  // ceil(nblk / 8)
+    int64_t launched = 0; // 8 * per_xcd
+};
+XcdGrid xcd_grid(int64_t nblk);
+
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t per_xcd) {
+    int64_t b = blockIdx.x;
+    return (b % kNumXcd) * per_xcd + b / kNumXcd;
+}
+
+// Execution plan of one handle -------------------------------------------------
+struct Plan {
+    int32_t opts = 0;        // CSR_OPT_* mask
+    int32_t G = 1;           // lanes per row (row-split kernels)
+    int32_t U = 1;           // independent accumulators per lane
+    int32_t rows_iter = 1;   // rows per lane group (static partition chunk)
+    int32_t L = 0;           // merge-path items per tile
+    int32_t idx = IDX_I32;   // index encoding
+    int32_t nt = 0;          // non-temporal val/col stream
+    int32_t long_rows = 0;   // decomposition active
+    int32_t variant_id = 0;
+};
+
+}  // namespace csr
+
+struct csr_matrix_s {
+    int device = 0;
+    int32_t n_rows = 0, n_cols = 0;
+    int64_t nnz = 0;
+    int32_t storage = CSR_VAL_F64;
+    int32_t rows_sorted = 0;
+    csr::DevBuf rp, col, val;      // CSR arrays (values in storage precision)
+    csr::DevBuf codes;             // delta codes (uint8 or uint16)
+    int32_t code_bits = 32;        // 8 / 16 when `codes` holds a valid encoding
+    csr::DevBuf tile_i, tile_j;    // merge-path tile table, T+1 entries each
+    csr::DevBuf tile_c;            // absolute column at each tile start (delta)
+    csr::DevBuf carry;             // per-tile carry of the merge-path kernel
+    int64_t n_tiles = 0;
+    int32_t tiles_L = 0;
+    csr::DevBuf long_list;         // decomposition: long rows (ascending)
+    csr::DevBuf long_part;         // decomposition: per-chunk partial sums
+    csr::DevBuf long_chunk_row;    // decomposition: chunk -> long-row slot
+    int32_t n_long = 0;
+    int64_t long_tau = -1;
+    int64_t n_long_chunks = 0;
+    csr::DevBuf short_rows;        // decomposition: rows that stay in the row pass
+    int32_t n_short = 0;
+    csr::Plan plan;
+    csr_plan_info_t info{};
+    int has_features = 0;
+    csr_features_t feat{};
+    csr::DevBuf scratch_x, scratch_y, scratch_col;  // selection probes
+};
+
+namespace csr {
+
+// Launchers (device code lives in the k_*.hip files) ----------------------------
+hipError_t launch_validate(const int32_t *rp, const int32_t *col, int32_t n_rows,
+                           int32_t n_cols, int64_t nnz, int32_t *d_flags, hipStream_t s);
+hipError_t launch_delta_encode(const int32_t *rp, const int32_t *col, int32_t n_rows, int bits,
+                               void *codes, int32_t *d_flags, hipStream_t s);
+// arr = {rp, col, codes, val, x, y}
+hipError_t launch_rowsplit_s0(int G, int idx, bool nt, int U, const void *const *arr,
+                              int32_t skip_above, int32_t n_rows, int32_t rows_iter,
+                              hipStream_t s);
+hipError_t launch_rowsplit_s1(int G, int idx, bool nt, int U, const void *const *arr,
+                              int32_t skip_above, int32_t n_rows, int32_t rows_iter,
+                              hipStream_t s);
+hipError_t launch_rowsplit_s2(int G, int idx, bool nt, int U, const void *const *arr,
+                              int32_t skip_above, int32_t n_rows, int32_t rows_iter,
+                              hipStream_t s);
+hipError_t launch_convert_values(const double *src, void *dst, int64_t n, int storage,
+                                 hipStream_t s);
+hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void *y,
+                       hipStream_t s);
+hipError_t launch_triad(double *a, const double *b, const double *c, double scalar,
+                        int64_t n, hipStream_t s);
+
+// Host helpers -------------------------------------------------------------------
+int default_lanes_per_row(double nnz_avg);
+size_t storage_bytes(int storage);
+
+}  // namespace csr

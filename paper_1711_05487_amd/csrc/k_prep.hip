@@ -1,0 +1,185 @@
+// Ingest kernels (CSR validation, value-precision conversion) and the B_max
+// probe (a STREAM-style triad, Sec. IV-A, Table III).
+#include "device.h"
+
+namespace csr {
+namespace {
+
+// One wave per row, grid-stride. Flags (integer atomics only):
+//   1 row_ptr[0] != 0 or row_ptr[n_rows] != nnz
+//   2 row_ptr decreasing or outside [0, nnz]
+//   4 a column outside [0, n_cols)
+//   8 a row that is not strictly increasing (a property, not an error)
+// A row whose bounds are invalid is not read, so malformed input never sends
+// a load out of the arrays' bounds.
+__global__ __launch_bounds__(kBlock) void k_validate(const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col,
+                                                     int32_t n_rows, int32_t n_cols, int64_t nnz,
+                                                     int32_t *__restrict__ flags) {
+    const int lane = threadIdx.x % kWave;
+    const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kBlock / kWave;
+    if (wave == 0 && lane == 0) {
+        if (rp[0] != 0 || (int64_t)rp[n_rows] != nnz) atomicOr(flags, 1);
+    }
+    for (int64_t r = wave; r < n_rows; r += nwaves) {
+        const int32_t b = rp[r], e = rp[r + 1];
+        if (e < b || b < 0 || (int64_t)e > nnz) {
+            if (lane == 0) atomicOr(flags, 2);
+            continue;
+        }
+        bool bad = false, unsorted = false;
+        for (int32_t j = b + lane; j < e; j += kWave) {
+            const int32_t c = col[j];
+            if (c < 0 || c >= n_cols) bad = true;
+            if (j > b && col[j - 1] >= c) unsorted = true;
+        }
+        const uint64_t mb = __ballot(bad), mu = __ballot(unsorted);
+        if (lane == 0 && (mb | mu)) atomicOr(flags, (mb ? 4 : 0) | (mu ? 8 : 0));
+    }
+}
+
+// FP64 -> BF16 with one round-to-nearest-even step, from the IEEE-754 binary64
+// fields: keep 8 significant bits (7 stored) at the exponent's BF16 quantum,
+// round on the discarded bits (ties to an even kept part), renormalize a carry
+// out of the significand, saturate to infinity above the largest finite value.
+__device__ __forceinline__ uint16_t f64_to_bf16(double d) {
+    const uint64_t b = (uint64_t)__double_as_longlong(d);
+    const uint16_t sign = (uint16_t)((b >> 48) & 0x8000u);
+    const int E = (int)((b >> 52) & 0x7FF);
+    const uint64_t m = b & 0xFFFFFFFFFFFFFull;
+    if (E == 0x7FF) return m ? (uint16_t)(sign | 0x7FC0u) : (uint16_t)(sign | 0x7F80u);
+    if (E == 0) return sign;  // |d| < 2^-1022: far below half the smallest BF16 step
+    const int e = E - 1023;
+    const uint64_t sig = m | (1ull << 52);  // 53-bit significand, value sig * 2^(e-52)
+    int shift;                              // bits of sig below the BF16 quantum
+    int ebias;                              // BF16 exponent field if no carry
+    if (e >= -126) {
+        shift = 45;                          // keep 8 bits
+        ebias = e + 127;
+    } else {
+        shift = -e - 81;                     // quantum 2^-133: sig * 2^(e+81)
+        ebias = 0;
+        if (shift > 60) return sign;         // below 2^-134 even before rounding
+    }
+    uint64_t q = sig >> shift;
+    const uint64_t rem = sig & ((1ull << shift) - 1);
+    const uint64_t half = 1ull << (shift - 1);
+    if (rem > half || (rem == half && (q & 1))) q += 1;
+    if (ebias == 0) {
+        // subnormal result; q <= 128, and q == 128 is exactly the smallest
+        // normal (exponent field 1, fraction 0), which the same bits encode
+        return (uint16_t)(sign | (uint16_t)q);
+    }
+    if (q == 256) {  // rounding carried into the next binade
+        q = 128;
+        ebias += 1;
+    }
+    if (ebias >= 255) return (uint16_t)(sign | 0x7F80u);
+    return (uint16_t)(sign | (uint16_t)(ebias << 7) | (uint16_t)(q & 0x7F));
+}
+
+__global__ __launch_bounds__(kBlock) void k_convert(const double *__restrict__ src,
+                                                    void *__restrict__ dst, int64_t n,
+                                                    int storage) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        const double v = src[i];
+        if (storage == CSR_VAL_F64) static_cast<double *>(dst)[i] = v;
+        else if (storage == CSR_VAL_F32) static_cast<float *>(dst)[i] = (float)v;
+        else static_cast<uint16_t *>(dst)[i] = f64_to_bf16(v);
+    }
+}
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(kBlock) void k_triad(dvec2 *__restrict__ a,
+                                                  const dvec2 *__restrict__ b,
+                                                  const dvec2 *__restrict__ c, double s,
+                                                  int64_t n2) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n2; i += stride) {
+        const dvec2 bb = __builtin_nontemporal_load(b + i);
+        const dvec2 cc = __builtin_nontemporal_load(c + i);
+        dvec2 r;
+        r.x = fma(s, cc.x, bb.x);
+        r.y = fma(s, cc.y, bb.y);
+        __builtin_nontemporal_store(r, a + i);
+    }
+}
+
+// Delta codes (MB remedy, Sec. III-E): entry j of row r stores col[j] - r
+// (signed, first entry) or col[j] - col[j-1] (unsigned, >= 1) in `bits` bits.
+// Flag 1 is raised when some entry does not fit; the codes are then unusable.
+template <int BITS>
+__global__ __launch_bounds__(kBlock) void k_delta_encode(const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ col,
+                                                         int32_t n_rows, void *__restrict__ codes,
+                                                         int32_t *__restrict__ flags) {
+    const int lane = threadIdx.x % kWave;
+    const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kBlock / kWave;
+    constexpr int64_t smin = -(1ll << (BITS - 1)), smax = (1ll << (BITS - 1)) - 1;
+    constexpr int64_t umax = (1ll << BITS) - 1;
+    bool bad = false;  // accumulated over all rows of this wave: one atomic at most
+    for (int64_t r = wave; r < n_rows; r += nwaves) {
+        const int32_t b = rp[r], e = rp[r + 1];
+        for (int32_t j = b + lane; j < e; j += kWave) {
+            const int64_t d = (j == b) ? (int64_t)col[j] - r : (int64_t)col[j] - col[j - 1];
+            if (j == b) bad |= (d < smin || d > smax);
+            else bad |= (d < 1 || d > umax);
+            if constexpr (BITS == 16) static_cast<uint16_t *>(codes)[j] = (uint16_t)(d & 0xFFFF);
+            else static_cast<uint8_t *>(codes)[j] = (uint8_t)(d & 0xFF);
+        }
+    }
+    const uint64_t m = __ballot(bad);
+    if (lane == 0 && m) atomicOr(flags, 1);
+}
+
+unsigned grid_for(int64_t n, int64_t per_block_items, unsigned cap) {
+    int64_t g = (n + per_block_items - 1) / per_block_items;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_validate(const int32_t *rp, const int32_t *col, int32_t n_rows,
+                           int32_t n_cols, int64_t nnz, int32_t *d_flags, hipStream_t s) {
+    const unsigned g = grid_for((int64_t)n_rows * kWave, kBlock, 256 * 16);
+    hipLaunchKernelGGL(k_validate, dim3(g), dim3(kBlock), 0, s, rp, col, n_rows, n_cols, nnz,
+                       d_flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_delta_encode(const int32_t *rp, const int32_t *col, int32_t n_rows, int bits,
+                               void *codes, int32_t *d_flags, hipStream_t s) {
+    const unsigned g = grid_for((int64_t)n_rows * kWave, kBlock, 256 * 16);
+    if (bits == 16)
+        hipLaunchKernelGGL(k_delta_encode<16>, dim3(g), dim3(kBlock), 0, s, rp, col, n_rows, codes,
+                           d_flags);
+    else
+        hipLaunchKernelGGL(k_delta_encode<8>, dim3(g), dim3(kBlock), 0, s, rp, col, n_rows, codes,
+                           d_flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_values(const double *src, void *dst, int64_t n, int storage,
+                                 hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned g = grid_for(n, kBlock * 4, 256 * 32);
+    hipLaunchKernelGGL(k_convert, dim3(g), dim3(kBlock), 0, s, src, dst, n, storage);
+    return hipGetLastError();
+}
+
+hipError_t launch_triad(double *a, const double *b, const double *c, double scalar, int64_t n,
+                        hipStream_t s) {
+    const int64_t n2 = n / 2;
+    const unsigned g = grid_for(n2, kBlock * 8, 256 * 64);
+    hipLaunchKernelGGL(k_triad, dim3(g), dim3(kBlock), 0, s, (dvec2 *)a, (const dvec2 *)b,
+                       (const dvec2 *)c, scalar, n2);
+    return hipGetLastError();
+}
+
+}  // namespace csr

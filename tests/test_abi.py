@@ -1,0 +1,63 @@
+"""Host-side checks of the C-ABI library: it loads, exports every entry point
+declared in include/csrspmv.h, and rejects bad arguments before touching the
+device. No compute call is made here (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1711_05487_amd as pkg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "csrspmv.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(csr_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pkg.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(pkg.EXPORTS)
+
+
+def test_status_strings_and_defaults():
+    L = pkg.lib()
+    for k, name in enumerate(pkg.STATUS):
+        assert L.csr_status_str(k).decode() == name
+    c = pkg.default_config()
+    assert (c.t_ml, c.t_imb, c.t_mb) == (1.25, 1.24, 0.8)
+    assert c.long_row_factor == 32.0 and c.long_row_floor == 4096 and c.timing_calls == 32
+
+
+def test_argument_errors_before_device_work():
+    L = pkg.lib()
+    P = ctypes.c_void_p
+    h = P()
+    assert L.csr_create(None, 1, 1, 0, P(1), None, None, 0, None) == 1
+    assert L.csr_create(ctypes.byref(h), -1, 1, 0, P(1), None, None, 0, None) == 1
+    assert h.value is None
+    assert L.csr_create(ctypes.byref(h), 2, 2, 1 << 31, P(1), P(1), P(1), 0, None) == 5
+    assert L.csr_create(ctypes.byref(h), 2, 2, 3, P(1), None, P(1), 0, None) == 1
+    assert L.csr_create(ctypes.byref(h), 2, 2, 3, P(1), P(1), P(1), 7, None) == 1
+    assert L.csr_spmv(None, P(1), P(2), None) == 1
+    assert L.csr_select(None, 0, None, None, None) == 1
+    assert L.csr_inspect(None, None, None) == 1
+    assert L.csr_query(None, None, None, None, None, None) == 1
+    assert L.csr_spmv_batched(-1, None, None, None, None) == 1
+    assert L.csr_triad(16, 1, None, None) == 1
+    assert b"NULL" in L.csr_last_error() or len(L.csr_last_error()) > 0
+    L.csr_destroy(None)  # accepted
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(pkg, "_lib", None)
+    monkeypatch.setattr(pkg, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        pkg.lib()
