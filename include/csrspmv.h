@@ -88,6 +88,8 @@ typedef struct {
     int32_t merge_items;     /* 0 = auto: merge-path items per tile L */
     int32_t autotune;        /* 1 = time a small parameter grid for the chosen remedies */
     int32_t timing_calls;    /* SpMV calls per timing run inside selection (default 32) */
+    int32_t rows_in_flight;  /* 0 = auto: rows per lane group loaded at once (1, 2 or 4) */
+    int32_t reserved;
 } csr_config_t;
 
 /* What csr_select decided and what it cost. */

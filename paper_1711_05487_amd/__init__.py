@@ -49,7 +49,8 @@ class Config(ctypes.Structure):
                 ("long_row_factor", ctypes.c_double), ("long_row_floor", ctypes.c_int32),
                 ("forced_opts", ctypes.c_int32), ("rows_per_group", ctypes.c_int32),
                 ("merge_items", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("timing_calls", ctypes.c_int32)]
+                ("timing_calls", ctypes.c_int32), ("rows_in_flight", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):

@@ -32,6 +32,9 @@ UNITS = [
     ("k_rowsplit_f64", "k_rowsplit.hip", ["-DCSR_STORAGE=0"]),
     ("k_rowsplit_f32", "k_rowsplit.hip", ["-DCSR_STORAGE=1"]),
     ("k_rowsplit_bf16", "k_rowsplit.hip", ["-DCSR_STORAGE=2"]),
+    ("k_merge_f64", "k_merge.hip", ["-DCSR_STORAGE=0"]),
+    ("k_merge_f32", "k_merge.hip", ["-DCSR_STORAGE=1"]),
+    ("k_merge_bf16", "k_merge.hip", ["-DCSR_STORAGE=2"]),
 ]
 
 

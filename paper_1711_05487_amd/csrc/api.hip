@@ -83,6 +83,21 @@ int default_lanes_per_row(double nnz_avg) {
     return 1 << e;
 }
 
+int device_cu_count(int device) {
+    static std::mutex mu;
+    static int cache[64] = {0};
+    std::lock_guard<std::mutex> lk(mu);
+    if (device < 0 || device >= 64) return 256;
+    if (!cache[device]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+            n < 1)
+            n = 256;
+        cache[device] = n;
+    }
+    return cache[device];
+}
+
 size_t storage_bytes(int storage) {
     return storage == CSR_VAL_F64 ? 8 : storage == CSR_VAL_F32 ? 4 : 2;
 }
@@ -91,13 +106,29 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
                        hipStream_t s) {
     const void *arr[6] = {A->rp.p, A->col.p, A->codes.p, A->val.p, x, y};
     const int32_t skip = INT32_MAX;
+    if (P.opts & CSR_OPT_MERGE) {
+        const int ipt = P.L / kBlock;
+        auto ti = A->tile_i.as<int32_t>();
+        auto tj = A->tile_j.as<int32_t>();
+        switch (A->storage) {
+        case CSR_VAL_F64:
+            return launch_merge_s0(ipt, P.nt != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles, s);
+        case CSR_VAL_F32:
+            return launch_merge_s1(ipt, P.nt != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles, s);
+        default:
+            return launch_merge_s2(ipt, P.nt != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles, s);
+        }
+    }
     switch (A->storage) {
     case CSR_VAL_F64:
-        return launch_rowsplit_s0(P.G, P.idx, P.nt != 0, P.U, arr, skip, A->n_rows, P.rows_iter, s);
+        return launch_rowsplit_s0(P.G, P.idx, P.nt != 0, P.U, P.R, P.probe, arr, skip, A->n_rows,
+                                  A->n_cols, s);
     case CSR_VAL_F32:
-        return launch_rowsplit_s1(P.G, P.idx, P.nt != 0, P.U, arr, skip, A->n_rows, P.rows_iter, s);
+        return launch_rowsplit_s1(P.G, P.idx, P.nt != 0, P.U, P.R, P.probe, arr, skip, A->n_rows,
+                                  A->n_cols, s);
     default:
-        return launch_rowsplit_s2(P.G, P.idx, P.nt != 0, P.U, arr, skip, A->n_rows, P.rows_iter, s);
+        return launch_rowsplit_s2(P.G, P.idx, P.nt != 0, P.U, P.R, P.probe, arr, skip, A->n_rows,
+                                  A->n_cols, s);
     }
 }
 
@@ -109,6 +140,10 @@ double plan_bytes(const csr_matrix_s *A, const Plan &P) {
     const double ib = P.idx == IDX_D16 ? 2.0 : P.idx == IDX_D8 ? 1.0 : 4.0;
     double b = (double)A->nnz * (vb + ib) + 4.0 * (A->n_rows + 1) + xb * A->n_cols +
                xb * A->n_rows;
+    if (P.opts & CSR_OPT_MERGE) {
+        const double T = (double)A->n_tiles;
+        b += 2.0 * 4.0 * (T + 1) + 2.0 * (A->storage == CSR_VAL_F64 ? 8.0 : 4.0) * T;  // table, carries
+    }
     return b;
 }
 
@@ -123,16 +158,43 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
     const int G0 = cfg.rows_per_group > 0 ? cfg.rows_per_group : default_lanes_per_row(nnz_avg);
     P.G = G0;
     P.U = 1;
-    P.rows_iter = 1;
+    P.R = 1;
     if (opts & CSR_OPT_UNROLL) {
-        P.G = G0 >= 4 ? G0 / 4 : 1;
+        P.G = cfg.rows_per_group > 0 ? G0 : (G0 >= 4 ? G0 / 4 : 1);
         P.U = 4;
     }
+    if (cfg.rows_in_flight > 0) P.R = cfg.rows_in_flight >= 4 ? 4 : cfg.rows_in_flight >= 2 ? 2 : 1;
     if (opts & CSR_OPT_PREFETCH) {
         P.nt = 1;
         P.U = 4;
     }
-    if (opts & CSR_OPT_DELTA) {
+    if (opts & CSR_OPT_MERGE) {
+        int L = cfg.merge_items > 0 ? cfg.merge_items : (A->storage == CSR_VAL_F64 ? 2048 : 4096);
+        if (cfg.merge_items <= 0 && (opts & CSR_OPT_UNROLL) && A->storage == CSR_VAL_F64)
+            L = 4096;  // CMP with merge: more path items (ILP) per thread
+        if (L != 1024 && L != 2048 && L != 4096)
+            return fail(CSR_ERR_INVALID_ARG, "merge_items must be 1024, 2048 or 4096");
+        P.L = L;
+        P.G = 0;
+        P.U = 1;
+        if (A->tiles_L != L) {
+            const int64_t total = (int64_t)A->n_rows + A->nnz;
+            const int64_t T = (total + L - 1) / L;
+            csr_status_t st;
+            if ((st = A->tile_i.alloc(sizeof(int32_t) * (T + 1))) != CSR_OK) return st;
+            if ((st = A->tile_j.alloc(sizeof(int32_t) * (T + 1))) != CSR_OK) return st;
+            if ((st = A->carry.alloc((A->storage == CSR_VAL_F64 ? 8 : 4) * (size_t)(T + 1))) != CSR_OK)
+                return st;
+            CSR_HIP(launch_merge_partition(A->rp.as<int32_t>(), A->n_rows, A->nnz, L, T,
+                                           A->tile_i.as<int32_t>(), A->tile_j.as<int32_t>(), s));
+            A->n_tiles = T;
+            A->tiles_L = L;
+        }
+    }
+    if ((opts & CSR_OPT_DELTA) && (opts & CSR_OPT_MERGE)) {
+        // the merge-path kernel streams int32 indices with vector loads: only
+        // the wide-load half of the MB remedy applies to it
+    } else if (opts & CSR_OPT_DELTA) {
         if (A->code_bits == 32 && A->rows_sorted) {
             for (int bits : {8, 16}) {
                 DevBuf flags;
@@ -225,7 +287,7 @@ int catalogue_id(int32_t opts) {
     return -1;
 }
 
-bool opts_available(int32_t opts) { return (opts & (CSR_OPT_MERGE | CSR_OPT_DECOMP)) == 0; }
+bool opts_available(int32_t opts) { return (opts & CSR_OPT_DECOMP) == 0; }
 
 void fill_info(const csr_matrix_s *A, const Plan &P, csr_plan_info_t *info) {
     info->opts = P.opts;
@@ -300,8 +362,9 @@ csr_status_t csr_create(csr_matrix_t *out, int32_t n_rows, int32_t n_cols, int64
     A->storage = storage;
     csr_status_t st;
     if ((st = A->rp.alloc(sizeof(int32_t) * ((size_t)n_rows + 1))) != CSR_OK) return bail(st);
-    if ((st = A->col.alloc(sizeof(int32_t) * (size_t)nnz)) != CSR_OK) return bail(st);
-    if ((st = A->val.alloc(storage_bytes(storage) * (size_t)nnz)) != CSR_OK) return bail(st);
+    if ((st = A->col.alloc(sizeof(int32_t) * (size_t)nnz + kPadBytes)) != CSR_OK) return bail(st);
+    if ((st = A->val.alloc(storage_bytes(storage) * (size_t)nnz + kPadBytes)) != CSR_OK)
+        return bail(st);
     DevBuf flags;
     if ((st = flags.alloc(sizeof(int32_t))) != CSR_OK) return bail(st);
     hipError_t e;
@@ -312,6 +375,9 @@ csr_status_t csr_create(csr_matrix_t *out, int32_t n_rows, int32_t n_cols, int64
     if (nnz > 0)
         STEP(hipMemcpyAsync(A->col.p, d_col_idx, sizeof(int32_t) * (size_t)nnz,
                             hipMemcpyDeviceToDevice, s));
+    // zero the tail padding so vector loads past nnz read defined bytes
+    STEP(hipMemsetAsync(A->col.as<char>() + sizeof(int32_t) * (size_t)nnz, 0, kPadBytes, s));
+    STEP(hipMemsetAsync(A->val.as<char>() + storage_bytes(storage) * (size_t)nnz, 0, kPadBytes, s));
     STEP(hipMemsetAsync(flags.p, 0, sizeof(int32_t), s));
     STEP(launch_validate(A->rp.as<int32_t>(), A->col.as<int32_t>(), n_rows, n_cols, nnz,
                          flags.as<int32_t>(), s));

@@ -15,6 +15,7 @@ namespace csr {
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64s)
 constexpr int kWave = 64;
 constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies
+constexpr size_t kPadBytes = 64;  // tail padding of val/col: vector loads may read past nnz
 
 enum IdxMode { IDX_I32 = 0, IDX_D16 = 1, IDX_D8 = 2 };
 
@@ -67,7 +68,8 @@ struct Plan {
     int32_t opts = 0;        // CSR_OPT_* mask
     int32_t G = 1;           // lanes per row (row-split kernels)
     int32_t U = 1;           // independent accumulators per lane
-    int32_t rows_iter = 1;   // rows per lane group (static partition chunk)
+    int32_t R = 1;           // rows per lane group in flight at once
+    int32_t probe = 0;       // 1: P_CMP micro-benchmark (no column stream, x[row])
     int32_t L = 0;           // merge-path items per tile
     int32_t idx = IDX_I32;   // index encoding
     int32_t nt = 0;          // non-temporal val/col stream
@@ -114,15 +116,28 @@ hipError_t launch_validate(const int32_t *rp, const int32_t *col, int32_t n_rows
 hipError_t launch_delta_encode(const int32_t *rp, const int32_t *col, int32_t n_rows, int bits,
                                void *codes, int32_t *d_flags, hipStream_t s);
 // arr = {rp, col, codes, val, x, y}
-hipError_t launch_rowsplit_s0(int G, int idx, bool nt, int U, const void *const *arr,
-                              int32_t skip_above, int32_t n_rows, int32_t rows_iter,
-                              hipStream_t s);
-hipError_t launch_rowsplit_s1(int G, int idx, bool nt, int U, const void *const *arr,
-                              int32_t skip_above, int32_t n_rows, int32_t rows_iter,
-                              hipStream_t s);
-hipError_t launch_rowsplit_s2(int G, int idx, bool nt, int U, const void *const *arr,
-                              int32_t skip_above, int32_t n_rows, int32_t rows_iter,
-                              hipStream_t s);
+hipError_t launch_rowsplit_s0(int G, int idx, bool nt, int U, int R, int probe,
+                              const void *const *arr, int32_t skip_above, int32_t n_rows,
+                              int32_t n_cols, hipStream_t s);
+hipError_t launch_rowsplit_s1(int G, int idx, bool nt, int U, int R, int probe,
+                              const void *const *arr, int32_t skip_above, int32_t n_rows,
+                              int32_t n_cols, hipStream_t s);
+hipError_t launch_rowsplit_s2(int G, int idx, bool nt, int U, int R, int probe,
+                              const void *const *arr, int32_t skip_above, int32_t n_rows,
+                              int32_t n_cols, hipStream_t s);
+hipError_t launch_merge_partition(const int32_t *rp, int32_t n_rows, int64_t nnz, int64_t L,
+                                  int64_t n_tiles, int32_t *tile_i, int32_t *tile_j,
+                                  hipStream_t s);
+// arr = {rp, col, codes, val, x, y}; L = 256 * ipt
+hipError_t launch_merge_s0(int ipt, bool nt, const void *const *arr, const int32_t *tile_i,
+                           const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
+                           hipStream_t s);
+hipError_t launch_merge_s1(int ipt, bool nt, const void *const *arr, const int32_t *tile_i,
+                           const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
+                           hipStream_t s);
+hipError_t launch_merge_s2(int ipt, bool nt, const void *const *arr, const int32_t *tile_i,
+                           const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
+                           hipStream_t s);
 hipError_t launch_convert_values(const double *src, void *dst, int64_t n, int storage,
                                  hipStream_t s);
 hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void *y,
@@ -132,6 +147,7 @@ hipError_t launch_triad(double *a, const double *b, const double *c, double scal
 
 // Host helpers -------------------------------------------------------------------
 int default_lanes_per_row(double nnz_avg);
+int device_cu_count(int device);
 size_t storage_bytes(int storage);
 
 }  // namespace csr

@@ -136,6 +136,28 @@ __global__ __launch_bounds__(kBlock) void k_delta_encode(const int32_t *__restri
     if (lane == 0 && m) atomicOr(flags, 1);
 }
 
+// Merge-path partition: for t = 0..T, d = min(t*L, N+NNZ) and
+// i_t = #{ i : rp[i+1] + i < d } (a lower-bound search), j_t = d - i_t.
+__global__ __launch_bounds__(kBlock) void k_merge_partition(const int32_t *__restrict__ rp,
+                                                            int32_t n_rows, int64_t nnz, int64_t L,
+                                                            int64_t n_tiles,
+                                                            int32_t *__restrict__ tile_i,
+                                                            int32_t *__restrict__ tile_j) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t > n_tiles) return;
+    const int64_t total = (int64_t)n_rows + nnz;
+    const int64_t d = t * L < total ? t * L : total;
+    int64_t lo = d - nnz > 0 ? d - nnz : 0;
+    int64_t hi = d < n_rows ? d : n_rows;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)rp[mid + 1] + mid < d) lo = mid + 1;
+        else hi = mid;
+    }
+    tile_i[t] = (int32_t)lo;
+    tile_j[t] = (int32_t)(d - lo);
+}
+
 unsigned grid_for(int64_t n, int64_t per_block_items, unsigned cap) {
     int64_t g = (n + per_block_items - 1) / per_block_items;
     if (g < 1) g = 1;
@@ -162,6 +184,15 @@ hipError_t launch_delta_encode(const int32_t *rp, const int32_t *col, int32_t n_
     else
         hipLaunchKernelGGL(k_delta_encode<8>, dim3(g), dim3(kBlock), 0, s, rp, col, n_rows, codes,
                            d_flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_partition(const int32_t *rp, int32_t n_rows, int64_t nnz, int64_t L,
+                                  int64_t n_tiles, int32_t *tile_i, int32_t *tile_j,
+                                  hipStream_t s) {
+    const unsigned g = (unsigned)((n_tiles + 1 + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_merge_partition, dim3(g), dim3(kBlock), 0, s, rp, n_rows, nnz, L, n_tiles,
+                       tile_i, tile_j);
     return hipGetLastError();
 }
 

@@ -1,0 +1,122 @@
+"""GPU parity of the nnz-balanced merge-path SpMV (IMB remedy, Sec. III-E,
+Table II): the tile table bit-exact against the oracle's merge-path definition,
+and y against the oracle on regular, skewed, empty-row and long-row inputs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1711_05487_amd as pkg
+import synth
+from spmv_cases import check_f64, check_reduced, matrix, xvec
+
+pytestmark = pytest.mark.gpu
+
+M = pkg.OPT_MERGE
+MERGE_OPTS = [M, M | pkg.OPT_PREFETCH, M | pkg.OPT_UNROLL, M | pkg.OPT_DELTA]
+
+
+def run(A, x, opts=None, L=0):
+    if opts is not None:
+        A.select("forced", forced_opts=opts, merge_items=L)
+    xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    y = A.spmv(xd)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def long_and_empty_rows():
+    lens = [0, 0, 5000, 1, 0, 3000, 0, 0, 2, 10000, 0] + [3] * 500 + [0] * 100 + [9000]
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    col = np.concatenate([np.sort(synth.uindex(5, i, np.arange(l, dtype=np.uint64), 20000))
+                          for i, l in enumerate(lens)]).astype(np.int32)
+    val = (synth.uindex(6, 0, np.arange(rp[-1], dtype=np.uint64), 9) - 4).astype(float)
+    return len(lens), 20000, rp, col, val
+
+
+@pytest.mark.parametrize("L", [1024, 2048, 4096])
+def test_tile_table_bit_exact(L):
+    for name in ("lap100", "rmat14", "st27_24"):
+        n, m, rp, col, val = matrix(name)
+        A = pkg.CsrMatrix(rp, col, val)
+        A.select("forced", forced_opts=M, merge_items=L)
+        ti, tj = oracle.merge_tiles(rp, L)
+        assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_I, np.int32), ti)
+        assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_J, np.int32), tj)
+
+
+@pytest.mark.parametrize("L", [1024, 2048, 4096])
+@pytest.mark.parametrize("opts", MERGE_OPTS)
+def test_dyadic_bit_exact(opts, L):
+    cases = [synth.tiny_random(700, 300, d, 11 + k, dyadic=True)
+             for k, d in enumerate((0.0, 0.002, 0.02, 0.3, 0.95))]
+    cases.append(long_and_empty_rows())
+    for n, m, rp, col, val in cases:
+        x = synth.dyadic_vector(m, 12)
+        A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+        assert np.array_equal(run(A, x, opts, L), oracle.spmv(rp, col, val, x)), (n, opts, L)
+
+
+def test_all_4x4_patterns_bit_exact():
+    pats = np.arange(1 << 16, dtype=np.int64)
+    bits = ((pats[:, None] >> np.arange(16)) & 1).astype(bool).reshape(-1, 4, 4)
+    vals = (synth.uindex(77, 0, np.arange(bits.size, dtype=np.uint64), 15) - 7).astype(np.float64)
+    vals[vals == 0] = 3.0
+    dense = np.where(bits, vals.reshape(bits.shape), 0.0)
+    b, r, c = np.nonzero(dense)
+    nb = dense.shape[0]
+    _, _, rp, col, val = synth.from_coo(b * 4 + r, b * 4 + c, dense[b, r, c], 4 * nb, 4 * nb)
+    x = synth.dyadic_vector(4 * nb, 78)
+    A = pkg.CsrMatrix(rp, col, val)
+    want = oracle.spmv(rp, col, val, x)
+    for L in (1024, 2048, 4096):
+        assert np.array_equal(run(A, x, M, L), want)
+
+
+@pytest.mark.parametrize("name", ["rmat14", "st27_24", "lap100"])
+def test_random_values_within_bound(name):
+    n, m, rp, col, val = matrix(name)
+    x = xvec(name, m)
+    A = pkg.CsrMatrix(rp, col, val)
+    for opts in MERGE_OPTS:
+        check_f64(run(A, x, opts), rp, col, val, x, f"{name} {opts}")
+
+
+def test_long_rows_random_values():
+    n, m, rp, col, _ = long_and_empty_rows()
+    val = synth.um11(8, 0, np.arange(len(col), dtype=np.uint64))
+    x = synth.vector(m, 9)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    for L in (1024, 2048, 4096):
+        check_f64(run(A, x, M, L), rp, col, val, x, f"long rows L={L}")
+
+
+def test_stencil27_full_size():
+    n, m, rp, col, val = matrix("st27_128")
+    x = xvec("st27_128", m)
+    A = pkg.CsrMatrix(rp, col, val)
+    for opts in MERGE_OPTS:
+        check_f64(run(A, x, opts), rp, col, val, x, f"st27 {opts}")
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_reduced_precision(storage):
+    for name in ("rmat14", "st27_24"):
+        n, m, rp, col, val = matrix(name)
+        x = xvec(name, m)
+        A = pkg.CsrMatrix(rp, col, val, storage=storage)
+        for L in (1024, 4096):
+            A.select("forced", forced_opts=M, merge_items=L)
+            y = A.spmv(torch.from_numpy(oracle.to_f32(x)).cuda())
+            torch.cuda.synchronize()
+            check_reduced(y.cpu().numpy(), rp, col, val, x, storage, f"{name} {storage} L={L}")
+
+
+def test_deterministic():
+    n, m, rp, col, val = matrix("rmat14")
+    x = synth.vector(m, 4)
+    A = pkg.CsrMatrix(rp, col, val)
+    for L in (1024, 2048):
+        y1 = run(A, x, M, L)
+        y2 = run(A, x)
+        assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
