@@ -208,6 +208,19 @@ csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t by
                             size_t *needed, void *stream);
 
 /*
+ * Test support: runs one micro-benchmark of the profile-guided classifier
+ * (Sec. III-B) on the caller's vectors so its arithmetic can be checked:
+ *   which = 1  P_ML probe: the baseline kernel with every column index
+ *              replaced by its own row index (clamped to n_cols - 1)
+ *   which = 2  P_CMP probe: the baseline kernel without the column-index
+ *              stream, reading x at the row index (clamped likewise)
+ * Either way y_i = x_min(i, n_cols-1) * (sum of row i's values). Vector types
+ * and ownership as for csr_spmv. Asynchronous on `stream`.
+ */
+csr_status_t csr_debug_probe(csr_matrix_t A, int32_t which, const void *d_x, void *d_y,
+                             void *stream);
+
+/*
  * B_max probe (Sec. III-B; Sec. IV-A, Table III: STREAM triad). Runs
  * a[i] = b[i] + s * c[i] over three FP64 arrays of `bytes_per_array` bytes
  * each (allocated and freed inside) and returns the sustained bandwidth in

@@ -35,7 +35,7 @@ STATUS = ["CSR_OK", "CSR_ERR_INVALID_ARG", "CSR_ERR_INVALID_MATRIX", "CSR_ERR_OU
 # Every entry point declared in include/csrspmv.h.
 EXPORTS = ("csr_config_default", "csr_create", "csr_destroy", "csr_inspect", "csr_select",
            "csr_spmv", "csr_spmv_batched", "csr_status_str", "csr_last_error", "csr_query",
-           "csr_debug_copy", "csr_triad")
+           "csr_debug_copy", "csr_debug_probe", "csr_triad")
 
 
 class CsrError(RuntimeError):
@@ -99,6 +99,7 @@ def lib():
                                          ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "csr_debug_copy": (ctypes.c_int, [P, i32, P, sz, ctypes.POINTER(sz), P]),
             "csr_triad": (ctypes.c_int, [sz, i32, ctypes.POINTER(ctypes.c_double), P]),
+            "csr_debug_probe": (ctypes.c_int, [P, i32, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -221,6 +222,14 @@ class CsrMatrix:
         _check(lib().csr_debug_copy(self._h, what, out.ctypes.data_as(ctypes.c_void_p),
                                     need.value, None, _stream(stream)))
         return out
+
+    def probe(self, which: int, x, y=None, stream=None):
+        """Run the P_ML (1) or P_CMP (2) micro-benchmark kernel on x."""
+        import torch
+        if y is None:
+            y = torch.empty(self.n_rows, dtype=x.dtype, device=x.device)
+        _check(lib().csr_debug_probe(self._h, which, _ptr(x), _ptr(y), _stream(stream)))
+        return y
 
     def query(self):
         a, b, d, e = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

@@ -28,7 +28,12 @@ FLAGS = [
 # (object name, source, extra defines)
 UNITS = [
     ("api", "api.hip", []),
+    ("select", "select.hip", []),
     ("k_prep", "k_prep.hip", []),
+    ("k_features", "k_features.hip", []),
+    ("k_long_f64", "k_long.hip", ["-DCSR_STORAGE=0"]),
+    ("k_long_f32", "k_long.hip", ["-DCSR_STORAGE=1"]),
+    ("k_long_bf16", "k_long.hip", ["-DCSR_STORAGE=2"]),
     ("k_rowsplit_f64", "k_rowsplit.hip", ["-DCSR_STORAGE=0"]),
     ("k_rowsplit_f32", "k_rowsplit.hip", ["-DCSR_STORAGE=1"]),
     ("k_rowsplit_bf16", "k_rowsplit.hip", ["-DCSR_STORAGE=2"]),

@@ -104,8 +104,8 @@ size_t storage_bytes(int storage) {
 
 hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void *y,
                        hipStream_t s) {
-    const void *arr[6] = {A->rp.p, A->col.p, A->codes.p, A->val.p, x, y};
-    const int32_t skip = INT32_MAX;
+    const void *arr[7] = {A->rp.p, A->col.p, A->codes.p, A->val.p, x, y, nullptr};
+    const int32_t skip = P.long_rows ? (int32_t)A->long_tau : INT32_MAX;
     if (P.opts & CSR_OPT_MERGE) {
         const int ipt = P.L / kBlock;
         auto ti = A->tile_i.as<int32_t>();
@@ -119,184 +119,36 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
             return launch_merge_s2(ipt, P.nt != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles, s);
         }
     }
+    hipError_t e;
     switch (A->storage) {
     case CSR_VAL_F64:
-        return launch_rowsplit_s0(P.G, P.idx, P.nt != 0, P.U, P.R, P.probe, arr, skip, A->n_rows,
+        e = launch_rowsplit_s0(P.G, P.idx, P.nt != 0, P.U, P.R, P.probe, arr, skip, A->n_rows,
                                   A->n_cols, s);
+        break;
     case CSR_VAL_F32:
-        return launch_rowsplit_s1(P.G, P.idx, P.nt != 0, P.U, P.R, P.probe, arr, skip, A->n_rows,
+        e = launch_rowsplit_s1(P.G, P.idx, P.nt != 0, P.U, P.R, P.probe, arr, skip, A->n_rows,
                                   A->n_cols, s);
+        break;
     default:
-        return launch_rowsplit_s2(P.G, P.idx, P.nt != 0, P.U, P.R, P.probe, arr, skip, A->n_rows,
+        e = launch_rowsplit_s2(P.G, P.idx, P.nt != 0, P.U, P.R, P.probe, arr, skip, A->n_rows,
                                   A->n_cols, s);
+        break;
     }
-}
-
-// Algorithmic bytes of one SpMV under plan P: every array read once, y written
-// once (values + indices or codes + row pointers + x + y + side tables).
-double plan_bytes(const csr_matrix_s *A, const Plan &P) {
-    const double vb = (double)storage_bytes(A->storage);
-    const double xb = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
-    const double ib = P.idx == IDX_D16 ? 2.0 : P.idx == IDX_D8 ? 1.0 : 4.0;
-    double b = (double)A->nnz * (vb + ib) + 4.0 * (A->n_rows + 1) + xb * A->n_cols +
-               xb * A->n_rows;
-    if (P.opts & CSR_OPT_MERGE) {
-        const double T = (double)A->n_tiles;
-        b += 2.0 * 4.0 * (T + 1) + 2.0 * (A->storage == CSR_VAL_F64 ? 8.0 : 4.0) * T;  // table, carries
+    if (e != hipSuccess || !P.long_rows || A->n_long == 0) return e;
+    const int32_t *cb = A->long_chunks.as<int32_t>();
+    const int32_t *lr = A->long_list.as<int32_t>();
+    const int32_t *rc = A->long_row_chunk.as<int32_t>();
+    switch (A->storage) {
+    case CSR_VAL_F64:
+        return launch_long_s0(A->col.as<int32_t>(), A->val.p, x, y, cb, A->long_part.p,
+                              A->n_long_chunks, lr, rc, A->n_long, s);
+    case CSR_VAL_F32:
+        return launch_long_s1(A->col.as<int32_t>(), A->val.p, x, y, cb, A->long_part.p,
+                              A->n_long_chunks, lr, rc, A->n_long, s);
+    default:
+        return launch_long_s2(A->col.as<int32_t>(), A->val.p, x, y, cb, A->long_part.p,
+                              A->n_long_chunks, lr, rc, A->n_long, s);
     }
-    return b;
-}
-
-int catalogue_id(int32_t opts);
-
-// Realize an optimization mask as a concrete plan, building what it needs.
-csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Plan *out,
-                     hipStream_t s) {
-    Plan P;
-    P.opts = opts;
-    const double nnz_avg = A->n_rows ? (double)A->nnz / A->n_rows : 0.0;
-    const int G0 = cfg.rows_per_group > 0 ? cfg.rows_per_group : default_lanes_per_row(nnz_avg);
-    P.G = G0;
-    P.U = 1;
-    P.R = 1;
-    if (opts & CSR_OPT_UNROLL) {
-        P.G = cfg.rows_per_group > 0 ? G0 : (G0 >= 4 ? G0 / 4 : 1);
-        P.U = 4;
-    }
-    if (cfg.rows_in_flight > 0) P.R = cfg.rows_in_flight >= 4 ? 4 : cfg.rows_in_flight >= 2 ? 2 : 1;
-    if (opts & CSR_OPT_PREFETCH) {
-        P.nt = 1;
-        P.U = 4;
-    }
-    if (opts & CSR_OPT_MERGE) {
-        int L = cfg.merge_items > 0 ? cfg.merge_items : (A->storage == CSR_VAL_F64 ? 2048 : 4096);
-        if (cfg.merge_items <= 0 && (opts & CSR_OPT_UNROLL) && A->storage == CSR_VAL_F64)
-            L = 4096;  // CMP with merge: more path items (ILP) per thread
-        if (L != 1024 && L != 2048 && L != 4096)
-            return fail(CSR_ERR_INVALID_ARG, "merge_items must be 1024, 2048 or 4096");
-        P.L = L;
-        P.G = 0;
-        P.U = 1;
-        if (A->tiles_L != L) {
-            const int64_t total = (int64_t)A->n_rows + A->nnz;
-            const int64_t T = (total + L - 1) / L;
-            csr_status_t st;
-            if ((st = A->tile_i.alloc(sizeof(int32_t) * (T + 1))) != CSR_OK) return st;
-            if ((st = A->tile_j.alloc(sizeof(int32_t) * (T + 1))) != CSR_OK) return st;
-            if ((st = A->carry.alloc((A->storage == CSR_VAL_F64 ? 8 : 4) * (size_t)(T + 1))) != CSR_OK)
-                return st;
-            CSR_HIP(launch_merge_partition(A->rp.as<int32_t>(), A->n_rows, A->nnz, L, T,
-                                           A->tile_i.as<int32_t>(), A->tile_j.as<int32_t>(), s));
-            A->n_tiles = T;
-            A->tiles_L = L;
-        }
-    }
-    if ((opts & CSR_OPT_DELTA) && (opts & CSR_OPT_MERGE)) {
-        // the merge-path kernel streams int32 indices with vector loads: only
-        // the wide-load half of the MB remedy applies to it
-    } else if (opts & CSR_OPT_DELTA) {
-        if (A->code_bits == 32 && A->rows_sorted) {
-            for (int bits : {8, 16}) {
-                DevBuf flags;
-                csr_status_t st = flags.alloc(sizeof(int32_t));
-                if (st != CSR_OK) return st;
-                CSR_HIP(hipMemsetAsync(flags.p, 0, sizeof(int32_t), s));
-                DevBuf codes;
-                st = codes.alloc((size_t)A->nnz * (bits / 8));
-                if (st != CSR_OK) return st;
-                CSR_HIP(launch_delta_encode(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->n_rows,
-                                            bits, codes.p, flags.as<int32_t>(), s));
-                int32_t h = 0;
-                CSR_HIP(hipMemcpyAsync(&h, flags.p, sizeof(h), hipMemcpyDeviceToHost, s));
-                CSR_HIP(hipStreamSynchronize(s));
-                if (h == 0) {
-                    std::swap(A->codes.p, codes.p);
-                    std::swap(A->codes.bytes, codes.bytes);
-                    A->code_bits = bits;
-                    break;
-                }
-            }
-            if (A->code_bits == 32) A->code_bits = 0;  // tried, not eligible
-        }
-        if (A->code_bits == 8 || A->code_bits == 16) {
-            P.idx = A->code_bits == 8 ? IDX_D8 : IDX_D16;
-            P.U = 1;
-        } else {
-            // Not eligible: only the wide-load half of the remedy applies.
-            P.U = 4;
-        }
-    }
-    P.variant_id = catalogue_id(opts);
-    *out = P;
-    return CSR_OK;
-}
-
-// Scratch vectors for timed selection runs (x = 0, so no value can turn into
-// a subnormal or non-finite operand that changes the timing).
-csr_status_t ensure_scratch(csr_matrix_s *A, hipStream_t s) {
-    const size_t xb = A->storage == CSR_VAL_F64 ? 8 : 4;
-    csr_status_t st;
-    if (!A->scratch_x.p) {
-        if ((st = A->scratch_x.alloc(xb * (size_t)A->n_cols)) != CSR_OK) return st;
-        CSR_HIP(hipMemsetAsync(A->scratch_x.p, 0, A->scratch_x.bytes, s));
-    }
-    if (!A->scratch_y.p) {
-        if ((st = A->scratch_y.alloc(xb * (size_t)A->n_rows)) != CSR_OK) return st;
-    }
-    return CSR_OK;
-}
-
-// Time `calls` back-to-back SpMVs under plan P between two events, `runs`
-// times after one untimed call; returns the run-summary time per call in ms:
-// the reciprocal of the harmonic mean of the per-run rates (Sec. IV-A).
-csr_status_t time_plan(csr_matrix_s *A, const Plan &P, int calls, int runs, hipStream_t s,
-                       double *ms_per_call) {
-    csr_status_t st = ensure_scratch(A, s);
-    if (st != CSR_OK) return st;
-    hipEvent_t e0, e1;
-    CSR_HIP(hipEventCreate(&e0));
-    CSR_HIP(hipEventCreate(&e1));
-    hipError_t e = launch_spmv(A, P, A->scratch_x.p, A->scratch_y.p, s);
-    double inv_rate_sum = 0.0;  // sum over runs of (ms per call) = sum of 1/rate
-    for (int r = 0; r < runs && e == hipSuccess; ++r) {
-        e = hipEventRecord(e0, s);
-        for (int c = 0; c < calls && e == hipSuccess; ++c)
-            e = launch_spmv(A, P, A->scratch_x.p, A->scratch_y.p, s);
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        inv_rate_sum += (double)ms / calls;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (e != hipSuccess) return hip_fail(e, "timed SpMV");
-    // harmonic mean of rates r_k = W / t_k is runs / sum(1/r_k) = W * runs / sum t_k
-    *ms_per_call = inv_rate_sum / runs;
-    return CSR_OK;
-}
-
-// Catalogue of optimization sets swept by the exhaustive selector: the
-// baseline, the 5 singles and the 10 pairs (Sec. IV-D, trivial optimizers).
-const int32_t kCatalogue[16] = {0,  1,  2,  4,  8,  16, 1 | 2, 1 | 4, 1 | 8, 1 | 16,
-                                2 | 4, 2 | 8, 2 | 16, 4 | 8, 4 | 16, 8 | 16};
-
-int catalogue_id(int32_t opts) {
-    for (int k = 0; k < 16; ++k)
-        if (kCatalogue[k] == opts) return k;
-    return -1;
-}
-
-bool opts_available(int32_t opts) { return (opts & CSR_OPT_DECOMP) == 0; }
-
-void fill_info(const csr_matrix_s *A, const Plan &P, csr_plan_info_t *info) {
-    info->opts = P.opts;
-    info->lanes_per_row = P.G;
-    info->merge_items = P.L;
-    info->delta_bits = P.idx == IDX_D16 ? 16 : P.idx == IDX_D8 ? 8 : 32;
-    info->n_long_rows = P.long_rows ? A->n_long : 0;
-    info->variant_id = P.variant_id;
-    info->format_bytes = plan_bytes(A, P);
 }
 
 }  // namespace csr
@@ -398,6 +250,7 @@ csr_status_t csr_create(csr_matrix_t *out, int32_t n_rows, int32_t n_cols, int64
     csr_config_t cfg;
     csr_config_default(&cfg);
     if ((st = realize(A, 0, cfg, &A->plan, s)) != CSR_OK) return bail(st);
+    A->info = csr_plan_info_t{};
     A->info.classes = -1;
     fill_info(A, A->plan, &A->info);
     *out = A;
@@ -435,66 +288,6 @@ csr_status_t csr_spmv(csr_matrix_t A, const void *d_x, void *d_y, void *stream) 
     DeviceGuard g(A->device);
     CSR_HIP(launch_spmv(A, A->plan, d_x, d_y, (hipStream_t)stream));
     return CSR_OK;
-}
-
-csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in,
-                        csr_plan_info_t *out, void *stream) {
-    if (!A) return fail(CSR_ERR_INVALID_ARG, "NULL handle");
-    csr_config_t cfg;
-    if (cfg_in) cfg = *cfg_in;
-    else csr_config_default(&cfg);
-    DeviceGuard g(A->device);
-    hipStream_t s = (hipStream_t)stream;
-    const auto t0 = std::chrono::steady_clock::now();
-    Plan P;
-    csr_status_t st;
-    switch (mode) {
-    case CSR_SEL_PLAIN:
-        st = realize(A, 0, cfg, &P, s);
-        break;
-    case CSR_SEL_FORCED:
-        if (cfg.forced_opts & ~31) return fail(CSR_ERR_INVALID_ARG, "unknown optimization bits");
-        if (!opts_available(cfg.forced_opts))
-            return fail(CSR_ERR_UNSUPPORTED, "optimization not available");
-        st = realize(A, cfg.forced_opts, cfg, &P, s);
-        break;
-    case CSR_SEL_EXHAUSTIVE: {
-        // Time every available catalogue variant; keep the fastest.
-        double best = 1e300;
-        st = CSR_OK;
-        const int calls = cfg.timing_calls > 0 ? cfg.timing_calls : 32;
-        for (int k = 0; k < 16 && st == CSR_OK; ++k) {
-            if (!opts_available(kCatalogue[k])) continue;
-            Plan Q;
-            if ((st = realize(A, kCatalogue[k], cfg, &Q, s)) != CSR_OK) break;
-            double ms = 0;
-            if ((st = time_plan(A, Q, calls, 3, s, &ms)) != CSR_OK) break;
-            if (ms < best) {
-                best = ms;
-                P = Q;
-            }
-        }
-        break;
-    }
-    default:
-        return fail(CSR_ERR_UNSUPPORTED, "selection mode not available");
-    }
-    if (st != CSR_OK) return st;
-    CSR_HIP(hipStreamSynchronize(s));
-    A->plan = P;
-    A->info = csr_plan_info_t{};
-    A->info.classes = -1;
-    fill_info(A, P, &A->info);
-    A->info.t_select_ms =
-        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    if (out) *out = A->info;
-    return CSR_OK;
-}
-
-csr_status_t csr_inspect(csr_matrix_t A, csr_features_t *out, void *stream) {
-    (void)stream;
-    if (!A || !out) return fail(CSR_ERR_INVALID_ARG, "NULL argument");
-    return fail(CSR_ERR_UNSUPPORTED, "feature extraction not built");
 }
 
 csr_status_t csr_spmv_batched(int32_t count, const csr_matrix_t *h_A, const void *const *h_x,

@@ -48,6 +48,18 @@ template <int G, class A> __device__ __forceinline__ A group_sum(A v) {
     return v;
 }
 
+template <int G> __device__ __forceinline__ int32_t group_max(int32_t v) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, G));
+    return v;
+}
+
+template <int G> __device__ __forceinline__ int32_t group_isum(int32_t v) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    return v;
+}
+
 // Inclusive prefix sum over the G lanes of a lane group.
 template <int G> __device__ __forceinline__ int32_t group_scan(int32_t v, int lane) {
 #pragma unroll

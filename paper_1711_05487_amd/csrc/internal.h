@@ -94,18 +94,19 @@ struct csr_matrix_s {
     int64_t n_tiles = 0;
     int32_t tiles_L = 0;
     csr::DevBuf long_list;         // decomposition: long rows (ascending)
+    csr::DevBuf long_chunks;       // decomposition: (begin, end) nonzero range per chunk
+    csr::DevBuf long_row_chunk;    // decomposition: first chunk of each long row, n_long+1
     csr::DevBuf long_part;         // decomposition: per-chunk partial sums
-    csr::DevBuf long_chunk_row;    // decomposition: chunk -> long-row slot
     int32_t n_long = 0;
-    int64_t long_tau = -1;
+    int64_t long_tau = -1;         // threshold the current list was built for
     int64_t n_long_chunks = 0;
-    csr::DevBuf short_rows;        // decomposition: rows that stay in the row pass
-    int32_t n_short = 0;
     csr::Plan plan;
     csr_plan_info_t info{};
     int has_features = 0;
     csr_features_t feat{};
     csr::DevBuf scratch_x, scratch_y, scratch_col;  // selection probes
+    csr::DevBuf feat_parts, feat_reuse;             // feature-extraction partials
+    double t_inspect_ms = 0.0;
 };
 
 namespace csr {
@@ -115,7 +116,7 @@ hipError_t launch_validate(const int32_t *rp, const int32_t *col, int32_t n_rows
                            int32_t n_cols, int64_t nnz, int32_t *d_flags, hipStream_t s);
 hipError_t launch_delta_encode(const int32_t *rp, const int32_t *col, int32_t n_rows, int bits,
                                void *codes, int32_t *d_flags, hipStream_t s);
-// arr = {rp, col, codes, val, x, y}
+// arr = {rp, col, codes, val, x, y, instrumentation records (probe 2)}
 hipError_t launch_rowsplit_s0(int G, int idx, bool nt, int U, int R, int probe,
                               const void *const *arr, int32_t skip_above, int32_t n_rows,
                               int32_t n_cols, hipStream_t s);
@@ -138,12 +139,46 @@ hipError_t launch_merge_s1(int ipt, bool nt, const void *const *arr, const int32
 hipError_t launch_merge_s2(int ipt, bool nt, const void *const *arr, const int32_t *tile_i,
                            const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
                            hipStream_t s);
+hipError_t launch_fill_row_index(const int32_t *rp, int32_t n_rows, int32_t n_cols, int32_t *out,
+                                 hipStream_t s);
 hipError_t launch_convert_values(const double *src, void *dst, int64_t n, int storage,
                                  hipStream_t s);
 hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void *y,
                        hipStream_t s);
 hipError_t launch_triad(double *a, const double *b, const double *c, double scalar,
                         int64_t n, hipStream_t s);
+
+// Partial feature sums of one workgroup (folded in a fixed order).
+struct FeatPart {
+    int64_t s_nnz2, s_bw, s_bw2, s_miss, s_grp, s_len1;
+    int32_t nnz_min, nnz_max, bw_min, bw_max;
+    double sc_n, sc_mean, sc_m2;  // Welford state of scatter_i
+    double s_cl;                  // sum of clustering_i
+};
+int32_t features_partials(int32_t n_rows, int G, int32_t *rows_per_block);
+int32_t xreuse_samples(int32_t n_rows);
+hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int G,
+                           FeatPart *parts, int32_t n_parts, int32_t rows_per_block,
+                           int32_t *reuse_out, hipStream_t s);
+
+hipError_t launch_long_s0(const int32_t *col, const void *val, const void *x, void *y,
+                          const int32_t *chunk_beg, void *part, int64_t n_chunks,
+                          const int32_t *long_rows, const int32_t *row_chunk, int32_t n_long,
+                          hipStream_t s);
+hipError_t launch_long_s1(const int32_t *col, const void *val, const void *x, void *y,
+                          const int32_t *chunk_beg, void *part, int64_t n_chunks,
+                          const int32_t *long_rows, const int32_t *row_chunk, int32_t n_long,
+                          hipStream_t s);
+hipError_t launch_long_s2(const int32_t *col, const void *val, const void *x, void *y,
+                          const int32_t *chunk_beg, void *part, int64_t n_chunks,
+                          const int32_t *long_rows, const int32_t *row_chunk, int32_t n_long,
+                          hipStream_t s);
+
+// Plans and selection (select.hip) -----------------------------------------------
+double plan_bytes(const csr_matrix_s *A, const Plan &P);
+csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Plan *out,
+                     hipStream_t s);
+void fill_info(const csr_matrix_s *A, const Plan &P, csr_plan_info_t *info);
 
 // Host helpers -------------------------------------------------------------------
 int default_lanes_per_row(double nnz_avg);

@@ -1,0 +1,239 @@
+// Matrix features (Sec. III-D, Table I) in one sweep over row_ptr and col_idx.
+//
+// Per row i (entries in storage order): nnz_i; bw_i = max col - min col;
+// misses_i = entries whose distance from the previous entry exceeds 16
+// columns (one 128-byte line of FP64 x), the first entry counting as a miss;
+// ngroups_i = maximal runs of consecutive columns; scatter_i = nnz_i /
+// max(bw_i, 1) and clustering_i = ngroups_i / nnz_i (both 0 for an empty row).
+//
+// G lanes share a row (the previous entry of a lane's element comes from the
+// neighbouring lane by a shuffle, so col is read once). Integer totals are
+// exact int64 sums; the scatter mean and variance use Welford updates per
+// thread merged with Chan's pairwise formula in a fixed tree, so the result
+// is deterministic. A second small kernel samples row pairs for the x-reuse
+// estimate, and a one-block kernel folds the per-block partials in order.
+#include "device.h"
+
+namespace csr {
+
+namespace {
+
+constexpr int kFeatE = 16;   // FP64 values per 128-byte cache line
+constexpr int kReuseP = 256; // entries per sampled row
+constexpr int kReuseS = 4096;
+
+__device__ __forceinline__ void welford_push(double &n, double &mean, double &m2, double v) {
+    n += 1.0;
+    const double d = v - mean;
+    mean += d / n;
+    m2 += d * (v - mean);
+}
+
+__device__ __forceinline__ void chan_merge(FeatPart &a, const FeatPart &b) {
+    a.s_nnz2 += b.s_nnz2;
+    a.s_bw += b.s_bw;
+    a.s_bw2 += b.s_bw2;
+    a.s_miss += b.s_miss;
+    a.s_grp += b.s_grp;
+    a.s_len1 += b.s_len1;
+    a.nnz_min = min(a.nnz_min, b.nnz_min);
+    a.nnz_max = max(a.nnz_max, b.nnz_max);
+    a.bw_min = min(a.bw_min, b.bw_min);
+    a.bw_max = max(a.bw_max, b.bw_max);
+    a.s_cl += b.s_cl;
+    if (b.sc_n > 0.0) {
+        if (a.sc_n == 0.0) {
+            a.sc_n = b.sc_n;
+            a.sc_mean = b.sc_mean;
+            a.sc_m2 = b.sc_m2;
+        } else {
+            const double n = a.sc_n + b.sc_n;
+            const double d = b.sc_mean - a.sc_mean;
+            a.sc_mean += d * (b.sc_n / n);
+            a.sc_m2 += b.sc_m2 + d * d * (a.sc_n * b.sc_n / n);
+            a.sc_n = n;
+        }
+    }
+}
+
+__device__ __forceinline__ void part_init(FeatPart &p) {
+    p.s_nnz2 = p.s_bw = p.s_bw2 = p.s_miss = p.s_grp = p.s_len1 = 0;
+    p.nnz_min = INT32_MAX;
+    p.nnz_max = INT32_MIN;
+    p.bw_min = INT32_MAX;
+    p.bw_max = INT32_MIN;
+    p.sc_n = p.sc_mean = p.sc_m2 = 0.0;
+    p.s_cl = 0.0;
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_features(const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col,
+                                                     int32_t n_rows, int32_t rows_per_block,
+                                                     FeatPart *__restrict__ out) {
+    __shared__ FeatPart s_part[kBlock / G];
+    constexpr int NG = kBlock / G;
+    const int lane = threadIdx.x % G;
+    const int grp = threadIdx.x / G;
+    FeatPart p;
+    part_init(p);
+    const int64_t r_begin = (int64_t)blockIdx.x * rows_per_block;
+    int64_t r_end = r_begin + rows_per_block;
+    if (r_end > n_rows) r_end = n_rows;
+    for (int64_t r = r_begin + grp; r < r_end; r += NG) {
+        const int32_t b = rp[r], e = rp[r + 1];
+        int32_t mn = INT32_MAX, mx = INT32_MIN, miss = 0, grps = 0;
+        int32_t prev_last = 0;  // last column of the previous chunk (lane G-1's)
+        for (int32_t j0 = b; j0 < e; j0 += G) {
+            const int32_t j = j0 + lane;
+            const bool ok = j < e;
+            const int32_t c = ok ? col[j] : 0;
+            int32_t prev = __shfl_up(c, 1, G);
+            if (lane == 0) prev = prev_last;
+            if (ok) {
+                mn = min(mn, c);
+                mx = max(mx, c);
+                if (j == b) {
+                    miss += 1;
+                    grps += 1;
+                } else {
+                    const int64_t d = (int64_t)c - prev;
+                    miss += (d > kFeatE || d < -kFeatE) ? 1 : 0;
+                    grps += (d != 1) ? 1 : 0;
+                }
+            }
+            prev_last = __shfl(c, G - 1, G);
+        }
+        mn = -group_max<G>(-mn);
+        mx = group_max<G>(mx);
+        miss = group_isum<G>(miss);
+        grps = group_isum<G>(grps);
+        if (lane == 0) {
+            const int32_t k = e - b;
+            const int32_t bw = k > 0 ? mx - mn : 0;
+            p.s_nnz2 += (int64_t)k * k;
+            p.s_bw += bw;
+            p.s_bw2 += (int64_t)bw * bw;
+            p.s_miss += miss;
+            p.s_grp += grps;
+            p.s_len1 += k > 0 ? k - 1 : 0;
+            p.nnz_min = min(p.nnz_min, k);
+            p.nnz_max = max(p.nnz_max, k);
+            p.bw_min = min(p.bw_min, bw);
+            p.bw_max = max(p.bw_max, bw);
+            const double sc = k > 0 ? (double)k / (double)(bw > 1 ? bw : 1) : 0.0;
+            welford_push(p.sc_n, p.sc_mean, p.sc_m2, sc);
+            p.s_cl += k > 0 ? (double)grps / (double)k : 0.0;
+        }
+    }
+    if (lane == 0) s_part[grp] = p;
+    __syncthreads();
+    for (int w = NG / 2; w > 0; w >>= 1) {
+        if (lane == 0 && grp < w) chan_merge(s_part[grp], s_part[grp + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = s_part[0];
+}
+
+// Fold the per-block partials in block order (one workgroup, fixed tree).
+__global__ __launch_bounds__(kBlock) void k_features_fold(FeatPart *__restrict__ parts,
+                                                          int32_t n_parts) {
+    __shared__ FeatPart s[kBlock];
+    FeatPart p;
+    part_init(p);
+    // thread t folds parts t*chunk .. (t+1)*chunk-1 in order
+    const int32_t chunk = (n_parts + kBlock - 1) / kBlock;
+    const int32_t a = threadIdx.x * chunk;
+    const int32_t b = min(a + chunk, n_parts);
+    for (int32_t q = a; q < b; ++q) chan_merge(p, parts[q]);
+    s[threadIdx.x] = p;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) chan_merge(s[threadIdx.x], s[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) parts[0] = s[0];
+}
+
+// x-reuse sample s: rows r = 1 + floor(s (N-1) / S) and r-1, first P entries
+// each; line ids col >> 4. distinct = run heads of row r's line ids, shared =
+// run heads that also occur among row r-1's line ids.
+__global__ __launch_bounds__(kWave) void k_xreuse(const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ col, int32_t n_rows,
+                                                  int32_t n_samples,
+                                                  int32_t *__restrict__ out /* 2 per sample */) {
+    __shared__ int32_t s_prev[kReuseP];
+    const int s = blockIdx.x;
+    if (s >= n_samples) return;
+    const int64_t r = 1 + ((int64_t)s * (n_rows - 1)) / n_samples;
+    const int32_t b1 = rp[r], e1 = min(rp[r + 1], b1 + kReuseP);
+    const int32_t b0 = rp[r - 1], e0 = min(rp[r], b0 + kReuseP);
+    const int n0 = e0 - b0;
+    for (int k = threadIdx.x; k < n0; k += kWave) s_prev[k] = col[b0 + k] >> 4;
+    __syncthreads();
+    int distinct = 0, shared = 0;
+    for (int32_t j = b1 + threadIdx.x; j < e1; j += kWave) {
+        const int32_t line = col[j] >> 4;
+        if (j > b1 && (col[j - 1] >> 4) == line) continue;
+        ++distinct;
+        for (int q = 0; q < n0; ++q)
+            if (s_prev[q] == line) {
+                ++shared;
+                break;
+            }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        distinct += __shfl_xor(distinct, off);
+        shared += __shfl_xor(shared, off);
+    }
+    if (threadIdx.x == 0) {
+        out[2 * s] = shared;
+        out[2 * s + 1] = distinct;
+    }
+}
+
+template <int G>
+hipError_t go(const int32_t *rp, const int32_t *col, int32_t n_rows, FeatPart *parts,
+              int32_t n_parts, int32_t rows_per_block, hipStream_t s) {
+    hipLaunchKernelGGL(k_features<G>, dim3(n_parts), dim3(kBlock), 0, s, rp, col, n_rows,
+                       rows_per_block, parts);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int32_t features_partials(int32_t n_rows, int G, int32_t *rows_per_block) {
+    const int NG = kBlock / G;
+    // 4 row groups per lane group, so a block sweeps 4 * 256/G rows
+    int32_t rpb = NG * 4;
+    *rows_per_block = rpb;
+    return n_rows > 0 ? (n_rows + rpb - 1) / rpb : 1;
+}
+
+int32_t xreuse_samples(int32_t n_rows) { return n_rows > 1 ? min(n_rows - 1, kReuseS) : 0; }
+
+hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int G,
+                           FeatPart *parts, int32_t n_parts, int32_t rows_per_block,
+                           int32_t *reuse_out, hipStream_t s) {
+    hipError_t e;
+    switch (G) {
+    case 1: e = go<1>(rp, col, n_rows, parts, n_parts, rows_per_block, s); break;
+    case 2: e = go<2>(rp, col, n_rows, parts, n_parts, rows_per_block, s); break;
+    case 4: e = go<4>(rp, col, n_rows, parts, n_parts, rows_per_block, s); break;
+    case 8: e = go<8>(rp, col, n_rows, parts, n_parts, rows_per_block, s); break;
+    case 16: e = go<16>(rp, col, n_rows, parts, n_parts, rows_per_block, s); break;
+    case 32: e = go<32>(rp, col, n_rows, parts, n_parts, rows_per_block, s); break;
+    default: e = go<64>(rp, col, n_rows, parts, n_parts, rows_per_block, s); break;
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_features_fold, dim3(1), dim3(kBlock), 0, s, parts, n_parts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int32_t ns = xreuse_samples(n_rows);
+    if (ns > 0) {
+        hipLaunchKernelGGL(k_xreuse, dim3(ns), dim3(kWave), 0, s, rp, col, n_rows, ns, reuse_out);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+}  // namespace csr

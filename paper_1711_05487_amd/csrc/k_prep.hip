@@ -93,21 +93,6 @@ __global__ __launch_bounds__(kBlock) void k_convert(const double *__restrict__ s
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
-__global__ __launch_bounds__(kBlock) void k_triad(dvec2 *__restrict__ a,
-                                                  const dvec2 *__restrict__ b,
-                                                  const dvec2 *__restrict__ c, double s,
-                                                  int64_t n2) {
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n2; i += stride) {
-        const dvec2 bb = __builtin_nontemporal_load(b + i);
-        const dvec2 cc = __builtin_nontemporal_load(c + i);
-        dvec2 r;
-        r.x = fma(s, cc.x, bb.x);
-        r.y = fma(s, cc.y, bb.y);
-        __builtin_nontemporal_store(r, a + i);
-    }
-}
-
 // Delta codes (MB remedy, Sec. III-E): entry j of row r stores col[j] - r
 // (signed, first entry) or col[j] - col[j-1] (unsigned, >= 1) in `bits` bits.
 // Flag 1 is raised when some entry does not fit; the codes are then unusable.
@@ -158,6 +143,38 @@ __global__ __launch_bounds__(kBlock) void k_merge_partition(const int32_t *__res
     tile_j[t] = (int32_t)(d - lo);
 }
 
+// P_ML probe input (Sec. III-B): a column array holding, for every entry, the
+// index of its own row (clamped to the last column), so the probe reads the
+// same bytes as CSR but x regularly.
+__global__ __launch_bounds__(kBlock) void k_fill_row_index(const int32_t *__restrict__ rp,
+                                                           int32_t n_rows, int32_t n_cols,
+                                                           int32_t *__restrict__ out) {
+    const int lane = threadIdx.x % kWave;
+    const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kBlock / kWave;
+    for (int64_t r = wave; r < n_rows; r += nwaves) {
+        const int32_t b = rp[r], e = rp[r + 1];
+        const int32_t v = (int32_t)(r < n_cols ? r : n_cols - 1);
+        for (int32_t j = b + lane; j < e; j += kWave) out[j] = v;
+    }
+}
+
+// Triad for B_max: one 16-byte vector per array per thread, streamed.
+__global__ __launch_bounds__(kBlock) void k_triad1(dvec2 *__restrict__ a,
+                                                   const dvec2 *__restrict__ b,
+                                                   const dvec2 *__restrict__ c, double s,
+                                                   int64_t n2) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n2) {
+        const dvec2 bb = __builtin_nontemporal_load(b + i);
+        const dvec2 cc = __builtin_nontemporal_load(c + i);
+        dvec2 r;
+        r.x = fma(s, cc.x, bb.x);
+        r.y = fma(s, cc.y, bb.y);
+        __builtin_nontemporal_store(r, a + i);
+    }
+}
+
 unsigned grid_for(int64_t n, int64_t per_block_items, unsigned cap) {
     int64_t g = (n + per_block_items - 1) / per_block_items;
     if (g < 1) g = 1;
@@ -196,6 +213,13 @@ hipError_t launch_merge_partition(const int32_t *rp, int32_t n_rows, int64_t nnz
     return hipGetLastError();
 }
 
+hipError_t launch_fill_row_index(const int32_t *rp, int32_t n_rows, int32_t n_cols, int32_t *out,
+                                 hipStream_t s) {
+    const unsigned g = grid_for((int64_t)n_rows * kWave, kBlock, 256 * 16);
+    hipLaunchKernelGGL(k_fill_row_index, dim3(g), dim3(kBlock), 0, s, rp, n_rows, n_cols, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_convert_values(const double *src, void *dst, int64_t n, int storage,
                                  hipStream_t s) {
     if (n == 0) return hipSuccess;
@@ -207,8 +231,8 @@ hipError_t launch_convert_values(const double *src, void *dst, int64_t n, int st
 hipError_t launch_triad(double *a, const double *b, const double *c, double scalar, int64_t n,
                         hipStream_t s) {
     const int64_t n2 = n / 2;
-    const unsigned g = grid_for(n2, kBlock * 8, 256 * 64);
-    hipLaunchKernelGGL(k_triad, dim3(g), dim3(kBlock), 0, s, (dvec2 *)a, (const dvec2 *)b,
+    const unsigned g = (unsigned)((n2 + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_triad1, dim3(g), dim3(kBlock), 0, s, (dvec2 *)a, (const dvec2 *)b,
                        (const dvec2 *)c, scalar, n2);
     return hipGetLastError();
 }

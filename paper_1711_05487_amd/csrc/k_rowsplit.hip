@@ -13,6 +13,9 @@
 //
 // PROBE = 1 is the P_CMP micro-benchmark of Sec. III-B: the same kernel with
 // the column-index stream removed and x read at the row index (unit stride).
+// PROBE = 2 is the plain kernel instrumented for P_IMB: each workgroup
+// records its start and end times (100 MHz constant clock) and the compute
+// unit it ran on.
 //
 // This file is compiled once per storage type (-DCSR_STORAGE=0/1/2).
 #include "device.h"
@@ -34,9 +37,13 @@ __global__ __launch_bounds__(kBlock) void k_rowsplit(
     const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
     const void *__restrict__ codes, const V *__restrict__ val, const X *__restrict__ x,
     X *__restrict__ y, int32_t skip_above, int32_t n_rows, int32_t n_cols, int64_t per_xcd,
-    int64_t nblk) {
+    int64_t nblk, int64_t *__restrict__ rec) {
     const int64_t lb = xcd_logical_block(per_xcd);
     if (lb >= nblk) return;
+    int64_t t_start = 0;
+    if constexpr (PROBE == 2) {
+        if (threadIdx.x == 0) t_start = (int64_t)wall_clock64();
+    }
     constexpr int NG = kBlock / G;
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
@@ -136,6 +143,14 @@ __global__ __launch_bounds__(kBlock) void k_rowsplit(
         t = group_sum<G>(t);
         if (mine[k] && lane == 0) y[row[k]] = (X)t;
     }
+    if constexpr (PROBE == 2) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            rec[3 * lb] = t_start;
+            rec[3 * lb + 1] = (int64_t)wall_clock64();
+            rec[3 * lb + 2] = (int64_t)__smid();
+        }
+    }
 }
 
 template <int G, int IDX, bool NT, int U, int R, int PROBE>
@@ -148,7 +163,7 @@ hipError_t go(const void *const *arr, int32_t skip_above, int32_t n_rows, int32_
     hipLaunchKernelGGL((k_rowsplit<G, IDX, NT, U, R, PROBE>), dim3((unsigned)g.launched),
                        dim3(kBlock), 0, s, (const int32_t *)arr[0], (const int32_t *)arr[1],
                        arr[2], (const V *)arr[3], (const X *)arr[4], (X *)arr[5], skip_above,
-                       n_rows, n_cols, g.per_xcd, g.nblk);
+                       n_rows, n_cols, g.per_xcd, g.nblk, (int64_t *)arr[6]);
     return hipGetLastError();
 }
 
@@ -164,6 +179,7 @@ template <int G>
 hipError_t pick(int idx, bool nt, int U, int R, int probe, const void *const *arr,
                 int32_t skip, int32_t n_rows, int32_t n_cols, hipStream_t s) {
     if (probe == 1) return go<G, IDX_I32, false, 4, 1, 1>(arr, skip, n_rows, n_cols, s);
+    if (probe == 2) return go<G, IDX_I32, false, 1, 1, 2>(arr, skip, n_rows, n_cols, s);
     if (idx == IDX_I32) {
         if (nt) return U >= 4 ? pick_r<G, true, 4>(R, arr, skip, n_rows, n_cols, s)
                               : pick_r<G, true, 1>(R, arr, skip, n_rows, n_cols, s);
@@ -179,7 +195,7 @@ hipError_t pick(int idx, bool nt, int U, int R, int probe, const void *const *ar
 
 }  // namespace
 
-// arr = {rp, col, codes, val, x, y}
+// arr = {rp, col, codes, val, x, y, instrumentation records}
 #define CSR_CAT2(a, b) a##b
 #define CSR_CAT(a, b) CSR_CAT2(a, b)
 hipError_t CSR_CAT(launch_rowsplit_s, CSR_STORAGE)(int G, int idx, bool nt, int U, int R,

@@ -1,0 +1,696 @@
+// Plans and variant selection: realizing a set of optimizations as a concrete
+// kernel plan (with its preprocessing), feature extraction (Sec. III-D), the
+// profile-guided classifier with its micro-benchmarks and bounds (Sec. III-B,
+// III-C), the class-to-optimization map (Sec. III-E, Table II), a small
+// autotuner, and the exhaustive sweep over the 16-entry catalogue (the
+// trivial optimizers of Sec. IV-D).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+
+namespace csr {
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+constexpr double kCacheBytes = 256.0 * 1024 * 1024;  // MI355X Infinity Cache
+
+struct DeviceBandwidth {
+    double hbm = 0, cache = 0;
+};
+
+}  // namespace
+
+// Catalogue of optimization sets: the baseline, the 5 singles and the 10
+// pairs, the sets the trivial optimizers of Sec. IV-D sweep.
+const int32_t kCatalogue[16] = {0,     1,     2,     4,     8,     16,    1 | 2, 1 | 4,
+                                1 | 8, 1 | 16, 2 | 4, 2 | 8, 2 | 16, 4 | 8, 4 | 16, 8 | 16};
+
+int catalogue_id(int32_t opts) {
+    for (int k = 0; k < 16; ++k)
+        if (kCatalogue[k] == opts) return k;
+    return -1;
+}
+
+double plan_bytes(const csr_matrix_s *A, const Plan &P) {
+    const double vb = (double)storage_bytes(A->storage);
+    const double xb = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
+    const double ib = P.idx == IDX_D16 ? 2.0 : P.idx == IDX_D8 ? 1.0 : 4.0;
+    double b = (double)A->nnz * (vb + ib) + 4.0 * (A->n_rows + 1) + xb * A->n_cols +
+               xb * A->n_rows;
+    if (P.opts & CSR_OPT_MERGE) {
+        const double T = (double)A->n_tiles;
+        b += 2.0 * 4.0 * (T + 1) + 2.0 * (A->storage == CSR_VAL_F64 ? 8.0 : 4.0) * T;
+    }
+    if (P.long_rows && A->n_long > 0) {
+        const double ab = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
+        b += 8.0 * A->n_long_chunks + 4.0 * (2.0 * A->n_long + 1) + 2.0 * ab * A->n_long_chunks;
+    }
+    return b;
+}
+
+void fill_info(const csr_matrix_s *A, const Plan &P, csr_plan_info_t *info) {
+    info->opts = P.opts;
+    info->lanes_per_row = P.G;
+    info->merge_items = P.L;
+    info->delta_bits = P.idx == IDX_D16 ? 16 : P.idx == IDX_D8 ? 8 : 32;
+    info->n_long_rows = P.long_rows ? A->n_long : 0;
+    info->variant_id = catalogue_id(P.opts);
+    info->format_bytes = plan_bytes(A, P);
+}
+
+// --------------------------------------------------------------------------
+// Preprocessing of the individual remedies
+// --------------------------------------------------------------------------
+namespace {
+
+csr_status_t build_delta(csr_matrix_s *A, hipStream_t s) {
+    if (A->code_bits != 32) return CSR_OK;  // built already, or known ineligible (0)
+    A->code_bits = 0;
+    if (!A->rows_sorted) return CSR_OK;
+    for (int bits : {8, 16}) {
+        DevBuf flags, codes;
+        csr_status_t st;
+        if ((st = flags.alloc(sizeof(int32_t))) != CSR_OK) return st;
+        if ((st = codes.alloc((size_t)A->nnz * (bits / 8) + kPadBytes)) != CSR_OK) return st;
+        CSR_HIP(hipMemsetAsync(flags.p, 0, sizeof(int32_t), s));
+        CSR_HIP(launch_delta_encode(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->n_rows, bits,
+                                    codes.p, flags.as<int32_t>(), s));
+        int32_t h = 0;
+        CSR_HIP(hipMemcpyAsync(&h, flags.p, sizeof(h), hipMemcpyDeviceToHost, s));
+        CSR_HIP(hipStreamSynchronize(s));
+        if (h == 0) {
+            std::swap(A->codes.p, codes.p);
+            std::swap(A->codes.bytes, codes.bytes);
+            A->code_bits = bits;
+            return CSR_OK;
+        }
+    }
+    return CSR_OK;
+}
+
+csr_status_t build_tiles(csr_matrix_s *A, int L, hipStream_t s) {
+    if (A->tiles_L == L) return CSR_OK;
+    const int64_t total = (int64_t)A->n_rows + A->nnz;
+    const int64_t T = (total + L - 1) / L;
+    csr_status_t st;
+    if ((st = A->tile_i.alloc(sizeof(int32_t) * (T + 1))) != CSR_OK) return st;
+    if ((st = A->tile_j.alloc(sizeof(int32_t) * (T + 1))) != CSR_OK) return st;
+    if ((st = A->carry.alloc((A->storage == CSR_VAL_F64 ? 8 : 4) * (size_t)(T + 1))) != CSR_OK)
+        return st;
+    CSR_HIP(launch_merge_partition(A->rp.as<int32_t>(), A->n_rows, A->nnz, L, T,
+                                   A->tile_i.as<int32_t>(), A->tile_j.as<int32_t>(), s));
+    A->n_tiles = T;
+    A->tiles_L = L;
+    return CSR_OK;
+}
+
+// Long rows: nnz_i > tau. The list (ascending) and the chunk layout are built
+// on the host from a copy of row_ptr.
+constexpr int32_t kLongChunk = 8192;
+
+csr_status_t build_long_rows(csr_matrix_s *A, int64_t tau, hipStream_t s) {
+    if (A->long_tau == tau) return CSR_OK;
+    std::vector<int32_t> rp((size_t)A->n_rows + 1);
+    CSR_HIP(hipMemcpyAsync(rp.data(), A->rp.p, sizeof(int32_t) * rp.size(),
+                           hipMemcpyDeviceToHost, s));
+    CSR_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> rows, row_chunk{0}, chunks;
+    for (int32_t i = 0; i < A->n_rows; ++i) {
+        const int64_t k = (int64_t)rp[i + 1] - rp[i];
+        if (k <= tau) continue;
+        rows.push_back(i);
+        for (int64_t b = rp[i]; b < rp[i + 1]; b += kLongChunk) {
+            chunks.push_back((int32_t)b);
+            chunks.push_back((int32_t)std::min<int64_t>(b + kLongChunk, rp[i + 1]));
+        }
+        row_chunk.push_back((int32_t)(chunks.size() / 2));
+    }
+    A->n_long = (int32_t)rows.size();
+    A->n_long_chunks = (int64_t)chunks.size() / 2;
+    csr_status_t st;
+    if ((st = A->long_list.alloc(sizeof(int32_t) * rows.size())) != CSR_OK) return st;
+    if ((st = A->long_row_chunk.alloc(sizeof(int32_t) * row_chunk.size())) != CSR_OK) return st;
+    if ((st = A->long_chunks.alloc(sizeof(int32_t) * chunks.size())) != CSR_OK) return st;
+    if ((st = A->long_part.alloc(8 * (size_t)A->n_long_chunks)) != CSR_OK) return st;
+    if (!rows.empty()) {
+        CSR_HIP(hipMemcpyAsync(A->long_list.p, rows.data(), sizeof(int32_t) * rows.size(),
+                               hipMemcpyHostToDevice, s));
+        CSR_HIP(hipMemcpyAsync(A->long_row_chunk.p, row_chunk.data(),
+                               sizeof(int32_t) * row_chunk.size(), hipMemcpyHostToDevice, s));
+        CSR_HIP(hipMemcpyAsync(A->long_chunks.p, chunks.data(), sizeof(int32_t) * chunks.size(),
+                               hipMemcpyHostToDevice, s));
+        CSR_HIP(hipStreamSynchronize(s));
+    }
+    A->long_tau = tau;
+    return CSR_OK;
+}
+
+int64_t long_row_tau(const csr_matrix_s *A, const csr_config_t &cfg) {
+    const double nnz_avg = A->n_rows ? (double)A->nnz / A->n_rows : 0.0;
+    const double t = std::max(cfg.long_row_factor * nnz_avg, (double)cfg.long_row_floor);
+    return (int64_t)t;
+}
+
+}  // namespace
+
+// Realize an optimization mask as a concrete plan, building what it needs.
+// Parameters not fixed by cfg take the defaults below; the autotuner varies
+// them.
+csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Plan *out,
+                     hipStream_t s) {
+    Plan P;
+    P.opts = opts;
+    const double nnz_avg = A->n_rows ? (double)A->nnz / A->n_rows : 0.0;
+    const int G0 = default_lanes_per_row(nnz_avg);
+    P.G = G0;
+    if (opts & CSR_OPT_UNROLL) {  // CMP: more rows per wave, independent accumulators
+        P.G = G0 >= 2 ? G0 / 2 : 1;
+        P.U = 4;
+        P.R = 2;
+    }
+    if (opts & CSR_OPT_PREFETCH) {  // ML: streamed val/col, more gathers in flight
+        P.nt = 1;
+        P.R = 4;
+    }
+    if (cfg.rows_per_group > 0) P.G = cfg.rows_per_group;
+    if (cfg.rows_in_flight > 0) P.R = cfg.rows_in_flight >= 4 ? 4 : cfg.rows_in_flight >= 2 ? 2 : 1;
+    csr_status_t st;
+    if (opts & CSR_OPT_MERGE) {
+        // IMB (GPU counterpart of the runtime-chosen schedule). With DECOMP
+        // as well, the merge path already balances long rows.
+        const int L = cfg.merge_items > 0 ? cfg.merge_items : 2048;
+        if (L != 1024 && L != 2048 && L != 4096)
+            return fail(CSR_ERR_INVALID_ARG, "merge_items must be 1024, 2048 or 4096");
+        if ((st = build_tiles(A, L, s)) != CSR_OK) return st;
+        P.L = L;
+        P.G = 0;
+        P.U = 1;
+        P.R = 1;
+    } else if (opts & CSR_OPT_DECOMP) {
+        if ((st = build_long_rows(A, long_row_tau(A, cfg), s)) != CSR_OK) return st;
+        P.long_rows = 1;
+    }
+    if ((opts & CSR_OPT_DELTA) && !(opts & CSR_OPT_MERGE)) {
+        // MB: delta codes; when the matrix is not eligible only the wide-load
+        // half of the remedy applies
+        if ((st = build_delta(A, s)) != CSR_OK) return st;
+        if (A->code_bits == 8 || A->code_bits == 16) {
+            P.idx = A->code_bits == 8 ? IDX_D8 : IDX_D16;
+            P.U = 1;
+            P.R = 1;
+        } else {
+            P.U = 4;
+        }
+    }
+    *out = P;
+    return CSR_OK;
+}
+
+// --------------------------------------------------------------------------
+// Timing
+// --------------------------------------------------------------------------
+namespace {
+
+csr_status_t ensure_scratch(csr_matrix_s *A, hipStream_t s) {
+    const size_t xb = A->storage == CSR_VAL_F64 ? 8 : 4;
+    csr_status_t st;
+    if (!A->scratch_x.p) {
+        if ((st = A->scratch_x.alloc(xb * (size_t)A->n_cols)) != CSR_OK) return st;
+        CSR_HIP(hipMemsetAsync(A->scratch_x.p, 0, A->scratch_x.bytes, s));
+    }
+    if (!A->scratch_y.p) {
+        if ((st = A->scratch_y.alloc(xb * (size_t)A->n_rows)) != CSR_OK) return st;
+    }
+    return CSR_OK;
+}
+
+// `calls` back-to-back SpMVs between two events, `runs` times, after one
+// untimed call. Returns the time per call as the reciprocal of the harmonic
+// mean of the per-run rates (Sec. IV-A): the mean of the per-run times.
+template <class Launch>
+csr_status_t time_launches(Launch &&launch, int calls, int runs, hipStream_t s,
+                           double *ms_per_call) {
+    hipEvent_t e0, e1;
+    CSR_HIP(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    e = launch();
+    double sum = 0.0;
+    for (int r = 0; r < runs && e == hipSuccess; ++r) {
+        e = hipEventRecord(e0, s);
+        for (int c = 0; c < calls && e == hipSuccess; ++c) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        sum += (double)ms / calls;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "timed launches");
+    *ms_per_call = sum / runs;
+    return CSR_OK;
+}
+
+csr_status_t time_plan(csr_matrix_s *A, const Plan &P, int calls, int runs, hipStream_t s,
+                       double *ms) {
+    csr_status_t st = ensure_scratch(A, s);
+    if (st != CSR_OK) return st;
+    return time_launches([&] { return launch_spmv(A, P, A->scratch_x.p, A->scratch_y.p, s); },
+                         calls, runs, s, ms);
+}
+
+bool opts_realizable(int32_t opts) { return (opts & ~31) == 0; }
+
+csr_status_t ensure_row_index(csr_matrix_s *A, hipStream_t s) {
+    if (A->scratch_col.p) return CSR_OK;
+    csr_status_t st;
+    if ((st = A->scratch_col.alloc(sizeof(int32_t) * (size_t)A->nnz + kPadBytes)) != CSR_OK)
+        return st;
+    CSR_HIP(launch_fill_row_index(A->rp.as<int32_t>(), A->n_rows, A->n_cols,
+                                  A->scratch_col.as<int32_t>(), s));
+    return CSR_OK;
+}
+
+// The micro-benchmarks of Sec. III-B on the baseline kernel (G lanes per
+// row): which = 1 P_ML (colind := row index), 2 P_CMP (no colind, x[row]).
+hipError_t launch_probe(const csr_matrix_s *A, int G, int which, const void *x, void *y,
+                        hipStream_t s) {
+    const void *col = which == 1 ? A->scratch_col.p : A->col.p;
+    const int probe = which == 2 ? 1 : 0;
+    const void *arr[7] = {A->rp.p, col, nullptr, A->val.p, x, y, nullptr};
+    switch (A->storage) {
+    case CSR_VAL_F64:
+        return launch_rowsplit_s0(G, IDX_I32, false, 1, 1, probe, arr, INT32_MAX, A->n_rows,
+                                  A->n_cols, s);
+    case CSR_VAL_F32:
+        return launch_rowsplit_s1(G, IDX_I32, false, 1, 1, probe, arr, INT32_MAX, A->n_rows,
+                                  A->n_cols, s);
+    default:
+        return launch_rowsplit_s2(G, IDX_I32, false, 1, 1, probe, arr, INT32_MAX, A->n_rows,
+                                  A->n_cols, s);
+    }
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// B_max: triad bandwidth at an HBM-sized and an Infinity-Cache-sized
+// footprint, measured once per device (Sec. III-B footnote on cache-resident
+// working sets; Sec. IV-A, Table III).
+// --------------------------------------------------------------------------
+csr_status_t device_bandwidth(int device, hipStream_t s, double *hbm, double *cache) {
+    static std::mutex mu;
+    static std::map<int, DeviceBandwidth> known;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = known.find(device);
+        if (it != known.end()) {
+            *hbm = it->second.hbm;
+            *cache = it->second.cache;
+            return CSR_OK;
+        }
+    }
+    DeviceBandwidth d;
+    csr_status_t st;
+    if ((st = csr_triad((size_t)1 << 30, 3, &d.hbm, s)) != CSR_OK) return st;
+    if ((st = csr_triad((size_t)48 << 20, 5, &d.cache, s)) != CSR_OK) return st;
+    if (d.cache < d.hbm) d.cache = d.hbm;
+    std::lock_guard<std::mutex> lk(mu);
+    known[device] = d;
+    *hbm = d.hbm;
+    *cache = d.cache;
+    return CSR_OK;
+}
+
+// --------------------------------------------------------------------------
+// Features (Sec. III-D, Table I)
+// --------------------------------------------------------------------------
+csr_status_t inspect(csr_matrix_s *A, hipStream_t s) {
+    const auto t0 = Clock::now();
+    csr_features_t F{};
+    F.rows_sorted = A->rows_sorted;
+    const int64_t N = A->n_rows;
+    if (N > 0) {
+        const double nnz_avg = (double)A->nnz / N;
+        const int G = default_lanes_per_row(nnz_avg);
+        int32_t rpb = 0;
+        const int32_t n_parts = features_partials(A->n_rows, G, &rpb);
+        const int32_t n_samp = xreuse_samples(A->n_rows);
+        csr_status_t st;
+        if (A->feat_parts.bytes < sizeof(FeatPart) * (size_t)n_parts &&
+            (st = A->feat_parts.alloc(sizeof(FeatPart) * (size_t)n_parts)) != CSR_OK)
+            return st;
+        if (A->feat_reuse.bytes < sizeof(int32_t) * 2 * (size_t)n_samp + 8 &&
+            (st = A->feat_reuse.alloc(sizeof(int32_t) * 2 * (size_t)n_samp + 8)) != CSR_OK)
+            return st;
+        CSR_HIP(launch_features(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->n_rows, G,
+                                A->feat_parts.as<FeatPart>(), n_parts, rpb,
+                                A->feat_reuse.as<int32_t>(), s));
+        FeatPart p;
+        std::vector<int32_t> reuse(2 * (size_t)n_samp);
+        CSR_HIP(hipMemcpyAsync(&p, A->feat_parts.p, sizeof(p), hipMemcpyDeviceToHost, s));
+        if (n_samp > 0)
+            CSR_HIP(hipMemcpyAsync(reuse.data(), A->feat_reuse.p, sizeof(int32_t) * reuse.size(),
+                                   hipMemcpyDeviceToHost, s));
+        CSR_HIP(hipStreamSynchronize(s));
+        int64_t shared = 0, distinct = 0;
+        for (int32_t q = 0; q < n_samp; ++q) {
+            shared += reuse[2 * q];
+            distinct += reuse[2 * q + 1];
+        }
+        const int64_t s1 = A->nnz;
+        const double dN = (double)N;
+        // population variance from exact integer sums: (N*S2 - S1^2) / N^2
+        auto ivar = [&](int64_t sum, int64_t sum2) {
+            const __int128 num = (__int128)N * sum2 - (__int128)sum * sum;
+            return (double)num / (dN * dN);
+        };
+        const double bytes = 12.0 * (double)A->nnz + 4.0 * (double)(N + 1) +
+                             8.0 * (double)A->n_cols + 8.0 * (double)N;
+        F.f[0] = dN;
+        F.f[1] = p.nnz_min;
+        F.f[2] = p.nnz_max;
+        F.f[3] = (double)s1 / dN;
+        F.f[4] = std::sqrt(std::max(0.0, ivar(s1, p.s_nnz2)));
+        F.f[5] = p.bw_min;
+        F.f[6] = p.bw_max;
+        F.f[7] = (double)p.s_bw / dN;
+        F.f[8] = std::sqrt(std::max(0.0, ivar(p.s_bw, p.s_bw2)));
+        F.f[9] = p.sc_mean;
+        F.f[10] = std::sqrt(std::max(0.0, p.sc_m2 / dN));
+        F.f[11] = p.s_cl / dN;
+        F.f[12] = (double)p.s_miss / dN;
+        F.f[13] = bytes <= kCacheBytes ? 1.0 : 0.0;
+        F.f[14] = p.s_len1 ? (double)p.s_bw / (double)p.s_len1 : 0.0;
+        F.f[15] = distinct ? (double)shared / (double)distinct : 0.0;
+        F.isum[0] = s1;
+        F.isum[1] = p.s_nnz2;
+        F.isum[2] = p.s_bw;
+        F.isum[3] = p.s_bw2;
+        F.isum[4] = p.s_miss;
+        F.isum[5] = p.s_grp;
+        F.isum[6] = shared;
+        F.isum[7] = distinct;
+    }
+    A->feat = F;
+    A->has_features = 1;
+    A->t_inspect_ms = ms_since(t0);
+    return CSR_OK;
+}
+
+// --------------------------------------------------------------------------
+// Profile-guided classification (Sec. III-B bounds, Sec. III-C rule)
+// --------------------------------------------------------------------------
+namespace {
+
+struct Bounds {
+    double p_csr, p_mb, p_ml, p_imb, p_cmp, p_peak, b_max;
+};
+
+csr_status_t measure_bounds(csr_matrix_s *A, const csr_config_t &cfg, hipStream_t s, Bounds *B) {
+    const int calls = cfg.timing_calls > 0 ? cfg.timing_calls : 32;
+    const double flops = 2.0 * (double)A->nnz;
+    csr_config_t dc;
+    csr_config_default(&dc);
+    Plan P0;
+    csr_status_t st;
+    if ((st = realize(A, 0, dc, &P0, s)) != CSR_OK) return st;
+    double t_csr = 0, t_ml = 0, t_cmp = 0;
+    if ((st = time_plan(A, P0, calls, 3, s, &t_csr)) != CSR_OK) return st;
+    // P_ML: the baseline kernel on colind := row (same bytes, regular x)
+    if ((st = ensure_row_index(A, s)) != CSR_OK) return st;
+    if ((st = time_launches([&] { return launch_probe(A, P0.G, 1, A->scratch_x.p, A->scratch_y.p, s); },
+                            calls, 3, s, &t_ml)) != CSR_OK)
+        return st;
+    // P_CMP: no column stream, x read at the row index
+    if ((st = time_launches([&] { return launch_probe(A, P0.G, 2, A->scratch_x.p, A->scratch_y.p, s); },
+                            calls, 3, s, &t_cmp)) != CSR_OK)
+        return st;
+    // P_IMB: per-CU busy spans of the instrumented baseline
+    double imb_ratio = 1.0;
+    {
+        const int NG = kBlock / P0.G;
+        const int64_t nblk = (A->n_rows + NG - 1) / NG;
+        DevBuf rec;
+        if ((st = rec.alloc(sizeof(int64_t) * 3 * (size_t)std::max<int64_t>(nblk, 1))) != CSR_OK)
+            return st;
+        const void *arr[7] = {A->rp.p, A->col.p, nullptr, A->val.p, A->scratch_x.p,
+                              A->scratch_y.p, rec.p};
+        hipError_t e;
+        switch (A->storage) {
+        case CSR_VAL_F64:
+            e = launch_rowsplit_s0(P0.G, IDX_I32, false, 1, 1, 2, arr, INT32_MAX, A->n_rows,
+                                   A->n_cols, s);
+            break;
+        case CSR_VAL_F32:
+            e = launch_rowsplit_s1(P0.G, IDX_I32, false, 1, 1, 2, arr, INT32_MAX, A->n_rows,
+                                   A->n_cols, s);
+            break;
+        default:
+            e = launch_rowsplit_s2(P0.G, IDX_I32, false, 1, 1, 2, arr, INT32_MAX, A->n_rows,
+                                   A->n_cols, s);
+            break;
+        }
+        if (e != hipSuccess) return hip_fail(e, "instrumented baseline");
+        std::vector<int64_t> h(3 * (size_t)nblk);
+        if (nblk > 0) {
+            CSR_HIP(hipMemcpyAsync(h.data(), rec.p, sizeof(int64_t) * h.size(),
+                                   hipMemcpyDeviceToHost, s));
+        }
+        CSR_HIP(hipStreamSynchronize(s));
+        std::map<int64_t, std::pair<int64_t, int64_t>> span;  // cu -> (min start, max end)
+        for (int64_t b = 0; b < nblk; ++b) {
+            auto it = span.find(h[3 * b + 2]);
+            if (it == span.end()) span[h[3 * b + 2]] = {h[3 * b], h[3 * b + 1]};
+            else {
+                it->second.first = std::min(it->second.first, h[3 * b]);
+                it->second.second = std::max(it->second.second, h[3 * b + 1]);
+            }
+        }
+        std::vector<double> d;
+        for (auto &kv : span) d.push_back((double)(kv.second.second - kv.second.first));
+        if (!d.empty()) {
+            std::sort(d.begin(), d.end());
+            const size_t m = d.size() / 2;
+            const double med = d.size() % 2 ? d[m] : 0.5 * (d[m - 1] + d[m]);
+            if (med > 0) imb_ratio = d.back() / med;
+        }
+    }
+    double b_hbm = 0, b_cache = 0;
+    if ((st = device_bandwidth(A->device, s, &b_hbm, &b_cache)) != CSR_OK) return st;
+    const double xb = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
+    const double vb = (double)storage_bytes(A->storage);
+    const double sx = xb * A->n_cols, sy = xb * A->n_rows;
+    const double s_fmt = (double)A->nnz * (vb + 4.0) + 4.0 * (A->n_rows + 1);
+    const double bmax = (s_fmt + sx + sy) <= kCacheBytes ? b_cache : b_hbm;
+    B->b_max = bmax;
+    B->p_csr = flops / (t_csr * 1e-3);
+    B->p_ml = flops / (t_ml * 1e-3);
+    B->p_cmp = flops / (t_cmp * 1e-3);
+    B->p_imb = B->p_csr * imb_ratio;  // 2 NNZ / t_median with t_median = t * median/max span
+    B->p_mb = flops / ((s_fmt + sx + sy) / bmax);
+    B->p_peak = flops / (((double)A->nnz * vb + sx + sy) / bmax);
+    return CSR_OK;
+}
+
+}  // namespace
+
+// Fig. 4: the profile-guided rule (cfg thresholds; "P_CSR ~ P_MB" read as
+// P_CSR >= t_mb * P_MB).
+int32_t classify(double p_csr, double p_mb, double p_ml, double p_imb, double p_cmp,
+                 double p_peak, const csr_config_t &cfg) {
+    int32_t c = 0;
+    if (p_imb / p_csr > cfg.t_imb) c |= CSR_CLS_IMB;
+    if (p_ml / p_csr > cfg.t_ml) c |= CSR_CLS_ML;
+    if (p_csr >= cfg.t_mb * p_mb && p_mb < p_cmp && p_cmp < p_peak) c |= CSR_CLS_MB;
+    if (p_mb > p_cmp || p_cmp > p_peak) c |= CSR_CLS_CMP;
+    return c;
+}
+
+// Table II: classes -> optimizations, applied jointly.
+int32_t remedies(int32_t classes, bool has_long_rows) {
+    int32_t o = 0;
+    if (classes & CSR_CLS_MB) o |= CSR_OPT_DELTA;
+    if (classes & CSR_CLS_ML) o |= CSR_OPT_PREFETCH;
+    if (classes & CSR_CLS_IMB) o |= has_long_rows ? CSR_OPT_DECOMP : CSR_OPT_MERGE;
+    if (classes & CSR_CLS_CMP) o |= CSR_OPT_UNROLL;
+    return o;
+}
+
+namespace {
+
+// A few parameter settings of the chosen optimization set, timed; the
+// fastest is kept.
+csr_status_t autotune(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, hipStream_t s,
+                      Plan *best) {
+    const int calls = cfg.timing_calls > 0 ? cfg.timing_calls : 32;
+    std::vector<csr_config_t> cands;
+    const double nnz_avg = A->n_rows ? (double)A->nnz / A->n_rows : 0.0;
+    const int G0 = default_lanes_per_row(nnz_avg);
+    if (opts & CSR_OPT_MERGE) {
+        for (int L : {1024, 2048, 4096}) {
+            csr_config_t c = cfg;
+            c.merge_items = L;
+            cands.push_back(c);
+        }
+    } else {
+        const int gs[3] = {G0, G0 >= 2 ? G0 / 2 : 1, G0 <= 32 ? G0 * 2 : 64};
+        for (int g : gs)
+            for (int r : {1, 4}) {
+                csr_config_t c = cfg;
+                c.rows_per_group = g;
+                c.rows_in_flight = r;
+                cands.push_back(c);
+            }
+    }
+    double best_ms = 1e300;
+    for (auto &c : cands) {
+        Plan Q;
+        csr_status_t st = realize(A, opts, c, &Q, s);
+        if (st != CSR_OK) return st;
+        double ms = 0;
+        if ((st = time_plan(A, Q, calls, 2, s, &ms)) != CSR_OK) return st;
+        if (ms < best_ms) {
+            best_ms = ms;
+            *best = Q;
+        }
+    }
+    return CSR_OK;
+}
+
+}  // namespace
+
+}  // namespace csr
+
+using namespace csr;
+
+extern "C" {
+
+csr_status_t csr_inspect(csr_matrix_t A, csr_features_t *out, void *stream) {
+    if (!A || !out) return fail(CSR_ERR_INVALID_ARG, "NULL argument");
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != A->device) (void)hipSetDevice(A->device);
+    csr_status_t st = inspect(A, (hipStream_t)stream);
+    if (prev >= 0 && prev != A->device) (void)hipSetDevice(prev);
+    if (st != CSR_OK) return st;
+    *out = A->feat;
+    return CSR_OK;
+}
+
+csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in,
+                        csr_plan_info_t *out, void *stream) {
+    if (!A) return fail(CSR_ERR_INVALID_ARG, "NULL handle");
+    csr_config_t cfg;
+    if (cfg_in) cfg = *cfg_in;
+    else csr_config_default(&cfg);
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != A->device) (void)hipSetDevice(A->device);
+    struct Restore {
+        int prev, dev;
+        ~Restore() {
+            if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+        }
+    } restore{prev, A->device};
+    hipStream_t s = (hipStream_t)stream;
+    const auto t0 = Clock::now();
+    Plan P;
+    csr_plan_info_t info{};
+    info.classes = -1;
+    csr_status_t st = CSR_OK;
+    double t_prep = 0.0;
+    switch (mode) {
+    case CSR_SEL_PLAIN:
+        st = realize(A, 0, cfg, &P, s);
+        break;
+    case CSR_SEL_FORCED:
+        if (!opts_realizable(cfg.forced_opts))
+            return fail(CSR_ERR_INVALID_ARG, "unknown optimization bits");
+        st = realize(A, cfg.forced_opts, cfg, &P, s);
+        break;
+    case CSR_SEL_EXHAUSTIVE: {
+        double best = 1e300;
+        const int calls = cfg.timing_calls > 0 ? cfg.timing_calls : 32;
+        for (int k = 0; k < 16 && st == CSR_OK; ++k) {
+            Plan Q;
+            if ((st = realize(A, kCatalogue[k], cfg, &Q, s)) != CSR_OK) break;
+            double ms = 0;
+            if ((st = time_plan(A, Q, calls, 3, s, &ms)) != CSR_OK) break;
+            if (ms < best) {
+                best = ms;
+                P = Q;
+            }
+        }
+        break;
+    }
+    case CSR_SEL_PROFILE: {
+        Bounds B{};
+        if ((st = measure_bounds(A, cfg, s, &B)) != CSR_OK) break;
+        if (!A->has_features && (st = inspect(A, s)) != CSR_OK) break;
+        const int32_t cls = classify(B.p_csr, B.p_mb, B.p_ml, B.p_imb, B.p_cmp, B.p_peak, cfg);
+        const bool has_long = A->feat.f[2] > (double)long_row_tau(A, cfg);
+        const int32_t opts = remedies(cls, has_long);
+        info.classes = cls;
+        info.p_csr = B.p_csr;
+        info.p_mb = B.p_mb;
+        info.p_ml = B.p_ml;
+        info.p_imb = B.p_imb;
+        info.p_cmp = B.p_cmp;
+        info.p_peak = B.p_peak;
+        info.b_max = B.b_max;
+        const auto tp = Clock::now();
+        if (cfg.autotune) st = autotune(A, opts, cfg, s, &P);
+        else st = realize(A, opts, cfg, &P, s);
+        t_prep = ms_since(tp);
+        break;
+    }
+    default:
+        return fail(CSR_ERR_UNSUPPORTED, "selection mode not available");
+    }
+    if (st != CSR_OK) return st;
+    CSR_HIP(hipStreamSynchronize(s));
+    A->plan = P;
+    fill_info(A, P, &info);
+    info.t_select_ms = ms_since(t0) - t_prep;
+    info.t_prep_ms = t_prep;
+    A->info = info;
+    if (out) *out = info;
+    return CSR_OK;
+}
+
+csr_status_t csr_debug_probe(csr_matrix_t A, int32_t which, const void *d_x, void *d_y,
+                             void *stream) {
+    if (!A || (which != 1 && which != 2) || (!d_x && A->n_cols > 0) || (!d_y && A->n_rows > 0))
+        return fail(CSR_ERR_INVALID_ARG, "bad probe arguments");
+    if (A->n_rows == 0) return CSR_OK;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != A->device) (void)hipSetDevice(A->device);
+    hipStream_t s = (hipStream_t)stream;
+    const double nnz_avg = (double)A->nnz / A->n_rows;
+    csr_status_t st = which == 1 ? ensure_row_index(A, s) : CSR_OK;
+    if (st == CSR_OK) {
+        const hipError_t e = launch_probe(A, default_lanes_per_row(nnz_avg), which, d_x, d_y, s);
+        if (e != hipSuccess) st = hip_fail(e, "probe");
+    }
+    if (prev >= 0 && prev != A->device) (void)hipSetDevice(prev);
+    return st;
+}
+
+}  // extern "C"

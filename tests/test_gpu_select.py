@@ -1,0 +1,176 @@
+"""GPU parity of the selection machinery: features (Sec. III-D, Table I), the
+micro-benchmark probes and the profile-guided rule (Sec. III-B/C, Fig. 4),
+the class-to-optimization map (Table II), the long-row decomposition
+(Sec. III-E, Figs. 5-6) and the exhaustive catalogue sweep (Sec. IV-D)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1711_05487_amd as pkg
+import synth
+from spmv_cases import check_f64, matrix, xvec
+
+pytestmark = pytest.mark.gpu
+
+F = {name: k for k, name in enumerate(oracle.FEATURE_NAMES)}
+
+
+def unsorted_with_empty_rows():
+    m, n = 300, 500
+    lens = synth.uindex(31, 0, np.arange(m, dtype=np.uint64), 40)
+    lens[::7] = 0
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    col = synth.uindex(32, 0, np.arange(rp[-1], dtype=np.uint64), n).astype(np.int32)
+    val = synth.vector(rp[-1], 33)
+    return m, n, rp, col, val
+
+
+FEATURE_CASES = ["lap100", "st27_24", "rmat14", "unif14", "tiny", "unsorted", "onerow"]
+
+
+def feature_case(name):
+    if name == "tiny":
+        return synth.tiny_random(333, 777, 0.03, 5)
+    if name == "unsorted":
+        return unsorted_with_empty_rows()
+    if name == "onerow":
+        return 1, 50, np.array([0, 4], dtype=np.int32), np.array([3, 4, 5, 40], dtype=np.int32), np.ones(4)
+    return matrix(name)
+
+
+@pytest.mark.parametrize("name", FEATURE_CASES)
+def test_features_match_oracle(name):
+    n, m, rp, col, val = feature_case(name)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    f, isum, sorted_flag = A.inspect()
+    rf, ri = oracle.features(n, m, rp, col)
+    assert np.array_equal(isum, ri)                       # exact integer sums
+    assert sorted_flag == int(oracle.rows_sorted(rp, col))
+    for k in ("N", "nnz_min", "nnz_max", "bw_min", "bw_max", "size", "x_reuse"):
+        assert f[F[k]] == rf[F[k]], k                     # exact
+    N = max(n, 1)
+    gam = 2 * N * 2.0 ** -53 / (1 - 2 * N * 2.0 ** -53)   # two summation orders of N terms
+    for k in ("nnz_avg", "bw_avg", "misses_avg", "mean_col_gap", "clustering_avg", "scatter_avg"):
+        assert math.isclose(f[F[k]], rf[F[k]], rel_tol=max(gam, 1e-13), abs_tol=1e-300), k
+    # standard deviations: the oracle's two-pass definition against exact
+    # integer variances (nnz, bw) and a Welford/Chan merge (scatter)
+    for k, scale in (("nnz_sd", "nnz_avg"), ("bw_sd", "bw_avg"), ("scatter_sd", "scatter_avg")):
+        assert math.isclose(f[F[k]], rf[F[k]], rel_tol=1e-10, abs_tol=1e-12 * max(rf[F[scale]], 1.0)), k
+
+
+def test_features_stencil27_full_size():
+    n, m, rp, col, val = matrix("st27_128")
+    A = pkg.CsrMatrix(rp, col, val)
+    f, isum, _ = A.inspect()
+    rf, ri = oracle.features(n, m, rp, col)
+    assert np.array_equal(isum, ri)
+    assert np.allclose(f, rf, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("which", [1, 2])
+def test_probes_compute_rowsum_times_x(which):
+    # both probes give y_i = x_min(i, n_cols-1) * sum_j a_ij (dyadic: exact)
+    for n, m, rp, col, val in (synth.tiny_random(400, 300, 0.05, 9, dyadic=True),
+                               synth.tiny_random(200, 450, 0.1, 10, dyadic=True)):
+        x = synth.dyadic_vector(m, 11)
+        A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+        y = A.probe(which, torch.from_numpy(x).cuda())
+        torch.cuda.synchronize()
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        ref = oracle.spmv(rp, np.minimum(rows, m - 1).astype(np.int32), val, x)
+        assert np.array_equal(y.cpu().numpy(), ref)
+
+
+def long_rows_matrix(seed=5):
+    lens = [0, 0, 5000, 1, 0, 30000, 0, 0, 2, 100000, 0] + [3] * 500 + [0] * 100 + [9000]
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    col = np.concatenate([np.sort(synth.uindex(seed, i, np.arange(l, dtype=np.uint64), 200000))
+                          for i, l in enumerate(lens)]).astype(np.int32)
+    return len(lens), 200000, rp, col
+
+
+@pytest.mark.parametrize("extra", [0, pkg.OPT_PREFETCH, pkg.OPT_UNROLL, pkg.OPT_DELTA])
+def test_decomposition(extra):
+    n, m, rp, col = long_rows_matrix()
+    # distinct sorted columns are required by delta codes: deduplicate rows
+    keep = np.ones(len(col), dtype=bool)
+    for i in range(n):
+        seg = col[rp[i]:rp[i + 1]]
+        keep[rp[i] + 1:rp[i + 1]] = seg[1:] != seg[:-1]
+    rows = np.repeat(np.arange(n), np.diff(rp))[keep]
+    _, _, rp, col, _ = synth.from_coo(rows, col[keep], np.zeros(keep.sum()), n, m)
+    val = (synth.uindex(6, 0, np.arange(len(col), dtype=np.uint64), 9) - 4).astype(float)
+    x = synth.dyadic_vector(m, 12)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    info = A.select("forced", forced_opts=pkg.OPT_DECOMP | extra, long_row_floor=1000,
+                    long_row_factor=4.0)
+    tau = oracle.long_row_threshold(len(col) / n, factor=4.0, floor=1000)
+    want_rows = oracle.long_rows(rp, tau)
+    assert info["n_long_rows"] == len(want_rows) > 0
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_LONG_ROWS, np.int32), want_rows)
+    xd = torch.from_numpy(x).cuda()
+    y = A.spmv(xd)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy(), oracle.spmv(rp, col, val, x))   # dyadic: exact
+    vr = synth.um11(7, 0, np.arange(len(col), dtype=np.uint64))
+    B = pkg.CsrMatrix(rp, col, vr, n_cols=m)
+    B.select("forced", forced_opts=pkg.OPT_DECOMP | extra, long_row_floor=1000, long_row_factor=4.0)
+    xr = synth.vector(m, 13)
+    y = B.spmv(torch.from_numpy(xr).cuda())
+    torch.cuda.synchronize()
+    check_f64(y.cpu().numpy(), rp, col, vr, xr, f"decomp {extra}")
+
+
+def test_decomposition_rmat():
+    n, m, rp, col, val = matrix("rmat14")
+    x = xvec("rmat14", m)
+    A = pkg.CsrMatrix(rp, col, val)
+    info = A.select("forced", forced_opts=pkg.OPT_DECOMP, long_row_floor=200, long_row_factor=8.0)
+    assert info["n_long_rows"] > 0
+    y = A.spmv(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    check_f64(y.cpu().numpy(), rp, col, val, x, "rmat14 decomp")
+
+
+@pytest.mark.parametrize("name", ["lap100", "st27_24", "rmat14", "unif14"])
+def test_profile_rule_and_remedies_match_oracle(name):
+    n, m, rp, col, val = matrix(name)
+    A = pkg.CsrMatrix(rp, col, val)
+    info = A.select("profile")
+    p = info
+    assert p["p_peak"] >= p["p_mb"] > 0 and p["p_csr"] > 0 and p["b_max"] > 1e11
+    cls = oracle.classify(p["p_csr"], p["p_mb"], p["p_ml"], p["p_imb"], p["p_cmp"], p["p_peak"])
+    assert info["classes"] == cls
+    f, _ = oracle.features(n, m, rp, col)
+    has_long = f[F["nnz_max"]] > oracle.long_row_threshold(f[F["nnz_avg"]])
+    assert info["opts"] == oracle.remedies(cls, has_long)
+    x = xvec(name, m)
+    y = A.spmv(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    check_f64(y.cpu().numpy(), rp, col, val, x, f"{name} profile")
+
+
+def test_exhaustive_selects_catalogue_variant():
+    n, m, rp, col, val = matrix("st27_24")
+    A = pkg.CsrMatrix(rp, col, val)
+    info = A.select("exhaustive", timing_calls=8)
+    assert 0 <= info["variant_id"] < 16
+    assert oracle.catalogue()[info["variant_id"]] == info["opts"]
+    x = xvec("st27_24", m)
+    y = A.spmv(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    check_f64(y.cpu().numpy(), rp, col, val, x, "exhaustive")
+
+
+def test_every_catalogue_variant_matches_oracle():
+    n, m, rp, col, val = matrix("rmat14")
+    x = xvec("rmat14", m)
+    A = pkg.CsrMatrix(rp, col, val)
+    for opts in oracle.catalogue():
+        A.select("forced", forced_opts=opts, long_row_floor=200)
+        y = A.spmv(torch.from_numpy(x).cuda())
+        torch.cuda.synchronize()
+        check_f64(y.cpu().numpy(), rp, col, val, x, f"catalogue {opts}")
