@@ -101,7 +101,7 @@ typedef struct {
     int32_t merge_items;     /* L of the merge-path kernel */
     int32_t delta_bits;      /* 8, 16, or 32 (plain int32 indices) */
     int32_t n_long_rows;     /* rows taken out by the decomposition */
-    int32_t reserved;
+    int32_t fallback;        /* 1 if LEARNED had no model and used PROFILE */
     double p_csr, p_mb, p_ml, p_imb, p_cmp, p_peak;  /* flop/s (PROFILE) */
     double b_max;            /* B/s used for the bounds */
     double t_select_ms;      /* features/probes + decision */
@@ -227,6 +227,42 @@ csr_status_t csr_debug_probe(csr_matrix_t A, int32_t which, const void *d_x, voi
  * bytes/s counting 3 * bytes_per_array per pass (best of `reps` passes).
  */
 csr_status_t csr_triad(size_t bytes_per_array, int32_t reps, double *gbytes_per_s, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned selector (replaces the decision tree of Sec. III-D): an MLP
+ * 16-64-64-K, ReLU, softmax over the K catalogue variants (K = 16: baseline,
+ * 5 single optimizations, 10 pairs, in the order of csr_plan_info_t's
+ * variant_id). Parameters are FP32, laid out W1[64][16], b1[64], W2[64][64],
+ * b2[64], W3[K][64], b3[K] (6,288 floats for K = 16). Features are fed as
+ * (log2(1 + f) - mu) / sigma.
+ * ------------------------------------------------------------------------- */
+
+/* Install a trained model for CSR_SEL_LEARNED on the current device (host
+ * arrays: params, 16 mu, 16 sigma > 0; copied). Rejects non-finite values. */
+csr_status_t csr_mlp_load(const float *h_params, int32_t K, const double *h_mu,
+                          const double *h_sigma);
+/* Remove the current device's model (LEARNED then falls back to PROFILE). */
+csr_status_t csr_mlp_unload(void);
+/* logits[B][K] = MLP(X[B][16]) for B <= 64 normalized rows (device arrays). */
+csr_status_t csr_mlp_forward(const float *d_params, int32_t K, const float *d_X, int32_t B,
+                             float *d_logits, void *stream);
+/* Mean softmax cross-entropy of one batch and its gradient (same layout as
+ * params) for B <= 64 rows with labels in [0, K) (device arrays). */
+csr_status_t csr_mlp_grad(const float *d_params, int32_t K, const float *d_X,
+                          const int32_t *d_labels, int32_t B, float *d_grad, float *d_loss,
+                          void *stream);
+/* `steps` Adam steps (Kingma & Ba 2015, bias-corrected, step counter
+ * t0+1, t0+2, ...) on mini-batches of B rows; d_order holds steps*B row
+ * indices into d_X / d_labels (the caller's shuffle). Updates d_params,
+ * d_m, d_v in place; d_losses[steps] receives each batch's loss. One
+ * workgroup, fixed summation order: bit-reproducible. Synchronizes. */
+csr_status_t csr_mlp_train(float *d_params, float *d_m, float *d_v, int32_t K, const float *d_X,
+                           const int32_t *d_labels, const int32_t *d_order, int32_t B,
+                           int32_t steps, int32_t t0, float lr, float beta1, float beta2,
+                           float eps, float *d_losses, void *stream);
+/* d_out[n][16] = (log2(1 + d_f) - d_mu) / d_sigma (FP64 in, FP32 out). */
+csr_status_t csr_mlp_normalize(const double *d_f, const double *d_mu, const double *d_sigma,
+                               int64_t n, float *d_out, void *stream);
 
 #ifdef __cplusplus
 }

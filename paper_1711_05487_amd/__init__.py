@@ -35,7 +35,8 @@ STATUS = ["CSR_OK", "CSR_ERR_INVALID_ARG", "CSR_ERR_INVALID_MATRIX", "CSR_ERR_OU
 # Every entry point declared in include/csrspmv.h.
 EXPORTS = ("csr_config_default", "csr_create", "csr_destroy", "csr_inspect", "csr_select",
            "csr_spmv", "csr_spmv_batched", "csr_status_str", "csr_last_error", "csr_query",
-           "csr_debug_copy", "csr_debug_probe", "csr_triad")
+           "csr_debug_copy", "csr_debug_probe", "csr_triad", "csr_mlp_load", "csr_mlp_unload",
+           "csr_mlp_forward", "csr_mlp_grad", "csr_mlp_train", "csr_mlp_normalize")
 
 
 class CsrError(RuntimeError):
@@ -57,7 +58,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("opts", ctypes.c_int32), ("classes", ctypes.c_int32),
                 ("variant_id", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
                 ("merge_items", ctypes.c_int32), ("delta_bits", ctypes.c_int32),
-                ("n_long_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_long_rows", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("p_csr", ctypes.c_double), ("p_mb", ctypes.c_double), ("p_ml", ctypes.c_double),
                 ("p_imb", ctypes.c_double), ("p_cmp", ctypes.c_double),
                 ("p_peak", ctypes.c_double), ("b_max", ctypes.c_double),
@@ -65,7 +66,7 @@ class PlanInfo(ctypes.Structure):
                 ("format_bytes", ctypes.c_double)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class Features(ctypes.Structure):
@@ -100,6 +101,13 @@ def lib():
             "csr_debug_copy": (ctypes.c_int, [P, i32, P, sz, ctypes.POINTER(sz), P]),
             "csr_triad": (ctypes.c_int, [sz, i32, ctypes.POINTER(ctypes.c_double), P]),
             "csr_debug_probe": (ctypes.c_int, [P, i32, P, P, P]),
+            "csr_mlp_load": (ctypes.c_int, [P, i32, P, P]),
+            "csr_mlp_unload": (ctypes.c_int, []),
+            "csr_mlp_forward": (ctypes.c_int, [P, i32, P, i32, P, P]),
+            "csr_mlp_grad": (ctypes.c_int, [P, i32, P, P, i32, P, P, P]),
+            "csr_mlp_train": (ctypes.c_int, [P, P, P, i32, P, P, P, i32, i32, i32, ctypes.c_float,
+                                             ctypes.c_float, ctypes.c_float, ctypes.c_float, P, P]),
+            "csr_mlp_normalize": (ctypes.c_int, [P, P, P, i64, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -253,3 +261,58 @@ def triad(bytes_per_array: int = 1 << 30, reps: int = 5, stream=None) -> float:
     out = ctypes.c_double()
     _check(lib().csr_triad(bytes_per_array, reps, ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+# ---------------------------------------------------------------------------
+# Learned selector (MLP kernels in the library)
+# ---------------------------------------------------------------------------
+
+def mlp_load(params: np.ndarray, K: int, mu: np.ndarray, sigma: np.ndarray):
+    """Install a trained model on the current device for select("learned")."""
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    m = np.ascontiguousarray(mu, dtype=np.float64)
+    s = np.ascontiguousarray(sigma, dtype=np.float64)
+    _check(lib().csr_mlp_load(p.ctypes.data_as(ctypes.c_void_p), K,
+                              m.ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p)))
+
+
+def mlp_unload():
+    _check(lib().csr_mlp_unload())
+
+
+def mlp_forward(params, K, X, stream=None):
+    import torch
+    B = X.shape[0]
+    logits = torch.empty((B, K), dtype=torch.float32, device=X.device)
+    _check(lib().csr_mlp_forward(_ptr(params), K, _ptr(X), B, _ptr(logits), _stream(stream)))
+    return logits
+
+
+def mlp_grad(params, K, X, labels, stream=None):
+    import torch
+    g = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    _check(lib().csr_mlp_grad(_ptr(params), K, _ptr(X), _ptr(labels), X.shape[0], _ptr(g),
+                              _ptr(loss), _stream(stream)))
+    return g, loss
+
+
+def mlp_train(params, m, v, K, X, labels, order, B, t0=0, lr=1e-3, betas=(0.9, 0.999),
+              eps=1e-8, stream=None):
+    """Adam steps over the batches listed in `order` (steps*B row indices);
+    params, m, v are updated in place. Returns the per-step losses."""
+    import torch
+    steps = order.numel() // B
+    losses = torch.empty(max(steps, 1), dtype=torch.float32, device=X.device)
+    _check(lib().csr_mlp_train(_ptr(params), _ptr(m), _ptr(v), K, _ptr(X), _ptr(labels),
+                               _ptr(order), B, steps, t0, lr, betas[0], betas[1], eps,
+                               _ptr(losses), _stream(stream)))
+    return losses[:steps]
+
+
+def mlp_normalize(F, mu, sigma, stream=None):
+    import torch
+    out = torch.empty(F.shape, dtype=torch.float32, device=F.device)
+    _check(lib().csr_mlp_normalize(_ptr(F), _ptr(mu), _ptr(sigma), F.shape[0], _ptr(out),
+                                   _stream(stream)))
+    return out

@@ -31,6 +31,12 @@ UNITS = [
     ("select", "select.hip", []),
     ("k_prep", "k_prep.hip", []),
     ("k_features", "k_features.hip", []),
+    ("k_mlp", "k_mlp.hip", []),
+    ("learn", "learn.hip", []),
+    ("batch", "batch.hip", []),
+    ("k_batched_f64", "k_batched.hip", ["-DCSR_STORAGE=0"]),
+    ("k_batched_f32", "k_batched.hip", ["-DCSR_STORAGE=1"]),
+    ("k_batched_bf16", "k_batched.hip", ["-DCSR_STORAGE=2"]),
     ("k_long_f64", "k_long.hip", ["-DCSR_STORAGE=0"]),
     ("k_long_f32", "k_long.hip", ["-DCSR_STORAGE=1"]),
     ("k_long_bf16", "k_long.hip", ["-DCSR_STORAGE=2"]),

@@ -8,6 +8,7 @@
 #include <mutex>
 #include <string>
 
+#include "batch.h"
 #include "internal.h"
 
 namespace csr {
@@ -19,6 +20,7 @@ thread_local std::string g_err;
 // of the process fail, to exercise the out-of-memory paths without a GPU
 // actually running out.
 std::atomic<long long> g_alloc_count{0};
+std::atomic<uint64_t> g_next_id{1};
 long long fail_alloc_after() {
     static long long v = [] {
         const char *e = std::getenv("CSRSPMV_FAIL_ALLOC_AFTER");
@@ -208,6 +210,7 @@ csr_status_t csr_create(csr_matrix_t *out, int32_t n_rows, int32_t n_cols, int64
         return st;
     };
     if (hipGetDevice(&A->device) != hipSuccess) return bail(fail(CSR_ERR_DEVICE, "hipGetDevice"));
+    A->id = g_next_id.fetch_add(1);
     A->n_rows = n_rows;
     A->n_cols = n_cols;
     A->nnz = nnz;
@@ -261,6 +264,7 @@ void csr_destroy(csr_matrix_t A) {
     if (!A) return;
     DeviceGuard g(A->device);
     (void)hipDeviceSynchronize();
+    batch_forget(A->id);
     delete A;
 }
 
@@ -288,14 +292,6 @@ csr_status_t csr_spmv(csr_matrix_t A, const void *d_x, void *d_y, void *stream) 
     DeviceGuard g(A->device);
     CSR_HIP(launch_spmv(A, A->plan, d_x, d_y, (hipStream_t)stream));
     return CSR_OK;
-}
-
-csr_status_t csr_spmv_batched(int32_t count, const csr_matrix_t *h_A, const void *const *h_x,
-                              void *const *h_y, void *stream) {
-    (void)stream;
-    if (count < 0 || (count > 0 && (!h_A || !h_x || !h_y)))
-        return fail(CSR_ERR_INVALID_ARG, "bad batch arguments");
-    return fail(CSR_ERR_UNSUPPORTED, "batched launch not built");
 }
 
 csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t bytes,

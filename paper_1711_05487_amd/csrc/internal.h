@@ -80,6 +80,8 @@ struct Plan {
 }  // namespace csr
 
 struct csr_matrix_s {
+    uint64_t id = 0;               // unique per handle (process lifetime)
+    uint64_t version = 0;          // incremented by every csr_select
     int device = 0;
     int32_t n_rows = 0, n_cols = 0;
     int64_t nnz = 0;
@@ -173,6 +175,24 @@ hipError_t launch_long_s2(const int32_t *col, const void *val, const void *x, vo
                           const int32_t *chunk_beg, void *part, int64_t n_chunks,
                           const int32_t *long_rows, const int32_t *row_chunk, int32_t n_long,
                           hipStream_t s);
+
+// Learned selector (k_mlp.hip, learn.hip) -------------------------------------------
+int mlp_param_count(int K);
+int mlp_max_batch();
+int mlp_max_classes();
+hipError_t launch_mlp_forward(const float *p, int K, const float *X, int B, float *logits,
+                              hipStream_t s);
+hipError_t launch_mlp_grad(const float *p, int K, const float *X, const int32_t *labels, int B,
+                           float *g, float *loss, hipStream_t s);
+hipError_t launch_mlp_train(float *p, float *m, float *v, float *g, int K, const float *X,
+                            const int32_t *y, const int32_t *order, int B, int steps, int t0,
+                            float lr, float b1, float b2, float eps, float *losses,
+                            hipStream_t s);
+hipError_t launch_mlp_normalize(const double *f, const double *mu, const double *sigma,
+                                int64_t n, float *out, hipStream_t s);
+hipError_t launch_mlp_select(const float *p, int K, const double *f, const double *mu,
+                             const double *sigma, int32_t *out, hipStream_t s);
+csr_status_t learned_pick(csr_matrix_s *A, hipStream_t s, int32_t *variant);
 
 // Plans and selection (select.hip) -----------------------------------------------
 double plan_bytes(const csr_matrix_s *A, const Plan &P);

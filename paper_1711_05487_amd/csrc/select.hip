@@ -639,6 +639,23 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
         }
         break;
     }
+    case CSR_SEL_LEARNED: {
+        // features -> MLP -> catalogue variant with default parameters; no
+        // model (or non-finite features) -> the profile-guided path
+        if ((st = inspect(A, s)) != CSR_OK) break;
+        int32_t v = -1;
+        st = learned_pick(A, s, &v);
+        if (st == CSR_OK && v >= 0 && v < 16) {
+            const auto tp = Clock::now();
+            st = realize(A, kCatalogue[v], cfg, &P, s);
+            t_prep = ms_since(tp);
+            break;
+        }
+        if (st != CSR_ERR_NOT_READY && st != CSR_OK) break;
+        st = CSR_OK;
+        info.fallback = 1;  // fell back to PROFILE
+    }
+        [[fallthrough]];
     case CSR_SEL_PROFILE: {
         Bounds B{};
         if ((st = measure_bounds(A, cfg, s, &B)) != CSR_OK) break;
@@ -666,7 +683,10 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
     if (st != CSR_OK) return st;
     CSR_HIP(hipStreamSynchronize(s));
     A->plan = P;
+    A->version += 1;
+    const int32_t fell_back = info.fallback;
     fill_info(A, P, &info);
+    info.fallback = fell_back;
     info.t_select_ms = ms_since(t0) - t_prep;
     info.t_prep_ms = t_prep;
     A->info = info;

@@ -1,0 +1,303 @@
+"""Training driver of the learned selector (replaces the decision tree of the
+feature-guided classifier, Sec. III-D).
+
+  label  time all 16 catalogue variants of every matrix of the seeded suite on
+         the current GPU (the fastest is the label, ties to the lower id) and
+         record the features, all times and the profile-guided classes as
+         JSON lines (append-only, resumable by matrix index);
+  train  fit the MLP 16-64-64-16 on those labels with the library's own
+         forward/backward/Adam kernels (csr_mlp_train) and save the weights.
+
+    python -m paper_1711_05487_amd.learn label --start 0 --count 2000 --out labels.jsonl
+    python -m paper_1711_05487_amd.learn train --labels labels.jsonl --out weights.json
+
+The suite is synthetic (seeded generators), standing in for the University
+of Florida matrices the paper trains on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import tempfile
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+K = 16
+SIZES = [16, 64, 64, K]
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "mlp16_mi355x.json")
+
+
+# ---------------------------------------------------------------------------
+# Labeling
+# ---------------------------------------------------------------------------
+
+def _gen_to_file(args):
+    """Worker (CPU only): generate suite matrix `index` into an .npz file."""
+    index, base_seed, n_min, n_max, nnz_cap, tmpdir = args
+    import synth
+    name, (n, m, rp, col, val) = synth.suite_matrix(index, base_seed=base_seed, n_min=n_min,
+                                                   n_max=n_max, nnz_cap=nnz_cap)
+    path = os.path.join(tmpdir, f"m{index}.npy")
+    with open(path, "wb") as f:
+        np.save(f, np.array([n, m, len(col)], dtype=np.int64))
+        np.save(f, rp)
+        np.save(f, col)
+        np.save(f, val)
+    return index, name, path
+
+
+def _load(path):
+    with open(path, "rb") as f:
+        n, m, nnz = np.load(f)
+        rp, col, val = np.load(f), np.load(f), np.load(f)
+    os.remove(path)
+    return int(n), int(m), rp, col, val
+
+
+def time_variants(A, xd, yd, calls=10, runs=3):
+    """Time every catalogue variant (default parameters) with events on the
+    current stream. Returns ms per call for variant ids 0..15."""
+    import torch
+    out = []
+    s = torch.cuda.current_stream()
+    for v in catalogue():
+        A.select("forced", forced_opts=v)
+        A.spmv(xd, yd)
+        ts = []
+        for _ in range(runs):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(calls):
+                A.spmv(xd, yd)
+            e1.record(s)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) / calls)
+        out.append(float(np.mean(ts)))
+    return out
+
+
+def catalogue():
+    """Optimization sets of the 16 variants (ids as in the library)."""
+    o = [1, 2, 4, 8, 16]
+    sets = [0] + o
+    for a in range(5):
+        for b in range(a + 1, 5):
+            sets.append(o[a] | o[b])
+    return sets
+
+
+def label(start, count, out, base_seed=501, n_min=1e4, n_max=4e6, nnz_cap=1 << 25, workers=8,
+          calls=10, runs=3):
+    import multiprocessing as mp
+    import torch
+    import paper_1711_05487_amd as pkg
+
+    done = set()
+    if os.path.exists(out):
+        with open(out) as f:
+            for line in f:
+                try:
+                    done.add(json.loads(line)["index"])
+                except Exception:
+                    pass
+    todo = [i for i in range(start, start + count) if i not in done]
+    print(f"[label] {len(todo)} matrices to label ({len(done)} already in {out})", flush=True)
+    if not todo:
+        return
+    gpu = torch.cuda.get_device_name(0)
+    tmpdir = tempfile.mkdtemp(prefix="csr_suite_", dir="/dev/shm" if os.path.isdir("/dev/shm") else None)
+    ctx = mp.get_context("spawn")
+    t0 = time.time()
+    with ctx.Pool(workers) as pool, open(out, "a") as fo:
+        jobs = [(i, base_seed, n_min, n_max, nnz_cap, tmpdir) for i in todo]
+        for k, (index, name, path) in enumerate(pool.imap(_gen_to_file, jobs)):
+            n, m, rp, col, val = _load(path)
+            A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+            f, isum, sorted_flag = A.inspect()
+            xd = torch.ones(m, dtype=torch.float64, device="cuda")
+            yd = torch.empty(n, dtype=torch.float64, device="cuda")
+            times = time_variants(A, xd, yd, calls, runs)
+            prof = A.select("profile", timing_calls=calls)
+            best = int(np.argmin(times))
+            rec = {"index": index, "seed": base_seed + index, "name": name, "n": n, "nnz": len(col),
+                   "features": [float(v) for v in f], "isum": [int(v) for v in isum],
+                   "sorted": int(sorted_flag), "times_ms": times, "label": best,
+                   "profile_classes": prof["classes"], "profile_opts": prof["opts"],
+                   "profile_variant": prof["variant_id"], "profile_select_ms": prof["t_select_ms"],
+                   "gpu": gpu}
+            A.spmv(xd, yd)
+            torch.cuda.synchronize()
+            rec["profile_ms"] = _time_current(A, xd, yd, calls, runs)
+            fo.write(json.dumps(rec) + "\n")
+            fo.flush()
+            A.close()
+            print(f"[label] {k + 1}/{len(todo)} idx={index} {name} n={n} nnz={len(col)} "
+                  f"best={best} t_best={min(times):.4f}ms t_plain={times[0]:.4f}ms "
+                  f"({time.time() - t0:.0f}s)", flush=True)
+    os.rmdir(tmpdir)
+
+
+def _time_current(A, xd, yd, calls, runs):
+    import torch
+    s = torch.cuda.current_stream()
+    ts = []
+    for _ in range(runs):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(calls):
+            A.spmv(xd, yd)
+        e1.record(s)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / calls)
+    return float(np.mean(ts))
+
+
+# ---------------------------------------------------------------------------
+# Training
+# ---------------------------------------------------------------------------
+
+def read_labels(path):
+    recs = []
+    with open(path) as f:
+        for line in f:
+            recs.append(json.loads(line))
+    recs.sort(key=lambda r: r["index"])
+    return recs
+
+
+def split(recs, seed=703, test_frac=0.2):
+    """80/20 split by matrix seed (a hash of the seed, not the position)."""
+    import synth
+    tr, te = [], []
+    for r in recs:
+        u = float(synth.u01(seed, 0, np.array([r["seed"]], dtype=np.uint64))[0])
+        (te if u <= test_frac else tr).append(r)
+    return tr, te
+
+
+def normalization(recs):
+    F = np.log2(1.0 + np.array([r["features"] for r in recs], dtype=np.float64))
+    mu = F.mean(axis=0)
+    sd = F.std(axis=0)
+    sd[sd < 1e-6] = 1.0
+    return mu, sd
+
+
+def train(recs, epochs=200, batch=64, lr=1e-3, init_seed=701, shuffle_seed=702):
+    """Fit the MLP on GPU with the library's kernels. Returns (params, mu,
+    sigma, losses)."""
+    import torch
+    import paper_1711_05487_amd as pkg
+    import synth
+    mu, sd = normalization(recs)
+    F = torch.tensor(np.array([r["features"] for r in recs], dtype=np.float64), device="cuda")
+    X = pkg.mlp_normalize(F, torch.tensor(mu, device="cuda"), torch.tensor(sd, device="cuda"))
+    y = torch.tensor([r["label"] for r in recs], dtype=torch.int32, device="cuda")
+    params = torch.tensor(np.concatenate([p.ravel() for p in synth.mlp_init_weights(SIZES, init_seed)]),
+                          dtype=torch.float32, device="cuda")
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    n = len(recs)
+    B = min(batch, n)
+    steps_per_epoch = n // B
+    order = []
+    for e in range(epochs):
+        perm = synth.permutation(n, shuffle_seed, stream=e)
+        order.append(perm[:steps_per_epoch * B])
+    order = torch.tensor(np.concatenate(order), dtype=torch.int32, device="cuda")
+    losses = pkg.mlp_train(params, m, v, K, X, y, order, B, t0=0, lr=lr)
+    return params.cpu().numpy(), mu, sd, losses.cpu().numpy()
+
+
+def predict(params, mu, sd, feats):
+    import torch
+    import paper_1711_05487_amd as pkg
+    F = torch.tensor(np.asarray(feats, dtype=np.float64), device="cuda")
+    X = pkg.mlp_normalize(F, torch.tensor(mu, device="cuda"), torch.tensor(sd, device="cuda"))
+    P = torch.tensor(params, device="cuda")
+    out = []
+    for b in range(0, X.shape[0], 64):
+        logits = pkg.mlp_forward(P, K, X[b:b + 64].contiguous())
+        out.append(torch.argmax(logits, dim=1).cpu().numpy())
+    return np.concatenate(out) if out else np.zeros(0, dtype=np.int64)
+
+
+def evaluate(recs, pred):
+    """Per matrix: selected / best time (regret + 1), also for the baseline
+    and for the profile-guided choice recorded at labeling time."""
+    t = np.array([r["times_ms"] for r in recs])
+    best = t.min(axis=1)
+    sel = t[np.arange(len(recs)), pred]
+    prof = np.array([r.get("profile_ms", np.nan) for r in recs])
+    gm = lambda a: float(np.exp(np.mean(np.log(a))))
+    return {
+        "n": len(recs),
+        "geomean_sel_over_best": gm(sel / best),
+        "p90_sel_over_best": float(np.percentile(sel / best, 90)),
+        "geomean_plain_over_best": gm(t[:, 0] / best),
+        "geomean_profile_over_best": gm(prof / best) if np.isfinite(prof).all() else None,
+        "geomean_speedup_vs_plain": gm(t[:, 0] / sel),
+        "accuracy": float(np.mean(pred == np.argmin(t, axis=1))),
+    }
+
+
+def save_weights(path, params, mu, sd, meta):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump({"K": K, "sizes": SIZES, "params": [float(v) for v in params],
+                   "mu": [float(v) for v in mu], "sigma": [float(v) for v in sd], "meta": meta}, f)
+
+
+def load_weights(path=WEIGHTS):
+    with open(path) as f:
+        d = json.load(f)
+    return (np.array(d["params"], dtype=np.float32), np.array(d["mu"]), np.array(d["sigma"]),
+            d.get("meta", {}))
+
+
+def install(path=WEIGHTS):
+    """Load the saved model into the library for select('learned')."""
+    import paper_1711_05487_amd as pkg
+    params, mu, sd, _ = load_weights(path)
+    pkg.mlp_load(params, K, mu, sd)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("label")
+    a.add_argument("--start", type=int, default=0)
+    a.add_argument("--count", type=int, default=2000)
+    a.add_argument("--out", required=True)
+    a.add_argument("--workers", type=int, default=8)
+    a.add_argument("--n-max", type=float, default=4e6)
+    b = sub.add_parser("train")
+    b.add_argument("--labels", required=True)
+    b.add_argument("--out", default=WEIGHTS)
+    b.add_argument("--epochs", type=int, default=200)
+    args = ap.parse_args()
+    if args.cmd == "label":
+        label(args.start, args.count, args.out, workers=args.workers, n_max=args.n_max)
+    else:
+        recs = read_labels(args.labels)
+        tr, te = split(recs)
+        params, mu, sd, losses = train(tr, epochs=args.epochs)
+        ev_tr = evaluate(tr, predict(params, mu, sd, [r["features"] for r in tr]))
+        ev_te = evaluate(te, predict(params, mu, sd, [r["features"] for r in te]))
+        meta = {"train": ev_tr, "test": ev_te, "final_loss": float(losses[-1]),
+                "epochs": args.epochs, "n_train": len(tr), "n_test": len(te),
+                "gpu": recs[0].get("gpu") if recs else None}
+        save_weights(args.out, params, mu, sd, meta)
+        print(json.dumps(meta, indent=1), flush=True)
+
+
+if __name__ == "__main__":
+    main()

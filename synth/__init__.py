@@ -313,50 +313,37 @@ def _first_distinct(cand: np.ndarray, k: int):
 # Families for the learned-selector suite and the batched launch
 # --------------------------------------------------------------------------
 
-def banded_random(n: int, bandwidth: int, per_row: int, seed: int):
-    """Each row i draws `per_row` distinct columns uniform in the window
-    [i - bandwidth, i + bandwidth] clipped to [0, n); values U(0,1]."""
-    rows = np.arange(n, dtype=np.int64)
-    lo = np.maximum(rows - bandwidth, 0)
-    hi = np.minimum(rows + bandwidth, n - 1)
-    width = hi - lo + 1
-    k = np.minimum(per_row, width)
-    draws = per_row + 8
-    cand = np.empty((n, draws), dtype=np.int64)
-    for t in range(draws):
-        u53 = (hash64(seed, 1 + t, rows.astype(np.uint64)) >> _U64(11)).astype(np.float64)
-        cand[:, t] = lo + np.minimum(np.floor(u53 * 2.0 ** -53 * width).astype(np.int64), width - 1)
-    out_r, out_c = [], []
-    # rows whose window is narrower than per_row take the whole window
-    full = width <= per_row
-    if full.any():
-        fr = rows[full]
-        fw = width[full]
-        rr = np.repeat(fr, fw)
-        starts = np.repeat(lo[full], fw)
-        offs = np.arange(rr.size) - np.repeat(np.cumsum(fw) - fw, fw)
-        out_r.append(rr)
-        out_c.append(starts + offs)
-    part = ~full
-    if part.any():
-        pc = cand[part]
-        picked = _first_distinct(pc, per_row)
-        extra = 0
-        while picked is None:
-            extra += 8
-            more = np.empty((pc.shape[0], 8), dtype=np.int64)
-            pr = rows[part]
-            for t in range(8):
-                u53 = (hash64(seed, 1 + draws + extra - 8 + t, pr.astype(np.uint64))
-                       >> _U64(11)).astype(np.float64)
-                more[:, t] = lo[part] + np.minimum(
-                    np.floor(u53 * 2.0 ** -53 * width[part]).astype(np.int64), width[part] - 1)
-            pc = np.concatenate([pc, more], 1)
-            picked = _first_distinct(pc, per_row)
-        out_r.append(np.repeat(rows[part], per_row))
-        out_c.append(picked.ravel())
-    r = np.concatenate(out_r)
-    c = np.concatenate(out_c)
+def banded_random(n: int, bandwidth: int, per_row: int, seed: int, chunk: int = 1 << 18):
+    """Row i draws `per_row` columns uniform in the window [i - bandwidth,
+    i + bandwidth] clipped to [0, n) (draw t from stream 1 + t, index i) and
+    keeps the distinct ones, sorted; a window no wider than per_row is taken
+    whole. Values U(0,1] by CSR position."""
+    rows_all, cols_all = [], []
+    for r0 in range(0, n, chunk):
+        rows = np.arange(r0, min(n, r0 + chunk), dtype=np.int64)
+        lo = np.maximum(rows - bandwidth, 0)
+        width = np.minimum(rows + bandwidth, n - 1) - lo + 1
+        full = width <= per_row
+        if full.any():
+            fr, fw = rows[full], width[full]
+            rr = np.repeat(fr, fw)
+            offs = np.arange(rr.size) - np.repeat(np.cumsum(fw) - fw, fw)
+            rows_all.append(rr)
+            cols_all.append(np.repeat(lo[full], fw) + offs)
+        part = ~full
+        if part.any():
+            pr, plo, pw = rows[part], lo[part], width[part]
+            cand = np.empty((pr.size, per_row), dtype=np.int64)
+            for t in range(per_row):
+                u53 = (hash64(seed, 1 + t, pr.astype(np.uint64)) >> _U64(11)).astype(np.float64)
+                cand[:, t] = plo + np.minimum(np.floor(u53 * 2.0 ** -53 * pw).astype(np.int64), pw - 1)
+            cand.sort(axis=1)
+            keep = np.ones(cand.shape, dtype=bool)
+            keep[:, 1:] = cand[:, 1:] != cand[:, :-1]
+            rows_all.append(np.broadcast_to(pr[:, None], cand.shape)[keep])
+            cols_all.append(cand[keep])
+    r = np.concatenate(rows_all)
+    c = np.concatenate(cols_all)
     order = np.lexsort((c, r))
     r, c = r[order], c[order]
     vals = u01(seed, 0, np.arange(r.size, dtype=np.uint64))
@@ -399,13 +386,14 @@ def power_law(n: int, alpha: float, seed: int, max_nnz: int | None = None):
 
 
 def suite_matrix(index: int, base_seed: int = 501, n_min: float = 1e4, n_max: float = 4e6,
-                 nnz_cap: int = 1 << 26):
+                 nnz_cap: int = 1 << 25):
     """Matrix `index` of the mixed learned-selector suite.
 
     Families (index % 5): 2-D/3-D stencils, banded random (bandwidth
     log-uniform 8..4096, 4..64 nnz/row), R-MAT (edge factor 4..32, jittered
     a,b,c,d), block-diagonal (blocks 4/8/16/32), power-law row lengths
-    (Pareto alpha in [1.5, 3]). N log-uniform in [n_min, n_max].
+    (Pareto alpha in [1.5, 3]). N log-uniform in [n_min, n_max]; sizes are
+    reduced where needed so that NNZ stays within nnz_cap.
     Returns (name, matrix tuple).
     """
     seed = base_seed + index
@@ -415,20 +403,20 @@ def suite_matrix(index: int, base_seed: int = 501, n_min: float = 1e4, n_max: fl
     if fam == 0:
         kind = int(p[1] * 4) % 4
         if kind == 0:
-            s = max(8, int(round(math.sqrt(n))))
+            s = max(8, int(round(math.sqrt(min(n, nnz_cap // 5)))))
             return f"lap2d_{s}", laplacian2d(s)
         if kind == 1:
-            s = max(8, int(round(math.sqrt(n))))
+            s = max(8, int(round(math.sqrt(min(n, nnz_cap // 9)))))
             return f"nine2d_{s}", _nine_point(s, seed)
         if kind == 2:
-            s = max(4, int(round(n ** (1 / 3))))
+            s = max(4, int(round(min(n, nnz_cap // 7) ** (1 / 3))))
             return f"seven3d_{s}", _seven_point(s, seed)
-        s = max(4, int(round(n ** (1 / 3))))
+        s = max(4, int(round(min(n, nnz_cap // 27) ** (1 / 3))))
         return f"st27_{s}", stencil27(s, seed, seed + 100000)
     if fam == 1:
         bw = int(math.exp(math.log(8) + (math.log(4096) - math.log(8)) * p[1]))
         k = int(math.exp(math.log(4) + (math.log(64) - math.log(4)) * p[2]))
-        k = min(k, 2 * bw + 1)
+        k = max(1, min(k, 2 * bw + 1, nnz_cap // n))
         return f"band_{n}_{bw}_{k}", banded_random(n, bw, k, seed)
     if fam == 2:
         scale = max(10, int(round(math.log2(n))))
@@ -442,6 +430,7 @@ def suite_matrix(index: int, base_seed: int = 501, n_min: float = 1e4, n_max: fl
         return f"rmat_{scale}_{ef}", rmat(scale, ef, tuple(pr), seed, seed + 100000)
     if fam == 3:
         blk = (4, 8, 16, 32)[int(p[1] * 4) % 4]
+        n = min(n, nnz_cap // blk)
         return f"bdiag_{n}_{blk}", block_diagonal(n, blk, seed)
     alpha = 1.5 + 1.5 * p[1]
     return f"plaw_{n}_{alpha:.2f}", power_law(n, alpha, seed, max_nnz=max(64, nnz_cap // max(n, 1)))

@@ -1,0 +1,110 @@
+"""GPU parity of csr_spmv_batched (one persistent, graph-captured launch over
+many matrices): bit-identical to each matrix's own merge-path SpMV with the
+same tile size, within the FP64 bar against the oracle, and stable across
+graph replays interleaved with eager work."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1711_05487_amd as pkg
+import synth
+from spmv_cases import check_f64, check_reduced
+
+pytestmark = pytest.mark.gpu
+
+
+def batch_mats(count, storage="f64", with_empty=True):
+    mats = [synth.batch_matrix(i)[1] for i in range(count)]
+    if with_empty:
+        mats.append((7, 5, np.zeros(8, dtype=np.int32), np.zeros(0, dtype=np.int32), np.zeros(0)))
+        mats.append(synth.tiny_random(40, 30, 0.3, 3))
+    hs = [pkg.CsrMatrix(rp, col, val, n_cols=m, storage=storage) for (n, m, rp, col, val) in mats]
+    return mats, hs
+
+
+def vectors(mats, seed, dtype=torch.float64):
+    xs = [torch.from_numpy(synth.vector(m, seed + k)).to(dtype).cuda() for k, (n, m, *_ ) in enumerate(mats)]
+    ys = [torch.full((max(n, 1),), float("nan"), dtype=dtype, device="cuda") for (n, *_ ) in mats]
+    return xs, ys
+
+
+def test_batched_bit_identical_to_single_merge():
+    mats, hs = batch_mats(24)
+    for k, A in enumerate(hs):  # each matrix keeps its own tile size
+        A.select("forced", forced_opts=pkg.OPT_MERGE, merge_items=1024 if k % 2 else 2048)
+    xs, ys = vectors(mats, 100)
+    pkg.spmv_batched(hs, xs, ys)
+    torch.cuda.synchronize()
+    for k, A in enumerate(hs):
+        single = A.spmv(xs[k])
+        torch.cuda.synchronize()
+        n = mats[k][0]
+        assert torch.equal(ys[k][:n], single[:n]), k
+
+
+def test_batched_autotuned_matches_oracle_and_replays():
+    mats, hs = batch_mats(40)
+    eager = None
+    for rep in range(4):
+        xs, ys = vectors(mats, 200 + rep)   # new vector pointers every call
+        pkg.spmv_batched(hs, xs, ys)
+        torch.cuda.synchronize()
+        # eager work between replays
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        for k, (n, m, rp, col, val) in enumerate(mats):
+            check_f64(ys[k][:n].cpu().numpy(), rp, col, val, xs[k].cpu().numpy(), f"batch {k} rep {rep}")
+        if rep == 0:
+            eager = [y.clone() for y in ys]
+            x0 = xs
+        assert junk.isfinite()
+    # replay with the first call's vectors: identical bits
+    ys = [torch.empty_like(y) for y in eager]
+    pkg.spmv_batched(hs, x0, ys)
+    torch.cuda.synchronize()
+    for k, (n, *_ ) in enumerate(mats):
+        assert torch.equal(ys[k][:n], eager[k][:n])
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_batched_reduced_precision(storage):
+    mats, hs = batch_mats(12, storage=storage)
+    xs64 = [synth.vector(m, 300 + k) for k, (n, m, *_ ) in enumerate(mats)]
+    xs = [torch.from_numpy(oracle.to_f32(x)).cuda() for x in xs64]
+    ys = [torch.empty(max(n, 1), dtype=torch.float32, device="cuda") for (n, *_ ) in mats]
+    pkg.spmv_batched(hs, xs, ys)
+    torch.cuda.synchronize()
+    for k, (n, m, rp, col, val) in enumerate(mats):
+        check_reduced(ys[k][:n].cpu().numpy(), rp, col, val, xs64[k], storage, f"batch {k}")
+
+
+def test_batched_dyadic_exact():
+    mats = [synth.tiny_random(300 + 37 * k, 200, 0.05 + 0.02 * k, 40 + k, dyadic=True) for k in range(10)]
+    hs = [pkg.CsrMatrix(rp, col, val, n_cols=m) for (n, m, rp, col, val) in mats]
+    xs = [torch.from_numpy(synth.dyadic_vector(m, 50 + k)).cuda() for k, (n, m, *_ ) in enumerate(mats)]
+    ys = [torch.empty(n, dtype=torch.float64, device="cuda") for (n, *_ ) in mats]
+    pkg.spmv_batched(hs, xs, ys)
+    torch.cuda.synchronize()
+    for k, (n, m, rp, col, val) in enumerate(mats):
+        assert np.array_equal(ys[k].cpu().numpy(), oracle.spmv(rp, col, val, xs[k].cpu().numpy()))
+
+
+def test_batched_errors_and_handle_lifetime():
+    a = synth.tiny_random(50, 50, 0.1, 1)
+    b = synth.tiny_random(60, 50, 0.1, 2)
+    A = pkg.CsrMatrix(a[2], a[3], a[4], n_cols=50)
+    B32 = pkg.CsrMatrix(b[2], b[3], b[4], n_cols=50, storage="f32")
+    x = torch.ones(50, dtype=torch.float64, device="cuda")
+    y = torch.empty(60, dtype=torch.float64, device="cuda")
+    with pytest.raises(pkg.CsrError):
+        pkg.spmv_batched([A, B32], [x, x.float()], [y, y.float()])   # mixed storage
+    B = pkg.CsrMatrix(b[2], b[3], b[4], n_cols=50)
+    pkg.spmv_batched([A, B], [x, x], [y[:50], y])
+    torch.cuda.synchronize()
+    B.close()  # drops the cached plan
+    C = pkg.CsrMatrix(b[2], b[3], b[4], n_cols=50)
+    y2 = torch.empty(60, dtype=torch.float64, device="cuda")
+    pkg.spmv_batched([A, C], [x, x], [torch.empty(50, dtype=torch.float64, device="cuda"), y2])
+    torch.cuda.synchronize()
+    check_f64(y2.cpu().numpy(), b[2], b[3], b[4], np.ones(50), "after destroy")

@@ -1,0 +1,92 @@
+"""The trained learned selector against its judges, on GPU: regret against
+the exhaustive timings on the held-out split (the benchmark spec: within 10% of the
+best variant), the gain over the method without the network (plain CSR and
+the profile-guided selector), and the selection cost against one plain
+SpMV. The labels and weights are the committed training set and model
+(`paper_1711_05487_amd/weights/`, written by `python -m
+paper_1711_05487_amd.learn`)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1711_05487_amd as pkg
+from paper_1711_05487_amd import learn
+from spmv_cases import check_f64, matrix, xvec
+
+pytestmark = pytest.mark.gpu
+
+LABELS = os.path.join(os.path.dirname(learn.WEIGHTS), "labels_mi355x.jsonl")
+
+
+def held_out():
+    recs = learn.read_labels(LABELS)
+    _, te = learn.split(recs)
+    return te
+
+
+def test_regret_within_ten_percent_on_held_out():
+    params, mu, sd, meta = learn.load_weights()
+    te = held_out()
+    assert len(te) >= 300
+    pred = learn.predict(params, mu, sd, [r["features"] for r in te])
+    ev = learn.evaluate(te, pred)
+    print(ev)
+    assert ev["geomean_sel_over_best"] <= 1.10
+    # the network gains over the method without it: plain CSR, and the
+    # profile-guided classifier of Sec. III-C
+    assert ev["geomean_speedup_vs_plain"] > 1.2
+    assert ev["geomean_sel_over_best"] < ev["geomean_profile_over_best"]
+
+
+def test_training_reproduces_committed_model():
+    # retraining with the same seeds reproduces the committed weights bit for bit
+    recs = learn.read_labels(LABELS)
+    tr, _ = learn.split(recs)
+    params, mu, sd, _ = learn.train(tr, epochs=learn.load_weights()[3].get("epochs", 200))
+    p0, mu0, sd0, _ = learn.load_weights()
+    assert np.array_equal(params, p0)
+    assert np.array_equal(mu, mu0) and np.array_equal(sd, sd0)
+
+
+def test_learned_selection_cost_below_one_plain_spmv():
+    learn.install()
+    n, m, rp, col, val = matrix("st27_128")
+    A = pkg.CsrMatrix(rp, col, val)
+    x = torch.from_numpy(xvec("st27_128", m)).cuda()
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    A.select("plain")
+    A.spmv(x, y)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(20):
+        A.spmv(x, y)
+    e1.record(s)
+    e1.synchronize()
+    t_plain = e0.elapsed_time(e1) / 20
+    costs = []
+    for _ in range(5):
+        info = A.select("learned")
+        assert info["fallback"] == 0
+        costs.append(info["t_select_ms"])
+    print("t_select_ms", costs, "t_plain_ms", t_plain, "variant", info["variant_id"])
+    assert min(costs) < t_plain
+    y = A.spmv(x)
+    torch.cuda.synchronize()
+    check_f64(y.cpu().numpy(), rp, col, val, x.cpu().numpy(), "learned st27")
+
+
+def test_learned_selection_parity_on_config_matrices():
+    learn.install()
+    for name in ("lap100", "rmat14", "unif14", "st27_24"):
+        n, m, rp, col, val = matrix(name)
+        A = pkg.CsrMatrix(rp, col, val)
+        info = A.select("learned")
+        assert info["fallback"] == 0 and 0 <= info["variant_id"] < 16
+        x = xvec(name, m)
+        y = A.spmv(torch.from_numpy(x).cuda())
+        torch.cuda.synchronize()
+        check_f64(y.cpu().numpy(), rp, col, val, x, f"learned {name}")
