@@ -1,10 +1,11 @@
 """Benchmark: SpMV effective HBM GB/s of the selected variant vs plain CSR.
 
-One step = one y = A x with the plan chosen by the selector, on the 27-point
-stencil over a 128^3 grid (N = 2,097,152, NNZ = 55,742,968, FP64 values,
-int32 indices), inputs resident in HBM. The selector runs once before the
-timed region (the inspector/executor split of the method); its cost is
-reported beside the rate.
+One step = one y = A x with the plan chosen by the selector (default: the
+learned selector with the committed model), on the 27-point stencil over a
+128^3 grid (N = 2,097,152, NNZ = 55,742,968, FP64 values, int32 indices),
+inputs resident in HBM. The selector runs once before the timed region (the
+inspector/executor split of the method); its cost is reported beside the
+rate, with the solver-iteration count that amortizes it (Sec. IV-D, Eq. (2)).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--select learned|profile|exhaustive|plain]
 
@@ -99,7 +100,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--select", default="exhaustive")
+    ap.add_argument("--select", default="learned",
+                    help="learned (committed MLP), profile, exhaustive or plain")
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -109,8 +111,10 @@ def main():
         sys.exit(2)
 
     import torch
+    import oracle
     import paper_1711_05487_amd as pkg
     import synth
+    from paper_1711_05487_amd import learn
 
     torch.cuda.set_device(0)
     n = args.grid
@@ -119,7 +123,10 @@ def main():
     x = synth.vector(M, 203)
     nnz = len(col)
     workload = f"27-point stencil {n}^3 FP64 CSR (N={N:,}, NNZ={nnz:,})"
+    t0 = time.perf_counter()
     A = pkg.CsrMatrix(rp, col, val)
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - t0) * 1e3
     xd = torch.from_numpy(x).cuda()
     yd = torch.empty(N, dtype=torch.float64, device="cuda")
 
@@ -131,15 +138,14 @@ def main():
     t_plain = harmonic_runs(A, xd, yd, 5, 128)
     plain_gbs = plain["format_bytes"] / (t_plain * 1e-3) / 1e9
 
+    if args.select == "learned" and os.path.exists(learn.WEIGHTS):
+        learn.install()
     log(f"selecting ({args.select})")
-    t0 = time.perf_counter()
     info = A.select(args.select)
-    t_sel_wall = (time.perf_counter() - t0) * 1e3
 
-    # correctness gate on the selected plan (untimed): full comparison
+    # correctness gate on the selected plan (untimed): every row
     A.spmv(xd, yd)
     torch.cuda.synchronize()
-    import oracle
     got = yd.cpu().numpy()
     ref = oracle.spmv_accurate(rp, col, val, x)
     ab = oracle.absax(rp, col, val, x)
@@ -163,14 +169,18 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
     fmt_bytes = info["format_bytes"]
     gbs = fmt_bytes / (ms * 1e-3) / 1e9
+    # dominant kernel alone: HIP events recorded on the launch stream around it
+    k_ms, call_ms, kernel = A.time_spmv(xd, yd, max(args.steps, 20))
+    achieved = fmt_bytes / (k_ms * 1e-3) / 1e9
     t_sel_proto = harmonic_runs(A, xd, yd, 5, 128)
+    t_pre = info["t_select_ms"] + info["t_prep_ms"]
 
     opts = [name for bit, name in pkg.OPT_NAMES.items() if info["opts"] & bit]
-    kernel = "k_rowsplit"
     traffic = traffic_from_profiles(kernel, workload, fmt_bytes)
-    roof = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": kernel, "algorithmic_bytes_per_launch": fmt_bytes}
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": kernel, "kernel_ms": round(k_ms, 5),
+            "algorithmic_bytes_per_launch": fmt_bytes}
     out = {
         "metric": METRIC,
         "value": round(gbs, 2),
@@ -187,9 +197,11 @@ def main():
         "config": {
             "workload": workload,
             "selector": args.select,
+            "selector_fallback": bool(info["fallback"]),
             "variant_opts": opts,
             "variant_id": info["variant_id"],
             "lanes_per_row": info["lanes_per_row"],
+            "merge_items": info["merge_items"],
             "delta_bits": info["delta_bits"],
             "pct_of_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
             "pct_of_triad": round(100 * gbs / triad, 2),
@@ -199,8 +211,11 @@ def main():
             "plain_ms": round(t_plain, 5),
             "speedup_vs_plain": round(t_plain / ms, 4),
             "selected_ms_protocol": round(t_sel_proto, 5),
-            "select_ms": round(info["t_select_ms"], 2),
-            "select_wall_ms": round(t_sel_wall, 2),
+            "create_ms": round(create_ms, 2),
+            "select_ms": round(info["t_select_ms"], 3),
+            "prep_ms": round(info["t_prep_ms"], 3),
+            "n_iters_min": (round(oracle.n_iters_min(t_pre, t_plain, ms), 1)
+                            if ms < t_plain else None),
             "parity_ok": ok,
             "timed_wall_ms": round(wall_ms, 2),
         },

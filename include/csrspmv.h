@@ -208,6 +208,18 @@ csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t by
                             size_t *needed, void *stream);
 
 /*
+ * Measurement support: `calls` back-to-back SpMVs with the current plan on
+ * the caller's vectors (after one warm call). *kernel_ms = mean duration of
+ * the plan's dominant kernel (HIP events recorded on `stream` immediately
+ * before and after it), *call_ms = mean duration of a whole call (events
+ * around all calls). kernel_name (may be NULL) receives the dominant kernel's
+ * name as a kernel trace shows it, truncated to name_bytes. Synchronizes.
+ */
+csr_status_t csr_time_spmv(csr_matrix_t A, const void *d_x, void *d_y, int32_t calls,
+                           double *kernel_ms, double *call_ms, char *kernel_name,
+                           size_t name_bytes, void *stream);
+
+/*
  * Test support: runs one micro-benchmark of the profile-guided classifier
  * (Sec. III-B) on the caller's vectors so its arithmetic can be checked:
  *   which = 1  P_ML probe: the baseline kernel with every column index

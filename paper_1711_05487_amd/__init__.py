@@ -35,7 +35,7 @@ STATUS = ["CSR_OK", "CSR_ERR_INVALID_ARG", "CSR_ERR_INVALID_MATRIX", "CSR_ERR_OU
 # Every entry point declared in include/csrspmv.h.
 EXPORTS = ("csr_config_default", "csr_create", "csr_destroy", "csr_inspect", "csr_select",
            "csr_spmv", "csr_spmv_batched", "csr_status_str", "csr_last_error", "csr_query",
-           "csr_debug_copy", "csr_debug_probe", "csr_triad", "csr_mlp_load", "csr_mlp_unload",
+           "csr_debug_copy", "csr_debug_probe", "csr_triad", "csr_time_spmv", "csr_mlp_load", "csr_mlp_unload",
            "csr_mlp_forward", "csr_mlp_grad", "csr_mlp_train", "csr_mlp_normalize")
 
 
@@ -101,6 +101,8 @@ def lib():
             "csr_debug_copy": (ctypes.c_int, [P, i32, P, sz, ctypes.POINTER(sz), P]),
             "csr_triad": (ctypes.c_int, [sz, i32, ctypes.POINTER(ctypes.c_double), P]),
             "csr_debug_probe": (ctypes.c_int, [P, i32, P, P, P]),
+            "csr_time_spmv": (ctypes.c_int, [P, P, P, i32, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double), ctypes.c_char_p, sz, P]),
             "csr_mlp_load": (ctypes.c_int, [P, i32, P, P]),
             "csr_mlp_unload": (ctypes.c_int, []),
             "csr_mlp_forward": (ctypes.c_int, [P, i32, P, i32, P, P]),
@@ -230,6 +232,15 @@ class CsrMatrix:
         _check(lib().csr_debug_copy(self._h, what, out.ctypes.data_as(ctypes.c_void_p),
                                     need.value, None, _stream(stream)))
         return out
+
+    def time_spmv(self, x, y, calls: int, stream=None):
+        """(dominant-kernel ms, whole-call ms, kernel name) averaged over
+        `calls` SpMVs, from HIP events on the launch stream."""
+        k, c = ctypes.c_double(), ctypes.c_double()
+        name = ctypes.create_string_buffer(128)
+        _check(lib().csr_time_spmv(self._h, _ptr(x), _ptr(y), calls, ctypes.byref(k),
+                                   ctypes.byref(c), name, 128, _stream(stream)))
+        return k.value, c.value, name.value.decode()
 
     def probe(self, which: int, x, y=None, stream=None):
         """Run the P_ML (1) or P_CMP (2) micro-benchmark kernel on x."""

@@ -4,9 +4,11 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "batch.h"
 #include "internal.h"
@@ -100,13 +102,26 @@ int device_cu_count(int device) {
     return cache[device];
 }
 
+std::string dominant_kernel(const csr_matrix_s *A, const Plan &P) {
+    (void)A;
+    if (P.opts & CSR_OPT_MERGE)
+        return "k_merge<" + std::to_string(P.L / kBlock) + ", " + (P.nt ? "true" : "false") + ">";
+    return "k_rowsplit<" + std::to_string(P.G) + ", " + std::to_string(P.idx) + ", " +
+           (P.nt ? "true" : "false") + ", " + std::to_string(P.U) + ", " + std::to_string(P.R) +
+           ", 0>";
+}
+
 size_t storage_bytes(int storage) {
     return storage == CSR_VAL_F64 ? 8 : storage == CSR_VAL_F32 ? 4 : 2;
 }
 
 hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void *y,
-                       hipStream_t s) {
+                       hipStream_t s, hipEvent_t before, hipEvent_t after) {
     const void *arr[7] = {A->rp.p, A->col.p, A->codes.p, A->val.p, x, y, nullptr};
+    if (before) {
+        const hipError_t e = hipEventRecord(before, s);
+        if (e != hipSuccess) return e;
+    }
     const int32_t skip = P.long_rows ? (int32_t)A->long_tau : INT32_MAX;
     if (P.opts & CSR_OPT_MERGE) {
         const int ipt = P.L / kBlock;
@@ -114,11 +129,14 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
         auto tj = A->tile_j.as<int32_t>();
         switch (A->storage) {
         case CSR_VAL_F64:
-            return launch_merge_s0(ipt, P.nt != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles, s);
+            return launch_merge_s0(ipt, P.nt != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
+                                   after, s);
         case CSR_VAL_F32:
-            return launch_merge_s1(ipt, P.nt != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles, s);
+            return launch_merge_s1(ipt, P.nt != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
+                                   after, s);
         default:
-            return launch_merge_s2(ipt, P.nt != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles, s);
+            return launch_merge_s2(ipt, P.nt != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
+                                   after, s);
         }
     }
     hipError_t e;
@@ -136,6 +154,7 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
                                   A->n_cols, s);
         break;
     }
+    if (e == hipSuccess && after) e = hipEventRecord(after, s);
     if (e != hipSuccess || !P.long_rows || A->n_long == 0) return e;
     const int32_t *cb = A->long_chunks.as<int32_t>();
     const int32_t *lr = A->long_list.as<int32_t>();
@@ -291,6 +310,40 @@ csr_status_t csr_spmv(csr_matrix_t A, const void *d_x, void *d_y, void *stream) 
     if (A->n_rows == 0) return CSR_OK;
     DeviceGuard g(A->device);
     CSR_HIP(launch_spmv(A, A->plan, d_x, d_y, (hipStream_t)stream));
+    return CSR_OK;
+}
+
+csr_status_t csr_time_spmv(csr_matrix_t A, const void *d_x, void *d_y, int32_t calls,
+                           double *kernel_ms, double *call_ms, char *kernel_name,
+                           size_t name_bytes, void *stream) {
+    if (!A || calls < 1 || !kernel_ms || !call_ms) return fail(CSR_ERR_INVALID_ARG, "bad arguments");
+    if ((!d_x && A->n_cols > 0) || (!d_y && A->n_rows > 0))
+        return fail(CSR_ERR_INVALID_ARG, "NULL vector");
+    DeviceGuard g(A->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<hipEvent_t> ev(2 * (size_t)calls + 2);
+    for (auto &e : ev) CSR_HIP(hipEventCreate(&e));
+    hipError_t e = launch_spmv(A, A->plan, d_x, d_y, s);  // warm
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * calls], s);
+    for (int c = 0; c < calls && e == hipSuccess; ++c)
+        e = launch_spmv(A, A->plan, d_x, d_y, s, ev[2 * c], ev[2 * c + 1]);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * calls + 1], s);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[2 * calls + 1]);
+    double k = 0.0;
+    float f = 0.f;
+    for (int c = 0; c < calls && e == hipSuccess; ++c) {
+        e = hipEventElapsedTime(&f, ev[2 * c], ev[2 * c + 1]);
+        k += f;
+    }
+    if (e == hipSuccess) e = hipEventElapsedTime(&f, ev[2 * calls], ev[2 * calls + 1]);
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(e, "timed SpMV");
+    *kernel_ms = k / calls;
+    *call_ms = (double)f / calls;
+    if (kernel_name && name_bytes > 0) {
+        const std::string n = dominant_kernel(A, A->plan);
+        std::snprintf(kernel_name, name_bytes, "%s", n.c_str());
+    }
     return CSR_OK;
 }
 

@@ -134,19 +134,23 @@ hipError_t launch_merge_partition(const int32_t *rp, int32_t n_rows, int64_t nnz
 // arr = {rp, col, codes, val, x, y}; L = 256 * ipt
 hipError_t launch_merge_s0(int ipt, bool nt, const void *const *arr, const int32_t *tile_i,
                            const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
-                           hipStream_t s);
+                           hipEvent_t after_main, hipStream_t s);
 hipError_t launch_merge_s1(int ipt, bool nt, const void *const *arr, const int32_t *tile_i,
                            const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
-                           hipStream_t s);
+                           hipEvent_t after_main, hipStream_t s);
 hipError_t launch_merge_s2(int ipt, bool nt, const void *const *arr, const int32_t *tile_i,
                            const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
-                           hipStream_t s);
+                           hipEvent_t after_main, hipStream_t s);
 hipError_t launch_fill_row_index(const int32_t *rp, int32_t n_rows, int32_t n_cols, int32_t *out,
                                  hipStream_t s);
 hipError_t launch_convert_values(const double *src, void *dst, int64_t n, int storage,
                                  hipStream_t s);
+// y = A x under plan P. If `before`/`after` are given, they are recorded on
+// `s` immediately around the plan's dominant (first) kernel.
 hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void *y,
-                       hipStream_t s);
+                       hipStream_t s, hipEvent_t before = nullptr, hipEvent_t after = nullptr);
+// Name of the plan's dominant kernel (as in a kernel trace).
+std::string dominant_kernel(const csr_matrix_s *A, const Plan &P);
 hipError_t launch_triad(double *a, const double *b, const double *c, double scalar,
                         int64_t n, hipStream_t s);
 
@@ -157,11 +161,10 @@ struct FeatPart {
     double sc_n, sc_mean, sc_m2;  // Welford state of scatter_i
     double s_cl;                  // sum of clustering_i
 };
-int32_t features_partials(int32_t n_rows, int G, int32_t *rows_per_block);
+int32_t features_partials(int32_t n_rows, int G);
 int32_t xreuse_samples(int32_t n_rows);
 hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int G,
-                           FeatPart *parts, int32_t n_parts, int32_t rows_per_block,
-                           int32_t *reuse_out, hipStream_t s);
+                           FeatPart *parts, int32_t n_parts, int32_t *reuse_out, hipStream_t s);
 
 hipError_t launch_long_s0(const int32_t *col, const void *val, const void *x, void *y,
                           const int32_t *chunk_beg, void *part, int64_t n_chunks,

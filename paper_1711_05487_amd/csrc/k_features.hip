@@ -21,6 +21,7 @@ namespace {
 constexpr int kFeatE = 16;   // FP64 values per 128-byte cache line
 constexpr int kReuseP = 256; // entries per sampled row
 constexpr int kReuseS = 4096;
+constexpr int kFeatBlocks = 2048;  // workgroups of the sweep (partials to fold)
 
 __device__ __forceinline__ void welford_push(double &n, double &mean, double &m2, double v) {
     n += 1.0;
@@ -69,47 +70,43 @@ __device__ __forceinline__ void part_init(FeatPart &p) {
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_features(const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ col,
-                                                     int32_t n_rows, int32_t rows_per_block,
-                                                     FeatPart *__restrict__ out) {
+                                                     int32_t n_rows, FeatPart *__restrict__ out) {
     __shared__ FeatPart s_part[kBlock / G];
     constexpr int NG = kBlock / G;
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
     FeatPart p;
     part_init(p);
-    const int64_t r_begin = (int64_t)blockIdx.x * rows_per_block;
-    int64_t r_end = r_begin + rows_per_block;
-    if (r_end > n_rows) r_end = n_rows;
-    for (int64_t r = r_begin + grp; r < r_end; r += NG) {
+    // workgroup b sweeps rows b*NG + grp, then + gridDim*NG, ... (fixed order)
+    const int64_t stride = (int64_t)gridDim.x * NG;
+    for (int64_t r = (int64_t)blockIdx.x * NG + grp; r < n_rows; r += stride) {
         const int32_t b = rp[r], e = rp[r + 1];
+        const int32_t k = e - b;
+        // lane takes the contiguous segment [s0, s1) of the row; the entry
+        // before the segment (if inside the row) gives its first gap
+        const int32_t q = (k + G - 1) / G;
+        const int32_t s0 = min(b + lane * q, e), s1 = min(s0 + q, e);
         int32_t mn = INT32_MAX, mx = INT32_MIN, miss = 0, grps = 0;
-        int32_t prev_last = 0;  // last column of the previous chunk (lane G-1's)
-        for (int32_t j0 = b; j0 < e; j0 += G) {
-            const int32_t j = j0 + lane;
-            const bool ok = j < e;
-            const int32_t c = ok ? col[j] : 0;
-            int32_t prev = __shfl_up(c, 1, G);
-            if (lane == 0) prev = prev_last;
-            if (ok) {
-                mn = min(mn, c);
-                mx = max(mx, c);
-                if (j == b) {
-                    miss += 1;
-                    grps += 1;
-                } else {
-                    const int64_t d = (int64_t)c - prev;
-                    miss += (d > kFeatE || d < -kFeatE) ? 1 : 0;
-                    grps += (d != 1) ? 1 : 0;
-                }
+        int32_t prev = s0 > b && s0 < e ? col[s0 - 1] : 0;
+        for (int32_t j = s0; j < s1; ++j) {
+            const int32_t c = col[j];
+            mn = min(mn, c);
+            mx = max(mx, c);
+            if (j == b) {
+                miss += 1;
+                grps += 1;
+            } else {
+                const int64_t d = (int64_t)c - prev;
+                miss += (d > kFeatE || d < -kFeatE) ? 1 : 0;
+                grps += (d != 1) ? 1 : 0;
             }
-            prev_last = __shfl(c, G - 1, G);
+            prev = c;
         }
         mn = -group_max<G>(-mn);
         mx = group_max<G>(mx);
         miss = group_isum<G>(miss);
         grps = group_isum<G>(grps);
         if (lane == 0) {
-            const int32_t k = e - b;
             const int32_t bw = k > 0 ? mx - mn : 0;
             p.s_nnz2 += (int64_t)k * k;
             p.s_bw += bw;
@@ -194,36 +191,32 @@ __global__ __launch_bounds__(kWave) void k_xreuse(const int32_t *__restrict__ rp
 
 template <int G>
 hipError_t go(const int32_t *rp, const int32_t *col, int32_t n_rows, FeatPart *parts,
-              int32_t n_parts, int32_t rows_per_block, hipStream_t s) {
-    hipLaunchKernelGGL(k_features<G>, dim3(n_parts), dim3(kBlock), 0, s, rp, col, n_rows,
-                       rows_per_block, parts);
+              int32_t n_parts, hipStream_t s) {
+    hipLaunchKernelGGL(k_features<G>, dim3(n_parts), dim3(kBlock), 0, s, rp, col, n_rows, parts);
     return hipGetLastError();
 }
 
 }  // namespace
 
-int32_t features_partials(int32_t n_rows, int G, int32_t *rows_per_block) {
-    const int NG = kBlock / G;
-    // 4 row groups per lane group, so a block sweeps 4 * 256/G rows
-    int32_t rpb = NG * 4;
-    *rows_per_block = rpb;
-    return n_rows > 0 ? (n_rows + rpb - 1) / rpb : 1;
+int32_t features_partials(int32_t n_rows, int G) {
+    const int64_t NG = kBlock / G;
+    const int64_t need = n_rows > 0 ? (n_rows + NG - 1) / NG : 1;
+    return (int32_t)(need < kFeatBlocks ? need : kFeatBlocks);
 }
 
 int32_t xreuse_samples(int32_t n_rows) { return n_rows > 1 ? min(n_rows - 1, kReuseS) : 0; }
 
 hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int G,
-                           FeatPart *parts, int32_t n_parts, int32_t rows_per_block,
-                           int32_t *reuse_out, hipStream_t s) {
+                           FeatPart *parts, int32_t n_parts, int32_t *reuse_out, hipStream_t s) {
     hipError_t e;
     switch (G) {
-    case 1: e = go<1>(rp, col, n_rows, parts, n_parts, rows_per_block, s); break;
-    case 2: e = go<2>(rp, col, n_rows, parts, n_parts, rows_per_block, s); break;
-    case 4: e = go<4>(rp, col, n_rows, parts, n_parts, rows_per_block, s); break;
-    case 8: e = go<8>(rp, col, n_rows, parts, n_parts, rows_per_block, s); break;
-    case 16: e = go<16>(rp, col, n_rows, parts, n_parts, rows_per_block, s); break;
-    case 32: e = go<32>(rp, col, n_rows, parts, n_parts, rows_per_block, s); break;
-    default: e = go<64>(rp, col, n_rows, parts, n_parts, rows_per_block, s); break;
+    case 1: e = go<1>(rp, col, n_rows, parts, n_parts, s); break;
+    case 2: e = go<2>(rp, col, n_rows, parts, n_parts, s); break;
+    case 4: e = go<4>(rp, col, n_rows, parts, n_parts, s); break;
+    case 8: e = go<8>(rp, col, n_rows, parts, n_parts, s); break;
+    case 16: e = go<16>(rp, col, n_rows, parts, n_parts, s); break;
+    case 32: e = go<32>(rp, col, n_rows, parts, n_parts, s); break;
+    default: e = go<64>(rp, col, n_rows, parts, n_parts, s); break;
     }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_features_fold, dim3(1), dim3(kBlock), 0, s, parts, n_parts);

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup(const int32_t *__restric
 
 template <int IPT, bool NT>
 hipError_t go(const void *const *arr, const int32_t *tile_i, const int32_t *tile_j, void *carry,
-              int32_t n_rows, int64_t n_tiles, hipStream_t s) {
+              int32_t n_rows, int64_t n_tiles, hipEvent_t after_main, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
     const XcdGrid g = xcd_grid(n_tiles);
     hipLaunchKernelGGL((k_merge<IPT, NT>), dim3((unsigned)g.launched), dim3(kBlock), 0, s,
@@ -65,6 +65,7 @@ hipError_t go(const void *const *arr, const int32_t *tile_i, const int32_t *tile
                        (const X *)arr[4], (X *)arr[5], tile_i, tile_j, (A *)carry, n_rows,
                        g.per_xcd, n_tiles);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess && after_main) e = hipEventRecord(after_main, s);
     if (e != hipSuccess || n_tiles < 2) return e;
     const unsigned fb = (unsigned)((n_tiles + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_merge_fixup, dim3(fb), dim3(kBlock), 0, s, (const int32_t *)arr[0],
@@ -80,14 +81,14 @@ hipError_t go(const void *const *arr, const int32_t *tile_i, const int32_t *tile
 hipError_t CSR_CAT(launch_merge_s, CSR_STORAGE)(int ipt, bool nt, const void *const *arr,
                                                 const int32_t *tile_i, const int32_t *tile_j,
                                                 void *carry, int32_t n_rows, int64_t n_tiles,
-                                                hipStream_t s) {
+                                                hipEvent_t after_main, hipStream_t s) {
     switch (ipt) {
-    case 4: return nt ? go<4, true>(arr, tile_i, tile_j, carry, n_rows, n_tiles, s)
-                      : go<4, false>(arr, tile_i, tile_j, carry, n_rows, n_tiles, s);
-    case 8: return nt ? go<8, true>(arr, tile_i, tile_j, carry, n_rows, n_tiles, s)
-                      : go<8, false>(arr, tile_i, tile_j, carry, n_rows, n_tiles, s);
-    case 16: return nt ? go<16, true>(arr, tile_i, tile_j, carry, n_rows, n_tiles, s)
-                       : go<16, false>(arr, tile_i, tile_j, carry, n_rows, n_tiles, s);
+    case 4: return nt ? go<4, true>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s)
+                      : go<4, false>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
+    case 8: return nt ? go<8, true>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s)
+                      : go<8, false>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
+    case 16: return nt ? go<16, true>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s)
+                       : go<16, false>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -347,9 +347,9 @@ csr_status_t inspect(csr_matrix_s *A, hipStream_t s) {
     const int64_t N = A->n_rows;
     if (N > 0) {
         const double nnz_avg = (double)A->nnz / N;
-        const int G = default_lanes_per_row(nnz_avg);
-        int32_t rpb = 0;
-        const int32_t n_parts = features_partials(A->n_rows, G, &rpb);
+        const int G0 = default_lanes_per_row(nnz_avg);
+        const int G = G0 >= 4 ? G0 / 4 : 1;  // contiguous segments of about 4 entries per lane
+        const int32_t n_parts = features_partials(A->n_rows, G);
         const int32_t n_samp = xreuse_samples(A->n_rows);
         csr_status_t st;
         if (A->feat_parts.bytes < sizeof(FeatPart) * (size_t)n_parts &&
@@ -359,7 +359,7 @@ csr_status_t inspect(csr_matrix_s *A, hipStream_t s) {
             (st = A->feat_reuse.alloc(sizeof(int32_t) * 2 * (size_t)n_samp + 8)) != CSR_OK)
             return st;
         CSR_HIP(launch_features(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->n_rows, G,
-                                A->feat_parts.as<FeatPart>(), n_parts, rpb,
+                                A->feat_parts.as<FeatPart>(), n_parts,
                                 A->feat_reuse.as<int32_t>(), s));
         FeatPart p;
         std::vector<int32_t> reuse(2 * (size_t)n_samp);
