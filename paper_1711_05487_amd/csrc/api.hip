@@ -105,7 +105,7 @@ int device_cu_count(int device) {
 std::string dominant_kernel(const csr_matrix_s *A, const Plan &P) {
     (void)A;
     if (P.opts & CSR_OPT_MERGE)
-        return "k_merge<" + std::to_string(P.L / kBlock) + ", " + (P.nt ? "true" : "false") + ">";
+        return "k_merge<" + std::to_string(P.L / kMergeBlock) + ", " + (P.nt ? "true" : "false") + ">";
     return "k_rowsplit<" + std::to_string(P.G) + ", " + std::to_string(P.idx) + ", " +
            (P.nt ? "true" : "false") + ", " + std::to_string(P.U) + ", " + std::to_string(P.R) +
            ", 0>";
@@ -124,7 +124,7 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
     }
     const int32_t skip = P.long_rows ? (int32_t)A->long_tau : INT32_MAX;
     if (P.opts & CSR_OPT_MERGE) {
-        const int ipt = P.L / kBlock;
+        const int ipt = P.L / kMergeBlock;
         auto ti = A->tile_i.as<int32_t>();
         auto tj = A->tile_j.as<int32_t>();
         switch (A->storage) {

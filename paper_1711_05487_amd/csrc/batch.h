@@ -15,7 +15,7 @@ struct BatchMat {
     const int32_t *tile_j;
     void *carry;            // T tile carries
     int32_t n_rows;
-    int32_t ipt;            // L = 256 * ipt (4 or 8)
+    int32_t ipt;            // L = 64 * ipt (4, 8 or 16)
     int64_t tile_base;      // index of this matrix's first tile in the work queue
 };
 

@@ -44,13 +44,13 @@ hipError_t launch(const BatchPlan &B, hipStream_t s) {
     }
 }
 
-// Tile tables for every matrix with tile size 256 * ipt[k]; descriptors and
+// Tile tables for every matrix with tile size 64 * ipt[k]; descriptors and
 // the item -> matrix table.
 csr_status_t build(BatchPlan &B, int32_t count, const csr_matrix_t *A, const void *const *x,
                    void *const *y, const std::vector<int> &ipt, hipStream_t s) {
     std::vector<int64_t> T(count), base(count + 1, 0), tbase(count + 1, 0);
     for (int k = 0; k < count; ++k) {
-        const int64_t L = 256LL * ipt[k];
+        const int64_t L = (int64_t)kMergeBlock * ipt[k];
         T[k] = ((int64_t)A[k]->n_rows + A[k]->nnz + L - 1) / L;
         base[k + 1] = base[k] + T[k];       // work items (tiles)
         tbase[k + 1] = tbase[k] + T[k] + 1; // tile-table entries
@@ -70,7 +70,7 @@ csr_status_t build(BatchPlan &B, int32_t count, const csr_matrix_t *A, const voi
         int32_t *ti = B.tile_i.as<int32_t>() + tbase[k];
         int32_t *tj = B.tile_j.as<int32_t>() + tbase[k];
         CSR_HIP(launch_merge_partition(A[k]->rp.as<int32_t>(), A[k]->n_rows, A[k]->nnz,
-                                       256LL * ipt[k], T[k], ti, tj, s));
+                                       (int64_t)kMergeBlock * ipt[k], T[k], ti, tj, s));
         BatchMat &M = B.mats_h[k];
         M.rp = A[k]->rp.as<int32_t>();
         M.col = A[k]->col.as<int32_t>();
@@ -177,7 +177,7 @@ extern "C" csr_status_t csr_spmv_batched(int32_t count, const csr_matrix_t *h_A,
     if (!B) {
         // Per-matrix tile size: a matrix whose own plan is the merge path
         // keeps its L; the others take the tile size the batch autotuner
-        // picks (all 1024, all 2048, or 1024 below the median nnz).
+        // picks (all 256, all 512, or 256 below the median nnz).
         std::vector<int64_t> nnz(count);
         for (int k = 0; k < count; ++k) nnz[k] = h_A[k]->nnz;
         std::vector<int64_t> sorted = nnz;
@@ -189,7 +189,7 @@ extern "C" csr_status_t csr_spmv_batched(int32_t count, const csr_matrix_t *h_A,
             std::vector<int> ipt(count);
             for (int k = 0; k < count; ++k) {
                 const Plan &P = h_A[k]->plan;
-                if ((P.opts & CSR_OPT_MERGE) && (P.L == 1024 || P.L == 2048)) ipt[k] = P.L / 256;
+                if (P.opts & CSR_OPT_MERGE) ipt[k] = P.L / kMergeBlock;
                 else ipt[k] = mode == 0 ? 4 : mode == 1 ? 8 : (nnz[k] < median ? 4 : 8);
             }
             auto cand = std::make_unique<BatchPlan>();

@@ -13,6 +13,7 @@
 namespace csr {
 
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64s)
+constexpr int kMergeBlock = 64;   // merge-path tile workgroup: one wave64
 constexpr int kWave = 64;
 constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies
 constexpr size_t kPadBytes = 64;  // tail padding of val/col: vector loads may read past nnz

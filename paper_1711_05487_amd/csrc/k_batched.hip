@@ -1,6 +1,6 @@
 // Batched SpMV: many independent y_k = A_k x_k in one persistent launch.
 // The work queue is the concatenation of every matrix's merge-path tiles
-// (each matrix with its own tile size L_k = 256 * ipt_k); workgroup b takes
+// (each matrix with its own tile size L_k = 64 * ipt_k); workgroup b takes
 // items b, b + nblk, b + 2 nblk, ... (tiles are equal-sized, so the static
 // assignment is balanced and no counter has to be reset between replays).
 // Every tile runs exactly the single-matrix tile code, so a matrix's result
@@ -25,9 +25,10 @@ using A = typename St<S>::A;
 union BatchLds {
     MergeLds<S, 4> l4;
     MergeLds<S, 8> l8;
+    MergeLds<S, 16> l16;
 };
 
-__global__ __launch_bounds__(kBlock) void k_batch(const BatchMat *__restrict__ mats,
+__global__ __launch_bounds__(kMergeBlock) void k_batch(const BatchMat *__restrict__ mats,
                                                   const int32_t *__restrict__ item_mat,
                                                   int64_t n_items, int64_t per_xcd, int64_t nblk) {
     __shared__ BatchLds lds;
@@ -39,9 +40,12 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchMat *__restrict__ m
         if (M.ipt == 4)
             merge_tile<S, 4, true>(t, M.rp, M.col, (const V *)M.val, (const X *)M.x, (X *)M.y,
                                    M.tile_i, M.tile_j, (A *)M.carry, M.n_rows, lds.l4);
-        else
+        else if (M.ipt == 8)
             merge_tile<S, 8, true>(t, M.rp, M.col, (const V *)M.val, (const X *)M.x, (X *)M.y,
                                    M.tile_i, M.tile_j, (A *)M.carry, M.n_rows, lds.l8);
+        else
+            merge_tile<S, 16, true>(t, M.rp, M.col, (const V *)M.val, (const X *)M.x, (X *)M.y,
+                                    M.tile_i, M.tile_j, (A *)M.carry, M.n_rows, lds.l16);
         __syncthreads();  // LDS is reused by the next item
     }
 }
@@ -59,7 +63,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_fixup(const BatchMat *__restri
 int blocks_per_cu() {
     static int v = [] {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch, kBlock, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch, kMergeBlock, 0) != hipSuccess ||
             n < 1)
             n = 1;
         return n;
@@ -77,7 +81,7 @@ hipError_t CSR_CAT(launch_batch_s, CSR_STORAGE)(const BatchMat *mats, const int3
     int64_t nb = (int64_t)n_cu * blocks_per_cu();
     if (nb > n_items) nb = n_items;
     const XcdGrid g = xcd_grid(nb);
-    hipLaunchKernelGGL(k_batch, dim3((unsigned)g.launched), dim3(kBlock), 0, s, mats, item_mat,
+    hipLaunchKernelGGL(k_batch, dim3((unsigned)g.launched), dim3(kMergeBlock), 0, s, mats, item_mat,
                        n_items, g.per_xcd, g.nblk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

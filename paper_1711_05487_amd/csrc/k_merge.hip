@@ -2,10 +2,15 @@
 // schedule that the optimization pool applies to thread imbalance (Sec. III-E,
 // Table II, IMB). The path merges the row ends rp[1..N] with the nonzero
 // indices 0..NNZ-1 (a nonzero j is taken before row end i while j < rp[i+1]);
-// tile t covers L = 256 * IPT consecutive path items, so every workgroup gets
+// tile t covers L = 64 * IPT consecutive path items, so every workgroup gets
 // the same amount of work whatever the row lengths.
 //
-// Per tile (one 256-thread workgroup):
+// A tile is one wave64 workgroup: small workgroups keep many independent
+// tiles resident per CU, which hides the gather latency of irregular
+// matrices far better than 256-thread tiles of the same L (and the
+// workgroup barriers reduce to wave-level ones).
+//
+// Per tile:
 //  1. row ends of the rows finishing in the tile -> LDS (tile-local offsets);
 //  2. the tile's nonzeros are streamed with aligned vector loads, x gathered,
 //     products rounded and stored in LDS (so every global load is coalesced);
@@ -34,7 +39,7 @@ using X = typename St<S>::X;
 using A = typename St<S>::A;
 
 template <int IPT, bool NT>
-__global__ __launch_bounds__(kBlock) void k_merge(
+__global__ __launch_bounds__(kMergeBlock) void k_merge(
     const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const V *__restrict__ val,
     const X *__restrict__ x, X *__restrict__ y, const int32_t *__restrict__ tile_i,
     const int32_t *__restrict__ tile_j, A *__restrict__ carry, int32_t n_rows, int64_t per_xcd,
@@ -60,7 +65,7 @@ hipError_t go(const void *const *arr, const int32_t *tile_i, const int32_t *tile
               int32_t n_rows, int64_t n_tiles, hipEvent_t after_main, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
     const XcdGrid g = xcd_grid(n_tiles);
-    hipLaunchKernelGGL((k_merge<IPT, NT>), dim3((unsigned)g.launched), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_merge<IPT, NT>), dim3((unsigned)g.launched), dim3(kMergeBlock), 0, s,
                        (const int32_t *)arr[0], (const int32_t *)arr[1], (const V *)arr[3],
                        (const X *)arr[4], (X *)arr[5], tile_i, tile_j, (A *)carry, n_rows,
                        g.per_xcd, n_tiles);
@@ -77,7 +82,7 @@ hipError_t go(const void *const *arr, const int32_t *tile_i, const int32_t *tile
 
 #define CSR_CAT2(a, b) a##b
 #define CSR_CAT(a, b) CSR_CAT2(a, b)
-// arr = {rp, col, codes, val, x, y}; L = 256 * ipt
+// arr = {rp, col, codes, val, x, y}; L = 64 * ipt
 hipError_t CSR_CAT(launch_merge_s, CSR_STORAGE)(int ipt, bool nt, const void *const *arr,
                                                 const int32_t *tile_i, const int32_t *tile_j,
                                                 void *carry, int32_t n_rows, int64_t n_tiles,

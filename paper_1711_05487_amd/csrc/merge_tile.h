@@ -1,5 +1,5 @@
-// One merge-path tile of y = A x (256 threads, L = 256 * IPT path items) and
-// the cross-tile fixup of one tile. Shared by the single-matrix merge kernel
+// One merge-path tile of y = A x (one wave64 workgroup, L = 64 * IPT path
+// items) and the cross-tile fixup of one tile. Shared by the single-matrix merge kernel
 // and the batched persistent kernel, so both perform the same arithmetic in
 // the same order.
 #pragma once
@@ -12,14 +12,16 @@ template <class T, int N> struct VecOf { typedef T type __attribute__((ext_vecto
 
 template <int S, int IPT> struct MergeLds {
     using A = typename St<S>::A;
-    int32_t end[kBlock * IPT];  // tile-local row ends
-    A prod[kBlock * IPT];       // rounded products of the tile's nonzeros
-    int32_t crow[kBlock];       // per-thread carry row
-    A cval[kBlock];             // per-thread carry value
+    static constexpr int BS = kMergeBlock;
+    int32_t end[BS * IPT];  // tile-local row ends
+    A prod[BS * IPT];       // rounded products of the tile's nonzeros
+    int32_t crow[BS];       // per-thread carry row
+    A cval[BS];             // per-thread carry value
 };
 
 // Tile t: rows i0 = tile_i[t] .. i1 = tile_i[t+1] end inside it; nonzeros
-// j0 = tile_j[t] .. j1 = tile_j[t+1] - 1 belong to it.
+// j0 = tile_j[t] .. j1 = tile_j[t+1] - 1 belong to it. BS = 64 threads,
+// L = BS * IPT.
 template <int S, int IPT, bool NT, class LDS>
 __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict__ rp,
                                            const int32_t *__restrict__ col,
@@ -36,7 +38,8 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
     constexpr int VEC = (S == CSR_VAL_F64) ? 2 : 4;  // elements per vector load (8..16 bytes)
     using VV = typename VecOf<V, VEC>::type;
     using IV = typename VecOf<int32_t, VEC>::type;
-    constexpr int L = kBlock * IPT;
+    constexpr int BS = kMergeBlock;
+    constexpr int L = BS * IPT;
     int32_t *s_end = lds.end;
     A *s_prod = lds.prod;
     int32_t *s_crow = lds.crow;
@@ -48,15 +51,20 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
     const int nre = i1 - i0;   // rows whose end lies in this tile
     const int nnz_t = j1 - j0; // nonzeros of this tile
 
-    // 1. tile-local row ends
-    for (int k = tid; k < nre; k += kBlock) s_end[k] = rp[i0 + k + 1] - j0;
+    // 1. the row ends of the rows finishing in the tile (k < nre <= L, so
+    //    IPT per thread) and the start of the first row: loads issued now,
+    //    written to LDS only after the nonzero loads below are in flight
+    int32_t re[IPT];
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) re[q] = rp[min(i0 + tid + q * BS + 1, i1)];
+    const int32_t rs_first = rp[i0] - j0;  // start of row i0 (local), <= 0
 
     // 2. products, with aligned vector loads covering [j0, j1). Addresses are
     //    clamped to the last needed vector so that every load can be issued
     //    unconditionally (all of them in flight before the first use); lanes
     //    outside [j0, j1) gather x[0] and discard the product.
     if (nnz_t > 0) {
-        constexpr int STEP = kBlock * VEC;
+        constexpr int STEP = BS * VEC;
         constexpr int NIT = L / STEP + 1;
         const int32_t a = j0 & ~(VEC - 1);
         const int32_t alast = (j1 - 1) & ~(VEC - 1);
@@ -87,6 +95,11 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
             }
         }
     }
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        const int k = tid + q * BS;
+        if (k < nre) s_end[k] = re[q] - j0;
+    }
     __syncthreads();
 
     // 3. walk this thread's IPT path items
@@ -106,7 +119,7 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
     A open_val = A(0);
     for (int d = d0; d < d1; ++d) {
         if (ri < nre && nj >= s_end[ri]) {
-            const int rs = ri == 0 ? rp[i0] - j0 : s_end[ri - 1];  // row start (local)
+            const int rs = ri == 0 ? rs_first : s_end[ri - 1];  // row start (local)
             if (ri == ri0 && rs < nj0) {
                 open = true;
                 open_val = acc;
@@ -136,11 +149,11 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
         y[i0 + ri0] = (X)sum;
     }
     // 4b. the row still open at the tile end leaves a carry for later tiles
-    if (tid == kBlock - 1 && i1 < n_rows) {
-        int tb = kBlock;
+    if (tid == BS - 1 && i1 < n_rows) {
+        int tb = BS;
         while (tb > 0 && s_crow[tb - 1] == nre) --tb;
         A sum = A(0);
-        for (int q = tb; q < kBlock; ++q) sum += s_cval[q];
+        for (int q = tb; q < BS; ++q) sum += s_cval[q];
         carry[t] = sum;
     }
 }

@@ -189,9 +189,9 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
     if (opts & CSR_OPT_MERGE) {
         // IMB (GPU counterpart of the runtime-chosen schedule). With DECOMP
         // as well, the merge path already balances long rows.
-        const int L = cfg.merge_items > 0 ? cfg.merge_items : 2048;
-        if (L != 1024 && L != 2048 && L != 4096)
-            return fail(CSR_ERR_INVALID_ARG, "merge_items must be 1024, 2048 or 4096");
+        const int L = cfg.merge_items > 0 ? cfg.merge_items : 512;
+        if (L != 256 && L != 512 && L != 1024)
+            return fail(CSR_ERR_INVALID_ARG, "merge_items must be 256, 512 or 1024");
         if ((st = build_tiles(A, L, s)) != CSR_OK) return st;
         P.L = L;
         P.G = 0;
@@ -543,7 +543,7 @@ csr_status_t autotune(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, hi
     const double nnz_avg = A->n_rows ? (double)A->nnz / A->n_rows : 0.0;
     const int G0 = default_lanes_per_row(nnz_avg);
     if (opts & CSR_OPT_MERGE) {
-        for (int L : {1024, 2048, 4096}) {
+        for (int L : {256, 512, 1024}) {
             csr_config_t c = cfg;
             c.merge_items = L;
             cands.push_back(c);
@@ -559,18 +559,22 @@ csr_status_t autotune(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, hi
             }
     }
     double best_ms = 1e300;
-    for (auto &c : cands) {
+    size_t best_k = 0;
+    for (size_t k = 0; k < cands.size(); ++k) {
         Plan Q;
-        csr_status_t st = realize(A, opts, c, &Q, s);
+        csr_status_t st = realize(A, opts, cands[k], &Q, s);
         if (st != CSR_OK) return st;
         double ms = 0;
         if ((st = time_plan(A, Q, calls, 2, s, &ms)) != CSR_OK) return st;
         if (ms < best_ms) {
             best_ms = ms;
-            *best = Q;
+            best_k = k;
         }
     }
-    return CSR_OK;
+    // The matrix holds one set of derived tables (tiles, long rows, codes),
+    // rebuilt by each candidate: realize the winner again so that its tables
+    // are the ones in place (cached per parameter, so this is cheap).
+    return realize(A, opts, cands[best_k], best, s);
 }
 
 }  // namespace
@@ -626,6 +630,7 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
         break;
     case CSR_SEL_EXHAUSTIVE: {
         double best = 1e300;
+        int best_k = 0;
         const int calls = cfg.timing_calls > 0 ? cfg.timing_calls : 32;
         for (int k = 0; k < 16 && st == CSR_OK; ++k) {
             Plan Q;
@@ -634,9 +639,10 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
             if ((st = time_plan(A, Q, calls, 3, s, &ms)) != CSR_OK) break;
             if (ms < best) {
                 best = ms;
-                P = Q;
+                best_k = k;
             }
         }
+        if (st == CSR_OK) st = realize(A, kCatalogue[best_k], cfg, &P, s);  // its tables in place
         break;
     }
     case CSR_SEL_LEARNED: {

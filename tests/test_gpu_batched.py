@@ -32,7 +32,7 @@ def vectors(mats, seed, dtype=torch.float64):
 def test_batched_bit_identical_to_single_merge():
     mats, hs = batch_mats(24)
     for k, A in enumerate(hs):  # each matrix keeps its own tile size
-        A.select("forced", forced_opts=pkg.OPT_MERGE, merge_items=1024 if k % 2 else 2048)
+        A.select("forced", forced_opts=pkg.OPT_MERGE, merge_items=(256, 512, 1024)[k % 3])
     xs, ys = vectors(mats, 100)
     pkg.spmv_batched(hs, xs, ys)
     torch.cuda.synchronize()

@@ -34,7 +34,7 @@ def long_and_empty_rows():
     return len(lens), 20000, rp, col, val
 
 
-@pytest.mark.parametrize("L", [1024, 2048, 4096])
+@pytest.mark.parametrize("L", [256, 512, 1024])
 def test_tile_table_bit_exact(L):
     for name in ("lap100", "rmat14", "st27_24"):
         n, m, rp, col, val = matrix(name)
@@ -45,7 +45,7 @@ def test_tile_table_bit_exact(L):
         assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_J, np.int32), tj)
 
 
-@pytest.mark.parametrize("L", [1024, 2048, 4096])
+@pytest.mark.parametrize("L", [256, 512, 1024])
 @pytest.mark.parametrize("opts", MERGE_OPTS)
 def test_dyadic_bit_exact(opts, L):
     cases = [synth.tiny_random(700, 300, d, 11 + k, dyadic=True)
@@ -69,7 +69,7 @@ def test_all_4x4_patterns_bit_exact():
     x = synth.dyadic_vector(4 * nb, 78)
     A = pkg.CsrMatrix(rp, col, val)
     want = oracle.spmv(rp, col, val, x)
-    for L in (1024, 2048, 4096):
+    for L in (256, 512, 1024):
         assert np.array_equal(run(A, x, M, L), want)
 
 
@@ -87,7 +87,7 @@ def test_long_rows_random_values():
     val = synth.um11(8, 0, np.arange(len(col), dtype=np.uint64))
     x = synth.vector(m, 9)
     A = pkg.CsrMatrix(rp, col, val, n_cols=m)
-    for L in (1024, 2048, 4096):
+    for L in (256, 512, 1024):
         check_f64(run(A, x, M, L), rp, col, val, x, f"long rows L={L}")
 
 
@@ -105,18 +105,26 @@ def test_reduced_precision(storage):
         n, m, rp, col, val = matrix(name)
         x = xvec(name, m)
         A = pkg.CsrMatrix(rp, col, val, storage=storage)
-        for L in (1024, 4096):
+        for L in (256, 1024):
             A.select("forced", forced_opts=M, merge_items=L)
             y = A.spmv(torch.from_numpy(oracle.to_f32(x)).cuda())
             torch.cuda.synchronize()
             check_reduced(y.cpu().numpy(), rp, col, val, x, storage, f"{name} {storage} L={L}")
 
 
+def test_invalid_tile_size_rejected():
+    n, m, rp, col, val = matrix("lap37")
+    A = pkg.CsrMatrix(rp, col, val)
+    for L in (128, 768, 2048):
+        with pytest.raises(pkg.CsrError):
+            A.select("forced", forced_opts=M, merge_items=L)
+
+
 def test_deterministic():
     n, m, rp, col, val = matrix("rmat14")
     x = synth.vector(m, 4)
     A = pkg.CsrMatrix(rp, col, val)
-    for L in (1024, 2048):
+    for L in (256, 512):
         y1 = run(A, x, M, L)
         y2 = run(A, x)
         assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))

@@ -135,6 +135,15 @@ def test_decomposition_rmat():
     check_f64(y.cpu().numpy(), rp, col, val, x, "rmat14 decomp")
 
 
+def check_tables_in_place(A, info, rp):
+    """The autotuner rebuilds the merge tile table per candidate tile size;
+    the one left in place must be the table of the plan it kept."""
+    if info["opts"] & pkg.OPT_MERGE:
+        ti, tj = oracle.merge_tiles(rp, info["merge_items"])
+        assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_I, np.int32), ti)
+        assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_J, np.int32), tj)
+
+
 @pytest.mark.parametrize("name", ["lap100", "st27_24", "rmat14", "unif14"])
 def test_profile_rule_and_remedies_match_oracle(name):
     n, m, rp, col, val = matrix(name)
@@ -147,6 +156,7 @@ def test_profile_rule_and_remedies_match_oracle(name):
     f, _ = oracle.features(n, m, rp, col)
     has_long = f[F["nnz_max"]] > oracle.long_row_threshold(f[F["nnz_avg"]])
     assert info["opts"] == oracle.remedies(cls, has_long)
+    check_tables_in_place(A, info, rp)
     x = xvec(name, m)
     y = A.spmv(torch.from_numpy(x).cuda())
     torch.cuda.synchronize()
@@ -159,6 +169,7 @@ def test_exhaustive_selects_catalogue_variant():
     info = A.select("exhaustive", timing_calls=8)
     assert 0 <= info["variant_id"] < 16
     assert oracle.catalogue()[info["variant_id"]] == info["opts"]
+    check_tables_in_place(A, info, rp)
     x = xvec("st27_24", m)
     y = A.spmv(torch.from_numpy(x).cuda())
     torch.cuda.synchronize()
