@@ -102,10 +102,15 @@ int device_cu_count(int device) {
     return cache[device];
 }
 
+bool x_fits_32(const csr_matrix_s *A) {
+    const uint64_t xb = A->storage == CSR_VAL_F64 ? 8 : 4;
+    return (uint64_t)A->n_cols * xb <= (uint64_t)UINT32_MAX + 1;
+}
+
 std::string dominant_kernel(const csr_matrix_s *A, const Plan &P) {
-    (void)A;
     if (P.opts & CSR_OPT_MERGE)
-        return "k_merge<" + std::to_string(P.L / kMergeBlock) + ", " + (P.nt ? "true" : "false") + ">";
+        return "k_merge<" + std::to_string(P.L / kMergeBlock) + ", " + (P.nt ? "true" : "false") +
+               ", " + (x_fits_32(A) ? "true" : "false") + ">";
     return "k_rowsplit<" + std::to_string(P.G) + ", " + std::to_string(P.idx) + ", " +
            (P.nt ? "true" : "false") + ", " + std::to_string(P.U) + ", " + std::to_string(P.R) +
            ", 0>";
@@ -125,17 +130,18 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
     const int32_t skip = P.long_rows ? (int32_t)A->long_tau : INT32_MAX;
     if (P.opts & CSR_OPT_MERGE) {
         const int ipt = P.L / kMergeBlock;
+        const bool x32 = x_fits_32(A);
         auto ti = A->tile_i.as<int32_t>();
         auto tj = A->tile_j.as<int32_t>();
         switch (A->storage) {
         case CSR_VAL_F64:
-            return launch_merge_s0(ipt, P.nt != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
+            return launch_merge_s0(ipt, P.nt != 0, x32, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
                                    after, s);
         case CSR_VAL_F32:
-            return launch_merge_s1(ipt, P.nt != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
+            return launch_merge_s1(ipt, P.nt != 0, x32, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
                                    after, s);
         default:
-            return launch_merge_s2(ipt, P.nt != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
+            return launch_merge_s2(ipt, P.nt != 0, x32, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
                                    after, s);
         }
     }

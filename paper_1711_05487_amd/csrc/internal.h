@@ -132,15 +132,15 @@ hipError_t launch_rowsplit_s2(int G, int idx, bool nt, int U, int R, int probe,
 hipError_t launch_merge_partition(const int32_t *rp, int32_t n_rows, int64_t nnz, int64_t L,
                                   int64_t n_tiles, int32_t *tile_i, int32_t *tile_j,
                                   hipStream_t s);
-// arr = {rp, col, codes, val, x, y}; L = 256 * ipt
-hipError_t launch_merge_s0(int ipt, bool nt, const void *const *arr, const int32_t *tile_i,
-                           const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
+// arr = {rp, col, codes, val, x, y}; L = 64 * ipt; x32: x spans < 4 GiB
+hipError_t launch_merge_s0(int ipt, bool nt, bool x32, const void *const *arr,
+                           const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
                            hipEvent_t after_main, hipStream_t s);
-hipError_t launch_merge_s1(int ipt, bool nt, const void *const *arr, const int32_t *tile_i,
-                           const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
+hipError_t launch_merge_s1(int ipt, bool nt, bool x32, const void *const *arr,
+                           const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
                            hipEvent_t after_main, hipStream_t s);
-hipError_t launch_merge_s2(int ipt, bool nt, const void *const *arr, const int32_t *tile_i,
-                           const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
+hipError_t launch_merge_s2(int ipt, bool nt, bool x32, const void *const *arr,
+                           const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
                            hipEvent_t after_main, hipStream_t s);
 hipError_t launch_fill_row_index(const int32_t *rp, int32_t n_rows, int32_t n_cols, int32_t *out,
                                  hipStream_t s);
@@ -151,6 +151,8 @@ hipError_t launch_convert_values(const double *src, void *dst, int64_t n, int st
 hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void *y,
                        hipStream_t s, hipEvent_t before = nullptr, hipEvent_t after = nullptr);
 // Name of the plan's dominant kernel (as in a kernel trace).
+// x of this matrix spans < 4 GiB, so gathers may use 32-bit byte offsets
+bool x_fits_32(const csr_matrix_s *A);
 std::string dominant_kernel(const csr_matrix_s *A, const Plan &P);
 hipError_t launch_triad(double *a, const double *b, const double *c, double scalar,
                         int64_t n, hipStream_t s);

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kMergeBlock) void k_batch(const BatchMat *__restric
         else
             merge_tile<S, 16, true>(t, M.rp, M.col, (const V *)M.val, (const X *)M.x, (X *)M.y,
                                     M.tile_i, M.tile_j, (A *)M.carry, M.n_rows, lds.l16);
-        __syncthreads();  // LDS is reused by the next item
+        wave_lds_sync();  // LDS is reused by the next item
     }
 }
 

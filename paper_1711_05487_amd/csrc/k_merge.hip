@@ -10,18 +10,13 @@
 // matrices far better than 256-thread tiles of the same L (and the
 // workgroup barriers reduce to wave-level ones).
 //
-// Per tile:
-//  1. row ends of the rows finishing in the tile -> LDS (tile-local offsets);
-//  2. the tile's nonzeros are streamed with aligned vector loads, x gathered,
-//     products rounded and stored in LDS (so every global load is coalesced);
-//  3. each thread walks IPT path items of the tile (its own merge-path
-//     diagonal, found by binary search in LDS), summing products and emitting
-//     rows as their ends go by;
-//  4. rows split across threads are completed from the per-thread carries in
-//     thread order; the row still open at the tile end leaves one carry per
-//     tile, and rows split across tiles are finished by k_merge_fixup, which
-//     adds the carries in tile order. Every sum has a fixed order, so results
-//     are deterministic.
+// Per tile (merge_tile): the nonzeros are streamed with coalesced vector
+// loads and their products staged in LDS; the tile is then reduced as one
+// segmented scan across the wave, with a segment starting at every row end
+// inside the tile, and each row reads its sum at its last nonzero. The row
+// still open at the tile end leaves one carry per tile; rows split across
+// tiles are finished by k_merge_fixup, which adds the carries in tile order.
+// Every sum has a fixed order, so results are deterministic.
 //
 // Compiled once per storage type (-DCSR_STORAGE=0/1/2).
 #include "merge_tile.h"
@@ -38,7 +33,7 @@ using V = typename St<S>::V;
 using X = typename St<S>::X;
 using A = typename St<S>::A;
 
-template <int IPT, bool NT>
+template <int IPT, bool NT, bool X32>
 __global__ __launch_bounds__(kMergeBlock) void k_merge(
     const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const V *__restrict__ val,
     const X *__restrict__ x, X *__restrict__ y, const int32_t *__restrict__ tile_i,
@@ -47,7 +42,8 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge(
     __shared__ MergeLds<S, IPT> lds;
     const int64_t t = xcd_logical_block(per_xcd);
     if (t >= n_tiles) return;
-    merge_tile<S, IPT, NT>(t, rp, col, val, x, y, tile_i, tile_j, carry, n_rows, lds);
+    merge_tile<S, IPT, NT, MergeLds<S, IPT>, X32>(t, rp, col, val, x, y, tile_i, tile_j, carry,
+                                                  n_rows, lds);
 }
 
 __global__ __launch_bounds__(kBlock) void k_merge_fixup(const int32_t *__restrict__ rp,
@@ -60,12 +56,12 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup(const int32_t *__restric
     if (t < n_tiles) merge_fixup_tile<S>(t, rp, tile_i, tile_j, carry, y, n_rows);
 }
 
-template <int IPT, bool NT>
+template <int IPT, bool NT, bool X32>
 hipError_t go(const void *const *arr, const int32_t *tile_i, const int32_t *tile_j, void *carry,
               int32_t n_rows, int64_t n_tiles, hipEvent_t after_main, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
     const XcdGrid g = xcd_grid(n_tiles);
-    hipLaunchKernelGGL((k_merge<IPT, NT>), dim3((unsigned)g.launched), dim3(kMergeBlock), 0, s,
+    hipLaunchKernelGGL((k_merge<IPT, NT, X32>), dim3((unsigned)g.launched), dim3(kMergeBlock), 0, s,
                        (const int32_t *)arr[0], (const int32_t *)arr[1], (const V *)arr[3],
                        (const X *)arr[4], (X *)arr[5], tile_i, tile_j, (A *)carry, n_rows,
                        g.per_xcd, n_tiles);
@@ -78,22 +74,30 @@ hipError_t go(const void *const *arr, const int32_t *tile_i, const int32_t *tile
     return hipGetLastError();
 }
 
+template <int IPT>
+hipError_t go_ipt(bool nt, bool x32, const void *const *arr, const int32_t *tile_i,
+                  const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
+                  hipEvent_t after_main, hipStream_t s) {
+    if (nt)
+        return x32 ? go<IPT, true, true>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s)
+                   : go<IPT, true, false>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
+    return x32 ? go<IPT, false, true>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s)
+               : go<IPT, false, false>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
+}
+
 }  // namespace
 
 #define CSR_CAT2(a, b) a##b
 #define CSR_CAT(a, b) CSR_CAT2(a, b)
-// arr = {rp, col, codes, val, x, y}; L = 64 * ipt
-hipError_t CSR_CAT(launch_merge_s, CSR_STORAGE)(int ipt, bool nt, const void *const *arr,
+// arr = {rp, col, codes, val, x, y}; L = 64 * ipt; x32: x spans < 4 GiB
+hipError_t CSR_CAT(launch_merge_s, CSR_STORAGE)(int ipt, bool nt, bool x32, const void *const *arr,
                                                 const int32_t *tile_i, const int32_t *tile_j,
                                                 void *carry, int32_t n_rows, int64_t n_tiles,
                                                 hipEvent_t after_main, hipStream_t s) {
     switch (ipt) {
-    case 4: return nt ? go<4, true>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s)
-                      : go<4, false>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
-    case 8: return nt ? go<8, true>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s)
-                      : go<8, false>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
-    case 16: return nt ? go<16, true>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s)
-                       : go<16, false>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
+    case 4: return go_ipt<4>(nt, x32, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
+    case 8: return go_ipt<8>(nt, x32, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
+    case 16: return go_ipt<16>(nt, x32, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
     default: return hipErrorInvalidValue;
     }
 }

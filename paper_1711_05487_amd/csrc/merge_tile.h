@@ -1,7 +1,7 @@
 // One merge-path tile of y = A x (one wave64 workgroup, L = 64 * IPT path
-// items) and the cross-tile fixup of one tile. Shared by the single-matrix merge kernel
-// and the batched persistent kernel, so both perform the same arithmetic in
-// the same order.
+// items) and the cross-tile fixup of one tile. Shared by the single-matrix
+// merge kernel and the batched persistent kernel, so both perform the same
+// arithmetic in the same order.
 #pragma once
 
 #include "device.h"
@@ -10,19 +10,79 @@ namespace csr {
 
 template <class T, int N> struct VecOf { typedef T type __attribute__((ext_vector_type(N))); };
 
+// Orders the LDS accesses of the lanes of one wave. A wave's LDS operations
+// complete in issue order, so no wait is needed: only fences that keep the
+// compiler from moving memory accesses across this point. Valid because a
+// merge tile is exactly one wave.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// DPP lane moves (GFX9 controls). Lanes whose source is outside the row, or
+// whose row is masked off, read 0, the identity of the segmented sum below.
+enum : int {
+    kDppRowShr = 0x110,   // + n: from lane - n within a row of 16
+    kDppWaveShr1 = 0x138, // from lane - 1 across the wave
+    kDppRowBcast15 = 0x142,
+    kDppRowBcast31 = 0x143,
+};
+template <int CTRL, int ROWS> __device__ __forceinline__ int dpp_move(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+template <int CTRL, int ROWS> __device__ __forceinline__ float dpp_move(float v) {
+    return __int_as_float(dpp_move<CTRL, ROWS>(__float_as_int(v)));
+}
+template <int CTRL, int ROWS> __device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_move<CTRL, ROWS>((int)(uint32_t)b);
+    const int hi = dpp_move<CTRL, ROWS>((int)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// One step of the inclusive segmented scan across the wave: combine with the
+// (v, h) pair that the DPP move brings, (v1, h1) then (v2, h2) ->
+// (h2 ? v2 : v1 + v2, h1 | h2).
+template <int CTRL, int ROWS, class A> __device__ __forceinline__ void seg_step(A &v, int &h) {
+    const A vu = dpp_move<CTRL, ROWS>(v);
+    const int hu = dpp_move<CTRL, ROWS>(h);
+    if (!h) v = vu + v;
+    h |= hu;
+}
+
+// Elements per vector load of the value stream (8..16 bytes per lane).
+template <int S> constexpr int merge_vec() { return S == CSR_VAL_F64 ? 2 : 4; }
+
 template <int S, int IPT> struct MergeLds {
     using A = typename St<S>::A;
     static constexpr int BS = kMergeBlock;
-    int32_t end[BS * IPT];  // tile-local row ends
-    A prod[BS * IPT];       // rounded products of the tile's nonzeros
-    int32_t crow[BS];       // per-thread carry row
-    A cval[BS];             // per-thread carry value
+    static constexpr int L = BS * IPT;
+    static constexpr int STEP = BS * merge_vec<S>();
+    static constexpr int SPAN = (L / STEP + 1) * STEP;  // aligned window over the tile's nonzeros
+    alignas(16) A prod[SPAN];         // products, then their segmented prefix sums
+    alignas(16) uint8_t head[L + BS]; // 1 where a row starts inside the tile; [L, L+BS) dummies
 };
 
 // Tile t: rows i0 = tile_i[t] .. i1 = tile_i[t+1] end inside it; nonzeros
-// j0 = tile_j[t] .. j1 = tile_j[t+1] - 1 belong to it. BS = 64 threads,
-// L = BS * IPT.
-template <int S, int IPT, bool NT, class LDS>
+// j0 = tile_j[t] .. j1 = tile_j[t+1] - 1 belong to it. One wave of BS = 64
+// lanes, L = BS * IPT path items.
+//
+// The tile is reduced as a segmented scan over its nonzeros, with a segment
+// starting at every row end that falls inside the tile:
+//  1. the tile's nonzeros are streamed with aligned vector loads (every lane
+//     issues all of its loads before the first use), x is gathered and the
+//     products are written to LDS at their position in the aligned window;
+//  2. the row ends mark segment heads in a byte map;
+//  3. lane l scans positions [l*IPT, (l+1)*IPT) in registers, the lanes are
+//     joined by a log-step segmented scan across the wave, and the inclusive
+//     segment sums go back to LDS;
+//  4. row r of the tile reads the sum at its last nonzero (coalesced y
+//     stores); the segment still open at the tile end is the tile's carry.
+// Every sum has a fixed order, so results are deterministic. The first row
+// of the tile may have begun in an earlier tile: it gets this tile's part
+// here, and merge_fixup_tile adds the earlier tiles' carries.
+template <int S, int IPT, bool NT, class LDS, bool X32 = false>
 __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict__ rp,
                                            const int32_t *__restrict__ col,
                                            const typename St<S>::V *__restrict__ val,
@@ -35,127 +95,153 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
     using V = typename St<S>::V;
     using X = typename St<S>::X;
     using A = typename St<S>::A;
-    constexpr int VEC = (S == CSR_VAL_F64) ? 2 : 4;  // elements per vector load (8..16 bytes)
+    constexpr int VEC = merge_vec<S>();
     using VV = typename VecOf<V, VEC>::type;
     using IV = typename VecOf<int32_t, VEC>::type;
+    using AV = typename VecOf<A, VEC>::type;
     constexpr int BS = kMergeBlock;
     constexpr int L = BS * IPT;
-    int32_t *s_end = lds.end;
+    constexpr int STEP = BS * VEC;
+    constexpr int NIT = L / STEP + 1;
+    static_assert(IPT % 4 == 0, "head bytes are cleared and read as 32-bit words");
     A *s_prod = lds.prod;
-    int32_t *s_crow = lds.crow;
-    A *s_cval = lds.cval;
+    uint8_t *s_head = lds.head;
 
     const int tid = threadIdx.x;
     const int32_t i0 = tile_i[t], i1 = tile_i[t + 1];
     const int32_t j0 = tile_j[t], j1 = tile_j[t + 1];
-    const int nre = i1 - i0;   // rows whose end lies in this tile
-    const int nnz_t = j1 - j0; // nonzeros of this tile
+    const int nre = i1 - i0;    // rows whose end lies in this tile (<= L)
+    const int nnz_t = j1 - j0;  // nonzeros of this tile (<= L)
+    const int32_t a = j0 & ~(VEC - 1);
+    const int off = j0 - a;     // window position of the tile's first nonzero
+    const int32_t last_end = rp[i1] - j0;  // end of the last row ending here (<= 0 if none)
 
-    // 1. the row ends of the rows finishing in the tile (k < nre <= L, so
-    //    IPT per thread) and the start of the first row: loads issued now,
-    //    written to LDS only after the nonzero loads below are in flight
+    // row ends of the tile's rows: row r = tid + q * BS (only the first
+    // ceil(nre / BS) groups exist; the guards are wave-uniform)
+    // (global; made tile-local where used, after the nonzero loads are issued)
+    const int32_t *rb = rp + i0;
     int32_t re[IPT];
+    if (nre <= BS) {  // the common case: one row per lane at most
+        re[0] = rb[min(tid + 1, nre)];
 #pragma unroll
-    for (int q = 0; q < IPT; ++q) re[q] = rp[min(i0 + tid + q * BS + 1, i1)];
-    const int32_t rs_first = rp[i0] - j0;  // start of row i0 (local), <= 0
+        for (int q = 1; q < IPT; ++q) re[q] = 0;
+    } else {
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) re[q] = rb[min(tid + q * BS + 1, nre)];
+    }
 
-    // 2. products, with aligned vector loads covering [j0, j1). Addresses are
-    //    clamped to the last needed vector so that every load can be issued
-    //    unconditionally (all of them in flight before the first use); lanes
-    //    outside [j0, j1) gather x[0] and discard the product.
+    // 1. products over the aligned window [a, alast + VEC) that covers the
+    //    tile's nonzeros. Every load is issued before the first use, from a
+    //    wave-uniform base; lanes past the window load its last vector again
+    //    (same cache lines, same x entries). Window positions outside
+    //    [j0, j1) hold real nonzeros of the neighbouring tiles (valid
+    //    columns); their products are never read into a row or carry sum, so
+    //    they need no masking.
     if (nnz_t > 0) {
-        constexpr int STEP = BS * VEC;
-        constexpr int NIT = L / STEP + 1;
-        const int32_t a = j0 & ~(VEC - 1);
-        const int32_t alast = (j1 - 1) & ~(VEC - 1);
+        // last vector, window-relative (>= 0, < L + VEC)
+        const uint32_t span = (uint32_t)(((j1 - 1) & ~(VEC - 1)) - a);
+        const char *vb = reinterpret_cast<const char *>(val + a);
+        const char *cb = reinterpret_cast<const char *>(col + a);
         VV vv[NIT];
         IV cv[NIT];
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int32_t kc = min(a + it * STEP + tid * VEC, alast);
-            vv[it] = ld<NT>(reinterpret_cast<const VV *>(val + kc));
-            cv[it] = ld<NT>(reinterpret_cast<const IV *>(col + kc));
+            const uint32_t o = min((uint32_t)(it * STEP + tid * VEC), span);
+            vv[it] = ld<NT>(reinterpret_cast<const VV *>(vb + o * (uint32_t)sizeof(V)));
+            cv[it] = ld<NT>(reinterpret_cast<const IV *>(cb + o * (uint32_t)sizeof(int32_t)));
         }
         X xs[NIT][VEC];
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
-                const int32_t k = a + it * STEP + tid * VEC + e;
-                const bool ok = k >= j0 && k < j1;
-                xs[it][e] = x[ok ? cv[it][e] : 0];
+                if constexpr (X32)  // x spans < 4 GiB: 32-bit byte offsets
+                    xs[it][e] = *reinterpret_cast<const X *>(
+                        reinterpret_cast<const char *>(x) + (uint32_t)cv[it][e] * (uint32_t)sizeof(X));
+                else
+                    xs[it][e] = x[cv[it][e]];
             }
         }
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
+            AV pv;
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                const int32_t k = a + it * STEP + tid * VEC + e;
-                if (k >= j0 && k < j1) s_prod[k - j0] = St<S>::cvt(vv[it][e]) * (A)xs[it][e];
-            }
+            for (int e = 0; e < VEC; ++e) pv[e] = St<S>::cvt(vv[it][e]) * (A)xs[it][e];
+            *reinterpret_cast<AV *>(s_prod + it * STEP + tid * VEC) = pv;
         }
     }
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) re[q] -= j0;
+    // 2. segment heads: clear, then mark the end of every row ending inside
+    //    the nonzero range (lanes with nothing to mark write their dummy)
+#pragma unroll
+    for (int w = 0; w < IPT / 4; ++w) reinterpret_cast<uint32_t *>(s_head)[tid * (IPT / 4) + w] = 0;
+    wave_lds_sync();
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-        const int k = tid + q * BS;
-        if (k < nre) s_end[k] = re[q] - j0;
-    }
-    __syncthreads();
-
-    // 3. walk this thread's IPT path items
-    const int total = nre + nnz_t;
-    const int d0 = min(tid * IPT, total);
-    const int d1 = min(d0 + IPT, total);
-    int lo = max(0, d0 - nnz_t), hi = min(d0, nre);
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (s_end[mid] + mid < d0) lo = mid + 1;
-        else hi = mid;
-    }
-    int ri = lo, nj = d0 - lo;
-    const int ri0 = ri, nj0 = nj;
-    A acc = A(0);
-    bool open = false;  // first emitted row started before this thread
-    A open_val = A(0);
-    for (int d = d0; d < d1; ++d) {
-        if (ri < nre && nj >= s_end[ri]) {
-            const int rs = ri == 0 ? rs_first : s_end[ri - 1];  // row start (local)
-            if (ri == ri0 && rs < nj0) {
-                open = true;
-                open_val = acc;
-            } else {
-                y[i0 + ri] = (X)acc;
-            }
-            acc = A(0);
-            ++ri;
-        } else {
-            acc += s_prod[nj];
-            ++nj;
+        if (q * BS < nre) {
+            const bool mark = tid + q * BS < nre && re[q] < nnz_t;
+            s_head[mark ? re[q] : L + tid] = 1;
         }
     }
-    s_crow[tid] = ri;
-    s_cval[tid] = acc;
-    __syncthreads();
+    wave_lds_sync();
 
-    // 4a. a row opened by earlier threads: their carries (in thread order), then ours
-    if (open) {
-        int ta = tid;
-        while (ta > 0 && s_crow[ta - 1] == ri0) --ta;
-        A sum = A(0);
-        for (int q = ta; q < tid; ++q) sum += s_cval[q];
-        sum += open_val;
-        // For the tile's first row begun in an earlier tile this is only the
-        // tile's part; the fixup adds the earlier tiles' carries.
-        y[i0 + ri0] = (X)sum;
+    // 3. segmented inclusive scan of positions [tid*IPT, (tid+1)*IPT)
+    const int base = tid * IPT;
+    A run = A(0);
+    bool seen = false;
+    A loc[IPT];
+    bool pre[IPT];  // position lies before the lane's first head
+#pragma unroll
+    for (int w = 0; w < IPT / 4; ++w) {
+        const uint32_t hw = reinterpret_cast<const uint32_t *>(s_head)[tid * (IPT / 4) + w];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int q = w * 4 + b;
+            const A p = s_prod[off + base + q];
+            const bool h = (hw >> (8 * b)) & 0xFFu;
+            run = h ? p : run + p;
+            seen = seen || h;
+            loc[q] = run;
+            pre[q] = !seen;
+        }
     }
-    // 4b. the row still open at the tile end leaves a carry for later tiles
-    if (tid == BS - 1 && i1 < n_rows) {
-        int tb = BS;
-        while (tb > 0 && s_crow[tb - 1] == nre) --tb;
-        A sum = A(0);
-        for (int q = tb; q < BS; ++q) sum += s_cval[q];
-        carry[t] = sum;
+    // join the lanes: inclusive segmented scan of the lanes' (tail, head)
+    // pairs, within rows of 16 lanes, then across rows; cin = the exclusive
+    // value (lane 0 gets 0)
+    A v = run;
+    int hv = seen;
+    seg_step<kDppRowShr + 1, 0xF>(v, hv);
+    seg_step<kDppRowShr + 2, 0xF>(v, hv);
+    seg_step<kDppRowShr + 4, 0xF>(v, hv);
+    seg_step<kDppRowShr + 8, 0xF>(v, hv);
+    seg_step<kDppRowBcast15, 0xA>(v, hv);
+    seg_step<kDppRowBcast31, 0xC>(v, hv);
+    const A cin = dpp_move<kDppWaveShr1, 0xF>(v);
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) s_prod[off + base + q] = pre[q] ? cin + loc[q] : loc[q];
+    wave_lds_sync();
+
+    // 4. rows: y = segment sum at the row's last nonzero, 0 for a row with no
+    //    nonzeros in this tile
+    X *yb = y + i0;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        if (q * BS < nre) {
+            const int r = tid + q * BS;
+            int32_t prev = dpp_move<kDppWaveShr1, 0xF>(re[q]);  // end of row r - 1
+            if (q > 0) {
+                const int32_t wrap = __builtin_amdgcn_readlane(re[q - 1], BS - 1);
+                if (tid == 0) prev = wrap;
+            }
+            const int32_t start = r == 0 ? 0 : prev;
+            const A sum = s_prod[off + max(re[q] - 1, 0)];
+            if (r < nre) yb[r] = re[q] > start ? (X)sum : X(0);
+        }
     }
+    // the segment open at the tile end leaves a carry for later tiles
+    if (tid == 0 && i1 < n_rows)
+        carry[t] = nnz_t > max(last_end, 0) ? s_prod[off + nnz_t - 1] : A(0);
 }
 
 // Rows spanning tiles: y[r] = (carries of the tiles that ended inside row r,
