@@ -9,6 +9,11 @@
 namespace csr {
 
 template <class T, int N> struct VecOf { typedef T type __attribute__((ext_vector_type(N))); };
+// The same vector with only the element's alignment (for loads at any
+// element index; the device runs in unaligned-access mode).
+template <class T, int N> struct VecOfU {
+    typedef T type __attribute__((ext_vector_type(N), aligned(sizeof(T))));
+};
 
 // Orders the LDS accesses of the lanes of one wave. A wave's LDS operations
 // complete in issue order, so no wait is needed: only fences that keep the
@@ -59,8 +64,8 @@ template <int S, int IPT> struct MergeLds {
     static constexpr int BS = kMergeBlock;
     static constexpr int L = BS * IPT;
     static constexpr int STEP = BS * merge_vec<S>();
-    static constexpr int SPAN = (L / STEP + 1) * STEP;  // aligned window over the tile's nonzeros
-    alignas(16) A prod[SPAN];         // products, then their segmented prefix sums
+    static_assert(L % STEP == 0, "a tile is a whole number of load blocks");
+    alignas(16) A prod[L];            // products, then their segmented prefix sums
     alignas(16) uint8_t head[L + BS]; // 1 where a row starts inside the tile; [L, L+BS) dummies
 };
 
@@ -70,108 +75,158 @@ template <int S, int IPT> struct MergeLds {
 //
 // The tile is reduced as a segmented scan over its nonzeros, with a segment
 // starting at every row end that falls inside the tile:
-//  1. the tile's nonzeros are streamed with aligned vector loads (every lane
-//     issues all of its loads before the first use), x is gathered and the
-//     products are written to LDS at their position in the aligned window;
-//  2. the row ends mark segment heads in a byte map;
-//  3. lane l scans positions [l*IPT, (l+1)*IPT) in registers, the lanes are
-//     joined by a log-step segmented scan across the wave, and the inclusive
-//     segment sums go back to LDS;
-//  4. row r of the tile reads the sum at its last nonzero (coalesced y
-//     stores); the segment still open at the tile end is the tile's carry.
+//  1. (merge_issue) the tile's nonzeros are streamed with vector
+//     loads, and the row ends of its rows are loaded; every load is issued
+//     before the first use;
+//  2. (merge_gather) x is gathered at the loaded columns;
+//  3. (merge_finish) the products are written to LDS at their position in
+//     the tile's window; the row ends mark segment heads in a byte map;
+//     lane l scans positions [l*IPT, (l+1)*IPT) in registers, the lanes are
+//     joined by a segmented scan across the wave, and the inclusive segment
+//     sums go back to LDS; row r of the tile reads the sum at its last
+//     nonzero (coalesced y stores), and the segment still open at the tile
+//     end is the tile's carry.
 // Every sum has a fixed order, so results are deterministic. The first row
 // of the tile may have begun in an earlier tile: it gets this tile's part
 // here, and merge_fixup_tile adds the earlier tiles' carries.
-template <int S, int IPT, bool NT, class LDS, bool X32 = false>
-__device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict__ rp,
-                                           const int32_t *__restrict__ col,
-                                           const typename St<S>::V *__restrict__ val,
-                                           const typename St<S>::X *__restrict__ x,
-                                           typename St<S>::X *__restrict__ y,
-                                           const int32_t *__restrict__ tile_i,
-                                           const int32_t *__restrict__ tile_j,
-                                           typename St<S>::A *__restrict__ carry, int32_t n_rows,
-                                           LDS &lds) {
+
+// What a lane holds for one tile between issuing its loads and reducing it.
+template <int S, int IPT> struct MergeTileRegs {
     using V = typename St<S>::V;
+    static constexpr int VEC = merge_vec<S>();
+    static constexpr int NIT = IPT / VEC;  // load blocks of STEP = BS * VEC elements
+    using VV = typename VecOfU<V, VEC>::type;
+    using IV = typename VecOfU<int32_t, VEC>::type;
+    int32_t i0, i1, j0, j1;  // the tile's bounds (wave-uniform)
+    int32_t last_end;        // rp[i1]: end of the last row ending in the tile
+    int32_t re[IPT];         // rp[i0 + r + 1] for rows r = lane + q * BS (clamped; only
+                             // the first ceil((i1 - i0) / BS) entries are loaded)
+    VV vv[NIT];              // values of the tile's window
+    IV cv[NIT];              // columns of the tile's window
+};
+
+// Stage 1: issue the tile's loads. The window [j0, j0 + L) starts at the
+// tile's first nonzero and is read in NIT blocks of BS vectors (at element
+// alignment); lanes past the last vector that holds tile nonzeros load that
+// vector again (same cache lines, same x entries), so at most VEC - 1
+// elements past j1 are read: a neighbouring tile's or the tail padding. A
+// tile without nonzeros loads the vector at j0. Row ends first (their count
+// depends on the tile), then columns (needed first), then values, so that
+// the wait for each column vector is a fixed count.
+template <int S, int IPT, bool NT>
+__device__ __forceinline__ void merge_issue(int64_t t, const int32_t *__restrict__ rp,
+                                            const int32_t *__restrict__ col,
+                                            const typename St<S>::V *__restrict__ val,
+                                            const int32_t *__restrict__ tile_i,
+                                            const int32_t *__restrict__ tile_j,
+                                            MergeTileRegs<S, IPT> &R) {
+    using Rg = MergeTileRegs<S, IPT>;
+    using V = typename St<S>::V;
+    constexpr int VEC = Rg::VEC, NIT = Rg::NIT;
+    constexpr int BS = kMergeBlock;
+    constexpr int STEP = BS * VEC;
+    const int tid = threadIdx.x;
+    R.i0 = tile_i[t];
+    R.i1 = tile_i[t + 1];
+    R.j0 = tile_j[t];
+    R.j1 = tile_j[t + 1];
+    const int32_t a = R.j0;
+    // start of the last vector that holds tile nonzeros, window-relative
+    // (a multiple of VEC, so a clamped lane never loads a tile position that
+    // another lane owns at a different place)
+    const uint32_t span = R.j1 > R.j0 ? (uint32_t)((R.j1 - 1 - R.j0) & ~(VEC - 1)) : 0u;
+    // row ends: one load per lane when the tile ends at most BS rows (the
+    // common case), else IPT (entries past the tile's rows are never used)
+    const uint32_t nre = (uint32_t)(R.i1 - R.i0);
+    const char *rb = reinterpret_cast<const char *>(rp + R.i0);
+    auto row_end = [&](int q) {
+        return *reinterpret_cast<const int32_t *>(
+            rb + min((uint32_t)(tid + q * BS + 1), nre) * (uint32_t)sizeof(int32_t));
+    };
+    if (nre <= (uint32_t)BS) {
+        R.re[0] = row_end(0);
+#pragma unroll
+        for (int q = 1; q < IPT; ++q) R.re[q] = 0;
+    } else {
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) R.re[q] = row_end(q);
+    }
+    const char *vb = reinterpret_cast<const char *>(val + a);
+    const char *cb = reinterpret_cast<const char *>(col + a);
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const uint32_t o = min((uint32_t)(it * STEP + tid * VEC), span);
+        R.cv[it] = ld<NT>(reinterpret_cast<const typename Rg::IV *>(cb + o * (uint32_t)sizeof(int32_t)));
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const uint32_t o = min((uint32_t)(it * STEP + tid * VEC), span);
+        R.vv[it] = ld<NT>(reinterpret_cast<const typename Rg::VV *>(vb + o * (uint32_t)sizeof(V)));
+    }
+    R.last_end = rp[R.i1];
+}
+
+// Stage 2: gather x at the window's columns (all valid: the window holds
+// real nonzeros of this tile or its neighbours, or zeroed padding).
+template <int S, int IPT, bool X32>
+__device__ __forceinline__ void merge_gather(const MergeTileRegs<S, IPT> &R,
+                                             const typename St<S>::X *__restrict__ x,
+                                             typename St<S>::X (&xs)[MergeTileRegs<S, IPT>::NIT]
+                                                                   [MergeTileRegs<S, IPT>::VEC]) {
+    using X = typename St<S>::X;
+    constexpr int VEC = MergeTileRegs<S, IPT>::VEC, NIT = MergeTileRegs<S, IPT>::NIT;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            if constexpr (X32)  // x spans < 4 GiB: 32-bit byte offsets
+                xs[it][e] = *reinterpret_cast<const X *>(reinterpret_cast<const char *>(x) +
+                                                         (uint32_t)R.cv[it][e] * (uint32_t)sizeof(X));
+            else
+                xs[it][e] = x[R.cv[it][e]];
+        }
+    }
+}
+
+// Stage 3: products, segmented scan, rows and carry.
+template <int S, int IPT, class LDS>
+__device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT> &R,
+                                             const typename St<S>::X (&xs)[MergeTileRegs<S, IPT>::NIT]
+                                                                          [MergeTileRegs<S, IPT>::VEC],
+                                             typename St<S>::X *__restrict__ y,
+                                             typename St<S>::A *__restrict__ carry,
+                                             int32_t n_rows, LDS &lds) {
     using X = typename St<S>::X;
     using A = typename St<S>::A;
-    constexpr int VEC = merge_vec<S>();
-    using VV = typename VecOf<V, VEC>::type;
-    using IV = typename VecOf<int32_t, VEC>::type;
+    constexpr int VEC = MergeTileRegs<S, IPT>::VEC, NIT = MergeTileRegs<S, IPT>::NIT;
     using AV = typename VecOf<A, VEC>::type;
     constexpr int BS = kMergeBlock;
     constexpr int L = BS * IPT;
     constexpr int STEP = BS * VEC;
-    constexpr int NIT = L / STEP + 1;
     static_assert(IPT % 4 == 0, "head bytes are cleared and read as 32-bit words");
     A *s_prod = lds.prod;
     uint8_t *s_head = lds.head;
-
     const int tid = threadIdx.x;
-    const int32_t i0 = tile_i[t], i1 = tile_i[t + 1];
-    const int32_t j0 = tile_j[t], j1 = tile_j[t + 1];
-    const int nre = i1 - i0;    // rows whose end lies in this tile (<= L)
-    const int nnz_t = j1 - j0;  // nonzeros of this tile (<= L)
-    const int32_t a = j0 & ~(VEC - 1);
-    const int off = j0 - a;     // window position of the tile's first nonzero
-    const int32_t last_end = rp[i1] - j0;  // end of the last row ending here (<= 0 if none)
+    const int32_t i0 = R.i0, j0 = R.j0;
+    const int nre = R.i1 - i0;     // rows whose end lies in this tile (<= L)
+    const int nnz_t = R.j1 - j0;   // nonzeros of this tile (<= L)
+    constexpr int off = 0;  // window position of the tile's first nonzero
+    const int32_t last_end = R.last_end - j0;  // <= 0 if no row ends in the tile
 
-    // row ends of the tile's rows: row r = tid + q * BS (only the first
-    // ceil(nre / BS) groups exist; the guards are wave-uniform)
-    // (global; made tile-local where used, after the nonzero loads are issued)
-    const int32_t *rb = rp + i0;
-    int32_t re[IPT];
-    if (nre <= BS) {  // the common case: one row per lane at most
-        re[0] = rb[min(tid + 1, nre)];
+    // 1. products to LDS (positions outside [j0, j1) are never read into a
+    //    row or carry sum, so they need no masking; a tile without nonzeros
+    //    writes products nobody reads)
 #pragma unroll
-        for (int q = 1; q < IPT; ++q) re[q] = 0;
-    } else {
+    for (int it = 0; it < NIT; ++it) {
+        AV pv;
 #pragma unroll
-        for (int q = 0; q < IPT; ++q) re[q] = rb[min(tid + q * BS + 1, nre)];
+        for (int e = 0; e < VEC; ++e) pv[e] = St<S>::cvt(R.vv[it][e]) * (A)xs[it][e];
+        *reinterpret_cast<AV *>(s_prod + it * STEP + tid * VEC) = pv;
     }
+    int32_t re[IPT];  // tile-local row ends
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) re[q] = R.re[q] - j0;
 
-    // 1. products over the aligned window [a, alast + VEC) that covers the
-    //    tile's nonzeros. Every load is issued before the first use, from a
-    //    wave-uniform base; lanes past the window load its last vector again
-    //    (same cache lines, same x entries). Window positions outside
-    //    [j0, j1) hold real nonzeros of the neighbouring tiles (valid
-    //    columns); their products are never read into a row or carry sum, so
-    //    they need no masking.
-    if (nnz_t > 0) {
-        // last vector, window-relative (>= 0, < L + VEC)
-        const uint32_t span = (uint32_t)(((j1 - 1) & ~(VEC - 1)) - a);
-        const char *vb = reinterpret_cast<const char *>(val + a);
-        const char *cb = reinterpret_cast<const char *>(col + a);
-        VV vv[NIT];
-        IV cv[NIT];
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const uint32_t o = min((uint32_t)(it * STEP + tid * VEC), span);
-            vv[it] = ld<NT>(reinterpret_cast<const VV *>(vb + o * (uint32_t)sizeof(V)));
-            cv[it] = ld<NT>(reinterpret_cast<const IV *>(cb + o * (uint32_t)sizeof(int32_t)));
-        }
-        X xs[NIT][VEC];
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                if constexpr (X32)  // x spans < 4 GiB: 32-bit byte offsets
-                    xs[it][e] = *reinterpret_cast<const X *>(
-                        reinterpret_cast<const char *>(x) + (uint32_t)cv[it][e] * (uint32_t)sizeof(X));
-                else
-                    xs[it][e] = x[cv[it][e]];
-            }
-        }
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            AV pv;
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) pv[e] = St<S>::cvt(vv[it][e]) * (A)xs[it][e];
-            *reinterpret_cast<AV *>(s_prod + it * STEP + tid * VEC) = pv;
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < IPT; ++q) re[q] -= j0;
     // 2. segment heads: clear, then mark the end of every row ending inside
     //    the nonzero range (lanes with nothing to mark write their dummy)
 #pragma unroll
@@ -240,8 +295,26 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
         }
     }
     // the segment open at the tile end leaves a carry for later tiles
-    if (tid == 0 && i1 < n_rows)
+    if (tid == 0 && R.i1 < n_rows)
         carry[t] = nnz_t > max(last_end, 0) ? s_prod[off + nnz_t - 1] : A(0);
+}
+
+// One tile, start to end.
+template <int S, int IPT, bool NT, class LDS, bool X32 = false>
+__device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict__ rp,
+                                           const int32_t *__restrict__ col,
+                                           const typename St<S>::V *__restrict__ val,
+                                           const typename St<S>::X *__restrict__ x,
+                                           typename St<S>::X *__restrict__ y,
+                                           const int32_t *__restrict__ tile_i,
+                                           const int32_t *__restrict__ tile_j,
+                                           typename St<S>::A *__restrict__ carry, int32_t n_rows,
+                                           LDS &lds) {
+    MergeTileRegs<S, IPT> R;
+    merge_issue<S, IPT, NT>(t, rp, col, val, tile_i, tile_j, R);
+    typename St<S>::X xs[MergeTileRegs<S, IPT>::NIT][MergeTileRegs<S, IPT>::VEC];
+    merge_gather<S, IPT, X32>(R, x, xs);
+    merge_finish<S, IPT>(t, R, xs, y, carry, n_rows, lds);
 }
 
 // Rows spanning tiles: y[r] = (carries of the tiles that ended inside row r,
