@@ -56,6 +56,31 @@ template <int CTRL, int ROWS, class A> __device__ __forceinline__ void seg_step(
     h |= hu;
 }
 
+// Raw buffer loads through a per-tile range: a lane whose offset lies past
+// the range reads zeros and makes no memory access, so windows need no
+// address clamping, and constant block offsets fold into the instruction.
+constexpr int kBufferWord3 = 0x00020000;  // raw buffer, 32-bit dwords (GFX9 family)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_range(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             kBufferWord3);
+}
+template <class T, bool NT>
+__device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    constexpr int aux = NT ? 2 : 0;  // non-temporal
+    if constexpr (sizeof(T) == 16)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, aux));
+    else if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, aux));
+    else if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, aux));
+    else {
+        static_assert(sizeof(T) == 2, "2, 4, 8 or 16 bytes");
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, aux));
+    }
+}
+
+
+
 // Elements per vector load of the value stream (8..16 bytes per lane).
 template <int S> constexpr int merge_vec() { return S == CSR_VAL_F64 ? 2 : 4; }
 
@@ -99,18 +124,19 @@ template <int S, int IPT> struct MergeTileRegs {
     using IV = typename VecOfU<int32_t, VEC>::type;
     int32_t i0, i1, j0, j1;  // the tile's bounds (wave-uniform)
     int32_t last_end;        // rp[i1]: end of the last row ending in the tile
-    int32_t re[IPT];         // rp[i0 + r + 1] for rows r = lane + q * BS (clamped; only
-                             // the first ceil((i1 - i0) / BS) entries are loaded)
+    int32_t re[IPT];         // rp[i0 + r + 1] for rows r = lane + q * BS (0 past the
+                             // tile's rows; only ceil((i1 - i0) / BS) entries loaded)
     VV vv[NIT];              // values of the tile's window
     IV cv[NIT];              // columns of the tile's window
 };
 
 // Stage 1: issue the tile's loads. The window [j0, j0 + L) starts at the
 // tile's first nonzero and is read in NIT blocks of BS vectors (at element
-// alignment); lanes past the last vector that holds tile nonzeros load that
-// vector again (same cache lines, same x entries), so at most VEC - 1
-// elements past j1 are read: a neighbouring tile's or the tail padding. A
-// tile without nonzeros loads the vector at j0. Row ends first (their count
+// alignment) through a buffer range that ends with the last vector holding
+// tile nonzeros: lanes past it read zeros (column 0, value 0) without a
+// memory access, and the last vector reads at most VEC - 1 elements past
+// j1, a neighbouring tile's or the tail padding. Row ends are read through
+// a range holding exactly the tile's rows. Row ends first (their count
 // depends on the tile), then columns (needed first), then values, so that
 // the wait for each column vector is a fixed count.
 template <int S, int IPT, bool NT>
@@ -125,44 +151,37 @@ __device__ __forceinline__ void merge_issue(int64_t t, const int32_t *__restrict
     constexpr int VEC = Rg::VEC, NIT = Rg::NIT;
     constexpr int BS = kMergeBlock;
     constexpr int STEP = BS * VEC;
-    const int tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
     R.i0 = tile_i[t];
     R.i1 = tile_i[t + 1];
     R.j0 = tile_j[t];
     R.j1 = tile_j[t + 1];
-    const int32_t a = R.j0;
-    // start of the last vector that holds tile nonzeros, window-relative
-    // (a multiple of VEC, so a clamped lane never loads a tile position that
-    // another lane owns at a different place)
-    const uint32_t span = R.j1 > R.j0 ? (uint32_t)((R.j1 - 1 - R.j0) & ~(VEC - 1)) : 0u;
-    // row ends: one load per lane when the tile ends at most BS rows (the
-    // common case), else IPT (entries past the tile's rows are never used)
+    // elements of the window up to the end of the last vector holding tile
+    // nonzeros (a multiple of VEC; 0 for a tile without nonzeros)
+    const uint32_t nwin = R.j1 > R.j0 ? ((uint32_t)(R.j1 - 1 - R.j0) & ~(uint32_t)(VEC - 1)) + VEC : 0u;
+    // row ends rp[i0 + 1 .. i1]: one load per lane when the tile ends at
+    // most BS rows (the common case), else IPT (zeros past the tile's rows)
     const uint32_t nre = (uint32_t)(R.i1 - R.i0);
-    const char *rb = reinterpret_cast<const char *>(rp + R.i0);
-    auto row_end = [&](int q) {
-        return *reinterpret_cast<const int32_t *>(
-            rb + min((uint32_t)(tid + q * BS + 1), nre) * (uint32_t)sizeof(int32_t));
-    };
+    const auto rr = buffer_range(rp + R.i0 + 1, nre * (uint32_t)sizeof(int32_t));
     if (nre <= (uint32_t)BS) {
-        R.re[0] = row_end(0);
+        R.re[0] = buffer_load<int32_t, false>(rr, tid * 4u, 0u);
 #pragma unroll
         for (int q = 1; q < IPT; ++q) R.re[q] = 0;
     } else {
 #pragma unroll
-        for (int q = 0; q < IPT; ++q) R.re[q] = row_end(q);
+        for (int q = 0; q < IPT; ++q)
+            R.re[q] = buffer_load<int32_t, false>(rr, tid * 4u, (uint32_t)(q * BS * 4));
     }
-    const char *vb = reinterpret_cast<const char *>(val + a);
-    const char *cb = reinterpret_cast<const char *>(col + a);
+    const auto rc = buffer_range(col + R.j0, nwin * (uint32_t)sizeof(int32_t));
+    const auto rv = buffer_range(val + R.j0, nwin * (uint32_t)sizeof(V));
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const uint32_t o = min((uint32_t)(it * STEP + tid * VEC), span);
-        R.cv[it] = ld<NT>(reinterpret_cast<const typename Rg::IV *>(cb + o * (uint32_t)sizeof(int32_t)));
-    }
+    for (int it = 0; it < NIT; ++it)
+        R.cv[it] = buffer_load<typename Rg::IV, NT>(rc, tid * (uint32_t)(VEC * sizeof(int32_t)),
+                                                   (uint32_t)(it * STEP * sizeof(int32_t)));
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const uint32_t o = min((uint32_t)(it * STEP + tid * VEC), span);
-        R.vv[it] = ld<NT>(reinterpret_cast<const typename Rg::VV *>(vb + o * (uint32_t)sizeof(V)));
-    }
+    for (int it = 0; it < NIT; ++it)
+        R.vv[it] = buffer_load<typename Rg::VV, NT>(rv, tid * (uint32_t)(VEC * sizeof(V)),
+                                                   (uint32_t)(it * STEP * sizeof(V)));
     R.last_end = rp[R.i1];
 }
 
