@@ -1,0 +1,85 @@
+"""Full-size parity at the benchmark configurations, in the launch
+configurations the benchmark times:
+
+  C1  2-D 5-point Laplacian 100^2 (cache-resident, launch bound)
+  C2  27-point stencil on 128^3 (HBM bound, the headline workload)
+  C3a R-MAT scale 22, edge factor 16 (skewed rows: merge path, long rows)
+  C3b uniform random 2^20 x 16 (gather bound)
+  C4  FP32 / BF16 value storage of C1 and C2
+
+Each case runs the learned and the profile-guided selection (Sec. III-E,
+IV) and every merge-path tile size, and compares every row with the oracle
+(FP64: |y - y_acc| <= 1e-12 (|A||x|)_i against the compensated product;
+FP32/BF16: the gamma bound of the stored values)."""
+import os
+
+import pytest
+import torch
+
+import oracle
+import paper_1711_05487_amd as pkg
+from paper_1711_05487_amd import learn
+from spmv_cases import check_f64, check_reduced, matrix, xvec
+
+pytestmark = pytest.mark.gpu
+
+CONFIGS = ["lap100", "st27_128", "rmat22", "unif20"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def learned_model():
+    assert os.path.exists(learn.WEIGHTS), "the committed selector model is missing"
+    learn.install()
+    yield
+
+
+def spmv(A, x):
+    y = A.spmv(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+@pytest.mark.parametrize("mode", ["learned", "profile"])
+@pytest.mark.parametrize("name", CONFIGS)
+def test_selected_plan_full_size(name, mode):
+    n, m, rp, col, val = matrix(name)
+    x = xvec(name, m)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    info = A.select(mode)
+    assert not info["fallback"]
+    check_f64(spmv(A, x), rp, col, val, x, f"{name} {mode} opts={info['opts']}")
+    A.close()
+
+
+@pytest.mark.parametrize("name", ["st27_128", "rmat22", "unif20"])
+def test_merge_tile_sizes_full_size(name):
+    n, m, rp, col, val = matrix(name)
+    x = xvec(name, m)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    for L in (256, 512, 1024):
+        A.select("forced", forced_opts=pkg.OPT_MERGE | pkg.OPT_PREFETCH, merge_items=L)
+        check_f64(spmv(A, x), rp, col, val, x, f"{name} merge L={L}")
+    A.close()
+
+
+def test_long_row_decomposition_rmat22():
+    n, m, rp, col, val = matrix("rmat22")
+    x = xvec("rmat22", m)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    info = A.select("forced", forced_opts=pkg.OPT_DECOMP)
+    assert info["n_long_rows"] > 0
+    check_f64(spmv(A, x), rp, col, val, x, "rmat22 decomposition")
+    A.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("name", ["lap100", "st27_128"])
+def test_reduced_precision_full_size(name, storage):
+    n, m, rp, col, val = matrix(name)
+    x = xvec(name, m)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m, storage=storage)
+    for mode in ("learned", "plain"):
+        A.select(mode)
+        y = spmv(A, oracle.to_f32(x))
+        check_reduced(y, rp, col, val, x, storage, f"{name} {storage} {mode}")
+    A.close()
