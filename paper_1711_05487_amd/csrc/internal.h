@@ -108,7 +108,7 @@ struct csr_matrix_s {
     int has_features = 0;
     csr_features_t feat{};
     csr::DevBuf scratch_x, scratch_y, scratch_col;  // selection probes
-    csr::DevBuf feat_parts, feat_reuse;             // feature-extraction partials
+    csr::DevBuf feat_parts, feat_reuse, feat_long;  // feature-extraction partials, long rows
     double t_inspect_ms = 0.0;
 };
 
@@ -166,8 +166,15 @@ struct FeatPart {
 };
 int32_t features_partials(int32_t n_rows, int G);
 int32_t xreuse_samples(int32_t n_rows);
-hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int G,
-                           FeatPart *parts, int32_t n_parts, int32_t *reuse_out, hipStream_t s);
+// Rows longer than this are reduced by a whole workgroup each (not by the
+// G lanes of the sweep); at most this many of them fit in nnz entries.
+int32_t features_long_row(int G);
+int64_t features_long_capacity(int64_t nnz, int G);
+// parts: n_parts + long capacity entries; long_list: long capacity + 1 ints.
+// Synchronizes the stream once (the long rows are sorted on the host).
+hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int64_t nnz,
+                           int G, FeatPart *parts, int32_t n_parts, int32_t *long_list,
+                           int32_t *reuse_out, hipStream_t s);
 
 hipError_t launch_long_s0(const int32_t *col, const void *val, const void *x, void *y,
                           const int32_t *chunk_beg, void *part, int64_t n_chunks,

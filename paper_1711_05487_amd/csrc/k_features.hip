@@ -6,12 +6,17 @@
 // ngroups_i = maximal runs of consecutive columns; scatter_i = nnz_i /
 // max(bw_i, 1) and clustering_i = ngroups_i / nnz_i (both 0 for an empty row).
 //
-// G lanes share a row (the previous entry of a lane's element comes from the
-// neighbouring lane by a shuffle, so col is read once). Integer totals are
+// G lanes share a row, each taking a contiguous segment (the entry before a
+// segment gives its first gap). Rows longer than 64 G entries are left out
+// of the sweep and listed; each is then reduced by a whole workgroup, in row
+// order, so one long row does not serialize a lane group. Integer totals are
 // exact int64 sums; the scatter mean and variance use Welford updates per
 // thread merged with Chan's pairwise formula in a fixed tree, so the result
 // is deterministic. A second small kernel samples row pairs for the x-reuse
 // estimate, and a one-block kernel folds the per-block partials in order.
+#include <algorithm>
+#include <vector>
+
 #include "device.h"
 
 namespace csr {
@@ -67,10 +72,55 @@ __device__ __forceinline__ void part_init(FeatPart &p) {
     p.s_cl = 0.0;
 }
 
+// Statistics of the entries [s0, s1) of a row that starts at b (the entry
+// before s0, when inside the row, gives the first gap).
+struct SegStats {
+    int32_t mn, mx, miss, grps;
+};
+__device__ __forceinline__ SegStats seg_stats(const int32_t *__restrict__ col, int32_t b,
+                                              int32_t e, int32_t s0, int32_t s1) {
+    SegStats g{INT32_MAX, INT32_MIN, 0, 0};
+    int32_t prev = s0 > b && s0 < e ? col[s0 - 1] : 0;
+    for (int32_t j = s0; j < s1; ++j) {
+        const int32_t c = col[j];
+        g.mn = min(g.mn, c);
+        g.mx = max(g.mx, c);
+        if (j == b) {
+            g.miss += 1;
+            g.grps += 1;
+        } else {
+            const int64_t d = (int64_t)c - prev;
+            g.miss += (d > kFeatE || d < -kFeatE) ? 1 : 0;
+            g.grps += (d != 1) ? 1 : 0;
+        }
+        prev = c;
+    }
+    return g;
+}
+
+// One row's contribution (k entries, bandwidth bw).
+__device__ __forceinline__ void part_push(FeatPart &p, int32_t k, int32_t bw, int32_t miss,
+                                          int32_t grps) {
+    p.s_nnz2 += (int64_t)k * k;
+    p.s_bw += bw;
+    p.s_bw2 += (int64_t)bw * bw;
+    p.s_miss += miss;
+    p.s_grp += grps;
+    p.s_len1 += k > 0 ? k - 1 : 0;
+    p.nnz_min = min(p.nnz_min, k);
+    p.nnz_max = max(p.nnz_max, k);
+    p.bw_min = min(p.bw_min, bw);
+    p.bw_max = max(p.bw_max, bw);
+    const double sc = k > 0 ? (double)k / (double)(bw > 1 ? bw : 1) : 0.0;
+    welford_push(p.sc_n, p.sc_mean, p.sc_m2, sc);
+    p.s_cl += k > 0 ? (double)grps / (double)k : 0.0;
+}
+
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_features(const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ col,
-                                                     int32_t n_rows, FeatPart *__restrict__ out) {
+                                                     int32_t n_rows, FeatPart *__restrict__ out,
+                                                     int32_t *__restrict__ long_list) {
     __shared__ FeatPart s_part[kBlock / G];
     constexpr int NG = kBlock / G;
     const int lane = threadIdx.x % G;
@@ -82,46 +132,19 @@ __global__ __launch_bounds__(kBlock) void k_features(const int32_t *__restrict__
     for (int64_t r = (int64_t)blockIdx.x * NG + grp; r < n_rows; r += stride) {
         const int32_t b = rp[r], e = rp[r + 1];
         const int32_t k = e - b;
-        // lane takes the contiguous segment [s0, s1) of the row; the entry
-        // before the segment (if inside the row) gives its first gap
+        if (k > 64 * G) {  // reduced by its own workgroup later
+            if (lane == 0) long_list[1 + atomicAdd(long_list, 1)] = (int32_t)r;
+            continue;
+        }
+        // lane takes the contiguous segment [s0, s1) of the row
         const int32_t q = (k + G - 1) / G;
         const int32_t s0 = min(b + lane * q, e), s1 = min(s0 + q, e);
-        int32_t mn = INT32_MAX, mx = INT32_MIN, miss = 0, grps = 0;
-        int32_t prev = s0 > b && s0 < e ? col[s0 - 1] : 0;
-        for (int32_t j = s0; j < s1; ++j) {
-            const int32_t c = col[j];
-            mn = min(mn, c);
-            mx = max(mx, c);
-            if (j == b) {
-                miss += 1;
-                grps += 1;
-            } else {
-                const int64_t d = (int64_t)c - prev;
-                miss += (d > kFeatE || d < -kFeatE) ? 1 : 0;
-                grps += (d != 1) ? 1 : 0;
-            }
-            prev = c;
-        }
-        mn = -group_max<G>(-mn);
-        mx = group_max<G>(mx);
-        miss = group_isum<G>(miss);
-        grps = group_isum<G>(grps);
-        if (lane == 0) {
-            const int32_t bw = k > 0 ? mx - mn : 0;
-            p.s_nnz2 += (int64_t)k * k;
-            p.s_bw += bw;
-            p.s_bw2 += (int64_t)bw * bw;
-            p.s_miss += miss;
-            p.s_grp += grps;
-            p.s_len1 += k > 0 ? k - 1 : 0;
-            p.nnz_min = min(p.nnz_min, k);
-            p.nnz_max = max(p.nnz_max, k);
-            p.bw_min = min(p.bw_min, bw);
-            p.bw_max = max(p.bw_max, bw);
-            const double sc = k > 0 ? (double)k / (double)(bw > 1 ? bw : 1) : 0.0;
-            welford_push(p.sc_n, p.sc_mean, p.sc_m2, sc);
-            p.s_cl += k > 0 ? (double)grps / (double)k : 0.0;
-        }
+        SegStats g = seg_stats(col, b, e, s0, s1);
+        const int32_t mn = -group_max<G>(-g.mn);
+        const int32_t mx = group_max<G>(g.mx);
+        const int32_t miss = group_isum<G>(g.miss);
+        const int32_t grps = group_isum<G>(g.grps);
+        if (lane == 0) part_push(p, k, k > 0 ? mx - mn : 0, miss, grps);
     }
     if (lane == 0) s_part[grp] = p;
     __syncthreads();
@@ -130,6 +153,41 @@ __global__ __launch_bounds__(kBlock) void k_features(const int32_t *__restrict__
         __syncthreads();
     }
     if (threadIdx.x == 0) out[blockIdx.x] = s_part[0];
+}
+
+// Long row list[1 + b], reduced by workgroup b (kBlock contiguous segments;
+// integer statistics, so the split does not change them): one partial.
+__global__ __launch_bounds__(kBlock) void k_features_long(const int32_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ col,
+                                                          const int32_t *__restrict__ long_list,
+                                                          FeatPart *__restrict__ out) {
+    __shared__ int32_t s_mn[kBlock], s_mx[kBlock], s_miss[kBlock], s_grp[kBlock];
+    const int32_t r = long_list[1 + blockIdx.x];
+    const int32_t b = rp[r], e = rp[r + 1];
+    const int32_t k = e - b;
+    const int32_t q = (k + kBlock - 1) / kBlock;
+    const int32_t s0 = min(b + (int32_t)threadIdx.x * q, e), s1 = min(s0 + q, e);
+    const SegStats g = seg_stats(col, b, e, s0, s1);
+    s_mn[threadIdx.x] = g.mn;
+    s_mx[threadIdx.x] = g.mx;
+    s_miss[threadIdx.x] = g.miss;
+    s_grp[threadIdx.x] = g.grps;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s_mn[threadIdx.x] = min(s_mn[threadIdx.x], s_mn[threadIdx.x + w]);
+            s_mx[threadIdx.x] = max(s_mx[threadIdx.x], s_mx[threadIdx.x + w]);
+            s_miss[threadIdx.x] += s_miss[threadIdx.x + w];
+            s_grp[threadIdx.x] += s_grp[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        FeatPart p;
+        part_init(p);
+        part_push(p, k, s_mx[0] - s_mn[0], s_miss[0], s_grp[0]);
+        out[blockIdx.x] = p;
+    }
 }
 
 // Fold the per-block partials in block order (one workgroup, fixed tree).
@@ -191,8 +249,9 @@ __global__ __launch_bounds__(kWave) void k_xreuse(const int32_t *__restrict__ rp
 
 template <int G>
 hipError_t go(const int32_t *rp, const int32_t *col, int32_t n_rows, FeatPart *parts,
-              int32_t n_parts, hipStream_t s) {
-    hipLaunchKernelGGL(k_features<G>, dim3(n_parts), dim3(kBlock), 0, s, rp, col, n_rows, parts);
+              int32_t n_parts, int32_t *long_list, hipStream_t s) {
+    hipLaunchKernelGGL(k_features<G>, dim3(n_parts), dim3(kBlock), 0, s, rp, col, n_rows, parts,
+                       long_list);
     return hipGetLastError();
 }
 
@@ -206,20 +265,52 @@ int32_t features_partials(int32_t n_rows, int G) {
 
 int32_t xreuse_samples(int32_t n_rows) { return n_rows > 1 ? min(n_rows - 1, kReuseS) : 0; }
 
-hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int G,
-                           FeatPart *parts, int32_t n_parts, int32_t *reuse_out, hipStream_t s) {
+int32_t features_long_row(int G) { return 64 * G; }
+
+int64_t features_long_capacity(int64_t nnz, int G) {
+    return nnz / ((int64_t)features_long_row(G) + 1) + 1;
+}
+
+hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int64_t nnz,
+                           int G, FeatPart *parts, int32_t n_parts, int32_t *long_list,
+                           int32_t *reuse_out, hipStream_t s) {
     hipError_t e;
+    if ((e = hipMemsetAsync(long_list, 0, sizeof(int32_t), s)) != hipSuccess) return e;
     switch (G) {
-    case 1: e = go<1>(rp, col, n_rows, parts, n_parts, s); break;
-    case 2: e = go<2>(rp, col, n_rows, parts, n_parts, s); break;
-    case 4: e = go<4>(rp, col, n_rows, parts, n_parts, s); break;
-    case 8: e = go<8>(rp, col, n_rows, parts, n_parts, s); break;
-    case 16: e = go<16>(rp, col, n_rows, parts, n_parts, s); break;
-    case 32: e = go<32>(rp, col, n_rows, parts, n_parts, s); break;
-    default: e = go<64>(rp, col, n_rows, parts, n_parts, s); break;
+    case 1: e = go<1>(rp, col, n_rows, parts, n_parts, long_list, s); break;
+    case 2: e = go<2>(rp, col, n_rows, parts, n_parts, long_list, s); break;
+    case 4: e = go<4>(rp, col, n_rows, parts, n_parts, long_list, s); break;
+    case 8: e = go<8>(rp, col, n_rows, parts, n_parts, long_list, s); break;
+    case 16: e = go<16>(rp, col, n_rows, parts, n_parts, long_list, s); break;
+    case 32: e = go<32>(rp, col, n_rows, parts, n_parts, long_list, s); break;
+    default: e = go<64>(rp, col, n_rows, parts, n_parts, long_list, s); break;
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_features_fold, dim3(1), dim3(kBlock), 0, s, parts, n_parts);
+    // long rows: listed in whatever order the sweep met them; sorted here so
+    // that their partials are folded in row order (deterministic features)
+    int32_t n_long = 0;
+    if ((e = hipMemcpyAsync(&n_long, long_list, sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return e;
+    if (n_long < 0 || n_long > features_long_capacity(nnz, G)) return hipErrorInvalidValue;
+    if (n_long > 0) {
+        std::vector<int32_t> rows((size_t)n_long);
+        if ((e = hipMemcpyAsync(rows.data(), long_list + 1, sizeof(int32_t) * rows.size(),
+                                hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return e;
+        std::sort(rows.begin(), rows.end());
+        if ((e = hipMemcpyAsync(long_list + 1, rows.data(), sizeof(int32_t) * rows.size(),
+                                hipMemcpyHostToDevice, s)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_features_long, dim3((unsigned)n_long), dim3(kBlock), 0, s, rp, col,
+                           long_list, parts + n_parts);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // rows lives until the copy has been consumed
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_features_fold, dim3(1), dim3(kBlock), 0, s, parts, n_parts + n_long);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int32_t ns = xreuse_samples(n_rows);
     if (ns > 0) {

@@ -350,16 +350,20 @@ csr_status_t inspect(csr_matrix_s *A, hipStream_t s) {
         const int G0 = default_lanes_per_row(nnz_avg);
         const int G = G0 >= 4 ? G0 / 4 : 1;  // contiguous segments of about 4 entries per lane
         const int32_t n_parts = features_partials(A->n_rows, G);
+        const int64_t long_cap = features_long_capacity(A->nnz, G);
         const int32_t n_samp = xreuse_samples(A->n_rows);
         csr_status_t st;
-        if (A->feat_parts.bytes < sizeof(FeatPart) * (size_t)n_parts &&
-            (st = A->feat_parts.alloc(sizeof(FeatPart) * (size_t)n_parts)) != CSR_OK)
+        if (A->feat_parts.bytes < sizeof(FeatPart) * (size_t)(n_parts + long_cap) &&
+            (st = A->feat_parts.alloc(sizeof(FeatPart) * (size_t)(n_parts + long_cap))) != CSR_OK)
+            return st;
+        if (A->feat_long.bytes < sizeof(int32_t) * (size_t)(long_cap + 1) &&
+            (st = A->feat_long.alloc(sizeof(int32_t) * (size_t)(long_cap + 1))) != CSR_OK)
             return st;
         if (A->feat_reuse.bytes < sizeof(int32_t) * 2 * (size_t)n_samp + 8 &&
             (st = A->feat_reuse.alloc(sizeof(int32_t) * 2 * (size_t)n_samp + 8)) != CSR_OK)
             return st;
-        CSR_HIP(launch_features(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->n_rows, G,
-                                A->feat_parts.as<FeatPart>(), n_parts,
+        CSR_HIP(launch_features(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->n_rows, A->nnz, G,
+                                A->feat_parts.as<FeatPart>(), n_parts, A->feat_long.as<int32_t>(),
                                 A->feat_reuse.as<int32_t>(), s));
         FeatPart p;
         std::vector<int32_t> reuse(2 * (size_t)n_samp);
