@@ -102,6 +102,10 @@ typedef struct {
     int32_t delta_bits;      /* 8, 16, or 32 (plain int32 indices) */
     int32_t n_long_rows;     /* rows taken out by the decomposition */
     int32_t fallback;        /* 1 if LEARNED had no model and used PROFILE */
+    int32_t merge_slack;     /* > 0: merge tiles cut at row ends (cuts every L - slack items
+                                moved to the end of the row in progress; no row spans two
+                                tiles); 0: plain cuts every L items */
+    int32_t reserved;
     double p_csr, p_mb, p_ml, p_imb, p_cmp, p_peak;  /* flop/s (PROFILE) */
     double b_max;            /* B/s used for the bounds */
     double t_select_ms;      /* features/probes + decision */

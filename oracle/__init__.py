@@ -62,7 +62,7 @@ def lib():
             "or_delta_eligible": (c_int, [i32, P, P, c_int]),
             "or_delta_encode": (c_int, [i32, P, P, c_int, P]),
             "or_delta_decode": (None, [i32, P, P, c_int, P]),
-            "or_merge_tiles": (i64, [i32, P, i64, P, P]),
+            "or_merge_tiles": (i64, [i32, P, i64, i64, P, P]),
             "or_long_rows": (i32, [i32, P, i64, P]),
             "or_features": (None, [i32, i32, P, P, P, P]),
         }
@@ -248,16 +248,18 @@ def delta_width(rp, col) -> int:
 # IMB remedies (Sec. III-E): merge-path tiles and long-row decomposition
 # ---------------------------------------------------------------------------
 
-def merge_tiles(rp, L: int):
+def merge_tiles(rp, L: int, slack: int = 0):
     """(i_t, j_t) for t = 0..T of the merge path of the row ends with the
-    nonzeros, cut every L items."""
+    nonzeros, cut every L items; with slack s > 0 cut every L - s items and
+    move each cut forward to the end of the row in progress (row-aligned
+    tiles of at most L items when every row has fewer than s nonzeros)."""
     rp = np.ascontiguousarray(rp, dtype=np.int32)
     n = rp.size - 1
     total = n + int(rp[-1])
-    T = (total + L - 1) // L
+    T = (total + (L - slack) - 1) // (L - slack)
     ti = np.empty(T + 1, dtype=np.int32)
     tj = np.empty(T + 1, dtype=np.int32)
-    lib().or_merge_tiles(n, _p(rp), L, _p(ti), _p(tj))
+    lib().or_merge_tiles(n, _p(rp), L, slack, _p(ti), _p(tj))
     return ti, tj
 
 

@@ -247,14 +247,19 @@ void or_delta_decode(int32_t n_rows, const int32_t *rp, const void *codes,
 /* Tile t covers items (d_t, d_{t+1}] with d_t = min(t*L, N+NNZ); the table  */
 /* holds (i_t, j_t) for t = 0..T, T = ceil((N+NNZ)/L).                       */
 /* ------------------------------------------------------------------------ */
-int64_t or_merge_tiles(int32_t n_rows, const int32_t *rp, int64_t L,
+/* Row-aligned variant (slack s > 0, used when every row has fewer than s  */
+/* nonzeros): cut every L - s items, then move each cut forward to the end */
+/* of the row in progress there, so no row spans two tiles and a tile      */
+/* still holds at most L items. s = 0 gives the plain partition.           */
+int64_t or_merge_tiles(int32_t n_rows, const int32_t *rp, int64_t L, int64_t slack,
                        int32_t *ti, int32_t *tj)
 {
     int64_t nnz = rp[n_rows];
     int64_t total = (int64_t)n_rows + nnz;
-    int64_t T = (total + L - 1) / L;
+    int64_t Lp = L - slack;
+    int64_t T = (total + Lp - 1) / Lp;
     for (int64_t t = 0; t <= T; ++t) {
-        int64_t d = t * L < total ? t * L : total;
+        int64_t d = t * Lp < total ? t * Lp : total;
         /* lower bound: first i with rp[i+1] + i >= d */
         int64_t lo = 0, hi = n_rows;
         while (lo < hi) {
@@ -262,8 +267,13 @@ int64_t or_merge_tiles(int32_t n_rows, const int32_t *rp, int64_t L,
             if ((int64_t)rp[mid + 1] + mid < d) lo = mid + 1;
             else hi = mid;
         }
+        int64_t j = d - lo;
+        if (slack > 0 && lo < n_rows && j > rp[lo]) { /* row lo in progress */
+            lo += 1;
+            j = rp[lo];
+        }
         ti[t] = (int32_t)lo;
-        tj[t] = (int32_t)(d - lo);
+        tj[t] = (int32_t)j;
     }
     return T;
 }

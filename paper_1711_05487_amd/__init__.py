@@ -59,6 +59,7 @@ class PlanInfo(ctypes.Structure):
                 ("variant_id", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
                 ("merge_items", ctypes.c_int32), ("delta_bits", ctypes.c_int32),
                 ("n_long_rows", ctypes.c_int32), ("fallback", ctypes.c_int32),
+                ("merge_slack", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("p_csr", ctypes.c_double), ("p_mb", ctypes.c_double), ("p_ml", ctypes.c_double),
                 ("p_imb", ctypes.c_double), ("p_cmp", ctypes.c_double),
                 ("p_peak", ctypes.c_double), ("b_max", ctypes.c_double),

@@ -102,6 +102,17 @@ int device_cu_count(int device) {
     return cache[device];
 }
 
+int64_t merge_slack(const csr_matrix_s *A, int64_t L) {
+    const int64_t s = (int64_t)A->max_row_nnz + 1;
+    return s <= kMergeRowAlignMax && s < L ? s : 0;
+}
+
+int64_t merge_tile_count(const csr_matrix_s *A, int64_t L) {
+    const int64_t total = (int64_t)A->n_rows + A->nnz;
+    const int64_t step = L - merge_slack(A, L);
+    return (total + step - 1) / step;
+}
+
 bool x_fits_32(const csr_matrix_s *A) {
     const uint64_t xb = A->storage == CSR_VAL_F64 ? 8 : 4;
     return (uint64_t)A->n_cols * xb <= (uint64_t)UINT32_MAX + 1;
@@ -135,13 +146,13 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
         auto tj = A->tile_j.as<int32_t>();
         switch (A->storage) {
         case CSR_VAL_F64:
-            return launch_merge_s0(ipt, P.nt != 0, x32, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
+            return launch_merge_s0(ipt, P.nt != 0, x32, A->tiles_fixup != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
                                    after, s);
         case CSR_VAL_F32:
-            return launch_merge_s1(ipt, P.nt != 0, x32, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
+            return launch_merge_s1(ipt, P.nt != 0, x32, A->tiles_fixup != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
                                    after, s);
         default:
-            return launch_merge_s2(ipt, P.nt != 0, x32, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
+            return launch_merge_s2(ipt, P.nt != 0, x32, A->tiles_fixup != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
                                    after, s);
         }
     }
@@ -246,7 +257,7 @@ csr_status_t csr_create(csr_matrix_t *out, int32_t n_rows, int32_t n_cols, int64
     if ((st = A->val.alloc(storage_bytes(storage) * (size_t)nnz + kPadBytes)) != CSR_OK)
         return bail(st);
     DevBuf flags;
-    if ((st = flags.alloc(sizeof(int32_t))) != CSR_OK) return bail(st);
+    if ((st = flags.alloc(2 * sizeof(int32_t))) != CSR_OK) return bail(st);
     hipError_t e;
 #define STEP(call)                                              \
     if ((e = (call)) != hipSuccess) return bail(hip_fail(e, #call));
@@ -258,12 +269,14 @@ csr_status_t csr_create(csr_matrix_t *out, int32_t n_rows, int32_t n_cols, int64
     // zero the tail padding so vector loads past nnz read defined bytes
     STEP(hipMemsetAsync(A->col.as<char>() + sizeof(int32_t) * (size_t)nnz, 0, kPadBytes, s));
     STEP(hipMemsetAsync(A->val.as<char>() + storage_bytes(storage) * (size_t)nnz, 0, kPadBytes, s));
-    STEP(hipMemsetAsync(flags.p, 0, sizeof(int32_t), s));
+    STEP(hipMemsetAsync(flags.p, 0, 2 * sizeof(int32_t), s));
     STEP(launch_validate(A->rp.as<int32_t>(), A->col.as<int32_t>(), n_rows, n_cols, nnz,
                          flags.as<int32_t>(), s));
-    int32_t h = 0;
-    STEP(hipMemcpyAsync(&h, flags.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    int32_t hv[2] = {0, 0};
+    STEP(hipMemcpyAsync(hv, flags.p, sizeof(hv), hipMemcpyDeviceToHost, s));
     STEP(hipStreamSynchronize(s));
+    const int32_t h = hv[0];
+    A->max_row_nnz = hv[1];
     if (h & 7) {
         std::string why;
         if (h & 1) why += " row_ptr[0]!=0 or row_ptr[n]!=nnz;";

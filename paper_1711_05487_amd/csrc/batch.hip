@@ -50,8 +50,7 @@ csr_status_t build(BatchPlan &B, int32_t count, const csr_matrix_t *A, const voi
                    void *const *y, const std::vector<int> &ipt, hipStream_t s) {
     std::vector<int64_t> T(count), base(count + 1, 0), tbase(count + 1, 0);
     for (int k = 0; k < count; ++k) {
-        const int64_t L = (int64_t)kMergeBlock * ipt[k];
-        T[k] = ((int64_t)A[k]->n_rows + A[k]->nnz + L - 1) / L;
+        T[k] = merge_tile_count(A[k], (int64_t)kMergeBlock * ipt[k]);
         base[k + 1] = base[k] + T[k];       // work items (tiles)
         tbase[k + 1] = tbase[k] + T[k] + 1; // tile-table entries
     }
@@ -69,8 +68,9 @@ csr_status_t build(BatchPlan &B, int32_t count, const csr_matrix_t *A, const voi
     for (int k = 0; k < count; ++k) {
         int32_t *ti = B.tile_i.as<int32_t>() + tbase[k];
         int32_t *tj = B.tile_j.as<int32_t>() + tbase[k];
-        CSR_HIP(launch_merge_partition(A[k]->rp.as<int32_t>(), A[k]->n_rows, A[k]->nnz,
-                                       (int64_t)kMergeBlock * ipt[k], T[k], ti, tj, s));
+        const int64_t L = (int64_t)kMergeBlock * ipt[k];
+        CSR_HIP(launch_merge_partition(A[k]->rp.as<int32_t>(), A[k]->n_rows, A[k]->nnz, L,
+                                       merge_slack(A[k], L), T[k], ti, tj, s));
         BatchMat &M = B.mats_h[k];
         M.rp = A[k]->rp.as<int32_t>();
         M.col = A[k]->col.as<int32_t>();

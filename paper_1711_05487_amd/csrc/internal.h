@@ -85,6 +85,7 @@ struct csr_matrix_s {
     uint64_t version = 0;          // incremented by every csr_select
     int device = 0;
     int32_t n_rows = 0, n_cols = 0;
+    int32_t max_row_nnz = 0;  // longest row (from validation)
     int64_t nnz = 0;
     int32_t storage = CSR_VAL_F64;
     int32_t rows_sorted = 0;
@@ -96,6 +97,8 @@ struct csr_matrix_s {
     csr::DevBuf carry;             // per-tile carry of the merge-path kernel
     int64_t n_tiles = 0;
     int32_t tiles_L = 0;
+    int64_t tiles_slack = 0;   // row-aligned tiles when > 0 (no cross-tile rows)
+    int32_t tiles_fixup = 1;   // the cross-tile fixup has work for this tile table
     csr::DevBuf long_list;         // decomposition: long rows (ascending)
     csr::DevBuf long_chunks;       // decomposition: (begin, end) nonzero range per chunk
     csr::DevBuf long_row_chunk;    // decomposition: first chunk of each long row, n_long+1
@@ -130,16 +133,21 @@ hipError_t launch_rowsplit_s2(int G, int idx, bool nt, int U, int R, int probe,
                               const void *const *arr, int32_t skip_above, int32_t n_rows,
                               int32_t n_cols, hipStream_t s);
 hipError_t launch_merge_partition(const int32_t *rp, int32_t n_rows, int64_t nnz, int64_t L,
-                                  int64_t n_tiles, int32_t *tile_i, int32_t *tile_j,
+                                  int64_t slack, int64_t n_tiles, int32_t *tile_i, int32_t *tile_j,
                                   hipStream_t s);
-// arr = {rp, col, codes, val, x, y}; L = 64 * ipt; x32: x spans < 4 GiB
-hipError_t launch_merge_s0(int ipt, bool nt, bool x32, const void *const *arr,
+// Merge tiles are cut at row ends (slack = longest row + 1) when every row is
+// shorter than this; otherwise slack = 0 and rows may span tiles.
+constexpr int32_t kMergeRowAlignMax = 64;
+
+// arr = {rp, col, codes, val, x, y}; L = 64 * ipt; x32: x spans < 4 GiB;
+// fixup: run the cross-tile fixup pass
+hipError_t launch_merge_s0(int ipt, bool nt, bool x32, bool fixup, const void *const *arr,
                            const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
                            hipEvent_t after_main, hipStream_t s);
-hipError_t launch_merge_s1(int ipt, bool nt, bool x32, const void *const *arr,
+hipError_t launch_merge_s1(int ipt, bool nt, bool x32, bool fixup, const void *const *arr,
                            const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
                            hipEvent_t after_main, hipStream_t s);
-hipError_t launch_merge_s2(int ipt, bool nt, bool x32, const void *const *arr,
+hipError_t launch_merge_s2(int ipt, bool nt, bool x32, bool fixup, const void *const *arr,
                            const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
                            hipEvent_t after_main, hipStream_t s);
 hipError_t launch_fill_row_index(const int32_t *rp, int32_t n_rows, int32_t n_cols, int32_t *out,
@@ -153,6 +161,10 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
 // Name of the plan's dominant kernel (as in a kernel trace).
 // x of this matrix spans < 4 GiB, so gathers may use 32-bit byte offsets
 bool x_fits_32(const csr_matrix_s *A);
+// slack of the row-aligned merge partition at tile size L (0: plain cuts),
+// and the number of tiles it gives
+int64_t merge_slack(const csr_matrix_s *A, int64_t L);
+int64_t merge_tile_count(const csr_matrix_s *A, int64_t L);
 std::string dominant_kernel(const csr_matrix_s *A, const Plan &P);
 hipError_t launch_triad(double *a, const double *b, const double *c, double scalar,
                         int64_t n, hipStream_t s);

@@ -16,6 +16,8 @@
 // inside the tile, and each row reads its sum at its last nonzero. The row
 // still open at the tile end leaves one carry per tile; rows split across
 // tiles are finished by k_merge_fixup, which adds the carries in tile order.
+// When every row has fewer than 64 nonzeros the tiles are cut at row ends
+// (the partition's slack), no row is split and the fixup is not launched.
 // Every sum has a fixed order, so results are deterministic.
 //
 // Compiled once per storage type (-DCSR_STORAGE=0/1/2).
@@ -57,8 +59,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup(const int32_t *__restric
 }
 
 template <int IPT, bool NT, bool X32>
-hipError_t go(const void *const *arr, const int32_t *tile_i, const int32_t *tile_j, void *carry,
-              int32_t n_rows, int64_t n_tiles, hipEvent_t after_main, hipStream_t s) {
+hipError_t go(bool fixup, const void *const *arr, const int32_t *tile_i, const int32_t *tile_j,
+              void *carry, int32_t n_rows, int64_t n_tiles, hipEvent_t after_main, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
     const XcdGrid g = xcd_grid(n_tiles);
     hipLaunchKernelGGL((k_merge<IPT, NT, X32>), dim3((unsigned)g.launched), dim3(kMergeBlock), 0, s,
@@ -67,7 +69,7 @@ hipError_t go(const void *const *arr, const int32_t *tile_i, const int32_t *tile
                        g.per_xcd, n_tiles);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && after_main) e = hipEventRecord(after_main, s);
-    if (e != hipSuccess || n_tiles < 2) return e;
+    if (e != hipSuccess || n_tiles < 2 || !fixup) return e;
     const unsigned fb = (unsigned)((n_tiles + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_merge_fixup, dim3(fb), dim3(kBlock), 0, s, (const int32_t *)arr[0],
                        tile_i, tile_j, (const A *)carry, (X *)arr[5], n_rows, n_tiles);
@@ -75,14 +77,14 @@ hipError_t go(const void *const *arr, const int32_t *tile_i, const int32_t *tile
 }
 
 template <int IPT>
-hipError_t go_ipt(bool nt, bool x32, const void *const *arr, const int32_t *tile_i,
+hipError_t go_ipt(bool nt, bool x32, bool fixup, const void *const *arr, const int32_t *tile_i,
                   const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
                   hipEvent_t after_main, hipStream_t s) {
     if (nt)
-        return x32 ? go<IPT, true, true>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s)
-                   : go<IPT, true, false>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
-    return x32 ? go<IPT, false, true>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s)
-               : go<IPT, false, false>(arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
+        return x32 ? go<IPT, true, true>(fixup, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s)
+                   : go<IPT, true, false>(fixup, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
+    return x32 ? go<IPT, false, true>(fixup, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s)
+               : go<IPT, false, false>(fixup, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
 }
 
 }  // namespace
@@ -90,14 +92,15 @@ hipError_t go_ipt(bool nt, bool x32, const void *const *arr, const int32_t *tile
 #define CSR_CAT2(a, b) a##b
 #define CSR_CAT(a, b) CSR_CAT2(a, b)
 // arr = {rp, col, codes, val, x, y}; L = 64 * ipt; x32: x spans < 4 GiB
-hipError_t CSR_CAT(launch_merge_s, CSR_STORAGE)(int ipt, bool nt, bool x32, const void *const *arr,
+hipError_t CSR_CAT(launch_merge_s, CSR_STORAGE)(int ipt, bool nt, bool x32, bool fixup,
+                                                const void *const *arr,
                                                 const int32_t *tile_i, const int32_t *tile_j,
                                                 void *carry, int32_t n_rows, int64_t n_tiles,
                                                 hipEvent_t after_main, hipStream_t s) {
     switch (ipt) {
-    case 4: return go_ipt<4>(nt, x32, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
-    case 8: return go_ipt<8>(nt, x32, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
-    case 16: return go_ipt<16>(nt, x32, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
+    case 4: return go_ipt<4>(nt, x32, fixup, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
+    case 8: return go_ipt<8>(nt, x32, fixup, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
+    case 16: return go_ipt<16>(nt, x32, fixup, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
     default: return hipErrorInvalidValue;
     }
 }

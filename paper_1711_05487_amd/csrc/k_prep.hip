@@ -36,6 +36,7 @@ __global__ __launch_bounds__(kBlock) void k_validate(const int32_t *__restrict__
         }
         const uint64_t mb = __ballot(bad), mu = __ballot(unsorted);
         if (lane == 0 && (mb | mu)) atomicOr(flags, (mb ? 4 : 0) | (mu ? 8 : 0));
+        if (lane == 0) atomicMax(flags + 1, e - b);  // longest row
     }
 }
 
@@ -123,15 +124,21 @@ __global__ __launch_bounds__(kBlock) void k_delta_encode(const int32_t *__restri
 
 // Merge-path partition: for t = 0..T, d = min(t*L, N+NNZ) and
 // i_t = #{ i : rp[i+1] + i < d } (a lower-bound search), j_t = d - i_t.
+// Merge-path partition (reading of the IMB "auto" schedule as an
+// nnz-balanced split): cut t lies at path step d = min(t (L - slack), N + NNZ),
+// i_t = #{i : rp[i+1] + i < d}, j_t = d - i_t. With slack > 0 (every row has
+// fewer than slack nonzeros) a cut inside a row moves forward to that row's
+// end, so no row spans two tiles and a tile still holds at most L steps.
 __global__ __launch_bounds__(kBlock) void k_merge_partition(const int32_t *__restrict__ rp,
                                                             int32_t n_rows, int64_t nnz, int64_t L,
-                                                            int64_t n_tiles,
+                                                            int64_t slack, int64_t n_tiles,
                                                             int32_t *__restrict__ tile_i,
                                                             int32_t *__restrict__ tile_j) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t > n_tiles) return;
     const int64_t total = (int64_t)n_rows + nnz;
-    const int64_t d = t * L < total ? t * L : total;
+    const int64_t step = L - slack;
+    const int64_t d = t * step < total ? t * step : total;
     int64_t lo = d - nnz > 0 ? d - nnz : 0;
     int64_t hi = d < n_rows ? d : n_rows;
     while (lo < hi) {
@@ -139,8 +146,13 @@ __global__ __launch_bounds__(kBlock) void k_merge_partition(const int32_t *__res
         if ((int64_t)rp[mid + 1] + mid < d) lo = mid + 1;
         else hi = mid;
     }
+    int64_t j = d - lo;
+    if (slack > 0 && lo < n_rows && j > rp[lo]) {  // row lo in progress: cut after its end
+        lo += 1;
+        j = rp[lo];
+    }
     tile_i[t] = (int32_t)lo;
-    tile_j[t] = (int32_t)(d - lo);
+    tile_j[t] = (int32_t)j;
 }
 
 // P_ML probe input (Sec. III-B): a column array holding, for every entry, the
@@ -205,11 +217,11 @@ hipError_t launch_delta_encode(const int32_t *rp, const int32_t *col, int32_t n_
 }
 
 hipError_t launch_merge_partition(const int32_t *rp, int32_t n_rows, int64_t nnz, int64_t L,
-                                  int64_t n_tiles, int32_t *tile_i, int32_t *tile_j,
+                                  int64_t slack, int64_t n_tiles, int32_t *tile_i, int32_t *tile_j,
                                   hipStream_t s) {
     const unsigned g = (unsigned)((n_tiles + 1 + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_merge_partition, dim3(g), dim3(kBlock), 0, s, rp, n_rows, nnz, L, n_tiles,
-                       tile_i, tile_j);
+    hipLaunchKernelGGL(k_merge_partition, dim3(g), dim3(kBlock), 0, s, rp, n_rows, nnz, L, slack,
+                       n_tiles, tile_i, tile_j);
     return hipGetLastError();
 }
 

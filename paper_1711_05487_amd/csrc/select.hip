@@ -63,6 +63,7 @@ void fill_info(const csr_matrix_s *A, const Plan &P, csr_plan_info_t *info) {
     info->opts = P.opts;
     info->lanes_per_row = P.G;
     info->merge_items = P.L;
+    info->merge_slack = (P.opts & CSR_OPT_MERGE) ? (int32_t)A->tiles_slack : 0;
     info->delta_bits = P.idx == IDX_D16 ? 16 : P.idx == IDX_D8 ? 8 : 32;
     info->n_long_rows = P.long_rows ? A->n_long : 0;
     info->variant_id = catalogue_id(P.opts);
@@ -101,17 +102,19 @@ csr_status_t build_delta(csr_matrix_s *A, hipStream_t s) {
 
 csr_status_t build_tiles(csr_matrix_s *A, int L, hipStream_t s) {
     if (A->tiles_L == L) return CSR_OK;
-    const int64_t total = (int64_t)A->n_rows + A->nnz;
-    const int64_t T = (total + L - 1) / L;
+    const int64_t slack = merge_slack(A, L);
+    const int64_t T = merge_tile_count(A, L);
     csr_status_t st;
     if ((st = A->tile_i.alloc(sizeof(int32_t) * (T + 1))) != CSR_OK) return st;
     if ((st = A->tile_j.alloc(sizeof(int32_t) * (T + 1))) != CSR_OK) return st;
     if ((st = A->carry.alloc((A->storage == CSR_VAL_F64 ? 8 : 4) * (size_t)(T + 1))) != CSR_OK)
         return st;
-    CSR_HIP(launch_merge_partition(A->rp.as<int32_t>(), A->n_rows, A->nnz, L, T,
+    CSR_HIP(launch_merge_partition(A->rp.as<int32_t>(), A->n_rows, A->nnz, L, slack, T,
                                    A->tile_i.as<int32_t>(), A->tile_j.as<int32_t>(), s));
     A->n_tiles = T;
     A->tiles_L = L;
+    A->tiles_slack = slack;
+    A->tiles_fixup = slack == 0;  // row-aligned tiles leave nothing to fix up
     return CSR_OK;
 }
 

@@ -34,15 +34,24 @@ def long_and_empty_rows():
     return len(lens), 20000, rp, col, val
 
 
+def expected_slack(rp, L):
+    """Row-aligned tiles when every row has at most 63 nonzeros."""
+    s = int(np.diff(rp).max(initial=0)) + 1
+    return s if s <= 64 and s < L else 0
+
+
 @pytest.mark.parametrize("L", [256, 512, 1024])
 def test_tile_table_bit_exact(L):
-    for name in ("lap100", "rmat14", "st27_24"):
+    for name in ("lap100", "rmat14", "st27_24", "unif14"):
         n, m, rp, col, val = matrix(name)
         A = pkg.CsrMatrix(rp, col, val)
-        A.select("forced", forced_opts=M, merge_items=L)
-        ti, tj = oracle.merge_tiles(rp, L)
+        info = A.select("forced", forced_opts=M, merge_items=L)
+        assert info["merge_slack"] == expected_slack(rp, L), name
+        ti, tj = oracle.merge_tiles(rp, L, info["merge_slack"])
         assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_I, np.int32), ti)
         assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_J, np.int32), tj)
+        if info["merge_slack"]:  # no row spans two tiles
+            assert np.array_equal(tj, rp[ti])
 
 
 @pytest.mark.parametrize("L", [256, 512, 1024])

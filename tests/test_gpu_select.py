@@ -139,7 +139,7 @@ def check_tables_in_place(A, info, rp):
     """The autotuner rebuilds the merge tile table per candidate tile size;
     the one left in place must be the table of the plan it kept."""
     if info["opts"] & pkg.OPT_MERGE:
-        ti, tj = oracle.merge_tiles(rp, info["merge_items"])
+        ti, tj = oracle.merge_tiles(rp, info["merge_items"], info["merge_slack"])
         assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_I, np.int32), ti)
         assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_J, np.int32), tj)
 

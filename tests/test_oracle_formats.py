@@ -229,6 +229,46 @@ def test_merge_tiles_match_step_simulation(case):
         assert len(ti) == (total + L - 1) // L + 1
 
 
+def _first_row_start_from(path, rp, p):
+    """Index of the first point at or after step p of the path that is a row
+    start (j == rp[i], row i not begun) or the end of the path."""
+    n = len(rp) - 1
+    for q in range(p, len(path)):
+        i, j = path[q]
+        if i == n or j == rp[i]:
+            return q
+    return len(path) - 1
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_row_aligned_tiles_by_path_walk(case):
+    if case == 0:
+        rp = np.array([0, 3, 3, 3, 10, 11, 11, 11, 14], dtype=np.int32)  # empty rows
+    elif case == 1:
+        rp = np.arange(0, 41, 4, dtype=np.int32)                          # equal rows
+    else:
+        _, _, rp, _, _ = synth.tiny_random(40 + 9 * case, 50, 0.04 * case, 70 + case)
+    n, nnz = len(rp) - 1, int(rp[-1])
+    s = int(np.diff(rp).max()) + 1            # every row has fewer than s nonzeros
+    path = _merge_path_by_steps(rp)
+    total = len(path) - 1
+    for L in (s + 1, s + 5, 64):
+        ti, tj = oracle.merge_tiles(rp, L, s)
+        pts = list(zip(ti.tolist(), tj.tolist()))
+        assert len(pts) == (total + (L - s) - 1) // (L - s) + 1
+        for t, pt in enumerate(pts):          # the cut at t(L-s), moved to a row start
+            assert pt == path[_first_row_start_from(path, rp, min(t * (L - s), total))]
+        assert pts[0] == (0, 0) and pts[-1] == (n, nnz)
+        for i, j in pts:                      # no tile cuts a row
+            assert i == n or j == rp[i]
+        sizes = np.diff(ti.astype(np.int64) + tj)
+        assert np.all(sizes >= 0) and np.all(sizes <= L)
+    # slack 0 is the plain partition
+    for L in (3, 7):
+        a, b = oracle.merge_tiles(rp, L, 0), oracle.merge_tiles(rp, L)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
 def test_merge_tiles_invariants_on_rmat():
     n, _, rp, _, _ = synth.rmat(14, 16)
     L = 256
