@@ -63,6 +63,7 @@ def lib():
             "or_delta_encode": (c_int, [i32, P, P, c_int, P]),
             "or_delta_decode": (None, [i32, P, P, c_int, P]),
             "or_merge_tiles": (i64, [i32, P, i64, i64, P, P]),
+            "or_merge_codes": (c_int, [i64, P, P, c_int, P, P]),
             "or_long_rows": (i32, [i32, P, i64, P]),
             "or_features": (None, [i32, i32, P, P, P, P]),
         }
@@ -247,6 +248,20 @@ def delta_width(rp, col) -> int:
 # ---------------------------------------------------------------------------
 # IMB remedies (Sec. III-E): merge-path tiles and long-row decomposition
 # ---------------------------------------------------------------------------
+
+def merge_codes(tj, col, w: int):
+    """Tile-base column codes of the merge path (MB remedy, Table II): per
+    tile the smallest column, per nonzero the w-bit offset from it; None when
+    some tile's column range does not fit in w bits."""
+    tj = np.ascontiguousarray(tj, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    T = tj.size - 1
+    base = np.zeros(max(T, 1), dtype=np.int32)
+    codes = np.zeros(max(col.size, 1), dtype=np.uint16 if w == 16 else np.uint8)
+    if not lib().or_merge_codes(T, _p(tj), _p(col), w, _p(base), codes.ctypes.data_as(ctypes.c_void_p)):
+        return None
+    return base[:T], codes[:col.size]
+
 
 def merge_tiles(rp, L: int, slack: int = 0):
     """(i_t, j_t) for t = 0..T of the merge path of the row ends with the

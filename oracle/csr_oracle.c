@@ -278,6 +278,31 @@ int64_t or_merge_tiles(int32_t n_rows, const int32_t *rp, int64_t L, int64_t sla
     return T;
 }
 
+/* MB remedy on the merge path (Table II, index compression): each merge   */
+/* tile t stores base_t = the smallest column among its nonzeros, and each  */
+/* nonzero j of the tile the unsigned w-bit offset col[j] - base_t. The     */
+/* matrix is eligible for w iff every tile's column range (max - min) fits  */
+/* in w bits. Returns 1 and fills base/codes when eligible, else 0.          */
+int or_merge_codes(int64_t T, const int32_t *tj, const int32_t *col, int w,
+                   int32_t *base, void *codes)
+{
+    int64_t lim = (int64_t)1 << w;
+    for (int64_t t = 0; t < T; ++t) {
+        int32_t mn = 0, mx = 0;
+        for (int64_t j = tj[t]; j < tj[t + 1]; ++j) {
+            if (j == tj[t] || col[j] < mn) mn = col[j];
+            if (j == tj[t] || col[j] > mx) mx = col[j];
+        }
+        if ((int64_t)mx - mn >= lim) return 0;
+        base[t] = mn;
+        for (int64_t j = tj[t]; j < tj[t + 1]; ++j) {
+            if (w == 16) ((uint16_t *)codes)[j] = (uint16_t)(col[j] - mn);
+            else ((uint8_t *)codes)[j] = (uint8_t)(col[j] - mn);
+        }
+    }
+    return 1;
+}
+
 /* ------------------------------------------------------------------------ */
 /* IMB remedy, decomposition (Sec. III-E, Figs. 5-6): rows with more than    */
 /* tau nonzeros are taken out of the row-parallel pass and computed          */

@@ -296,3 +296,61 @@ def test_long_rows_hand_built():
     assert oracle.long_rows(rp, 100000).tolist() == []
     assert oracle.long_row_threshold(4.0) == 4096
     assert oracle.long_row_threshold(1000.0) == 32000
+
+
+# ------------------------------------------------------- tile-base column codes
+
+def _tile_of_each_nonzero(tj, nnz):
+    return np.repeat(np.arange(len(tj) - 1), np.diff(tj.astype(np.int64)))[:nnz]
+
+
+@pytest.mark.parametrize("name,L,w", [("lap", 256, 16), ("lap", 512, 16), ("st27", 512, 16),
+                                       ("rand", 64, 8)])
+def test_merge_codes_round_trip_and_minimum(name, L, w):
+    if name == "lap":
+        n, _, rp, col, _ = synth.laplacian2d(100)
+    elif name == "st27":
+        n, _, rp, col, _ = synth.stencil27(12)
+    else:
+        n, _, rp, col, _ = synth.tiny_random(200, 40, 0.05, 3)
+    ti, tj = oracle.merge_tiles(rp, L)
+    got = oracle.merge_codes(tj, col, w)
+    assert got is not None
+    base, codes = got
+    t_of = _tile_of_each_nonzero(tj, len(col))
+    # decode(encode(col)) == col
+    assert np.array_equal(base[t_of].astype(np.int64) + codes.astype(np.int64), col)
+    # base_t is the smallest column of a non-empty tile: one code is 0
+    for t in range(len(tj) - 1):
+        if tj[t + 1] > tj[t]:
+            assert codes[tj[t]:tj[t + 1]].min() == 0
+
+
+def test_merge_codes_width_boundaries():
+    # one row, tile = whole matrix: columns {0, 2^w - 1} fit, {0, 2^w} do not
+    for w in (8, 16):
+        for top, ok in (((1 << w) - 1, True), (1 << w, False)):
+            rp = np.array([0, 2], dtype=np.int32)
+            col = np.array([0, top], dtype=np.int32)
+            ti, tj = oracle.merge_tiles(rp, 8)
+            assert (oracle.merge_codes(tj, col, w) is not None) == ok
+
+
+def test_merge_codes_laplacian_and_stencil_ranges():
+    # 5-point Laplacian on n x n: a tile holding rows [i0, i1) touches
+    # columns within [i0 - n, i1 - 1 + n], a range of at most rows - 1 + 2n
+    n = 100
+    _, _, rp, col, _ = synth.laplacian2d(n)
+    ti, tj = oracle.merge_tiles(rp, 256)
+    base, codes = oracle.merge_codes(tj, col, 16)
+    t_of = _tile_of_each_nonzero(tj, len(col))
+    rng = np.zeros(len(tj) - 1, dtype=np.int64)
+    np.maximum.at(rng, t_of, codes.astype(np.int64))
+    rows_touched = np.diff(ti.astype(np.int64)) + 1
+    assert np.all(rng <= rows_touched - 1 + 2 * n)
+    # 27-point on m^3: offsets reach +-(m^2 + m + 1); 16-bit fits, 8-bit does not
+    m = 20
+    _, _, rp, col, _ = synth.stencil27(m)
+    ti, tj = oracle.merge_tiles(rp, 512)
+    assert oracle.merge_codes(tj, col, 16) is not None
+    assert oracle.merge_codes(tj, col, 8) is None
