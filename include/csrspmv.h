@@ -203,7 +203,9 @@ csr_status_t csr_query(csr_matrix_t A, int32_t *n_rows, int32_t *n_cols, int64_t
  *   what: 0 stored values (nnz elements of the storage type),
  *         1 delta codes (nnz bytes or uint16), 2 merge tile rows int32[T+1],
  *         3 merge tile nonzero offsets int32[T+1], 4 long-row list int32[n],
- *         5 plan info (csr_plan_info_t)
+ *         5 plan info (csr_plan_info_t), 6 merge codes (nnz uint8 or uint16:
+ *         column - smallest column of the nonzero's merge tile), 7 merge tile
+ *         bases int32[T] (the smallest column of each tile)
  * Returns CSR_ERR_INVALID_ARG if `bytes` differs from the array's size
  * (*needed receives that size when non-NULL) or the array does not exist.
  * Synchronizes `stream`.

@@ -27,7 +27,8 @@ SEL_PLAIN, SEL_PROFILE, SEL_LEARNED, SEL_EXHAUSTIVE, SEL_FORCED = 0, 1, 2, 3, 4
 SELECT = {"plain": SEL_PLAIN, "profile": SEL_PROFILE, "learned": SEL_LEARNED,
           "exhaustive": SEL_EXHAUSTIVE, "forced": SEL_FORCED}
 
-DEBUG_VALUES, DEBUG_CODES, DEBUG_TILE_I, DEBUG_TILE_J, DEBUG_LONG_ROWS, DEBUG_PLAN = range(6)
+(DEBUG_VALUES, DEBUG_CODES, DEBUG_TILE_I, DEBUG_TILE_J, DEBUG_LONG_ROWS, DEBUG_PLAN,
+ DEBUG_MERGE_CODES, DEBUG_TILE_BASE) = range(8)
 
 STATUS = ["CSR_OK", "CSR_ERR_INVALID_ARG", "CSR_ERR_INVALID_MATRIX", "CSR_ERR_OUT_OF_MEMORY",
           "CSR_ERR_DEVICE", "CSR_ERR_UNSUPPORTED", "CSR_ERR_NOT_READY"]

@@ -121,7 +121,8 @@ bool x_fits_32(const csr_matrix_s *A) {
 std::string dominant_kernel(const csr_matrix_s *A, const Plan &P) {
     if (P.opts & CSR_OPT_MERGE)
         return "k_merge<" + std::to_string(P.L / kMergeBlock) + ", " + (P.nt ? "true" : "false") +
-               ", " + (x_fits_32(A) ? "true" : "false") + ">";
+               ", " + (P.idx == IDX_I32 && x_fits_32(A) ? "true" : "false") + ", " +
+               std::to_string(P.idx) + ">";
     return "k_rowsplit<" + std::to_string(P.G) + ", " + std::to_string(P.idx) + ", " +
            (P.nt ? "true" : "false") + ", " + std::to_string(P.U) + ", " + std::to_string(P.R) +
            ", 0>";
@@ -144,16 +145,19 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
         const bool x32 = x_fits_32(A);
         auto ti = A->tile_i.as<int32_t>();
         auto tj = A->tile_j.as<int32_t>();
+        const int32_t *tb = P.idx != IDX_I32 ? A->tile_base.as<int32_t>() : nullptr;
+        if (P.idx != IDX_I32) arr[2] = A->mcodes.p;
+        const bool fix = A->tiles_fixup != 0;
         switch (A->storage) {
         case CSR_VAL_F64:
-            return launch_merge_s0(ipt, P.nt != 0, x32, A->tiles_fixup != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
-                                   after, s);
+            return launch_merge_s0(ipt, P.nt != 0, x32, fix, P.idx, tb, A->n_cols, arr, ti, tj,
+                                   A->carry.p, A->n_rows, A->n_tiles, after, s);
         case CSR_VAL_F32:
-            return launch_merge_s1(ipt, P.nt != 0, x32, A->tiles_fixup != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
-                                   after, s);
+            return launch_merge_s1(ipt, P.nt != 0, x32, fix, P.idx, tb, A->n_cols, arr, ti, tj,
+                                   A->carry.p, A->n_rows, A->n_tiles, after, s);
         default:
-            return launch_merge_s2(ipt, P.nt != 0, x32, A->tiles_fixup != 0, arr, ti, tj, A->carry.p, A->n_rows, A->n_tiles,
-                                   after, s);
+            return launch_merge_s2(ipt, P.nt != 0, x32, fix, P.idx, tb, A->n_cols, arr, ti, tj,
+                                   A->carry.p, A->n_rows, A->n_tiles, after, s);
         }
     }
     hipError_t e;
@@ -383,6 +387,18 @@ csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t by
     case 2: if (A->n_tiles > 0) { src = A->tile_i.p; n = sizeof(int32_t) * (A->n_tiles + 1); } break;
     case 3: if (A->n_tiles > 0) { src = A->tile_j.p; n = sizeof(int32_t) * (A->n_tiles + 1); } break;
     case 4: if (A->n_long > 0) { src = A->long_list.p; n = sizeof(int32_t) * A->n_long; } break;
+    case 6:  // merge codes
+        if (A->mcode_bits == 8 || A->mcode_bits == 16) {
+            src = A->mcodes.p;
+            n = (size_t)A->nnz * (A->mcode_bits / 8);
+        }
+        break;
+    case 7:  // merge tile bases
+        if (A->mcode_bits == 8 || A->mcode_bits == 16) {
+            src = A->tile_base.p;
+            n = sizeof(int32_t) * (size_t)A->n_tiles;
+        }
+        break;
     case 5:
         if (needed) *needed = sizeof(csr_plan_info_t);
         if (bytes != sizeof(csr_plan_info_t) || !h_dst) return fail(CSR_ERR_INVALID_ARG, "size");

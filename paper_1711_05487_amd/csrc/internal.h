@@ -93,7 +93,10 @@ struct csr_matrix_s {
     csr::DevBuf codes;             // delta codes (uint8 or uint16)
     int32_t code_bits = 32;        // 8 / 16 when `codes` holds a valid encoding
     csr::DevBuf tile_i, tile_j;    // merge-path tile table, T+1 entries each
-    csr::DevBuf tile_c;            // absolute column at each tile start (delta)
+    csr::DevBuf tile_base;         // merge codes: smallest column of each tile, T entries
+    csr::DevBuf mcodes;            // merge codes: per-nonzero offset from its tile's base
+    int32_t mcode_bits = 0;        // 8 / 16 when mcodes is valid, 32 = not eligible, 0 = not built
+    int32_t mcodes_L = 0;          // tile size the merge codes were built for
     csr::DevBuf carry;             // per-tile carry of the merge-path kernel
     int64_t n_tiles = 0;
     int32_t tiles_L = 0;
@@ -135,19 +138,29 @@ hipError_t launch_rowsplit_s2(int G, int idx, bool nt, int U, int R, int probe,
 hipError_t launch_merge_partition(const int32_t *rp, int32_t n_rows, int64_t nnz, int64_t L,
                                   int64_t slack, int64_t n_tiles, int32_t *tile_i, int32_t *tile_j,
                                   hipStream_t s);
+// Merge codes: base[t] = smallest column of tile t, *max_range = largest
+// (max - min) column range over the tiles; then codes[j] = col[j] - base[t].
+hipError_t launch_merge_tile_range(const int32_t *col, const int32_t *tile_j, int64_t n_tiles,
+                                   int32_t *base, int32_t *max_range, hipStream_t s);
+hipError_t launch_merge_encode(const int32_t *col, const int32_t *tile_j, int64_t n_tiles,
+                               const int32_t *base, int bits, void *codes, hipStream_t s);
 // Merge tiles are cut at row ends (slack = longest row + 1) when every row is
 // shorter than this; otherwise slack = 0 and rows may span tiles.
 constexpr int32_t kMergeRowAlignMax = 64;
 
 // arr = {rp, col, codes, val, x, y}; L = 64 * ipt; x32: x spans < 4 GiB;
-// fixup: run the cross-tile fixup pass
-hipError_t launch_merge_s0(int ipt, bool nt, bool x32, bool fixup, const void *const *arr,
+// fixup: run the cross-tile fixup pass; idx != IDX_I32: arr[2] holds the
+// merge codes and tile_base the tile bases (columns = base + code)
+hipError_t launch_merge_s0(int ipt, bool nt, bool x32, bool fixup, int idx,
+                           const int32_t *tile_base, int32_t n_cols, const void *const *arr,
                            const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
                            hipEvent_t after_main, hipStream_t s);
-hipError_t launch_merge_s1(int ipt, bool nt, bool x32, bool fixup, const void *const *arr,
+hipError_t launch_merge_s1(int ipt, bool nt, bool x32, bool fixup, int idx,
+                           const int32_t *tile_base, int32_t n_cols, const void *const *arr,
                            const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
                            hipEvent_t after_main, hipStream_t s);
-hipError_t launch_merge_s2(int ipt, bool nt, bool x32, bool fixup, const void *const *arr,
+hipError_t launch_merge_s2(int ipt, bool nt, bool x32, bool fixup, int idx,
+                           const int32_t *tile_base, int32_t n_cols, const void *const *arr,
                            const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
                            hipEvent_t after_main, hipStream_t s);
 hipError_t launch_fill_row_index(const int32_t *rp, int32_t n_rows, int32_t n_cols, int32_t *out,

@@ -35,17 +35,17 @@ using V = typename St<S>::V;
 using X = typename St<S>::X;
 using A = typename St<S>::A;
 
-template <int IPT, bool NT, bool X32>
+template <int IPT, bool NT, bool X32, int IDX>
 __global__ __launch_bounds__(kMergeBlock) void k_merge(
-    const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const V *__restrict__ val,
+    const int32_t *__restrict__ rp, const void *__restrict__ cols, const V *__restrict__ val,
     const X *__restrict__ x, X *__restrict__ y, const int32_t *__restrict__ tile_i,
-    const int32_t *__restrict__ tile_j, A *__restrict__ carry, int32_t n_rows, int64_t per_xcd,
-    int64_t n_tiles) {
+    const int32_t *__restrict__ tile_j, const int32_t *__restrict__ tile_base,
+    A *__restrict__ carry, int32_t n_rows, int32_t n_cols, int64_t per_xcd, int64_t n_tiles) {
     __shared__ MergeLds<S, IPT> lds;
     const int64_t t = xcd_logical_block(per_xcd);
     if (t >= n_tiles) return;
-    merge_tile<S, IPT, NT, MergeLds<S, IPT>, X32>(t, rp, col, val, x, y, tile_i, tile_j, carry,
-                                                  n_rows, lds);
+    merge_tile<S, IPT, NT, MergeLds<S, IPT>, X32, IDX>(t, rp, cols, val, x, y, tile_i, tile_j,
+                                                       carry, n_rows, lds, tile_base, n_cols);
 }
 
 __global__ __launch_bounds__(kBlock) void k_merge_fixup(const int32_t *__restrict__ rp,
@@ -58,33 +58,47 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup(const int32_t *__restric
     if (t < n_tiles) merge_fixup_tile<S>(t, rp, tile_i, tile_j, carry, y, n_rows);
 }
 
-template <int IPT, bool NT, bool X32>
-hipError_t go(bool fixup, const void *const *arr, const int32_t *tile_i, const int32_t *tile_j,
-              void *carry, int32_t n_rows, int64_t n_tiles, hipEvent_t after_main, hipStream_t s) {
-    if (n_tiles == 0) return hipSuccess;
-    const XcdGrid g = xcd_grid(n_tiles);
-    hipLaunchKernelGGL((k_merge<IPT, NT, X32>), dim3((unsigned)g.launched), dim3(kMergeBlock), 0, s,
-                       (const int32_t *)arr[0], (const int32_t *)arr[1], (const V *)arr[3],
-                       (const X *)arr[4], (X *)arr[5], tile_i, tile_j, (A *)carry, n_rows,
-                       g.per_xcd, n_tiles);
+struct MergeArgs {
+    const void *const *arr;  // {rp, cols or codes, -, val, x, y}
+    const int32_t *tile_i, *tile_j, *tile_base;
+    void *carry;
+    int32_t n_rows, n_cols;
+    int64_t n_tiles;
+    bool fixup;
+    hipEvent_t after_main;
+};
+
+template <int IPT, bool NT, bool X32, int IDX>
+hipError_t go(const MergeArgs &a, hipStream_t s) {
+    if (a.n_tiles == 0) return hipSuccess;
+    const void *cols = IDX == IDX_I32 ? a.arr[1] : a.arr[2];
+    const XcdGrid g = xcd_grid(a.n_tiles);
+    hipLaunchKernelGGL((k_merge<IPT, NT, X32, IDX>), dim3((unsigned)g.launched), dim3(kMergeBlock),
+                       0, s, (const int32_t *)a.arr[0], cols, (const V *)a.arr[3],
+                       (const X *)a.arr[4], (X *)a.arr[5], a.tile_i, a.tile_j, a.tile_base,
+                       (A *)a.carry, a.n_rows, a.n_cols, g.per_xcd, a.n_tiles);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && after_main) e = hipEventRecord(after_main, s);
-    if (e != hipSuccess || n_tiles < 2 || !fixup) return e;
-    const unsigned fb = (unsigned)((n_tiles + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_merge_fixup, dim3(fb), dim3(kBlock), 0, s, (const int32_t *)arr[0],
-                       tile_i, tile_j, (const A *)carry, (X *)arr[5], n_rows, n_tiles);
+    if (e == hipSuccess && a.after_main) e = hipEventRecord(a.after_main, s);
+    if (e != hipSuccess || a.n_tiles < 2 || !a.fixup) return e;
+    const unsigned fb = (unsigned)((a.n_tiles + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_merge_fixup, dim3(fb), dim3(kBlock), 0, s, (const int32_t *)a.arr[0],
+                       a.tile_i, a.tile_j, (const A *)a.carry, (X *)a.arr[5], a.n_rows, a.n_tiles);
     return hipGetLastError();
 }
 
+// int32 columns: streaming and 32-bit gathers chosen at run time; merge
+// codes always stream (they are the MB remedy's compressed arrays) and
+// gather through the tile's x range
 template <int IPT>
-hipError_t go_ipt(bool nt, bool x32, bool fixup, const void *const *arr, const int32_t *tile_i,
-                  const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
-                  hipEvent_t after_main, hipStream_t s) {
+hipError_t go_ipt(bool nt, bool x32, int idx, const MergeArgs &a, hipStream_t s) {
+    switch (idx) {
+    case IDX_D16: return go<IPT, true, false, IDX_D16>(a, s);
+    case IDX_D8: return go<IPT, true, false, IDX_D8>(a, s);
+    default: break;
+    }
     if (nt)
-        return x32 ? go<IPT, true, true>(fixup, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s)
-                   : go<IPT, true, false>(fixup, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
-    return x32 ? go<IPT, false, true>(fixup, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s)
-               : go<IPT, false, false>(fixup, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
+        return x32 ? go<IPT, true, true, IDX_I32>(a, s) : go<IPT, true, false, IDX_I32>(a, s);
+    return x32 ? go<IPT, false, true, IDX_I32>(a, s) : go<IPT, false, false, IDX_I32>(a, s);
 }
 
 }  // namespace
@@ -92,15 +106,18 @@ hipError_t go_ipt(bool nt, bool x32, bool fixup, const void *const *arr, const i
 #define CSR_CAT2(a, b) a##b
 #define CSR_CAT(a, b) CSR_CAT2(a, b)
 // arr = {rp, col, codes, val, x, y}; L = 64 * ipt; x32: x spans < 4 GiB
-hipError_t CSR_CAT(launch_merge_s, CSR_STORAGE)(int ipt, bool nt, bool x32, bool fixup,
-                                                const void *const *arr,
-                                                const int32_t *tile_i, const int32_t *tile_j,
-                                                void *carry, int32_t n_rows, int64_t n_tiles,
-                                                hipEvent_t after_main, hipStream_t s) {
+hipError_t CSR_CAT(launch_merge_s, CSR_STORAGE)(int ipt, bool nt, bool x32, bool fixup, int idx,
+                                                const int32_t *tile_base, int32_t n_cols,
+                                                const void *const *arr, const int32_t *tile_i,
+                                                const int32_t *tile_j, void *carry, int32_t n_rows,
+                                                int64_t n_tiles, hipEvent_t after_main,
+                                                hipStream_t s) {
+    const MergeArgs a{arr, tile_i, tile_j, tile_base, carry, n_rows, n_cols, n_tiles, fixup,
+                      after_main};
     switch (ipt) {
-    case 4: return go_ipt<4>(nt, x32, fixup, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
-    case 8: return go_ipt<8>(nt, x32, fixup, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
-    case 16: return go_ipt<16>(nt, x32, fixup, arr, tile_i, tile_j, carry, n_rows, n_tiles, after_main, s);
+    case 4: return go_ipt<4>(nt, x32, idx, a, s);
+    case 8: return go_ipt<8>(nt, x32, idx, a, s);
+    case 16: return go_ipt<16>(nt, x32, idx, a, s);
     default: return hipErrorInvalidValue;
     }
 }

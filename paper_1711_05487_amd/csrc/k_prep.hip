@@ -1,5 +1,7 @@
 // Ingest kernels (CSR validation, value-precision conversion) and the B_max
 // probe (a STREAM-style triad, Sec. IV-A, Table III).
+#include <type_traits>
+
 #include "device.h"
 
 namespace csr {
@@ -155,6 +157,41 @@ __global__ __launch_bounds__(kBlock) void k_merge_partition(const int32_t *__res
     tile_j[t] = (int32_t)j;
 }
 
+// Merge codes (MB remedy on the merge path): one wave per tile. Pass 1:
+// base[t] = smallest column of the tile's nonzeros, *max_range = the largest
+// max - min over the tiles. Pass 2: codes[j] = col[j] - base[t].
+__global__ __launch_bounds__(kWave) void k_merge_tile_range(const int32_t *__restrict__ col,
+                                                            const int32_t *__restrict__ tile_j,
+                                                            int32_t *__restrict__ base,
+                                                            int32_t *__restrict__ max_range) {
+    const int64_t t = blockIdx.x;
+    const int32_t j0 = tile_j[t], j1 = tile_j[t + 1];
+    int32_t mn = INT32_MAX, mx = INT32_MIN;
+    for (int32_t j = j0 + (int32_t)threadIdx.x; j < j1; j += kWave) {
+        mn = min(mn, col[j]);
+        mx = max(mx, col[j]);
+    }
+    mn = -group_max<kWave>(-mn);
+    mx = group_max<kWave>(mx);
+    if (threadIdx.x == 0) {
+        base[t] = j1 > j0 ? mn : 0;
+        if (j1 > j0) atomicMax(max_range, mx - mn);
+    }
+}
+
+template <int BITS>
+__global__ __launch_bounds__(kWave) void k_merge_encode(const int32_t *__restrict__ col,
+                                                        const int32_t *__restrict__ tile_j,
+                                                        const int32_t *__restrict__ base,
+                                                        void *__restrict__ codes) {
+    using C = typename std::conditional<BITS == 16, uint16_t, uint8_t>::type;
+    const int64_t t = blockIdx.x;
+    const int32_t j0 = tile_j[t], j1 = tile_j[t + 1];
+    const int32_t b = base[t];
+    for (int32_t j = j0 + (int32_t)threadIdx.x; j < j1; j += kWave)
+        static_cast<C *>(codes)[j] = (C)(col[j] - b);
+}
+
 // P_ML probe input (Sec. III-B): a column array holding, for every entry, the
 // index of its own row (clamped to the last column), so the probe reads the
 // same bytes as CSR but x regularly.
@@ -222,6 +259,26 @@ hipError_t launch_merge_partition(const int32_t *rp, int32_t n_rows, int64_t nnz
     const unsigned g = (unsigned)((n_tiles + 1 + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_merge_partition, dim3(g), dim3(kBlock), 0, s, rp, n_rows, nnz, L, slack,
                        n_tiles, tile_i, tile_j);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_tile_range(const int32_t *col, const int32_t *tile_j, int64_t n_tiles,
+                                   int32_t *base, int32_t *max_range, hipStream_t s) {
+    if (n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_merge_tile_range, dim3((unsigned)n_tiles), dim3(kWave), 0, s, col, tile_j,
+                       base, max_range);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_encode(const int32_t *col, const int32_t *tile_j, int64_t n_tiles,
+                               const int32_t *base, int bits, void *codes, hipStream_t s) {
+    if (n_tiles == 0) return hipSuccess;
+    if (bits == 16)
+        hipLaunchKernelGGL(k_merge_encode<16>, dim3((unsigned)n_tiles), dim3(kWave), 0, s, col,
+                           tile_j, base, codes);
+    else
+        hipLaunchKernelGGL(k_merge_encode<8>, dim3((unsigned)n_tiles), dim3(kWave), 0, s, col,
+                           tile_j, base, codes);
     return hipGetLastError();
 }
 

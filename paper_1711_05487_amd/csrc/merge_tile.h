@@ -115,39 +115,50 @@ template <int S, int IPT> struct MergeLds {
 // of the tile may have begun in an earlier tile: it gets this tile's part
 // here, and merge_fixup_tile adds the earlier tiles' carries.
 
+// Column type of the window: int32 columns, or the w-bit offsets of the
+// merge codes (columns = base of the tile + code).
+template <int IDX> struct MergeCol { using type = int32_t; };
+template <> struct MergeCol<IDX_D16> { using type = uint16_t; };
+template <> struct MergeCol<IDX_D8> { using type = uint8_t; };
+
 // What a lane holds for one tile between issuing its loads and reducing it.
-template <int S, int IPT> struct MergeTileRegs {
+template <int S, int IPT, int IDX = IDX_I32> struct MergeTileRegs {
     using V = typename St<S>::V;
+    using C = typename MergeCol<IDX>::type;
     static constexpr int VEC = merge_vec<S>();
     static constexpr int NIT = IPT / VEC;  // load blocks of STEP = BS * VEC elements
     using VV = typename VecOfU<V, VEC>::type;
-    using IV = typename VecOfU<int32_t, VEC>::type;
+    using CV = typename VecOfU<C, VEC>::type;
     int32_t i0, i1, j0, j1;  // the tile's bounds (wave-uniform)
     int32_t last_end;        // rp[i1]: end of the last row ending in the tile
+    int32_t base;            // merge codes: the tile's smallest column
     int32_t re[IPT];         // rp[i0 + r + 1] for rows r = lane + q * BS (0 past the
                              // tile's rows; only ceil((i1 - i0) / BS) entries loaded)
     VV vv[NIT];              // values of the tile's window
-    IV cv[NIT];              // columns of the tile's window
+    CV cv[NIT];              // columns (or codes) of the tile's window
 };
 
 // Stage 1: issue the tile's loads. The window [j0, j0 + L) starts at the
 // tile's first nonzero and is read in NIT blocks of BS vectors (at element
 // alignment) through a buffer range that ends with the last vector holding
-// tile nonzeros: lanes past it read zeros (column 0, value 0) without a
-// memory access, and the last vector reads at most VEC - 1 elements past
-// j1, a neighbouring tile's or the tail padding. Row ends are read through
-// a range holding exactly the tile's rows. Row ends first (their count
-// depends on the tile), then columns (needed first), then values, so that
-// the wait for each column vector is a fixed count.
-template <int S, int IPT, bool NT>
+// tile nonzeros: lanes past it read zeros (column or code 0, value 0)
+// without a memory access, and the last vector reads at most VEC - 1
+// elements past j1, a neighbouring tile's or the tail padding. Row ends are
+// read through a range holding exactly the tile's rows. Row ends first
+// (their count depends on the tile), then columns (needed first), then
+// values, so that the wait for each column vector is a fixed count.
+// `cols` is the int32 column array, or the merge codes for IDX_D16/D8.
+template <int S, int IPT, bool NT, int IDX = IDX_I32>
 __device__ __forceinline__ void merge_issue(int64_t t, const int32_t *__restrict__ rp,
-                                            const int32_t *__restrict__ col,
+                                            const void *__restrict__ cols,
                                             const typename St<S>::V *__restrict__ val,
                                             const int32_t *__restrict__ tile_i,
                                             const int32_t *__restrict__ tile_j,
-                                            MergeTileRegs<S, IPT> &R) {
-    using Rg = MergeTileRegs<S, IPT>;
+                                            const int32_t *__restrict__ tile_base,
+                                            MergeTileRegs<S, IPT, IDX> &R) {
+    using Rg = MergeTileRegs<S, IPT, IDX>;
     using V = typename St<S>::V;
+    using C = typename Rg::C;
     constexpr int VEC = Rg::VEC, NIT = Rg::NIT;
     constexpr int BS = kMergeBlock;
     constexpr int STEP = BS * VEC;
@@ -156,6 +167,7 @@ __device__ __forceinline__ void merge_issue(int64_t t, const int32_t *__restrict
     R.i1 = tile_i[t + 1];
     R.j0 = tile_j[t];
     R.j1 = tile_j[t + 1];
+    R.base = IDX == IDX_I32 ? 0 : tile_base[t];
     // elements of the window up to the end of the last vector holding tile
     // nonzeros (a multiple of VEC; 0 for a tile without nonzeros)
     const uint32_t nwin = R.j1 > R.j0 ? ((uint32_t)(R.j1 - 1 - R.j0) & ~(uint32_t)(VEC - 1)) + VEC : 0u;
@@ -172,12 +184,12 @@ __device__ __forceinline__ void merge_issue(int64_t t, const int32_t *__restrict
         for (int q = 0; q < IPT; ++q)
             R.re[q] = buffer_load<int32_t, false>(rr, tid * 4u, (uint32_t)(q * BS * 4));
     }
-    const auto rc = buffer_range(col + R.j0, nwin * (uint32_t)sizeof(int32_t));
+    const auto rc = buffer_range(static_cast<const C *>(cols) + R.j0, nwin * (uint32_t)sizeof(C));
     const auto rv = buffer_range(val + R.j0, nwin * (uint32_t)sizeof(V));
 #pragma unroll
     for (int it = 0; it < NIT; ++it)
-        R.cv[it] = buffer_load<typename Rg::IV, NT>(rc, tid * (uint32_t)(VEC * sizeof(int32_t)),
-                                                   (uint32_t)(it * STEP * sizeof(int32_t)));
+        R.cv[it] = buffer_load<typename Rg::CV, NT>(rc, tid * (uint32_t)(VEC * sizeof(C)),
+                                                   (uint32_t)(it * STEP * sizeof(C)));
 #pragma unroll
     for (int it = 0; it < NIT; ++it)
         R.vv[it] = buffer_load<typename Rg::VV, NT>(rv, tid * (uint32_t)(VEC * sizeof(V)),
@@ -186,38 +198,55 @@ __device__ __forceinline__ void merge_issue(int64_t t, const int32_t *__restrict
 }
 
 // Stage 2: gather x at the window's columns (all valid: the window holds
-// real nonzeros of this tile or its neighbours, or zeroed padding).
-template <int S, int IPT, bool X32>
-__device__ __forceinline__ void merge_gather(const MergeTileRegs<S, IPT> &R,
+// real nonzeros of this tile or its neighbours, or zeroed padding). With
+// merge codes, x is read through the range [x + base, x + n_cols): a code
+// that is not this tile's (the window's tail) cannot leave x.
+template <int S, int IPT, bool X32, int IDX = IDX_I32>
+__device__ __forceinline__ void merge_gather(const MergeTileRegs<S, IPT, IDX> &R,
                                              const typename St<S>::X *__restrict__ x,
-                                             typename St<S>::X (&xs)[MergeTileRegs<S, IPT>::NIT]
-                                                                   [MergeTileRegs<S, IPT>::VEC]) {
+                                             int32_t n_cols,
+                                             typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX>::NIT]
+                                                                   [MergeTileRegs<S, IPT, IDX>::VEC]) {
     using X = typename St<S>::X;
-    constexpr int VEC = MergeTileRegs<S, IPT>::VEC, NIT = MergeTileRegs<S, IPT>::NIT;
+    constexpr int VEC = MergeTileRegs<S, IPT, IDX>::VEC, NIT = MergeTileRegs<S, IPT, IDX>::NIT;
+    if constexpr (IDX != IDX_I32) {
+        // a code reaches at most 2^16 - 1 past the base: the range never
+        // needs more than 2^16 elements (and stays far below 4 GiB)
+        const uint32_t nx = (uint32_t)min(n_cols - R.base, 1 << 16);
+        const auto rx = buffer_range(x + R.base, nx * (uint32_t)sizeof(X));
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
+        for (int it = 0; it < NIT; ++it) {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-            if constexpr (X32)  // x spans < 4 GiB: 32-bit byte offsets
-                xs[it][e] = *reinterpret_cast<const X *>(reinterpret_cast<const char *>(x) +
-                                                         (uint32_t)R.cv[it][e] * (uint32_t)sizeof(X));
-            else
-                xs[it][e] = x[R.cv[it][e]];
+            for (int e = 0; e < VEC; ++e)
+                xs[it][e] = buffer_load<X, false>(rx, (uint32_t)R.cv[it][e] * (uint32_t)sizeof(X), 0u);
+        }
+    } else {
+        (void)n_cols;
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                if constexpr (X32)  // x spans < 4 GiB: 32-bit byte offsets
+                    xs[it][e] = *reinterpret_cast<const X *>(
+                        reinterpret_cast<const char *>(x) + (uint32_t)R.cv[it][e] * (uint32_t)sizeof(X));
+                else
+                    xs[it][e] = x[R.cv[it][e]];
+            }
         }
     }
 }
 
 // Stage 3: products, segmented scan, rows and carry.
-template <int S, int IPT, class LDS>
-__device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT> &R,
-                                             const typename St<S>::X (&xs)[MergeTileRegs<S, IPT>::NIT]
-                                                                          [MergeTileRegs<S, IPT>::VEC],
+template <int S, int IPT, class LDS, int IDX = IDX_I32>
+__device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT, IDX> &R,
+                                             const typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX>::NIT]
+                                                                          [MergeTileRegs<S, IPT, IDX>::VEC],
                                              typename St<S>::X *__restrict__ y,
                                              typename St<S>::A *__restrict__ carry,
                                              int32_t n_rows, LDS &lds) {
     using X = typename St<S>::X;
     using A = typename St<S>::A;
-    constexpr int VEC = MergeTileRegs<S, IPT>::VEC, NIT = MergeTileRegs<S, IPT>::NIT;
+    constexpr int VEC = MergeTileRegs<S, IPT, IDX>::VEC, NIT = MergeTileRegs<S, IPT, IDX>::NIT;
     using AV = typename VecOf<A, VEC>::type;
     constexpr int BS = kMergeBlock;
     constexpr int L = BS * IPT;
@@ -318,22 +347,24 @@ __device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT> &R
         carry[t] = nnz_t > max(last_end, 0) ? s_prod[off + nnz_t - 1] : A(0);
 }
 
-// One tile, start to end.
-template <int S, int IPT, bool NT, class LDS, bool X32 = false>
+// One tile, start to end. `cols` is the int32 column array, or the merge
+// codes with their tile bases for IDX_D16/D8.
+template <int S, int IPT, bool NT, class LDS, bool X32 = false, int IDX = IDX_I32>
 __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict__ rp,
-                                           const int32_t *__restrict__ col,
+                                           const void *__restrict__ cols,
                                            const typename St<S>::V *__restrict__ val,
                                            const typename St<S>::X *__restrict__ x,
                                            typename St<S>::X *__restrict__ y,
                                            const int32_t *__restrict__ tile_i,
                                            const int32_t *__restrict__ tile_j,
                                            typename St<S>::A *__restrict__ carry, int32_t n_rows,
-                                           LDS &lds) {
-    MergeTileRegs<S, IPT> R;
-    merge_issue<S, IPT, NT>(t, rp, col, val, tile_i, tile_j, R);
-    typename St<S>::X xs[MergeTileRegs<S, IPT>::NIT][MergeTileRegs<S, IPT>::VEC];
-    merge_gather<S, IPT, X32>(R, x, xs);
-    merge_finish<S, IPT>(t, R, xs, y, carry, n_rows, lds);
+                                           LDS &lds, const int32_t *__restrict__ tile_base = nullptr,
+                                           int32_t n_cols = 0) {
+    MergeTileRegs<S, IPT, IDX> R;
+    merge_issue<S, IPT, NT, IDX>(t, rp, cols, val, tile_i, tile_j, tile_base, R);
+    typename St<S>::X xs[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC];
+    merge_gather<S, IPT, X32, IDX>(R, x, n_cols, xs);
+    merge_finish<S, IPT, LDS, IDX>(t, R, xs, y, carry, n_rows, lds);
 }
 
 // Rows spanning tiles: y[r] = (carries of the tiles that ended inside row r,

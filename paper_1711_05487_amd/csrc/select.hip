@@ -49,8 +49,12 @@ double plan_bytes(const csr_matrix_s *A, const Plan &P) {
     double b = (double)A->nnz * (vb + ib) + 4.0 * (A->n_rows + 1) + xb * A->n_cols +
                xb * A->n_rows;
     if (P.opts & CSR_OPT_MERGE) {
+        // tile table, carries written (and read back by the fixup pass),
+        // and the tile bases of the merge codes
         const double T = (double)A->n_tiles;
-        b += 2.0 * 4.0 * (T + 1) + 2.0 * (A->storage == CSR_VAL_F64 ? 8.0 : 4.0) * T;
+        const double ab = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
+        b += 2.0 * 4.0 * (T + 1) + (A->tiles_fixup ? 2.0 : 1.0) * ab * T;
+        if (P.idx != IDX_I32) b += 4.0 * T;
     }
     if (P.long_rows && A->n_long > 0) {
         const double ab = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
@@ -113,8 +117,39 @@ csr_status_t build_tiles(csr_matrix_s *A, int L, hipStream_t s) {
                                    A->tile_i.as<int32_t>(), A->tile_j.as<int32_t>(), s));
     A->n_tiles = T;
     A->tiles_L = L;
+    A->mcodes_L = 0;  // merge codes belong to the previous tiles
     A->tiles_slack = slack;
     A->tiles_fixup = slack == 0;  // row-aligned tiles leave nothing to fix up
+    return CSR_OK;
+}
+
+// Merge codes (MB remedy on the merge path, Table II): the narrowest width
+// (8, else 16 bits) that holds every tile's column range; 32 = not eligible.
+csr_status_t build_merge_codes(csr_matrix_s *A, hipStream_t s) {
+    if (A->mcodes_L == A->tiles_L && A->mcode_bits != 0) return CSR_OK;
+    const int64_t T = A->n_tiles;
+    csr_status_t st;
+    if ((st = A->tile_base.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(T, 1))) != CSR_OK)
+        return st;
+    DevBuf range;
+    if ((st = range.alloc(sizeof(int32_t))) != CSR_OK) return st;
+    CSR_HIP(hipMemsetAsync(range.p, 0, sizeof(int32_t), s));
+    CSR_HIP(launch_merge_tile_range(A->col.as<int32_t>(), A->tile_j.as<int32_t>(), T,
+                                    A->tile_base.as<int32_t>(), range.as<int32_t>(), s));
+    int32_t r = 0;
+    CSR_HIP(hipMemcpyAsync(&r, range.p, sizeof(r), hipMemcpyDeviceToHost, s));
+    CSR_HIP(hipStreamSynchronize(s));
+    const int bits = r < (1 << 8) ? 8 : r < (1 << 16) ? 16 : 32;
+    if (bits != 32) {
+        if ((st = A->mcodes.alloc((size_t)A->nnz * (bits / 8) + kPadBytes)) != CSR_OK) return st;
+        CSR_HIP(hipMemsetAsync(A->mcodes.as<char>() + (size_t)A->nnz * (bits / 8), 0, kPadBytes,
+                               s));
+        CSR_HIP(launch_merge_encode(A->col.as<int32_t>(), A->tile_j.as<int32_t>(), T,
+                                    A->tile_base.as<int32_t>(), bits, A->mcodes.p, s));
+        CSR_HIP(hipStreamSynchronize(s));
+    }
+    A->mcode_bits = bits;
+    A->mcodes_L = A->tiles_L;
     return CSR_OK;
 }
 
@@ -197,6 +232,15 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
             return fail(CSR_ERR_INVALID_ARG, "merge_items must be 256, 512 or 1024");
         if ((st = build_tiles(A, L, s)) != CSR_OK) return st;
         P.L = L;
+        if (opts & CSR_OPT_DELTA) {
+            // MB: tile-base codes when every tile's column range fits 8 or
+            // 16 bits (streamed, like the compressed arrays of the remedy)
+            if ((st = build_merge_codes(A, s)) != CSR_OK) return st;
+            if (A->mcode_bits == 8 || A->mcode_bits == 16) {
+                P.idx = A->mcode_bits == 8 ? IDX_D8 : IDX_D16;
+                P.nt = 1;
+            }
+        }
         P.G = 0;
         P.U = 1;
         P.R = 1;

@@ -43,6 +43,22 @@ def test_batched_bit_identical_to_single_merge():
         assert torch.equal(ys[k][:n], single[:n]), k
 
 
+def test_batched_bit_identical_to_single_merge_codes():
+    """Single launches on merge codes (MERGE|DELTA) against the batch, which
+    reads int32 columns: the same partition and arithmetic, the same bits."""
+    mats, hs = batch_mats(12)
+    for k, A in enumerate(hs):
+        A.select("forced", forced_opts=pkg.OPT_MERGE | pkg.OPT_DELTA, merge_items=(256, 512)[k % 2])
+    xs, ys = vectors(mats, 150)
+    pkg.spmv_batched(hs, xs, ys)
+    torch.cuda.synchronize()
+    for k, A in enumerate(hs):
+        single = A.spmv(xs[k])
+        torch.cuda.synchronize()
+        n = mats[k][0]
+        assert torch.equal(ys[k][:n], single[:n]), k
+
+
 def test_batched_autotuned_matches_oracle_and_replays():
     mats, hs = batch_mats(40)
     eager = None

@@ -66,6 +66,45 @@ def test_dyadic_bit_exact(opts, L):
         assert np.array_equal(run(A, x, opts, L), oracle.spmv(rp, col, val, x)), (n, opts, L)
 
 
+@pytest.mark.parametrize("L", [256, 512])
+def test_merge_codes_bit_exact(L):
+    """MERGE|DELTA: tile bases and per-nonzero codes equal the oracle's at the
+    narrowest width that holds every tile's column range; matrices whose
+    tiles span more than 2^16 columns keep int32 columns."""
+    for name in ("lap100", "st27_24", "rmat14", "unif14", "unif17"):
+        n, m, rp, col, val = matrix(name)
+        A = pkg.CsrMatrix(rp, col, val)
+        info = A.select("forced", forced_opts=M | pkg.OPT_DELTA, merge_items=L)
+        ti, tj = oracle.merge_tiles(rp, L, info["merge_slack"])
+        want = 32
+        for w in (8, 16):
+            if oracle.merge_codes(tj, col, w) is not None:
+                want = w
+                break
+        assert info["delta_bits"] == want, (name, L)
+        if want == 32:
+            continue
+        base, codes = oracle.merge_codes(tj, col, want)
+        assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_BASE, np.int32), base)
+        got = A.debug_copy(pkg.DEBUG_MERGE_CODES, np.uint16 if want == 16 else np.uint8)
+        assert np.array_equal(got, codes), (name, L)
+
+
+def test_merge_codes_same_bits_as_int32_columns():
+    """The codes decode to the same columns: y is bit-identical to the int32
+    merge tiles of the same size."""
+    for name in ("lap100", "st27_24", "rmat14"):
+        n, m, rp, col, val = matrix(name)
+        x = xvec(name, m)
+        A = pkg.CsrMatrix(rp, col, val)
+        for L in (256, 512, 1024):
+            info = A.select("forced", forced_opts=M | pkg.OPT_DELTA, merge_items=L)
+            assert info["delta_bits"] in (8, 16)
+            y_codes = run(A, x)
+            y_i32 = run(A, x, M | pkg.OPT_PREFETCH, L)
+            assert np.array_equal(y_codes.view(np.uint64), y_i32.view(np.uint64)), (name, L)
+
+
 def test_all_4x4_patterns_bit_exact():
     pats = np.arange(1 << 16, dtype=np.int64)
     bits = ((pats[:, None] >> np.arange(16)) & 1).astype(bool).reshape(-1, 4, 4)
