@@ -8,8 +8,13 @@ inspector/executor split of the method); its cost is reported beside the
 rate, with the solver-iteration count that amortizes it (Sec. IV-D, Eq. (2)).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--select learned|profile|exhaustive|plain]
+    python bench.py --suite     # every configuration, one JSON line per case
 
-Prints one JSON line.
+Prints one JSON line (the suite: one per case). The product path is
+checked on the GPU against the plain row-split kernel (FP64: within
+2e-12 (|A||x|)_i, the scale from a second SpMV with |A| and |x|); the
+oracle is only timed, as the CPU baseline, and the parity tests compare
+every kernel with it.
 """
 from __future__ import annotations
 
@@ -49,6 +54,42 @@ def harmonic_runs(A, x, y, runs, calls):
         e1.synchronize()
         t.append(e0.elapsed_time(e1) / calls)
     return float(np.mean(t))  # 1 / harmonic mean of rates = arithmetic mean of times
+
+
+def n_iters_min(t_pre_ms, t_plain_ms, t_sel_ms):
+    """Solver iterations that amortize selection and preprocessing
+    (Sec. IV-D, Eq. (2)); None when the selected variant is not faster."""
+    return t_pre_ms / (t_plain_ms - t_sel_ms) if t_sel_ms < t_plain_ms else None
+
+
+class GpuCheck:
+    """The product path checked on the GPU: the plain row-split result and
+    the per-row scale (|A||x|)_i from a plain SpMV of |A| with |x|."""
+
+    def __init__(self, pkg, rp, col, val, x, n_cols):
+        import torch
+        self.x = torch.from_numpy(x).cuda()
+        P = pkg.CsrMatrix(rp, col, val, n_cols=n_cols)
+        self.y_plain = P.spmv(self.x)
+        Q = pkg.CsrMatrix(rp, col, np.abs(val), n_cols=n_cols)
+        self.absax = Q.spmv(self.x.abs())
+        torch.cuda.synchronize()
+        P.close()
+        Q.close()
+
+    def f64_ok(self, y):
+        import torch
+        return bool(torch.all((y - self.y_plain).abs() <= 2e-12 * self.absax).item())
+
+    def rel_errors(self, y):
+        """max and 99th percentile over rows of |y - y_f64| / (|A||x|)_i."""
+        import torch
+        ab = self.absax
+        m = ab > 0
+        rel = ((y.double() - self.y_plain).abs()[m] / ab[m]).cpu().numpy()
+        if rel.size == 0:
+            return 0.0, 0.0
+        return float(rel.max()), float(np.percentile(rel, 99))
 
 
 def kernel_source_sha():
@@ -104,14 +145,18 @@ def main():
                     help="learned (committed MLP), profile, exhaustive or plain")
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--suite", action="store_true",
+                    help="measure every configuration (one JSON line per case)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU row sharding is a design, not a built path)", file=sys.stderr)
         sys.exit(2)
 
+    if args.suite:
+        return suite(args)
+
     import torch
-    import oracle
     import paper_1711_05487_amd as pkg
     import synth
     from paper_1711_05487_amd import learn
@@ -151,12 +196,10 @@ def main():
     info = A.select(args.select)
 
     # correctness gate on the selected plan (untimed): every row
+    chk = GpuCheck(pkg, rp, col, val, x, M)
     A.spmv(xd, yd)
     torch.cuda.synchronize()
-    got = yd.cpu().numpy()
-    ref = oracle.spmv_accurate(rp, col, val, x)
-    ab = oracle.absax(rp, col, val, x)
-    ok = bool(np.all(np.abs(got - ref) <= 1e-12 * ab))
+    ok = chk.f64_ok(yd)
     if not ok:
         log("PARITY FAILURE on the selected plan")
 
@@ -221,7 +264,7 @@ def main():
             "create_ms": round(create_ms, 2),
             "select_ms": round(info["t_select_ms"], 3),
             "prep_ms": round(info["t_prep_ms"], 3),
-            "n_iters_min": (round(oracle.n_iters_min(t_pre, t_plain, ms), 1)
+            "n_iters_min": (round(n_iters_min(t_pre, t_plain, ms), 1)
                             if ms < t_plain else None),
             "parity_ok": ok,
             "timed_wall_ms": round(wall_ms, 2),
@@ -235,6 +278,186 @@ def main():
     A.close()
     if not ok:
         sys.exit(1)
+
+
+# ---------------------------------------------------------------------------
+# --suite: every configuration
+# ---------------------------------------------------------------------------
+
+def emit(rec):
+    print(json.dumps(rec), flush=True)
+
+
+def permuted(mat, seed=304):
+    """Symmetric permutation P A P^T with a seeded Fisher-Yates permutation."""
+    import synth
+    n, m, rp, col, val = mat
+    p = synth.permutation(n, seed)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    return synth.from_coo(p[rows], p[col.astype(np.int64)], val, n, m)
+
+
+def time_plan(A, xd, yd, runs=5, calls=128):
+    """(harmonic-protocol ms per call, dominant-kernel ms, kernel name)."""
+    t = harmonic_runs(A, xd, yd, runs, calls)
+    k_ms, _, kern = A.time_spmv(xd, yd, calls)
+    return t, k_ms, kern
+
+
+def suite(args):
+    import torch
+    import paper_1711_05487_amd as pkg
+    import synth
+    from paper_1711_05487_amd import learn
+
+    torch.cuda.set_device(0)
+    learn.install()
+    _, wm, wrp, wcol, wval = synth.laplacian2d(64)  # load the selection kernels once
+    W = pkg.CsrMatrix(wrp, wcol, wval, n_cols=wm)
+    for mode in ("learned", "profile"):
+        W.select(mode)
+    W.close()
+    triad = pkg.triad(1 << 30, 5) / 1e9
+    triad_mall = pkg.triad(48 << 20, 20) / 1e9
+    emit({"case": "triad", "hbm_gbs": round(triad, 1), "mall_gbs": round(triad_mall, 1),
+          "device": torch.cuda.get_device_name(0)})
+
+    configs = [
+        ("C1", "2-D 5-point Laplacian 100^2", lambda: synth.laplacian2d(100), 101),
+        ("C2", "27-point stencil 128^3", lambda: synth.stencil27(128), 203),
+        ("C3a", "R-MAT scale 22, edge factor 16", lambda: synth.rmat(22), 303),
+        ("C3a-perm", "R-MAT scale 22, seeded symmetric permutation",
+         lambda: permuted(synth.rmat(22)), 303),
+        ("C3b", "uniform random 2^20 x 16", lambda: synth.uniform_random(1 << 20, 16), 403),
+    ]
+    for tag, desc, gen, xseed in configs:
+        log(f"{tag}: generating {desc}")
+        n, m, rp, col, val = gen()
+        nnz = len(col)
+        x = synth.vector(m, xseed)
+        chk = GpuCheck(pkg, rp, col, val, x, m)
+        xd = chk.x
+        yd = torch.empty(n, dtype=torch.float64, device="cuda")
+        A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+        plain = A.select("plain")
+        t_plain, k_plain, kern_plain = time_plan(A, xd, yd)
+        for mode in ("plain", "learned", "profile", "exhaustive"):
+            log(f"{tag}: {mode}")
+            info = plain if mode == "plain" else A.select(mode)
+            t, k_ms, kern = (t_plain, k_plain, kern_plain) if mode == "plain" else time_plan(A, xd, yd)
+            A.spmv(xd, yd)
+            torch.cuda.synchronize()
+            ok = chk.f64_ok(yd)
+            fb = info["format_bytes"]
+            t_pre = info["t_select_ms"] + info["t_prep_ms"]
+            emit({"case": tag, "workload": f"{desc} (N={n:,}, NNZ={nnz:,})", "selector": mode,
+                  "opts": [nm for bit, nm in pkg.OPT_NAMES.items() if info["opts"] & bit],
+                  "variant_id": info["variant_id"], "merge_items": info["merge_items"],
+                  "lanes_per_row": info["lanes_per_row"], "delta_bits": info["delta_bits"],
+                  "ms": round(t, 5), "kernel_ms": round(k_ms, 5), "kernel": kern,
+                  "format_bytes": fb, "gbs": round(fb / (t * 1e-3) / 1e9, 1),
+                  "kernel_gbs": round(fb / (k_ms * 1e-3) / 1e9, 1),
+                  "pct_hbm_peak": round(100 * fb / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
+                  "pct_triad": round(100 * fb / (t * 1e-3) / 1e9 / triad, 2),
+                  "gflops": round(2 * nnz / (t * 1e-3) / 1e9, 2),
+                  "speedup_vs_plain": round(t_plain / t, 4),
+                  "select_ms": round(info["t_select_ms"], 3), "prep_ms": round(info["t_prep_ms"], 3),
+                  "select_cost_in_plain_spmvs": round(info["t_select_ms"] / t_plain, 2),
+                  "n_iters_min": (None if mode == "plain" or n_iters_min(t_pre, t_plain, t) is None
+                                  else round(n_iters_min(t_pre, t_plain, t), 1)),
+                  "classes": info["classes"], "parity_ok": ok})
+        if tag == "C3b":
+            # cold runs: a 1 GiB write between calls evicts L2 and the MALL
+            info = A.select("learned")
+            flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+            ts = []
+            for _ in range(20):
+                flush.zero_()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                A.spmv(xd, yd)
+                e1.record()
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            del flush
+            t = float(np.mean(ts[2:]))
+            fb = info["format_bytes"]
+            emit({"case": tag, "selector": "learned", "cold": True, "ms": round(t, 5),
+                  "gbs": round(fb / (t * 1e-3) / 1e9, 1)})
+        A.close()
+        del chk
+
+    # C4: value storage x index format on C1 and C2 (FP32 accumulation for f32/bf16)
+    for tag, desc, gen, xseed in configs[:2]:
+        n, m, rp, col, val = gen()
+        x = synth.vector(m, xseed)
+        chk = GpuCheck(pkg, rp, col, val, x, m)
+        x32 = chk.x.float()
+        for storage in ("f64", "f32", "bf16"):
+            A = pkg.CsrMatrix(rp, col, val, n_cols=m, storage=storage)
+            xs = chk.x if storage == "f64" else x32
+            ys = torch.empty(n, dtype=xs.dtype, device="cuda")
+            for index in ("int32", "delta"):
+                info = A.select("learned") if index == "int32" else A.select(
+                    "forced", forced_opts=pkg.OPT_DELTA)
+                if index == "delta" and info["delta_bits"] == 32:
+                    continue  # not eligible
+                t, k_ms, kern = time_plan(A, xs, ys)
+                A.spmv(xs, ys)
+                torch.cuda.synchronize()
+                mx, p99 = chk.rel_errors(ys)
+                fb = info["format_bytes"]
+                emit({"case": "C4", "config": tag, "storage": storage,
+                      "index": "int32" if info["delta_bits"] == 32 else f"delta{info['delta_bits']}",
+                      "opts": [nm for bit, nm in pkg.OPT_NAMES.items() if info["opts"] & bit],
+                      "ms": round(t, 5), "kernel_ms": round(k_ms, 5), "format_bytes": fb,
+                      "gbs": round(fb / (t * 1e-3) / 1e9, 1),
+                      "max_rel_err": mx, "p99_rel_err": p99})
+            A.close()
+        del chk
+
+    # C5-batch: 512 matrices, one graph-captured persistent launch against
+    # 512 separate launches, each matrix with its own selected plan
+    log("C5-batch: generating 512 matrices")
+    mats = [synth.batch_matrix(i) for i in range(512)]
+    hs, xs, ys, fbytes, rows = [], [], [], 0, 0
+    for k, (_, (n, m, rp, col, val)) in enumerate(mats):
+        A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+        fbytes += A.select("learned")["format_bytes"]
+        rows += n
+        hs.append(A)
+        xs.append(torch.from_numpy(synth.vector(m, 602 + k)).cuda())
+        ys.append(torch.empty(max(n, 1), dtype=torch.float64, device="cuda"))
+    pkg.spmv_batched(hs, xs, ys)  # plans, tiles and the graph are built here
+    torch.cuda.synchronize()
+    ref = [y.clone() for y in ys]
+
+    def timed(fn, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_batch = timed(lambda: pkg.spmv_batched(hs, xs, ys))
+    batch_ok = all(torch.equal(a, b) for a, b in zip(ys, ref))
+
+    def separate():
+        for A, x, y in zip(hs, xs, ys):
+            A.spmv(x, y)
+
+    t_sep = timed(separate)
+    emit({"case": "C5-batch", "matrices": len(hs), "rows": rows, "format_bytes": fbytes,
+          "batched_ms": round(t_batch, 4), "separate_ms": round(t_sep, 4),
+          "batched_gbs": round(fbytes / (t_batch * 1e-3) / 1e9, 1),
+          "separate_gbs": round(fbytes / (t_sep * 1e-3) / 1e9, 1),
+          "speedup": round(t_sep / t_batch, 3), "replay_identical": batch_ok})
+    for A in hs:
+        A.close()
 
 
 if __name__ == "__main__":
