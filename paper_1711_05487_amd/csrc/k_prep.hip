@@ -24,12 +24,14 @@ __global__ __launch_bounds__(kBlock) void k_validate(const int32_t *__restrict__
     if (wave == 0 && lane == 0) {
         if (rp[0] != 0 || (int64_t)rp[n_rows] != nnz) atomicOr(flags, 1);
     }
+    int32_t longest = 0;  // this wave's longest row; one atomic per wave at the end
     for (int64_t r = wave; r < n_rows; r += nwaves) {
         const int32_t b = rp[r], e = rp[r + 1];
         if (e < b || b < 0 || (int64_t)e > nnz) {
             if (lane == 0) atomicOr(flags, 2);
             continue;
         }
+        longest = max(longest, e - b);
         bool bad = false, unsorted = false;
         for (int32_t j = b + lane; j < e; j += kWave) {
             const int32_t c = col[j];
@@ -38,8 +40,8 @@ __global__ __launch_bounds__(kBlock) void k_validate(const int32_t *__restrict__
         }
         const uint64_t mb = __ballot(bad), mu = __ballot(unsorted);
         if (lane == 0 && (mb | mu)) atomicOr(flags, (mb ? 4 : 0) | (mu ? 8 : 0));
-        if (lane == 0) atomicMax(flags + 1, e - b);  // longest row
     }
+    if (lane == 0 && longest > 0) atomicMax(flags + 1, longest);
 }
 
 // FP64 -> BF16 with one round-to-nearest-even step, from the IEEE-754 binary64
@@ -160,23 +162,28 @@ __global__ __launch_bounds__(kBlock) void k_merge_partition(const int32_t *__res
 // Merge codes (MB remedy on the merge path): one wave per tile. Pass 1:
 // base[t] = smallest column of the tile's nonzeros, *max_range = the largest
 // max - min over the tiles. Pass 2: codes[j] = col[j] - base[t].
-__global__ __launch_bounds__(kWave) void k_merge_tile_range(const int32_t *__restrict__ col,
-                                                            const int32_t *__restrict__ tile_j,
-                                                            int32_t *__restrict__ base,
-                                                            int32_t *__restrict__ max_range) {
-    const int64_t t = blockIdx.x;
-    const int32_t j0 = tile_j[t], j1 = tile_j[t + 1];
-    int32_t mn = INT32_MAX, mx = INT32_MIN;
-    for (int32_t j = j0 + (int32_t)threadIdx.x; j < j1; j += kWave) {
-        mn = min(mn, col[j]);
-        mx = max(mx, col[j]);
+__global__ __launch_bounds__(kBlock) void k_merge_tile_range(const int32_t *__restrict__ col,
+                                                             const int32_t *__restrict__ tile_j,
+                                                             int64_t n_tiles,
+                                                             int32_t *__restrict__ base,
+                                                             int32_t *__restrict__ max_range) {
+    const int lane = threadIdx.x % kWave;
+    const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kBlock / kWave;
+    int32_t widest = 0;  // this wave's largest range; one atomic per wave at the end
+    for (int64_t t = wave; t < n_tiles; t += nwaves) {
+        const int32_t j0 = tile_j[t], j1 = tile_j[t + 1];
+        int32_t mn = INT32_MAX, mx = INT32_MIN;
+        for (int32_t j = j0 + lane; j < j1; j += kWave) {
+            mn = min(mn, col[j]);
+            mx = max(mx, col[j]);
+        }
+        mn = -group_max<kWave>(-mn);
+        mx = group_max<kWave>(mx);
+        if (lane == 0) base[t] = j1 > j0 ? mn : 0;
+        if (j1 > j0) widest = max(widest, mx - mn);
     }
-    mn = -group_max<kWave>(-mn);
-    mx = group_max<kWave>(mx);
-    if (threadIdx.x == 0) {
-        base[t] = j1 > j0 ? mn : 0;
-        if (j1 > j0) atomicMax(max_range, mx - mn);
-    }
+    if (lane == 0 && widest > 0) atomicMax(max_range, widest);
 }
 
 template <int BITS>
@@ -265,8 +272,9 @@ hipError_t launch_merge_partition(const int32_t *rp, int32_t n_rows, int64_t nnz
 hipError_t launch_merge_tile_range(const int32_t *col, const int32_t *tile_j, int64_t n_tiles,
                                    int32_t *base, int32_t *max_range, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_merge_tile_range, dim3((unsigned)n_tiles), dim3(kWave), 0, s, col, tile_j,
-                       base, max_range);
+    const unsigned g = grid_for(n_tiles * kWave, kBlock, 256 * 16);
+    hipLaunchKernelGGL(k_merge_tile_range, dim3(g), dim3(kBlock), 0, s, col, tile_j, n_tiles, base,
+                       max_range);
     return hipGetLastError();
 }
 
