@@ -16,6 +16,8 @@ struct BatchMat {
     void *carry;            // T tile carries
     int32_t n_rows;
     int32_t ipt;            // L = 64 * ipt (4, 8 or 16)
+    int32_t aligned;        // 1: tiles cut at row ends (no carries, rows reduced by lane groups)
+    int32_t reserved;
     int64_t tile_base;      // index of this matrix's first tile in the work queue
 };
 

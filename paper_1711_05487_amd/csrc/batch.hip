@@ -82,6 +82,8 @@ csr_status_t build(BatchPlan &B, int32_t count, const csr_matrix_t *A, const voi
         M.carry = B.carry.as<char>() + ab * base[k];
         M.n_rows = A[k]->n_rows;
         M.ipt = ipt[k];
+        M.aligned = merge_slack(A[k], L) > 0;
+        M.reserved = 0;
         M.tile_base = base[k];
         std::fill(im.begin() + base[k], im.begin() + base[k + 1], k);
     }

@@ -28,6 +28,13 @@ union BatchLds {
     MergeLds<S, 16> l16;
 };
 
+template <int IPT, bool ALN>
+__device__ __forceinline__ void tile(const BatchMat &M, int64_t t, MergeLds<S, IPT> &lds) {
+    merge_tile<S, IPT, true, MergeLds<S, IPT>, false, IDX_I32, ALN>(
+        t, M.rp, M.col, (const V *)M.val, (const X *)M.x, (X *)M.y, M.tile_i, M.tile_j,
+        (A *)M.carry, M.n_rows, lds);
+}
+
 __global__ __launch_bounds__(kMergeBlock) void k_batch(const BatchMat *__restrict__ mats,
                                                   const int32_t *__restrict__ item_mat,
                                                   int64_t n_items, int64_t per_xcd, int64_t nblk) {
@@ -37,15 +44,21 @@ __global__ __launch_bounds__(kMergeBlock) void k_batch(const BatchMat *__restric
     for (int64_t g = lb; g < n_items; g += nblk) {
         const BatchMat &M = mats[item_mat[g]];
         const int64_t t = g - M.tile_base;
-        if (M.ipt == 4)
-            merge_tile<S, 4, true>(t, M.rp, M.col, (const V *)M.val, (const X *)M.x, (X *)M.y,
-                                   M.tile_i, M.tile_j, (A *)M.carry, M.n_rows, lds.l4);
-        else if (M.ipt == 8)
-            merge_tile<S, 8, true>(t, M.rp, M.col, (const V *)M.val, (const X *)M.x, (X *)M.y,
-                                   M.tile_i, M.tile_j, (A *)M.carry, M.n_rows, lds.l8);
-        else
-            merge_tile<S, 16, true>(t, M.rp, M.col, (const V *)M.val, (const X *)M.x, (X *)M.y,
-                                    M.tile_i, M.tile_j, (A *)M.carry, M.n_rows, lds.l16);
+        if (M.aligned) {
+            if (M.ipt == 4)
+                tile<4, true>(M, t, lds.l4);
+            else if (M.ipt == 8)
+                tile<8, true>(M, t, lds.l8);
+            else
+                tile<16, true>(M, t, lds.l16);
+        } else {
+            if (M.ipt == 4)
+                tile<4, false>(M, t, lds.l4);
+            else if (M.ipt == 8)
+                tile<8, false>(M, t, lds.l8);
+            else
+                tile<16, false>(M, t, lds.l16);
+        }
         wave_lds_sync();  // LDS is reused by the next item
     }
 }
@@ -56,6 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_fixup(const BatchMat *__restri
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (g >= n_items) return;
     const BatchMat &M = mats[item_mat[g]];
+    if (M.aligned) return;  // no row spans two tiles
     merge_fixup_tile<S>(g - M.tile_base, M.rp, M.tile_i, M.tile_j, (const A *)M.carry, (X *)M.y,
                         M.n_rows);
 }

@@ -17,7 +17,8 @@
 // still open at the tile end leaves one carry per tile; rows split across
 // tiles are finished by k_merge_fixup, which adds the carries in tile order.
 // When every row has fewer than 64 nonzeros the tiles are cut at row ends
-// (the partition's slack), no row is split and the fixup is not launched.
+// (the partition's slack): no row is split, the fixup is not launched, and
+// each row is summed from LDS by its own group of lanes instead of the scan.
 // Every sum has a fixed order, so results are deterministic.
 //
 // Compiled once per storage type (-DCSR_STORAGE=0/1/2).
@@ -35,17 +36,18 @@ using V = typename St<S>::V;
 using X = typename St<S>::X;
 using A = typename St<S>::A;
 
-template <int IPT, bool NT, bool X32, int IDX>
+template <int IPT, bool NT, bool X32, int IDX, bool ALN>
 __global__ __launch_bounds__(kMergeBlock) void k_merge(
     const int32_t *__restrict__ rp, const void *__restrict__ cols, const V *__restrict__ val,
     const X *__restrict__ x, X *__restrict__ y, const int32_t *__restrict__ tile_i,
     const int32_t *__restrict__ tile_j, const int32_t *__restrict__ tile_base,
     A *__restrict__ carry, int32_t n_rows, int32_t n_cols, int64_t per_xcd, int64_t n_tiles) {
-    __shared__ MergeLds<S, IPT> lds;
+    using Lds = std::conditional_t<ALN, MergeLdsRows<S, IPT>, MergeLds<S, IPT>>;
+    __shared__ Lds lds;
     const int64_t t = xcd_logical_block(per_xcd);
     if (t >= n_tiles) return;
-    merge_tile<S, IPT, NT, MergeLds<S, IPT>, X32, IDX>(t, rp, cols, val, x, y, tile_i, tile_j,
-                                                       carry, n_rows, lds, tile_base, n_cols);
+    merge_tile<S, IPT, NT, Lds, X32, IDX, ALN>(t, rp, cols, val, x, y, tile_i, tile_j,
+                                                            carry, n_rows, lds, tile_base, n_cols);
 }
 
 __global__ __launch_bounds__(kBlock) void k_merge_fixup(const int32_t *__restrict__ rp,
@@ -68,18 +70,18 @@ struct MergeArgs {
     hipEvent_t after_main;
 };
 
-template <int IPT, bool NT, bool X32, int IDX>
+template <int IPT, bool NT, bool X32, int IDX, bool ALN>
 hipError_t go(const MergeArgs &a, hipStream_t s) {
     if (a.n_tiles == 0) return hipSuccess;
     const void *cols = IDX == IDX_I32 ? a.arr[1] : a.arr[2];
     const XcdGrid g = xcd_grid(a.n_tiles);
-    hipLaunchKernelGGL((k_merge<IPT, NT, X32, IDX>), dim3((unsigned)g.launched), dim3(kMergeBlock),
+    hipLaunchKernelGGL((k_merge<IPT, NT, X32, IDX, ALN>), dim3((unsigned)g.launched), dim3(kMergeBlock),
                        0, s, (const int32_t *)a.arr[0], cols, (const V *)a.arr[3],
                        (const X *)a.arr[4], (X *)a.arr[5], a.tile_i, a.tile_j, a.tile_base,
                        (A *)a.carry, a.n_rows, a.n_cols, g.per_xcd, a.n_tiles);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && a.after_main) e = hipEventRecord(a.after_main, s);
-    if (e != hipSuccess || a.n_tiles < 2 || !a.fixup) return e;
+    if (e != hipSuccess || a.n_tiles < 2 || ALN) return e;
     const unsigned fb = (unsigned)((a.n_tiles + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_merge_fixup, dim3(fb), dim3(kBlock), 0, s, (const int32_t *)a.arr[0],
                        a.tile_i, a.tile_j, (const A *)a.carry, (X *)a.arr[5], a.n_rows, a.n_tiles);
@@ -89,16 +91,16 @@ hipError_t go(const MergeArgs &a, hipStream_t s) {
 // int32 columns: streaming and 32-bit gathers chosen at run time; merge
 // codes always stream (they are the MB remedy's compressed arrays) and
 // gather through the tile's x range
-template <int IPT>
+template <int IPT, bool ALN>
 hipError_t go_ipt(bool nt, bool x32, int idx, const MergeArgs &a, hipStream_t s) {
     switch (idx) {
-    case IDX_D16: return go<IPT, true, false, IDX_D16>(a, s);
-    case IDX_D8: return go<IPT, true, false, IDX_D8>(a, s);
+    case IDX_D16: return go<IPT, true, false, IDX_D16, ALN>(a, s);
+    case IDX_D8: return go<IPT, true, false, IDX_D8, ALN>(a, s);
     default: break;
     }
     if (nt)
-        return x32 ? go<IPT, true, true, IDX_I32>(a, s) : go<IPT, true, false, IDX_I32>(a, s);
-    return x32 ? go<IPT, false, true, IDX_I32>(a, s) : go<IPT, false, false, IDX_I32>(a, s);
+        return x32 ? go<IPT, true, true, IDX_I32, ALN>(a, s) : go<IPT, true, false, IDX_I32, ALN>(a, s);
+    return x32 ? go<IPT, false, true, IDX_I32, ALN>(a, s) : go<IPT, false, false, IDX_I32, ALN>(a, s);
 }
 
 }  // namespace
@@ -114,10 +116,13 @@ hipError_t CSR_CAT(launch_merge_s, CSR_STORAGE)(int ipt, bool nt, bool x32, bool
                                                 hipStream_t s) {
     const MergeArgs a{arr, tile_i, tile_j, tile_base, carry, n_rows, n_cols, n_tiles, fixup,
                       after_main};
+    // row-aligned tiles (no fixup) reduce by rows, the others by a
+    // segmented scan with carries
     switch (ipt) {
-    case 4: return go_ipt<4>(nt, x32, idx, a, s);
-    case 8: return go_ipt<8>(nt, x32, idx, a, s);
-    case 16: return go_ipt<16>(nt, x32, idx, a, s);
+    case 4: return fixup ? go_ipt<4, false>(nt, x32, idx, a, s) : go_ipt<4, true>(nt, x32, idx, a, s);
+    case 8: return fixup ? go_ipt<8, false>(nt, x32, idx, a, s) : go_ipt<8, true>(nt, x32, idx, a, s);
+    case 16:
+        return fixup ? go_ipt<16, false>(nt, x32, idx, a, s) : go_ipt<16, true>(nt, x32, idx, a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -93,6 +93,11 @@ template <int S, int IPT> struct MergeLds {
     alignas(16) A prod[L];            // products, then their segmented prefix sums
     alignas(16) uint8_t head[L + BS]; // 1 where a row starts inside the tile; [L, L+BS) dummies
 };
+// Row-aligned tiles need only the products. LDS is what bounds the number of
+// resident tiles per CU, so the smaller footprint raises the loads in flight.
+template <int S, int IPT> struct MergeLdsRows {
+    alignas(16) typename St<S>::A prod[kMergeBlock * IPT];
+};
 
 // Tile t: rows i0 = tile_i[t] .. i1 = tile_i[t+1] end inside it; nonzeros
 // j0 = tile_j[t] .. j1 = tile_j[t+1] - 1 belong to it. One wave of BS = 64
@@ -347,9 +352,238 @@ __device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT, ID
         carry[t] = nnz_t > max(last_end, 0) ? s_prod[off + nnz_t - 1] : A(0);
 }
 
+// Sum of s[b .. e) in index order, starting from +0.
+template <class A> __device__ __forceinline__ A lds_run_sum(const A *s, int b, int e) {
+    A v = A(0);
+    int p = b;
+    for (; p + 4 <= e; p += 4) {
+        v += s[p];
+        v += s[p + 1];
+        v += s[p + 2];
+        v += s[p + 3];
+    }
+    for (; p < e; ++p) v += s[p];
+    return v;
+}
+
+// Row-aligned tiles (the partition cut every tile at a row end, so each row
+// of the tile has all of its nonzeros in it and nothing is carried). The
+// vector memory pipeline, not the arithmetic, bounds these tiles: every
+// 64-lane load costs the texture path one cache access per group of four
+// lanes and distinct line. So the columns (or codes) are read as one wide
+// vector per lane (lane l: window elements [l IPT, (l+1) IPT)), passed
+// through LDS so that gather k reads element 64 k + l (four lanes of a
+// group gather consecutive nonzeros, which share lines on banded and
+// stencil rows), and the gathered x goes back through LDS to meet the
+// values, which keep their wide loads.
+template <int S, int IPT, int IDX = IDX_I32> struct MergeRowRegs {
+    using V = typename St<S>::V;
+    using C = typename MergeCol<IDX>::type;
+    static constexpr int VEC = merge_vec<S>();
+    static constexpr int NIT = IPT / VEC;
+    static constexpr int CW = IPT * (int)sizeof(C) >= 16 ? 16 / (int)sizeof(C) : IPT;
+    static constexpr int NCC = IPT / CW;  // column vectors per lane
+    using VV = typename VecOfU<V, VEC>::type;
+    using CC = typename VecOfU<C, CW>::type;
+    int32_t i0, i1, j0, j1;  // the tile's bounds (wave-uniform)
+    int32_t base;            // merge codes: the tile's smallest column
+    int32_t re[IPT];         // rp[i0 + r + 1] for rows r = lane + q * BS, as in MergeTileRegs
+    VV vv[NIT];              // values: blocks of BS vectors, as in MergeTileRegs
+    CC cc[NCC];              // columns (or codes) of window elements [lane IPT, (lane+1) IPT)
+};
+
+template <int S, int IPT, bool NT, int IDX = IDX_I32>
+__device__ __forceinline__ void merge_issue_rows(int64_t t, const int32_t *__restrict__ rp,
+                                                 const void *__restrict__ cols,
+                                                 const typename St<S>::V *__restrict__ val,
+                                                 const int32_t *__restrict__ tile_i,
+                                                 const int32_t *__restrict__ tile_j,
+                                                 const int32_t *__restrict__ tile_base,
+                                                 MergeRowRegs<S, IPT, IDX> &R) {
+    using Rg = MergeRowRegs<S, IPT, IDX>;
+    using V = typename St<S>::V;
+    using C = typename Rg::C;
+    constexpr int VEC = Rg::VEC, NIT = Rg::NIT, CW = Rg::CW, NCC = Rg::NCC;
+    constexpr int BS = kMergeBlock;
+    constexpr int STEP = BS * VEC;
+    const uint32_t tid = threadIdx.x;
+    R.i0 = tile_i[t];
+    R.i1 = tile_i[t + 1];
+    R.j0 = tile_j[t];
+    R.j1 = tile_j[t + 1];
+    R.base = IDX == IDX_I32 ? 0 : tile_base[t];
+    const uint32_t nnz_t = (uint32_t)(R.j1 - R.j0);
+    // value window: whole VEC vectors; column window: whole CW vectors (at
+    // most CW - 1 elements past j1, a neighbouring tile's or the padding)
+    const uint32_t nwin = nnz_t ? ((nnz_t - 1) & ~(uint32_t)(VEC - 1)) + VEC : 0u;
+    const uint32_t ncw = nnz_t ? ((nnz_t - 1) / CW + 1) * CW : 0u;
+    const uint32_t nre = (uint32_t)(R.i1 - R.i0);
+    const auto rr = buffer_range(rp + R.i0 + 1, nre * (uint32_t)sizeof(int32_t));
+    if (nre <= (uint32_t)BS) {
+        R.re[0] = buffer_load<int32_t, false>(rr, tid * 4u, 0u);
+#pragma unroll
+        for (int q = 1; q < IPT; ++q) R.re[q] = 0;
+    } else {
+#pragma unroll
+        for (int q = 0; q < IPT; ++q)
+            R.re[q] = buffer_load<int32_t, false>(rr, tid * 4u, (uint32_t)(q * BS * 4));
+    }
+    const auto rc = buffer_range(static_cast<const C *>(cols) + R.j0, ncw * (uint32_t)sizeof(C));
+    const auto rv = buffer_range(val + R.j0, nwin * (uint32_t)sizeof(V));
+#pragma unroll
+    for (int c = 0; c < NCC; ++c)
+        R.cc[c] = buffer_load<typename Rg::CC, NT>(rc, tid * (uint32_t)(IPT * sizeof(C)),
+                                                   (uint32_t)(c * CW * sizeof(C)));
+#pragma unroll
+    for (int it = 0; it < NIT; ++it)
+        R.vv[it] = buffer_load<typename Rg::VV, NT>(rv, tid * (uint32_t)(VEC * sizeof(V)),
+                                                   (uint32_t)(it * STEP * sizeof(V)));
+}
+
+// x at window element k * BS + lane, for k < IPT (the columns pass through
+// the LDS buffer, which is free again on return).
+template <int S, int IPT, bool X32, int IDX, class LDS>
+__device__ __forceinline__ void merge_gather_rows(const MergeRowRegs<S, IPT, IDX> &R,
+                                                  const typename St<S>::X *__restrict__ x,
+                                                  int32_t n_cols, LDS &lds,
+                                                  typename St<S>::X (&xv)[IPT]) {
+    using Rg = MergeRowRegs<S, IPT, IDX>;
+    using X = typename St<S>::X;
+    using C = typename Rg::C;
+    constexpr int CW = Rg::CW, NCC = Rg::NCC;
+    constexpr int BS = kMergeBlock;
+    static_assert(sizeof(C) <= sizeof(lds.prod[0]), "columns fit the product buffer");
+    C *s_col = reinterpret_cast<C *>(lds.prod);
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < NCC; ++c)
+        *reinterpret_cast<typename Rg::CC *>(s_col + tid * IPT + c * CW) = R.cc[c];
+    wave_lds_sync();
+    C cl[IPT];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) cl[k] = s_col[k * BS + tid];
+    wave_lds_sync();
+    if constexpr (IDX != IDX_I32) {
+        // a code reaches at most 2^16 - 1 past the base (see merge_gather)
+        const uint32_t nx = (uint32_t)min(n_cols - R.base, 1 << 16);
+        const auto rx = buffer_range(x + R.base, nx * (uint32_t)sizeof(X));
+#pragma unroll
+        for (int k = 0; k < IPT; ++k)
+            xv[k] = buffer_load<X, false>(rx, (uint32_t)cl[k] * (uint32_t)sizeof(X), 0u);
+    } else {
+        (void)n_cols;
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            if constexpr (X32)
+                xv[k] = *reinterpret_cast<const X *>(reinterpret_cast<const char *>(x) +
+                                                     (uint32_t)cl[k] * (uint32_t)sizeof(X));
+            else
+                xv[k] = x[cl[k]];
+        }
+    }
+}
+
+// Row sums of a row-aligned tile from its products in LDS (window order).
+// With at most 64 rows, every row gets a group of g = 2^k lanes (the
+// largest g with g * rows <= 64): lane `sub` of the group sums the sub-th
+// contiguous chunk of the row in index order, and the group adds its chunks
+// pairwise. With more rows than lanes, lane l sums rows l, l + 64, ...
+// alone. `re` holds the row ends as MergeTileRegs does.
+template <int IPT, class A, class X>
+__device__ __forceinline__ void merge_row_sums(int32_t i0, int32_t i1, int32_t j0,
+                                               const int32_t (&re)[IPT], const A *s_prod,
+                                               X *__restrict__ y) {
+    constexpr int BS = kMergeBlock;
+    const int tid = threadIdx.x;
+    const int nre = i1 - i0;  // rows of the tile
+    X *yb = y + i0;
+    if (nre > BS) {
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) {
+            if (q * BS < nre) {
+                const int r = tid + q * BS;
+                const int32_t end = re[q] - j0;
+                int32_t prev = dpp_move<kDppWaveShr1, 0xF>(end);  // end of row r - 1
+                if (q > 0) {
+                    const int32_t wrap = __builtin_amdgcn_readlane(re[q - 1], BS - 1) - j0;
+                    if (tid == 0) prev = wrap;
+                }
+                const int32_t start = r == 0 ? 0 : prev;
+                if (r < nre) yb[r] = (X)lds_run_sum(s_prod, start, end);
+            }
+        }
+    } else if (nre > 0) {
+        const int lg = 6 - (nre <= 1 ? 0 : 32 - __clz(nre - 1));  // g * nre <= 64
+        const int k = tid >> lg, sub = tid & ((1 << lg) - 1);
+        const int32_t e0 = re[0] - j0;
+        const int32_t end = __shfl(e0, min(k, nre - 1));
+        const int32_t start = __shfl(e0, max(min(k - 1, nre - 1), 0));
+        const int32_t b = k == 0 ? 0 : start;
+        const int32_t chunk = (end - b + (1 << lg) - 1) >> lg;
+        const int32_t cb = min(b + sub * chunk, end);
+        A v = lds_run_sum(s_prod, cb, min(cb + chunk, end));
+        for (int off = (1 << lg) >> 1; off > 0; off >>= 1) v += __shfl_down(v, off);
+        if (sub == 0 && k < nre) yb[k] = (X)v;
+    }
+}
+
+// Products of a row-aligned tile whose x was gathered in the values' layout.
+template <int S, int IPT, class LDS, int IDX>
+__device__ __forceinline__ void merge_finish_rows(const MergeTileRegs<S, IPT, IDX> &R,
+                                                  const typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX>::NIT]
+                                                                               [MergeTileRegs<S, IPT, IDX>::VEC],
+                                                  typename St<S>::X *__restrict__ y, LDS &lds) {
+    using A = typename St<S>::A;
+    constexpr int VEC = MergeTileRegs<S, IPT, IDX>::VEC, NIT = MergeTileRegs<S, IPT, IDX>::NIT;
+    using AV = typename VecOf<A, VEC>::type;
+    constexpr int STEP = kMergeBlock * VEC;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        AV pv;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) pv[e] = St<S>::cvt(R.vv[it][e]) * (A)xs[it][e];
+        *reinterpret_cast<AV *>(lds.prod + it * STEP + tid * VEC) = pv;
+    }
+    wave_lds_sync();
+    merge_row_sums<IPT>(R.i0, R.i1, R.j0, R.re, lds.prod, y);
+}
+
+// Products of a row-aligned tile whose x was gathered in window order
+// (element k * 64 + lane): x goes through LDS to meet the values.
+template <int S, int IPT, class LDS, int IDX>
+__device__ __forceinline__ void merge_finish_rows(const MergeRowRegs<S, IPT, IDX> &R,
+                                                  const typename St<S>::X (&xv)[IPT],
+                                                  typename St<S>::X *__restrict__ y, LDS &lds) {
+    using X = typename St<S>::X;
+    using A = typename St<S>::A;
+    constexpr int VEC = MergeRowRegs<S, IPT, IDX>::VEC, NIT = MergeRowRegs<S, IPT, IDX>::NIT;
+    using AV = typename VecOf<A, VEC>::type;
+    using XV = typename VecOf<X, VEC>::type;
+    static_assert(sizeof(X) == sizeof(A), "x is staged in the product buffer");
+    constexpr int BS = kMergeBlock;
+    constexpr int STEP = BS * VEC;
+    A *s_prod = lds.prod;
+    X *s_x = reinterpret_cast<X *>(lds.prod);
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) s_x[k * BS + tid] = xv[k];
+    wave_lds_sync();
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const XV xp = *reinterpret_cast<const XV *>(s_x + it * STEP + tid * VEC);
+        AV pv;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) pv[e] = St<S>::cvt(R.vv[it][e]) * (A)xp[e];
+        *reinterpret_cast<AV *>(s_prod + it * STEP + tid * VEC) = pv;
+    }
+    wave_lds_sync();
+    merge_row_sums<IPT>(R.i0, R.i1, R.j0, R.re, s_prod, y);
+}
+
 // One tile, start to end. `cols` is the int32 column array, or the merge
 // codes with their tile bases for IDX_D16/D8.
-template <int S, int IPT, bool NT, class LDS, bool X32 = false, int IDX = IDX_I32>
+template <int S, int IPT, bool NT, class LDS, bool X32 = false, int IDX = IDX_I32, bool ALN = false>
 __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict__ rp,
                                            const void *__restrict__ cols,
                                            const typename St<S>::V *__restrict__ val,
@@ -360,11 +594,30 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
                                            typename St<S>::A *__restrict__ carry, int32_t n_rows,
                                            LDS &lds, const int32_t *__restrict__ tile_base = nullptr,
                                            int32_t n_cols = 0) {
-    MergeTileRegs<S, IPT, IDX> R;
-    merge_issue<S, IPT, NT, IDX>(t, rp, cols, val, tile_i, tile_j, tile_base, R);
-    typename St<S>::X xs[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC];
-    merge_gather<S, IPT, X32, IDX>(R, x, n_cols, xs);
-    merge_finish<S, IPT, LDS, IDX>(t, R, xs, y, carry, n_rows, lds);
+    if constexpr (ALN && IDX != IDX_I32) {
+        // codes: one wide load per lane, gathers in window order
+        (void)carry;
+        (void)n_rows;
+        MergeRowRegs<S, IPT, IDX> R;
+        merge_issue_rows<S, IPT, NT, IDX>(t, rp, cols, val, tile_i, tile_j, tile_base, R);
+        typename St<S>::X xv[IPT];
+        merge_gather_rows<S, IPT, X32, IDX>(R, x, n_cols, lds, xv);
+        merge_finish_rows<S, IPT, LDS, IDX>(R, xv, y, lds);
+    } else if constexpr (ALN) {
+        (void)carry;
+        (void)n_rows;
+        MergeTileRegs<S, IPT, IDX> R;
+        merge_issue<S, IPT, NT, IDX>(t, rp, cols, val, tile_i, tile_j, tile_base, R);
+        typename St<S>::X xs[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC];
+        merge_gather<S, IPT, X32, IDX>(R, x, n_cols, xs);
+        merge_finish_rows<S, IPT, LDS, IDX>(R, xs, y, lds);
+    } else {
+        MergeTileRegs<S, IPT, IDX> R;
+        merge_issue<S, IPT, NT, IDX>(t, rp, cols, val, tile_i, tile_j, tile_base, R);
+        typename St<S>::X xs[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC];
+        merge_gather<S, IPT, X32, IDX>(R, x, n_cols, xs);
+        merge_finish<S, IPT, LDS, IDX>(t, R, xs, y, carry, n_rows, lds);
+    }
 }
 
 // Rows spanning tiles: y[r] = (carries of the tiles that ended inside row r,
