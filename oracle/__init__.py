@@ -64,6 +64,7 @@ def lib():
             "or_delta_decode": (None, [i32, P, P, c_int, P]),
             "or_merge_tiles": (i64, [i32, P, i64, i64, P, P]),
             "or_merge_codes": (c_int, [i64, P, P, c_int, P, P]),
+            "or_window_codes": (c_int, [i64, P, P, c_int, P, P, P, P]),
             "or_long_rows": (i32, [i32, P, i64, P]),
             "or_features": (None, [i32, i32, P, P, P, P]),
         }
@@ -261,6 +262,27 @@ def merge_codes(tj, col, w: int):
     if not lib().or_merge_codes(T, _p(tj), _p(col), w, _p(base), codes.ctypes.data_as(ctypes.c_void_p)):
         return None
     return base[:T], codes[:col.size]
+
+
+def window_codes(tj, col, maxw: int = 256):
+    """Window codes of row-aligned merge tiles (MB + ML remedies, Table II):
+    per tile t the ascending distinct columns u_0 < ... < u_{m-1}, stored as
+    base_t = u_0 and dict[t, k] = u_k - u_0; per nonzero the rank of its
+    column in the window. Returns (base, wlen, dict, codes) with dict of
+    shape (T, maxw), zero past wlen; None when some tile has more than maxw
+    distinct columns or a column range of 2^16 or more."""
+    tj = np.ascontiguousarray(tj, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    T = tj.size - 1
+    base = np.zeros(max(T, 1), dtype=np.int32)
+    wlen = np.zeros(max(T, 1), dtype=np.int32)
+    dct = np.zeros((max(T, 1), maxw), dtype=np.uint16)
+    codes = np.zeros(max(col.size, 1), dtype=np.uint8)
+    if not lib().or_window_codes(T, _p(tj), _p(col), maxw, _p(base), _p(wlen),
+                                 dct.ctypes.data_as(ctypes.c_void_p),
+                                 codes.ctypes.data_as(ctypes.c_void_p)):
+        return None
+    return base[:T], wlen[:T], dct[:T], codes[:col.size]
 
 
 def merge_tiles(rp, L: int, slack: int = 0):

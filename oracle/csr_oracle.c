@@ -303,6 +303,56 @@ int or_merge_codes(int64_t T, const int32_t *tj, const int32_t *col, int w,
     return 1;
 }
 
+/* MB and ML remedies together on row-aligned merge tiles (Table II: index  */
+/* compression; x brought close before use, the counterpart of prefetching  */
+/* x). Tile t's distinct columns, ascending, u_0 < ... < u_{m-1}, form its  */
+/* window: base_t = u_0, dict[t][k] = u_k - u_0 (16 bits), and nonzero j    */
+/* of the tile stores the 8-bit rank k of col[j] in the window. Eligible    */
+/* iff every tile has m <= maxw (at most 256) and u_{m-1} - u_0 < 2^16.      */
+/* dict is T rows of maxw entries, zero past wlen[t] = m. Returns 1 and     */
+/* fills the outputs when eligible, else 0.                                  */
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+int or_window_codes(int64_t T, const int32_t *tj, const int32_t *col, int maxw,
+                    int32_t *base, int32_t *wlen, uint16_t *dict, uint8_t *codes)
+{
+    int64_t cap = 0;
+    for (int64_t t = 0; t < T; ++t)
+        if ((int64_t)tj[t + 1] - tj[t] > cap) cap = (int64_t)tj[t + 1] - tj[t];
+    int32_t *u = (int32_t *)malloc(sizeof(int32_t) * (size_t)(cap > 0 ? cap : 1));
+    int ok = 1;
+    for (int64_t t = 0; t < T && ok; ++t) {
+        int64_t n = (int64_t)tj[t + 1] - tj[t], m = 0;
+        for (int64_t k = 0; k < n; ++k) u[k] = col[tj[t] + k];
+        qsort(u, (size_t)n, sizeof(int32_t), cmp_i32);
+        for (int64_t k = 0; k < n; ++k)
+            if (k == 0 || u[k] != u[m - 1]) u[m++] = u[k];
+        if (m > maxw || (m > 0 && (int64_t)u[m - 1] - u[0] >= 65536)) {
+            ok = 0;
+            break;
+        }
+        base[t] = m > 0 ? u[0] : 0;
+        wlen[t] = (int32_t)m;
+        for (int64_t k = 0; k < maxw; ++k)
+            dict[t * maxw + k] = k < m ? (uint16_t)(u[k] - u[0]) : 0;
+        for (int64_t j = tj[t]; j < tj[t + 1]; ++j) {
+            int64_t lo = 0, hi = m - 1; /* col[j] is in u[0..m) */
+            while (lo < hi) {
+                int64_t mid = (lo + hi) / 2;
+                if (u[mid] < col[j]) lo = mid + 1;
+                else hi = mid;
+            }
+            codes[j] = (uint8_t)lo;
+        }
+    }
+    free(u);
+    return ok;
+}
+
 /* ------------------------------------------------------------------------ */
 /* IMB remedy, decomposition (Sec. III-E, Figs. 5-6): rows with more than    */
 /* tau nonzeros are taken out of the row-parallel pass and computed          */

@@ -354,3 +354,80 @@ def test_merge_codes_laplacian_and_stencil_ranges():
     ti, tj = oracle.merge_tiles(rp, 512)
     assert oracle.merge_codes(tj, col, 16) is not None
     assert oracle.merge_codes(tj, col, 8) is None
+
+
+# ------------------------------------------------- window codes (row-aligned tiles)
+
+def _aligned_tiles(rp, L):
+    """Row-aligned merge tiles: slack = longest row + 1 (rows under 64 nonzeros)."""
+    s = int(np.diff(rp.astype(np.int64)).max()) + 1
+    assert s <= 64 and s < L
+    return oracle.merge_tiles(rp, L, s)
+
+
+@pytest.mark.parametrize("name,L", [("lap", 256), ("lap", 512), ("st27", 512), ("rand", 128)])
+def test_window_codes_decode_and_window_order(name, L):
+    if name == "lap":
+        n, _, rp, col, _ = synth.laplacian2d(60)
+    elif name == "st27":
+        n, _, rp, col, _ = synth.stencil27(12)
+    else:
+        n, _, rp, col, _ = synth.tiny_random(300, 2000, 0.01, 5)
+    ti, tj = _aligned_tiles(rp, L)
+    got = oracle.window_codes(tj, col)
+    assert got is not None
+    base, wlen, dct, codes = got
+    t_of = _tile_of_each_nonzero(tj, len(col))
+    # decode: base_t + dict[t, code_j] == col_j, and every code lies in the window
+    assert np.all(codes < wlen[t_of])
+    assert np.array_equal(base[t_of].astype(np.int64) + dct[t_of, codes].astype(np.int64), col)
+    for t in range(len(tj) - 1):
+        w = dct[t, :wlen[t]].astype(np.int64)
+        cols = col[tj[t]:tj[t + 1]]
+        # the window is exactly the tile's distinct columns, ascending (brute force)
+        assert list(w + base[t]) == sorted(set(int(c) for c in cols))
+        assert np.all(dct[t, wlen[t]:] == 0)
+
+
+def test_window_codes_laplacian_closed_form():
+    # 5-point Laplacian on n x n, row r = (y, x): columns r - n, r - 1, r, r + 1,
+    # r + n where they exist. A row-aligned tile holding rows [a, b) of one grid
+    # interior (1 <= x, y and x, y <= n - 2 for every row, b - a + 2 < n) has the
+    # three disjoint bands [a-n, b-1-n], [a-1, b], [a+n, b-1+n]: 3 (b - a) + 2
+    # distinct columns, the smallest a - n.
+    n = 100
+    _, _, rp, col, _ = synth.laplacian2d(n)
+    ti, tj = _aligned_tiles(rp, 256)
+    base, wlen, _, _ = oracle.window_codes(tj, col)
+    checked = 0
+    for t in range(len(tj) - 1):
+        a, b = int(ti[t]), int(ti[t + 1])
+        rows = np.arange(a, b)
+        if b <= a or b - a + 2 >= n:
+            continue
+        x, y = rows % n, rows // n
+        if x.min() < 1 or x.max() > n - 2 or y.min() < 1 or y.max() > n - 2:
+            continue
+        assert wlen[t] == 3 * (b - a) + 2
+        assert base[t] == a - n
+        checked += 1
+    assert checked > 10
+
+
+def test_window_codes_boundaries():
+    # one row per case; tile = whole matrix (L well above the row)
+    def one_row(cols):
+        rp = np.array([0, len(cols)], dtype=np.int32)
+        c = np.array(cols, dtype=np.int32)
+        ti, tj = oracle.merge_tiles(rp, 1024, len(cols) + 1)
+        return oracle.window_codes(tj, c)
+    # width: 256 distinct columns fit, 257 do not (maxw = 256)
+    assert one_row(list(range(0, 512, 2))) is not None          # 256 distinct
+    assert one_row(list(range(0, 514, 2))) is None              # 257 distinct
+    # range: max - min = 2^16 - 1 fits, 2^16 does not
+    assert one_row([5, 5 + 65535]) is not None
+    assert one_row([5, 5 + 65536]) is None
+    # repeated columns share one window entry and one code
+    base, wlen, dct, codes = one_row([7, 9, 9, 7, 12])
+    assert base[0] == 7 and wlen[0] == 3
+    assert list(dct[0, :3]) == [0, 2, 5] and list(codes) == [0, 1, 1, 0, 2]
