@@ -252,7 +252,7 @@ def main():
             "variant_id": info["variant_id"],
             "lanes_per_row": info["lanes_per_row"],
             "merge_items": info["merge_items"],
-            "delta_bits": info["delta_bits"],
+            "delta_bits": info["delta_bits"], "window_codes": bool(info["window_codes"]),
             "pct_of_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
             "pct_of_triad": round(100 * gbs / triad, 2),
             "triad_gbs": round(triad, 1),
@@ -398,8 +398,10 @@ def suite(args):
             xs = chk.x if storage == "f64" else x32
             ys = torch.empty(n, dtype=xs.dtype, device="cuda")
             for index in ("int32", "delta"):
-                info = A.select("learned") if index == "int32" else A.select(
-                    "forced", forced_opts=pkg.OPT_DELTA)
+                # merge-path tiles with int32 columns, then with the MB
+                # remedy's codes (window ranks or offsets, whichever applies)
+                opts = pkg.OPT_MERGE | (pkg.OPT_PREFETCH if index == "int32" else pkg.OPT_DELTA)
+                info = A.select("forced", forced_opts=opts)
                 if index == "delta" and info["delta_bits"] == 32:
                     continue  # not eligible
                 t, k_ms, kern = time_plan(A, xs, ys)
@@ -408,7 +410,8 @@ def suite(args):
                 mx, p99 = chk.rel_errors(ys)
                 fb = info["format_bytes"]
                 emit({"case": "C4", "config": tag, "storage": storage,
-                      "index": "int32" if info["delta_bits"] == 32 else f"delta{info['delta_bits']}",
+                      "index": ("int32" if info["delta_bits"] == 32 else "window8"
+                                if info["window_codes"] else f"delta{info['delta_bits']}"),
                       "opts": [nm for bit, nm in pkg.OPT_NAMES.items() if info["opts"] & bit],
                       "ms": round(t, 5), "kernel_ms": round(k_ms, 5), "format_bytes": fb,
                       "gbs": round(fb / (t * 1e-3) / 1e9, 1),

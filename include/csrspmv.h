@@ -105,7 +105,10 @@ typedef struct {
     int32_t merge_slack;     /* > 0: merge tiles cut at row ends (cuts every L - slack items
                                 moved to the end of the row in progress; no row spans two
                                 tiles); 0: plain cuts every L items */
-    int32_t reserved;
+    int32_t window_codes;    /* 1: the merge path's column codes are window ranks (delta_bits
+                                8): each row-aligned tile stores its distinct columns as
+                                16-bit offsets from its smallest one, each nonzero the 8-bit
+                                rank of its column among them */
     double p_csr, p_mb, p_ml, p_imb, p_cmp, p_peak;  /* flop/s (PROFILE) */
     double b_max;            /* B/s used for the bounds */
     double t_select_ms;      /* features/probes + decision */
@@ -205,7 +208,10 @@ csr_status_t csr_query(csr_matrix_t A, int32_t *n_rows, int32_t *n_cols, int64_t
  *         3 merge tile nonzero offsets int32[T+1], 4 long-row list int32[n],
  *         5 plan info (csr_plan_info_t), 6 merge codes (nnz uint8 or uint16:
  *         column - smallest column of the nonzero's merge tile), 7 merge tile
- *         bases int32[T] (the smallest column of each tile)
+ *         bases int32[T] (the smallest column of each tile), 8 window
+ *         dictionaries uint16[T][256] (the tile's distinct columns, ascending,
+ *         minus its base; zero past the window), 9 window lengths int32[T],
+ *         10 window codes uint8[nnz] (rank of the column in its tile's window)
  * Returns CSR_ERR_INVALID_ARG if `bytes` differs from the array's size
  * (*needed receives that size when non-NULL) or the array does not exist.
  * Synchronizes `stream`.

@@ -28,7 +28,8 @@ SELECT = {"plain": SEL_PLAIN, "profile": SEL_PROFILE, "learned": SEL_LEARNED,
           "exhaustive": SEL_EXHAUSTIVE, "forced": SEL_FORCED}
 
 (DEBUG_VALUES, DEBUG_CODES, DEBUG_TILE_I, DEBUG_TILE_J, DEBUG_LONG_ROWS, DEBUG_PLAN,
- DEBUG_MERGE_CODES, DEBUG_TILE_BASE) = range(8)
+ DEBUG_MERGE_CODES, DEBUG_TILE_BASE, DEBUG_WINDOW_DICT, DEBUG_WINDOW_LEN,
+ DEBUG_WINDOW_CODES) = range(11)
 
 STATUS = ["CSR_OK", "CSR_ERR_INVALID_ARG", "CSR_ERR_INVALID_MATRIX", "CSR_ERR_OUT_OF_MEMORY",
           "CSR_ERR_DEVICE", "CSR_ERR_UNSUPPORTED", "CSR_ERR_NOT_READY"]
@@ -60,7 +61,7 @@ class PlanInfo(ctypes.Structure):
                 ("variant_id", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
                 ("merge_items", ctypes.c_int32), ("delta_bits", ctypes.c_int32),
                 ("n_long_rows", ctypes.c_int32), ("fallback", ctypes.c_int32),
-                ("merge_slack", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("merge_slack", ctypes.c_int32), ("window_codes", ctypes.c_int32),
                 ("p_csr", ctypes.c_double), ("p_mb", ctypes.c_double), ("p_ml", ctypes.c_double),
                 ("p_imb", ctypes.c_double), ("p_cmp", ctypes.c_double),
                 ("p_peak", ctypes.c_double), ("b_max", ctypes.c_double),

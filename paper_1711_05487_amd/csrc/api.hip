@@ -134,7 +134,7 @@ size_t storage_bytes(int storage) {
 
 hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void *y,
                        hipStream_t s, hipEvent_t before, hipEvent_t after) {
-    const void *arr[7] = {A->rp.p, A->col.p, A->codes.p, A->val.p, x, y, nullptr};
+    const void *arr[8] = {A->rp.p, A->col.p, A->codes.p, A->val.p, x, y, nullptr, nullptr};
     if (before) {
         const hipError_t e = hipEventRecord(before, s);
         if (e != hipSuccess) return e;
@@ -146,7 +146,13 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
         auto ti = A->tile_i.as<int32_t>();
         auto tj = A->tile_j.as<int32_t>();
         const int32_t *tb = P.idx != IDX_I32 ? A->tile_base.as<int32_t>() : nullptr;
-        if (P.idx != IDX_I32) arr[2] = A->mcodes.p;
+        if (P.idx == IDX_W8) {
+            arr[2] = A->wcodes.p;
+            arr[6] = A->wdict.p;
+            arr[7] = A->wlen.p;
+        } else if (P.idx != IDX_I32) {
+            arr[2] = A->mcodes.p;
+        }
         const bool fix = A->tiles_fixup != 0;
         switch (A->storage) {
         case CSR_VAL_F64:
@@ -397,6 +403,24 @@ csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t by
         if (A->mcode_bits == 8 || A->mcode_bits == 16) {
             src = A->tile_base.p;
             n = sizeof(int32_t) * (size_t)A->n_tiles;
+        }
+        break;
+    case 8:  // window dictionaries
+        if (A->wcode_state == 1) {
+            src = A->wdict.p;
+            n = sizeof(uint16_t) * kWindowMax * (size_t)A->n_tiles;
+        }
+        break;
+    case 9:  // window lengths
+        if (A->wcode_state == 1) {
+            src = A->wlen.p;
+            n = sizeof(int32_t) * (size_t)A->n_tiles;
+        }
+        break;
+    case 10:  // window codes
+        if (A->wcode_state == 1) {
+            src = A->wcodes.p;
+            n = (size_t)A->nnz;
         }
         break;
     case 5:

@@ -18,7 +18,10 @@ constexpr int kWave = 64;
 constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies
 constexpr size_t kPadBytes = 64;  // tail padding of val/col: vector loads may read past nnz
 
-enum IdxMode { IDX_I32 = 0, IDX_D16 = 1, IDX_D8 = 2 };
+// IDX_W8: window codes of row-aligned merge tiles (8-bit rank of the column
+// among the tile's distinct columns; the tile's window dictionary maps it back)
+enum IdxMode { IDX_I32 = 0, IDX_D16 = 1, IDX_D8 = 2, IDX_W8 = 3 };
+constexpr int kWindowMax = 256;  // window entries per tile (8-bit ranks)
 
 // Error plumbing -------------------------------------------------------------
 void set_error(const std::string &msg);
@@ -97,6 +100,12 @@ struct csr_matrix_s {
     csr::DevBuf mcodes;            // merge codes: per-nonzero offset from its tile's base
     int32_t mcode_bits = 0;        // 8 / 16 when mcodes is valid, 32 = not eligible, 0 = not built
     int32_t mcodes_L = 0;          // tile size the merge codes were built for
+    csr::DevBuf wdict;             // window codes: per tile kWindowMax uint16 column offsets
+    csr::DevBuf wlen;              // window codes: window entries of each tile, T int32
+    csr::DevBuf wcodes;            // window codes: per-nonzero rank in its tile's window (uint8)
+    int32_t wcode_state = 0;       // 1 valid, -1 not eligible, 0 not built
+    int32_t wcodes_L = 0;          // tile size the window codes were built for
+    int64_t wdict_entries = 0;     // sum of the window lengths
     csr::DevBuf carry;             // per-tile carry of the merge-path kernel
     int64_t n_tiles = 0;
     int32_t tiles_L = 0;
@@ -144,13 +153,21 @@ hipError_t launch_merge_tile_range(const int32_t *col, const int32_t *tile_j, in
                                    int32_t *base, int32_t *max_range, hipStream_t s);
 hipError_t launch_merge_encode(const int32_t *col, const int32_t *tile_j, int64_t n_tiles,
                                const int32_t *base, int bits, void *codes, hipStream_t s);
+// Window codes: dict[t * kWindowMax + k] = k-th distinct column of tile t -
+// base[t], wlen[t] = distinct columns, codes[j] = rank of col[j]; *max_m =
+// the largest window (tiles over kWindowMax write nothing). Every tile's
+// column range must be below 2^16.
+hipError_t launch_window_encode(const int32_t *col, const int32_t *tile_j, const int32_t *base,
+                                int64_t n_tiles, uint16_t *dict, int32_t *wlen, uint8_t *codes,
+                                int32_t *max_m, hipStream_t s);
 // Merge tiles are cut at row ends (slack = longest row + 1) when every row is
 // shorter than this; otherwise slack = 0 and rows may span tiles.
 constexpr int32_t kMergeRowAlignMax = 64;
 
-// arr = {rp, col, codes, val, x, y}; L = 64 * ipt; x32: x spans < 4 GiB;
-// fixup: run the cross-tile fixup pass; idx != IDX_I32: arr[2] holds the
-// merge codes and tile_base the tile bases (columns = base + code)
+// arr = {rp, col, codes, val, x, y, window dict, window lengths}; L = 64 *
+// ipt; x32: x spans < 4 GiB; fixup: run the cross-tile fixup pass (tiles not
+// row-aligned); idx != IDX_I32: arr[2] holds the merge codes (or the window
+// ranks, IDX_W8, row-aligned tiles only) and tile_base the tile bases
 hipError_t launch_merge_s0(int ipt, bool nt, bool x32, bool fixup, int idx,
                            const int32_t *tile_base, int32_t n_cols, const void *const *arr,
                            const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,

@@ -41,13 +41,15 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge(
     const int32_t *__restrict__ rp, const void *__restrict__ cols, const V *__restrict__ val,
     const X *__restrict__ x, X *__restrict__ y, const int32_t *__restrict__ tile_i,
     const int32_t *__restrict__ tile_j, const int32_t *__restrict__ tile_base,
-    A *__restrict__ carry, int32_t n_rows, int32_t n_cols, int64_t per_xcd, int64_t n_tiles) {
+    A *__restrict__ carry, int32_t n_rows, int32_t n_cols, int64_t per_xcd, int64_t n_tiles,
+    const uint16_t *__restrict__ wdict, const int32_t *__restrict__ wlen) {
     using Lds = std::conditional_t<ALN, MergeLdsRows<S, IPT>, MergeLds<S, IPT>>;
     __shared__ Lds lds;
     const int64_t t = xcd_logical_block(per_xcd);
     if (t >= n_tiles) return;
     merge_tile<S, IPT, NT, Lds, X32, IDX, ALN>(t, rp, cols, val, x, y, tile_i, tile_j,
-                                                            carry, n_rows, lds, tile_base, n_cols);
+                                                            carry, n_rows, lds, tile_base, n_cols,
+                                                            wdict, wlen);
 }
 
 __global__ __launch_bounds__(kBlock) void k_merge_fixup(const int32_t *__restrict__ rp,
@@ -78,7 +80,8 @@ hipError_t go(const MergeArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_merge<IPT, NT, X32, IDX, ALN>), dim3((unsigned)g.launched), dim3(kMergeBlock),
                        0, s, (const int32_t *)a.arr[0], cols, (const V *)a.arr[3],
                        (const X *)a.arr[4], (X *)a.arr[5], a.tile_i, a.tile_j, a.tile_base,
-                       (A *)a.carry, a.n_rows, a.n_cols, g.per_xcd, a.n_tiles);
+                       (A *)a.carry, a.n_rows, a.n_cols, g.per_xcd, a.n_tiles,
+                       (const uint16_t *)a.arr[6], (const int32_t *)a.arr[7]);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && a.after_main) e = hipEventRecord(a.after_main, s);
     if (e != hipSuccess || a.n_tiles < 2 || ALN) return e;
@@ -89,13 +92,16 @@ hipError_t go(const MergeArgs &a, hipStream_t s) {
 }
 
 // int32 columns: streaming and 32-bit gathers chosen at run time; merge
-// codes always stream (they are the MB remedy's compressed arrays) and
-// gather through the tile's x range
+// codes and window codes always stream (they are the MB remedy's compressed
+// arrays) and gather through the tile's x range
 template <int IPT, bool ALN>
 hipError_t go_ipt(bool nt, bool x32, int idx, const MergeArgs &a, hipStream_t s) {
     switch (idx) {
     case IDX_D16: return go<IPT, true, false, IDX_D16, ALN>(a, s);
     case IDX_D8: return go<IPT, true, false, IDX_D8, ALN>(a, s);
+    case IDX_W8:
+        if constexpr (ALN) return go<IPT, true, false, IDX_W8, true>(a, s);
+        else return hipErrorInvalidValue;  // window codes need row-aligned tiles
     default: break;
     }
     if (nt)

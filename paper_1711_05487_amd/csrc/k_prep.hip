@@ -199,6 +199,83 @@ __global__ __launch_bounds__(kWave) void k_merge_encode(const int32_t *__restric
         static_cast<C *>(codes)[j] = (C)(col[j] - b);
 }
 
+// Window codes of row-aligned merge tiles (MB + ML remedies on the merge
+// path): tile t's distinct columns u_0 < ... < u_{m-1} are its x window,
+// stored as offsets from the tile base (dict, kWindowMax entries per tile,
+// zero past m), and each nonzero stores the rank of its column in the
+// window. One wave per tile (waves stride over the tiles): the columns mark
+// a bitmap of the tile's column range (< 2^16, checked beforehand) in LDS,
+// per-word popcount prefixes give every column its rank, and the set bits,
+// in order, are the window. The largest m of every wave goes to *max_m
+// (one atomic per wave); a tile with m > kWindowMax writes nothing.
+constexpr int kWindowWords = 65536 / 32;
+__global__ __launch_bounds__(kWave) void k_window_encode(const int32_t *__restrict__ col,
+                                                         const int32_t *__restrict__ tile_j,
+                                                         const int32_t *__restrict__ base,
+                                                         int64_t n_tiles,
+                                                         uint16_t *__restrict__ dict,
+                                                         int32_t *__restrict__ wlen,
+                                                         uint8_t *__restrict__ codes,
+                                                         int32_t *__restrict__ max_m) {
+    __shared__ uint32_t bm[kWindowWords];
+    __shared__ uint16_t pre[kWindowWords];
+    const int lane = threadIdx.x;
+    int32_t most = 0;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const int32_t j0 = tile_j[t], j1 = tile_j[t + 1];
+        const int32_t b = base[t];
+        int32_t hi = 0;
+        for (int32_t j = j0 + lane; j < j1; j += kWave) hi = max(hi, col[j] - b);
+        hi = group_max<kWave>(hi);
+        if (hi >= 65536) {  // not eligible (the caller checks the ranges first)
+            most = INT32_MAX;
+            continue;
+        }
+        const int nw = (hi >> 5) + 1;
+        for (int w = lane; w < nw; w += kWave) bm[w] = 0u;
+        __syncthreads();
+        for (int32_t j = j0 + lane; j < j1; j += kWave) {
+            const int32_t off = col[j] - b;
+            atomicOr(&bm[off >> 5], 1u << (off & 31));
+        }
+        __syncthreads();
+        // lane l owns words [l W, (l + 1) W)
+        const int W = (nw + kWave - 1) / kWave;
+        const int w0 = min(lane * W, nw), w1 = min(w0 + W, nw);
+        int32_t cnt = 0;
+        for (int w = w0; w < w1; ++w) cnt += __popc(bm[w]);
+        const int32_t incl = group_scan<kWave>(cnt, lane);
+        const int32_t m = __shfl(incl, kWave - 1);
+        most = max(most, m);
+        if (m <= kWindowMax) {
+            int32_t run = incl - cnt;
+            for (int w = w0; w < w1; ++w) {
+                pre[w] = (uint16_t)run;
+                uint32_t bits = bm[w];
+                while (bits) {
+                    const int q = __ffs(bits) - 1;
+                    dict[t * kWindowMax + run] = (uint16_t)((w << 5) + q);
+                    bits &= bits - 1;
+                    ++run;
+                }
+            }
+            for (int k = m + lane; k < kWindowMax; k += kWave) dict[t * kWindowMax + k] = 0;
+            if (lane == 0) wlen[t] = m;
+        }
+        __syncthreads();
+        if (m <= kWindowMax) {
+            for (int32_t j = j0 + lane; j < j1; j += kWave) {
+                const int32_t off = col[j] - b;
+                const int w = off >> 5;
+                const uint32_t below = bm[w] & ((1u << (off & 31)) - 1u);
+                codes[j] = (uint8_t)(pre[w] + __popc(below));
+            }
+        }
+        __syncthreads();  // the bitmap is cleared for the next tile
+    }
+    if (lane == 0 && most > 0) atomicMax(max_m, most);
+}
+
 // P_ML probe input (Sec. III-B): a column array holding, for every entry, the
 // index of its own row (clamped to the last column), so the probe reads the
 // same bytes as CSR but x regularly.
@@ -287,6 +364,16 @@ hipError_t launch_merge_encode(const int32_t *col, const int32_t *tile_j, int64_
     else
         hipLaunchKernelGGL(k_merge_encode<8>, dim3((unsigned)n_tiles), dim3(kWave), 0, s, col,
                            tile_j, base, codes);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_encode(const int32_t *col, const int32_t *tile_j, const int32_t *base,
+                                int64_t n_tiles, uint16_t *dict, int32_t *wlen, uint8_t *codes,
+                                int32_t *max_m, hipStream_t s) {
+    if (n_tiles == 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<int64_t>(n_tiles, 256 * 8);
+    hipLaunchKernelGGL(k_window_encode, dim3(g), dim3(kWave), 0, s, col, tile_j, base, n_tiles,
+                       dict, wlen, codes, max_m);
     return hipGetLastError();
 }
 

@@ -125,6 +125,7 @@ template <int S, int IPT> struct MergeLdsRows {
 template <int IDX> struct MergeCol { using type = int32_t; };
 template <> struct MergeCol<IDX_D16> { using type = uint16_t; };
 template <> struct MergeCol<IDX_D8> { using type = uint8_t; };
+template <> struct MergeCol<IDX_W8> { using type = uint8_t; };
 
 // What a lane holds for one tile between issuing its loads and reducing it.
 template <int S, int IPT, int IDX = IDX_I32> struct MergeTileRegs {
@@ -141,6 +142,8 @@ template <int S, int IPT, int IDX = IDX_I32> struct MergeTileRegs {
                              // tile's rows; only ceil((i1 - i0) / BS) entries loaded)
     VV vv[NIT];              // values of the tile's window
     CV cv[NIT];              // columns (or codes) of the tile's window
+    int32_t wl;              // window codes: entries of the tile's x window
+    typename VecOfU<uint16_t, 4>::type dv;  // window codes: entries [4 lane, 4 lane + 4)
 };
 
 // Stage 1: issue the tile's loads. The window [j0, j0 + L) starts at the
@@ -160,7 +163,9 @@ __device__ __forceinline__ void merge_issue(int64_t t, const int32_t *__restrict
                                             const int32_t *__restrict__ tile_i,
                                             const int32_t *__restrict__ tile_j,
                                             const int32_t *__restrict__ tile_base,
-                                            MergeTileRegs<S, IPT, IDX> &R) {
+                                            MergeTileRegs<S, IPT, IDX> &R,
+                                            const uint16_t *__restrict__ wdict = nullptr,
+                                            const int32_t *__restrict__ wlen = nullptr) {
     using Rg = MergeTileRegs<S, IPT, IDX>;
     using V = typename St<S>::V;
     using C = typename Rg::C;
@@ -188,6 +193,14 @@ __device__ __forceinline__ void merge_issue(int64_t t, const int32_t *__restrict
 #pragma unroll
         for (int q = 0; q < IPT; ++q)
             R.re[q] = buffer_load<int32_t, false>(rr, tid * 4u, (uint32_t)(q * BS * 4));
+    }
+    if constexpr (IDX == IDX_W8) {
+        // the window's dictionary entries, read as whole 4-entry vectors (a
+        // vector crossing the range end would read zeros; the dictionary
+        // row is zero past the window anyway)
+        R.wl = wlen[t];
+        const auto rd = buffer_range(wdict + t * kWindowMax, (uint32_t)((R.wl + 3) & ~3) * 2u);
+        R.dv = buffer_load<typename VecOfU<uint16_t, 4>::type, NT>(rd, tid * 8u, 0u);
     }
     const auto rc = buffer_range(static_cast<const C *>(cols) + R.j0, nwin * (uint32_t)sizeof(C));
     const auto rv = buffer_range(val + R.j0, nwin * (uint32_t)sizeof(V));
@@ -350,6 +363,40 @@ __device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT, ID
     // the segment open at the tile end leaves a carry for later tiles
     if (tid == 0 && R.i1 < n_rows)
         carry[t] = nnz_t > max(last_end, 0) ? s_prod[off + nnz_t - 1] : A(0);
+}
+
+// Window codes (row-aligned tiles): the tile's x window (its distinct
+// columns, at most kWindowMax) is read with one load per lane and entry
+// block (lane l: entries 4l .. 4l+3, consecutive columns on banded rows),
+// staged in LDS, and every nonzero reads its x there by its rank. The
+// window occupies the front of the product buffer, which is overwritten
+// only after the last rank has been read.
+template <int S, int IPT, class LDS>
+__device__ __forceinline__ void merge_gather_window(const MergeTileRegs<S, IPT, IDX_W8> &R,
+                                                    const typename St<S>::X *__restrict__ x,
+                                                    int32_t n_cols, LDS &lds,
+                                                    typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX_W8>::NIT]
+                                                                          [MergeTileRegs<S, IPT, IDX_W8>::VEC]) {
+    using X = typename St<S>::X;
+    constexpr int VEC = MergeTileRegs<S, IPT, IDX_W8>::VEC, NIT = MergeTileRegs<S, IPT, IDX_W8>::NIT;
+    static_assert(kWindowMax * sizeof(X) <= sizeof(lds.prod), "the window fits the product buffer");
+    static_assert(kWindowMax == 4 * kMergeBlock, "four window entries per lane");
+    using XV4 = typename VecOf<X, 4>::type;
+    // an entry is below 2^16: the range never needs more than 2^16 elements
+    const uint32_t nx = (uint32_t)min(n_cols - R.base, 1 << 16);
+    const auto rx = buffer_range(x + R.base, nx * (uint32_t)sizeof(X));
+    XV4 w;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = buffer_load<X, false>(rx, (uint32_t)R.dv[k] * (uint32_t)sizeof(X), 0u);
+    X *s_win = reinterpret_cast<X *>(lds.prod);
+    *reinterpret_cast<XV4 *>(s_win + 4 * threadIdx.x) = w;
+    wave_lds_sync();
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) xs[it][e] = s_win[R.cv[it][e]];
+    }
+    wave_lds_sync();
 }
 
 // Sum of s[b .. e) in index order, starting from +0.
@@ -593,8 +640,19 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
                                            const int32_t *__restrict__ tile_j,
                                            typename St<S>::A *__restrict__ carry, int32_t n_rows,
                                            LDS &lds, const int32_t *__restrict__ tile_base = nullptr,
-                                           int32_t n_cols = 0) {
-    if constexpr (ALN && IDX != IDX_I32) {
+                                           int32_t n_cols = 0,
+                                           const uint16_t *__restrict__ wdict = nullptr,
+                                           const int32_t *__restrict__ wlen = nullptr) {
+    static_assert(IDX != IDX_W8 || ALN, "window codes need row-aligned tiles");
+    if constexpr (IDX == IDX_W8) {
+        (void)carry;
+        (void)n_rows;
+        MergeTileRegs<S, IPT, IDX> R;
+        merge_issue<S, IPT, NT, IDX>(t, rp, cols, val, tile_i, tile_j, tile_base, R, wdict, wlen);
+        typename St<S>::X xs[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC];
+        merge_gather_window<S, IPT>(R, x, n_cols, lds, xs);
+        merge_finish_rows<S, IPT, LDS, IDX>(R, xs, y, lds);
+    } else if constexpr (ALN && IDX != IDX_I32) {
         // codes: one wide load per lane, gathers in window order
         (void)carry;
         (void)n_rows;

@@ -45,7 +45,7 @@ int catalogue_id(int32_t opts) {
 double plan_bytes(const csr_matrix_s *A, const Plan &P) {
     const double vb = (double)storage_bytes(A->storage);
     const double xb = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
-    const double ib = P.idx == IDX_D16 ? 2.0 : P.idx == IDX_D8 ? 1.0 : 4.0;
+    const double ib = P.idx == IDX_D16 ? 2.0 : (P.idx == IDX_D8 || P.idx == IDX_W8) ? 1.0 : 4.0;
     double b = (double)A->nnz * (vb + ib) + 4.0 * (A->n_rows + 1) + xb * A->n_cols +
                xb * A->n_rows;
     if (P.opts & CSR_OPT_MERGE) {
@@ -55,6 +55,8 @@ double plan_bytes(const csr_matrix_s *A, const Plan &P) {
         const double ab = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
         b += 2.0 * 4.0 * (T + 1) + (A->tiles_fixup ? 2.0 : 1.0) * ab * T;
         if (P.idx != IDX_I32) b += 4.0 * T;
+        // window codes: the dictionaries (window entries read) and lengths
+        if (P.idx == IDX_W8) b += 2.0 * (double)A->wdict_entries + 4.0 * T;
     }
     if (P.long_rows && A->n_long > 0) {
         const double ab = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
@@ -68,7 +70,8 @@ void fill_info(const csr_matrix_s *A, const Plan &P, csr_plan_info_t *info) {
     info->lanes_per_row = P.G;
     info->merge_items = P.L;
     info->merge_slack = (P.opts & CSR_OPT_MERGE) ? (int32_t)A->tiles_slack : 0;
-    info->delta_bits = P.idx == IDX_D16 ? 16 : P.idx == IDX_D8 ? 8 : 32;
+    info->delta_bits = P.idx == IDX_D16 ? 16 : (P.idx == IDX_D8 || P.idx == IDX_W8) ? 8 : 32;
+    info->window_codes = P.idx == IDX_W8;
     info->n_long_rows = P.long_rows ? A->n_long : 0;
     info->variant_id = catalogue_id(P.opts);
     info->format_bytes = plan_bytes(A, P);
@@ -118,6 +121,8 @@ csr_status_t build_tiles(csr_matrix_s *A, int L, hipStream_t s) {
     A->n_tiles = T;
     A->tiles_L = L;
     A->mcodes_L = 0;  // merge codes belong to the previous tiles
+    A->wcodes_L = 0;
+    A->wcode_state = 0;
     A->tiles_slack = slack;
     A->tiles_fixup = slack == 0;  // row-aligned tiles leave nothing to fix up
     return CSR_OK;
@@ -150,6 +155,46 @@ csr_status_t build_merge_codes(csr_matrix_s *A, hipStream_t s) {
     }
     A->mcode_bits = bits;
     A->mcodes_L = A->tiles_L;
+    return CSR_OK;
+}
+
+// Window codes (MB and ML remedies on row-aligned merge tiles): needs the
+// tile bases and every tile's column range below 2^16 (the merge codes'
+// check), then every tile's window within kWindowMax entries.
+csr_status_t build_window_codes(csr_matrix_s *A, hipStream_t s) {
+    if (A->wcodes_L == A->tiles_L && A->wcode_state != 0) return CSR_OK;
+    csr_status_t st;
+    if ((st = build_merge_codes(A, s)) != CSR_OK) return st;
+    A->wcodes_L = A->tiles_L;
+    A->wcode_state = -1;
+    if (A->tiles_slack <= 0 || A->mcode_bits > 16) return CSR_OK;
+    const int64_t T = A->n_tiles;
+    if ((st = A->wdict.alloc(sizeof(uint16_t) * kWindowMax * (size_t)std::max<int64_t>(T, 1))) !=
+        CSR_OK)
+        return st;
+    if ((st = A->wlen.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(T, 1))) != CSR_OK) return st;
+    if ((st = A->wcodes.alloc((size_t)A->nnz + kPadBytes)) != CSR_OK) return st;
+    CSR_HIP(hipMemsetAsync(A->wcodes.as<char>() + A->nnz, 0, kPadBytes, s));
+    DevBuf most;
+    if ((st = most.alloc(sizeof(int32_t))) != CSR_OK) return st;
+    CSR_HIP(hipMemsetAsync(most.p, 0, sizeof(int32_t), s));
+    CSR_HIP(launch_window_encode(A->col.as<int32_t>(), A->tile_j.as<int32_t>(),
+                                 A->tile_base.as<int32_t>(), T, A->wdict.as<uint16_t>(),
+                                 A->wlen.as<int32_t>(), A->wcodes.as<uint8_t>(),
+                                 most.as<int32_t>(), s));
+    int32_t m = 0;
+    CSR_HIP(hipMemcpyAsync(&m, most.p, sizeof(m), hipMemcpyDeviceToHost, s));
+    CSR_HIP(hipStreamSynchronize(s));
+    if (m > kWindowMax) return CSR_OK;
+    std::vector<int32_t> wl((size_t)T);
+    if (T > 0)
+        CSR_HIP(hipMemcpyAsync(wl.data(), A->wlen.p, sizeof(int32_t) * (size_t)T,
+                               hipMemcpyDeviceToHost, s));
+    CSR_HIP(hipStreamSynchronize(s));
+    int64_t sum = 0;
+    for (int32_t v : wl) sum += v;
+    A->wdict_entries = sum;
+    A->wcode_state = 1;
     return CSR_OK;
 }
 
@@ -234,9 +279,17 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
         P.L = L;
         if (opts & CSR_OPT_DELTA) {
             // MB: tile-base codes when every tile's column range fits 8 or
-            // 16 bits (streamed, like the compressed arrays of the remedy)
+            // 16 bits (streamed, like the compressed arrays of the remedy);
+            // on row-aligned tiles whose ranges need 16 bits, window codes
+            // when every tile has at most kWindowMax distinct columns
             if ((st = build_merge_codes(A, s)) != CSR_OK) return st;
-            if (A->mcode_bits == 8 || A->mcode_bits == 16) {
+            if (A->mcode_bits == 16 && A->tiles_slack > 0) {
+                if ((st = build_window_codes(A, s)) != CSR_OK) return st;
+            }
+            if (A->mcode_bits == 16 && A->wcode_state == 1) {
+                P.idx = IDX_W8;
+                P.nt = 1;
+            } else if (A->mcode_bits == 8 || A->mcode_bits == 16) {
                 P.idx = A->mcode_bits == 8 ? IDX_D8 : IDX_D16;
                 P.nt = 1;
             }

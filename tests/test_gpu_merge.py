@@ -66,11 +66,14 @@ def test_dyadic_bit_exact(opts, L):
         assert np.array_equal(run(A, x, opts, L), oracle.spmv(rp, col, val, x)), (n, opts, L)
 
 
-@pytest.mark.parametrize("L", [256, 512])
+@pytest.mark.parametrize("L", [256, 512, 1024])
 def test_merge_codes_bit_exact(L):
-    """MERGE|DELTA: tile bases and per-nonzero codes equal the oracle's at the
-    narrowest width that holds every tile's column range; matrices whose
-    tiles span more than 2^16 columns keep int32 columns."""
+    """MERGE|DELTA: on row-aligned tiles whose column ranges need 16 bits and
+    whose windows hold at most 256 distinct columns, window codes (tile
+    bases, dictionaries, lengths and ranks equal to the oracle's); otherwise
+    tile bases and per-nonzero offsets at the narrowest width that holds
+    every tile's column range; int32 columns when no width fits."""
+    seen = set()
     for name in ("lap100", "st27_24", "rmat14", "unif14", "unif17"):
         n, m, rp, col, val = matrix(name)
         A = pkg.CsrMatrix(rp, col, val)
@@ -81,13 +84,32 @@ def test_merge_codes_bit_exact(L):
             if oracle.merge_codes(tj, col, w) is not None:
                 want = w
                 break
+        win = (oracle.window_codes(tj, col)
+               if want == 16 and info["merge_slack"] > 0 else None)
+        assert info["window_codes"] == (win is not None), (name, L)
+        if win is not None:
+            seen.add("window")
+            assert info["delta_bits"] == 8
+            base, wlen, dct, codes = win
+            assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_BASE, np.int32), base)
+            assert np.array_equal(A.debug_copy(pkg.DEBUG_WINDOW_LEN, np.int32), wlen), (name, L)
+            got = A.debug_copy(pkg.DEBUG_WINDOW_DICT, np.uint16).reshape(dct.shape)
+            assert np.array_equal(got, dct), (name, L)
+            assert np.array_equal(A.debug_copy(pkg.DEBUG_WINDOW_CODES, np.uint8), codes), (name, L)
+            continue
         assert info["delta_bits"] == want, (name, L)
         if want == 32:
+            seen.add("int32")
             continue
+        seen.add(f"delta{want}")
         base, codes = oracle.merge_codes(tj, col, want)
         assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_BASE, np.int32), base)
         got = A.debug_copy(pkg.DEBUG_MERGE_CODES, np.uint16 if want == 16 else np.uint8)
         assert np.array_equal(got, codes), (name, L)
+    if L == 1024:  # windows outgrow 256 entries: the 16-bit offsets take over
+        assert "delta16" in seen
+    else:
+        assert "window" in seen
 
 
 def test_merge_codes_same_bits_as_int32_columns():
@@ -176,3 +198,34 @@ def test_deterministic():
         y1 = run(A, x, M, L)
         y2 = run(A, x)
         assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_window_codes_parity(storage):
+    """Window-coded tiles against the oracle, with empty rows and tiles
+    (rows of a banded matrix removed in runs), in every value storage."""
+    n, m, rp, col, val = matrix("st27_24")
+    keep = np.ones(n, dtype=bool)
+    for k in range(0, n, 997):
+        keep[k:k + 40] = False  # runs of emptied rows, some longer than a tile's rows
+    lens = np.where(keep, np.diff(rp), 0)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    sel = keep[rows]
+    rp2 = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    col2, val2 = col[sel], val[sel]
+    x = xvec("st27_24", m)
+    A = pkg.CsrMatrix(rp2, col2, val2, n_cols=m, storage=storage)
+    info = A.select("forced", forced_opts=M | pkg.OPT_DELTA, merge_items=512)
+    assert info["window_codes"] == 1
+    if storage == "f64":
+        y = run(A, x)
+        check_f64(y, rp2, col2, val2, x, "window codes with empty rows")
+        # the window ranks decode to the same columns: bit-identical to int32 tiles
+        y_i32 = run(A, x, M | pkg.OPT_PREFETCH, 512)
+        assert np.array_equal(y.view(np.uint64), y_i32.view(np.uint64))
+        assert np.all(y[~keep] == 0)
+    else:
+        xs = torch.from_numpy(oracle.to_f32(x)).cuda()
+        y = A.spmv(xs)
+        torch.cuda.synchronize()
+        check_reduced(y.cpu().numpy(), rp2, col2, val2, x, storage, f"window codes {storage}")
