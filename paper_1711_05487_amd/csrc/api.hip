@@ -122,7 +122,7 @@ std::string dominant_kernel(const csr_matrix_s *A, const Plan &P) {
     if (P.opts & CSR_OPT_MERGE)
         return "k_merge<" + std::to_string(P.L / kMergeBlock) + ", " + (P.nt ? "true" : "false") +
                ", " + (P.idx == IDX_I32 && x_fits_32(A) ? "true" : "false") + ", " +
-               std::to_string(P.idx) + ">";
+               std::to_string(P.idx) + ", " + (A->tiles_fixup ? "false" : "true") + ">";
     return "k_rowsplit<" + std::to_string(P.G) + ", " + std::to_string(P.idx) + ", " +
            (P.nt ? "true" : "false") + ", " + std::to_string(P.U) + ", " + std::to_string(P.R) +
            ", 0>";
