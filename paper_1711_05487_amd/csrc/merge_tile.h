@@ -93,8 +93,8 @@ template <int S, int IPT> struct MergeLds {
     alignas(16) A prod[L];            // products, then their segmented prefix sums
     alignas(16) uint8_t head[L + BS]; // 1 where a row starts inside the tile; [L, L+BS) dummies
 };
-// Row-aligned tiles need only the products. LDS is what bounds the number of
-// resident tiles per CU, so the smaller footprint raises the loads in flight.
+// Row-aligned tiles need only the products (the x window of window-coded
+// tiles and the staged codes share the same buffer, one after the other).
 template <int S, int IPT> struct MergeLdsRows {
     alignas(16) typename St<S>::A prod[kMergeBlock * IPT];
 };
@@ -119,6 +119,13 @@ template <int S, int IPT> struct MergeLdsRows {
 // Every sum has a fixed order, so results are deterministic. The first row
 // of the tile may have begun in an earlier tile: it gets this tile's part
 // here, and merge_fixup_tile adds the earlier tiles' carries.
+//
+// Row-aligned tiles (the partition cut every tile at a row end) need no
+// scan and no carry: the products go to LDS and merge_row_sums gives every
+// row a group of lanes that sums it there. Their column codes, if any, are
+// either tile-base offsets gathered in window order (merge_issue_rows,
+// merge_gather_rows) or window ranks whose x comes from an LDS copy of the
+// tile's distinct columns (merge_gather_window).
 
 // Column type of the window: int32 columns, or the w-bit offsets of the
 // merge codes (columns = base of the tile + code).
@@ -413,16 +420,15 @@ template <class A> __device__ __forceinline__ A lds_run_sum(const A *s, int b, i
     return v;
 }
 
-// Row-aligned tiles (the partition cut every tile at a row end, so each row
-// of the tile has all of its nonzeros in it and nothing is carried). The
-// vector memory pipeline, not the arithmetic, bounds these tiles: every
-// 64-lane load costs the texture path one cache access per group of four
-// lanes and distinct line. So the columns (or codes) are read as one wide
-// vector per lane (lane l: window elements [l IPT, (l+1) IPT)), passed
-// through LDS so that gather k reads element 64 k + l (four lanes of a
-// group gather consecutive nonzeros, which share lines on banded and
-// stencil rows), and the gathered x goes back through LDS to meet the
-// values, which keep their wide loads.
+// Tile-base codes on row-aligned tiles (the partition cut every tile at a
+// row end, so each row of the tile has all of its nonzeros in it and
+// nothing is carried). The codes are read as one wide vector per lane (lane
+// l: window elements [l IPT, (l+1) IPT)) and passed through LDS so that
+// gather k reads element 64 k + l: four neighbouring lanes then gather
+// consecutive nonzeros, which share cache lines on banded and stencil rows,
+// so a gather instruction touches fewer distinct lines than in the values'
+// layout. The gathered x goes back through LDS to meet the values, which
+// keep their wide loads.
 template <int S, int IPT, int IDX = IDX_I32> struct MergeRowRegs {
     using V = typename St<S>::V;
     using C = typename MergeCol<IDX>::type;

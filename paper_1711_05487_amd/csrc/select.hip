@@ -49,11 +49,11 @@ double plan_bytes(const csr_matrix_s *A, const Plan &P) {
     double b = (double)A->nnz * (vb + ib) + 4.0 * (A->n_rows + 1) + xb * A->n_cols +
                xb * A->n_rows;
     if (P.opts & CSR_OPT_MERGE) {
-        // tile table, carries written (and read back by the fixup pass),
-        // and the tile bases of the merge codes
+        // tile table, carries written and read back by the fixup pass (none
+        // on row-aligned tiles), and the tile bases of the merge codes
         const double T = (double)A->n_tiles;
         const double ab = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
-        b += 2.0 * 4.0 * (T + 1) + (A->tiles_fixup ? 2.0 : 1.0) * ab * T;
+        b += 2.0 * 4.0 * (T + 1) + (A->tiles_fixup ? 2.0 * ab * T : 0.0);
         if (P.idx != IDX_I32) b += 4.0 * T;
         // window codes: the dictionaries (window entries read) and lengths
         if (P.idx == IDX_W8) b += 2.0 * (double)A->wdict_entries + 4.0 * T;
