@@ -136,6 +136,18 @@ def cpu_baseline(rp, col, val, x, bytes_per_call, budget_s=12.0):
                       f"({el:.1f} s, single thread)"}
 
 
+def cpu_multicore(rp, col, val, x, bytes_per_call, budget_s=4.0):
+    """The OpenMP CSR baseline (Sec. IV-A: contiguous nnz-balanced row blocks,
+    one per thread) on all host threads OpenMP is given: context beside the
+    single-threaded oracle, never the target."""
+    from oracle import omp
+    sec, th = omp.time_spmv(rp, col, val, x, 4)
+    calls = max(4, min(2048, int(budget_s / max(sec / 4, 1e-6))))
+    sec, th = omp.time_spmv(rp, col, val, x, calls)
+    return {"value": round(bytes_per_call * calls / sec / 1e9, 3), "unit": "GB/s", "threads": th,
+            "kind": "openmp csr", "sample": f"{calls} full SpMV calls ({sec:.1f} s)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +286,8 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(rp, col, val, x, plain["format_bytes"])
+        log("cpu baseline (openmp)")
+        out["cpu_multicore"] = cpu_multicore(rp, col, val, x, plain["format_bytes"])
     print(json.dumps(out), flush=True)
     A.close()
     if not ok:

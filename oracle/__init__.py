@@ -10,6 +10,8 @@ Two halves:
   SpMV in storage order, |A||x|, the Dot2 accurate reference, dense matvec,
   CSR validation, FP32/BF16 rounding, delta codes, merge-path tiles, long-row
   list and the matrix features.
+* ``csr_omp.c`` / ``omp.py``: the multi-core OpenMP CSR baseline that the
+  benchmark reports beside the single-threaded oracle (measurement only).
 * Pure Python/numpy here: the per-class bounds, the profile-guided rule, the
   class-to-optimization map, the amortization count, the reduced-precision
   error report, feature normalization and the FP64 MLP with its gradients and
