@@ -159,6 +159,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--suite", action="store_true",
                     help="measure every configuration (one JSON line per case)")
+    ap.add_argument("--amortize", action="store_true",
+                    help="amortization study (Sec. IV-D, Table V; one JSON line per case)")
+    ap.add_argument("--amortize-matrices", type=int, default=40,
+                    help="held-out suite matrices in the Table V study")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -167,6 +171,8 @@ def main():
 
     if args.suite:
         return suite(args)
+    if args.amortize:
+        return amortize(args)
 
     import torch
     import paper_1711_05487_amd as pkg
@@ -475,6 +481,166 @@ def suite(args):
           "speedup": round(t_sep / t_batch, 3), "replay_identical": batch_ok})
     for A in hs:
         A.close()
+
+
+
+# ---------------------------------------------------------------------------
+# --amortize: what the selection costs against what it saves (Sec. IV-D)
+# ---------------------------------------------------------------------------
+
+# (label, csr_select mode, config overrides): the optimizers of Table V. The
+# trivial optimizers time every candidate (the baseline and the 5 single
+# remedies, or the whole 16-entry catalogue) and keep the fastest.
+OPTIMIZERS = [
+    ("plain", "plain", {}),
+    ("trivial-single", "exhaustive", {"exhaustive_set": 1}),
+    ("trivial-combined", "exhaustive", {"exhaustive_set": 0}),
+    ("profile-guided", "profile", {}),
+    ("feature-guided (MLP)", "learned", {}),
+]
+
+
+def pcg(A, b, dinv, tol=1e-8, max_iter=4000, check_every=8):
+    """Jacobi-preconditioned conjugate gradients around the library's SpMV.
+    The vector updates are the same torch operations for every plan (t_other
+    of Eq. (2)); the residual norm is read back every `check_every` steps.
+    Returns (x, iterations)."""
+    import torch
+    x = torch.zeros_like(b)
+    r = b.clone()
+    z = dinv * r
+    p = z.clone()
+    q = torch.empty_like(b)
+    rz = torch.dot(r, z)
+    stop = tol * float(torch.linalg.vector_norm(b))
+    it = 0
+    while it < max_iter:
+        A.spmv(p, q)
+        alpha = rz / torch.dot(p, q)
+        x.add_(alpha * p)
+        r.sub_(alpha * q)
+        it += 1
+        if it % check_every == 0 and float(torch.linalg.vector_norm(r)) <= stop:
+            break
+        torch.mul(dinv, r, out=z)
+        rz_new = torch.dot(r, z)
+        p.mul_(rz_new / rz).add_(z)
+        rz = rz_new
+    return x, it
+
+
+def select_timed(pkg, A, mode, over):
+    """Host wall time of csr_select (features or probes, decision, format
+    preparation): the t_pre of Eq. (2)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = A.select(mode, **over)
+    torch.cuda.synchronize()
+    return info, (time.perf_counter() - t0) * 1e3
+
+
+def amortize(args):
+    import torch
+    import paper_1711_05487_amd as pkg
+    import synth
+    from paper_1711_05487_amd import learn
+
+    torch.cuda.set_device(0)
+    learn.install()
+    # load every selection kernel once (a process cost, not a per-matrix one)
+    _, wm, wrp, wcol, wval = synth.laplacian2d(64)
+    W = pkg.CsrMatrix(wrp, wcol, wval, n_cols=wm)
+    for _, mode, over in OPTIMIZERS:
+        W.select(mode, **over)
+    W.close()
+
+    # 1. Table V: N_iters,min over held-out matrices of the selector's suite
+    recs = learn.read_labels(os.path.join(ROOT, "paper_1711_05487_amd", "weights",
+                                          "labels_mi355x.jsonl"))
+    _, test = learn.split(recs)
+    big = [r for r in test if r["nnz"] >= 100_000]
+    step = max(1, len(big) // max(1, args.amortize_matrices))
+    picks = big[::step][:args.amortize_matrices]
+    per_opt = {lab: [] for lab, _, _ in OPTIMIZERS[1:]}
+    for k, r in enumerate(picks):
+        name, (n, m, rp, col, val) = synth.suite_matrix(r["index"])
+        x = torch.from_numpy(synth.vector(m, 602 + r["index"])).cuda()
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        times = {}
+        for lab, mode, over in OPTIMIZERS:
+            A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+            info, t_pre = select_timed(pkg, A, mode, over)
+            t_spmv, _, _ = time_plan(A, x, y, runs=3, calls=64)
+            times[lab] = (t_pre, t_spmv, info)
+            A.close()
+        t_plain = times["plain"][1]
+        for lab, _, _ in OPTIMIZERS[1:]:
+            t_pre, t_spmv, info = times[lab]
+            nim = n_iters_min(t_pre, t_plain, t_spmv)
+            per_opt[lab].append(nim)
+            emit({"case": "table5", "matrix": name, "index": r["index"], "nnz": int(len(col)),
+                  "optimizer": lab, "t_pre_ms": round(t_pre, 3), "t_spmv_ms": round(t_spmv, 5),
+                  "t_plain_ms": round(t_plain, 5),
+                  "speedup_vs_plain": round(t_plain / t_spmv, 4),
+                  "opts": [nm for bit, nm in pkg.OPT_NAMES.items() if info["opts"] & bit],
+                  "n_iters_min": None if nim is None else round(nim, 1)})
+        log(f"table5 {k + 1}/{len(picks)} {name}")
+    for lab, vals in per_opt.items():
+        fin = [v for v in vals if v is not None]
+        emit({"case": "table5-summary", "optimizer": lab, "matrices": len(vals),
+              "never_amortized": len(vals) - len(fin),
+              "n_iters_best": round(min(fin), 1) if fin else None,
+              "n_iters_avg": round(float(np.mean(fin)), 1) if fin else None,
+              "n_iters_median": round(float(np.median(fin)), 1) if fin else None,
+              "n_iters_worst": round(max(fin), 1) if fin else None})
+
+    # 2. Conjugate-gradient solves on SPD systems, end to end
+    systems = [
+        ("lap3d_128", "7-point 3-D Laplacian 128^3", lambda: synth.laplacian3d(128)),
+        ("spd27_128", "SPD 27-point stencil 128^3 (symmetric, diagonally dominant)",
+         lambda: synth.spd_stencil27(128)),
+        ("lap2d_1024", "5-point 2-D Laplacian 1024^2", lambda: synth.laplacian2d(1024)),
+    ]
+    for tag, desc, gen in systems:
+        n, m, rp, col, val = gen()
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        diag = np.zeros(n)
+        diag[rows[col == rows]] = val[col == rows]
+        dinv = torch.from_numpy(1.0 / diag).cuda()
+        x_true = torch.from_numpy(synth.vector(m, 901)).cuda()
+        P = pkg.CsrMatrix(rp, col, val, n_cols=m)
+        b = P.spmv(x_true)
+        P.close()
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        base = None
+        for lab, mode, over in OPTIMIZERS:
+            A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+            info, t_pre = select_timed(pkg, A, mode, over)
+            t_spmv, _, _ = time_plan(A, x_true, y, runs=3, calls=64)
+            pcg(A, b, dinv, max_iter=16)  # warm the solver's own kernels
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            xs, it = pcg(A, b, dinv)
+            e1.record()
+            torch.cuda.synchronize()
+            t_solve = e0.elapsed_time(e1)
+            err = float(torch.linalg.vector_norm(xs - x_true) / torch.linalg.vector_norm(x_true))
+            if base is None:
+                base = (t_spmv, t_solve)
+            nim = None if lab == "plain" else n_iters_min(t_pre, base[0], t_spmv)
+            emit({"case": "cg", "system": tag, "workload": f"{desc} (N={n:,}, NNZ={len(col):,})",
+                  "optimizer": lab,
+                  "opts": [nm for bit, nm in pkg.OPT_NAMES.items() if info["opts"] & bit],
+                  "window_codes": bool(info["window_codes"]), "iterations": it,
+                  "rel_error": err, "t_pre_ms": round(t_pre, 3), "t_spmv_ms": round(t_spmv, 5),
+                  "t_solve_ms": round(t_solve, 3), "t_total_ms": round(t_pre + t_solve, 3),
+                  "solve_speedup_vs_plain": round(base[1] / t_solve, 4),
+                  "total_speedup_vs_plain": round(base[1] / (t_pre + t_solve), 4),
+                  "n_iters_min": None if nim is None else round(nim, 1)})
+            A.close()
+        log(f"cg {tag} done")
 
 
 if __name__ == "__main__":

@@ -89,7 +89,9 @@ typedef struct {
     int32_t autotune;        /* 1 = time a small parameter grid for the chosen remedies */
     int32_t timing_calls;    /* SpMV calls per timing run inside selection (default 32) */
     int32_t rows_in_flight;  /* 0 = auto: rows per lane group loaded at once (1, 2 or 4) */
-    int32_t reserved;
+    int32_t exhaustive_set;  /* CSR_SEL_EXHAUSTIVE: 0 = the 16-entry catalogue (the "trivial
+                                combined" optimizer of Sec. IV-D), 1 = the baseline and the
+                                5 single remedies ("trivial single") */
 } csr_config_t;
 
 /* What csr_select decided and what it cost. */

@@ -53,7 +53,7 @@ class Config(ctypes.Structure):
                 ("forced_opts", ctypes.c_int32), ("rows_per_group", ctypes.c_int32),
                 ("merge_items", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("timing_calls", ctypes.c_int32), ("rows_in_flight", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("exhaustive_set", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):

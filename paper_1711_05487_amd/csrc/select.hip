@@ -736,7 +736,13 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
         double best = 1e300;
         int best_k = 0;
         const int calls = cfg.timing_calls > 0 ? cfg.timing_calls : 32;
-        for (int k = 0; k < 16 && st == CSR_OK; ++k) {
+        // the catalogue lists the baseline and the singles first
+        const int n_sets = cfg.exhaustive_set == 1 ? 6 : 16;
+        if (cfg.exhaustive_set != 0 && cfg.exhaustive_set != 1) {
+            st = fail(CSR_ERR_INVALID_ARG, "exhaustive_set must be 0 or 1");
+            break;
+        }
+        for (int k = 0; k < n_sets && st == CSR_OK; ++k) {
             Plan Q;
             if ((st = realize(A, kCatalogue[k], cfg, &Q, s)) != CSR_OK) break;
             double ms = 0;

@@ -475,6 +475,37 @@ def _seven_point(s: int, seed: int):
     return n, n, _check_int32(rp), col, val
 
 
+def laplacian3d(s: int = 128):
+    """7-point 3-D Laplacian on an s^3 grid (x fastest), columns ascending.
+
+    Diagonal 6, off-diagonals -1, Dirichlet boundary (missing neighbours
+    dropped): symmetric positive definite. 128^3 gives N = 2,097,152 and
+    NNZ = 14,581,760.
+    """
+    n, _, rp, col, _ = _seven_point(s, 0)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp.astype(np.int64)))
+    val = np.where(col == rows, 6.0, -1.0)
+    return n, n, rp, col, val
+
+
+def spd_stencil27(s: int = 128, seed: int = 211):
+    """Symmetric positive definite matrix on the 27-point pattern of an s^3
+    grid: a_ij = a_ji = -U(0,1] drawn from the unordered pair (i, j), and
+    a_ii = 1 + sum_j |a_ij| (strictly diagonally dominant with a positive
+    diagonal, hence SPD). The pattern and sizes are those of stencil27(s).
+    """
+    n, _, rp, col, _ = stencil27(s)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp.astype(np.int64)))
+    c = col.astype(np.int64)
+    lo, hi = np.minimum(rows, c), np.maximum(rows, c)
+    val = -u01(seed, 0, (lo * n + hi).astype(np.uint64))
+    diag = c == rows
+    val[diag] = 0.0
+    rowsum = np.add.reduceat(np.abs(val), rp[:-1].astype(np.int64))
+    val[diag] = 1.0 + rowsum[rows[diag]]
+    return n, n, rp, col, val
+
+
 def batch_matrix(index: int, base_seed: int = 601):
     """Matrix `index` of the batched-launch set: suite families, N log-uniform
     in [1024, 65536]."""

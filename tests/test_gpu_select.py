@@ -176,6 +176,24 @@ def test_exhaustive_selects_catalogue_variant():
     check_f64(y.cpu().numpy(), rp, col, val, x, "exhaustive")
 
 
+def test_exhaustive_single_remedies_only():
+    """exhaustive_set = 1 (the trivial-single optimizer of Sec. IV-D) keeps
+    the fastest of the baseline and the 5 single remedies; other values are
+    rejected."""
+    n, m, rp, col, val = matrix("rmat14")
+    A = pkg.CsrMatrix(rp, col, val)
+    info = A.select("exhaustive", timing_calls=8, exhaustive_set=1)
+    assert 0 <= info["variant_id"] <= 5
+    assert info["opts"] in (0, 1, 2, 4, 8, 16)
+    check_tables_in_place(A, info, rp)
+    x = xvec("rmat14", m)
+    y = A.spmv(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    check_f64(y.cpu().numpy(), rp, col, val, x, "exhaustive singles")
+    with pytest.raises(pkg.CsrError):
+        A.select("exhaustive", exhaustive_set=2)
+
+
 def test_every_catalogue_variant_matches_oracle():
     n, m, rp, col, val = matrix("rmat14")
     x = xvec("rmat14", m)

@@ -431,3 +431,25 @@ def test_window_codes_boundaries():
     base, wlen, dct, codes = one_row([7, 9, 9, 7, 12])
     assert base[0] == 7 and wlen[0] == 3
     assert list(dct[0, :3]) == [0, 2, 5] and list(codes) == [0, 1, 1, 0, 2]
+
+
+# ------------------------------------------------------- SPD study matrices
+
+def test_spd_generators_symmetric_and_dominant():
+    """The amortization study's SPD systems: symmetric, positive diagonal,
+    strictly diagonally dominant (27-point) or the Laplacian's weak
+    dominance; the 7-point Laplacian has 7 s^3 - 6 s^2 nonzeros."""
+    import scipy.sparse as sp
+    for s in (5, 9):
+        n, m, rp, col, val = synth.laplacian3d(s)
+        assert len(col) == 7 * s ** 3 - 6 * s ** 2
+        A = sp.csr_matrix((val, col, rp), shape=(n, m))
+        assert (A - A.T).count_nonzero() == 0
+        assert np.all(A.diagonal() == 6.0)
+        n, m, rp, col, val = synth.spd_stencil27(s)
+        A = sp.csr_matrix((val, col, rp), shape=(n, m))
+        assert (A - A.T).count_nonzero() == 0
+        d = A.diagonal()
+        off = np.asarray(abs(A).sum(axis=1)).ravel() - d
+        assert np.all(d > off)
+        assert np.all(d >= 1.0)
