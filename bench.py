@@ -496,6 +496,7 @@ OPTIMIZERS = [
     ("trivial-single", "exhaustive", {"exhaustive_set": 1}),
     ("trivial-combined", "exhaustive", {"exhaustive_set": 0}),
     ("profile-guided", "profile", {}),
+    ("feature-guided (tree)", "tree", {}),
     ("feature-guided (MLP)", "learned", {}),
 ]
 
@@ -546,8 +547,10 @@ def amortize(args):
     import synth
     from paper_1711_05487_amd import learn
 
+    from paper_1711_05487_amd import tree
     torch.cuda.set_device(0)
     learn.install()
+    tree.install()
     # load every selection kernel once (a process cost, not a per-matrix one)
     _, wm, wrp, wcol, wval = synth.laplacian2d(64)
     W = pkg.CsrMatrix(wrp, wcol, wval, n_cols=wm)

@@ -73,7 +73,10 @@ typedef enum {
     CSR_SEL_PROFILE = 1,     /* micro-benchmarks + the rule of Sec. III-C, Fig. 4 */
     CSR_SEL_LEARNED = 2,     /* features + the loaded MLP (falls back to PROFILE) */
     CSR_SEL_EXHAUSTIVE = 3,  /* time every catalogue variant, keep the fastest */
-    CSR_SEL_FORCED = 4       /* use cfg->forced_opts / cfg parameters as given */
+    CSR_SEL_FORCED = 4,      /* use cfg->forced_opts / cfg parameters as given */
+    CSR_SEL_TREE = 5         /* features + the loaded decision tree (the paper's feature-guided
+                                classifier): predicted classes -> Table II remedies (falls
+                                back to PROFILE without a tree) */
 } csr_sel_t;
 
 /* Tunables; csr_config_default() fills the defaults. */
@@ -289,6 +292,20 @@ csr_status_t csr_mlp_train(float *d_params, float *d_m, float *d_v, int32_t K, c
 /* d_out[n][16] = (log2(1 + d_f) - d_mu) / d_sigma (FP64 in, FP32 out). */
 csr_status_t csr_mlp_normalize(const double *d_f, const double *d_mu, const double *d_sigma,
                                int64_t n, float *d_out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Feature-guided classifier of Sec. III-D: a CART decision tree over the 16
+ * features of csr_features_t that predicts the bottleneck classes the
+ * profile-guided rule would assign (a CSR_CLS_* mask; 0 = the paper's dummy
+ * class, nothing worth optimizing). Node k: feature[k] in [0, 16) with
+ * children left[k], right[k] (both > k; go left when f[feature] <=
+ * threshold[k]), or feature[k] = -1 for a leaf whose value[k] in [0, 16) is
+ * the mask. The root is node 0. Host arrays, copied; one tree per process.
+ * ------------------------------------------------------------------------- */
+csr_status_t csr_tree_load(int32_t n_nodes, const int32_t *feature, const double *threshold,
+                           const int32_t *left, const int32_t *right, const int32_t *value);
+/* Remove the tree (TREE then falls back to PROFILE). */
+csr_status_t csr_tree_unload(void);
 
 #ifdef __cplusplus
 }

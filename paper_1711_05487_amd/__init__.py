@@ -23,9 +23,9 @@ OPT_NAMES = {OPT_DELTA: "delta", OPT_PREFETCH: "prefetch", OPT_DECOMP: "decomp",
              OPT_MERGE: "merge", OPT_UNROLL: "unroll"}
 CLS_MB, CLS_ML, CLS_IMB, CLS_CMP = 1, 2, 4, 8
 
-SEL_PLAIN, SEL_PROFILE, SEL_LEARNED, SEL_EXHAUSTIVE, SEL_FORCED = 0, 1, 2, 3, 4
+SEL_PLAIN, SEL_PROFILE, SEL_LEARNED, SEL_EXHAUSTIVE, SEL_FORCED, SEL_TREE = 0, 1, 2, 3, 4, 5
 SELECT = {"plain": SEL_PLAIN, "profile": SEL_PROFILE, "learned": SEL_LEARNED,
-          "exhaustive": SEL_EXHAUSTIVE, "forced": SEL_FORCED}
+          "exhaustive": SEL_EXHAUSTIVE, "forced": SEL_FORCED, "tree": SEL_TREE}
 
 (DEBUG_VALUES, DEBUG_CODES, DEBUG_TILE_I, DEBUG_TILE_J, DEBUG_LONG_ROWS, DEBUG_PLAN,
  DEBUG_MERGE_CODES, DEBUG_TILE_BASE, DEBUG_WINDOW_DICT, DEBUG_WINDOW_LEN,
@@ -38,7 +38,8 @@ STATUS = ["CSR_OK", "CSR_ERR_INVALID_ARG", "CSR_ERR_INVALID_MATRIX", "CSR_ERR_OU
 EXPORTS = ("csr_config_default", "csr_create", "csr_destroy", "csr_inspect", "csr_select",
            "csr_spmv", "csr_spmv_batched", "csr_status_str", "csr_last_error", "csr_query",
            "csr_debug_copy", "csr_debug_probe", "csr_triad", "csr_time_spmv", "csr_mlp_load", "csr_mlp_unload",
-           "csr_mlp_forward", "csr_mlp_grad", "csr_mlp_train", "csr_mlp_normalize")
+           "csr_mlp_forward", "csr_mlp_grad", "csr_mlp_train", "csr_mlp_normalize",
+           "csr_tree_load", "csr_tree_unload")
 
 
 class CsrError(RuntimeError):
@@ -113,6 +114,8 @@ def lib():
             "csr_mlp_train": (ctypes.c_int, [P, P, P, i32, P, P, P, i32, i32, i32, ctypes.c_float,
                                              ctypes.c_float, ctypes.c_float, ctypes.c_float, P, P]),
             "csr_mlp_normalize": (ctypes.c_int, [P, P, P, i64, P, P]),
+            "csr_tree_load": (ctypes.c_int, [i32, P, P, P, P, P]),
+            "csr_tree_unload": (ctypes.c_int, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -292,6 +295,21 @@ def mlp_load(params: np.ndarray, K: int, mu: np.ndarray, sigma: np.ndarray):
 
 def mlp_unload():
     _check(lib().csr_mlp_unload())
+
+
+def tree_load(tree: dict):
+    """Install a decision tree (flat arrays feature, threshold, left, right,
+    value) for select("tree")."""
+    n = len(tree["feature"])
+    arr = {k: np.ascontiguousarray(tree[k], dtype=np.float64 if k == "threshold" else np.int32)
+           for k in ("feature", "threshold", "left", "right", "value")}
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _check(lib().csr_tree_load(n, vp(arr["feature"]), vp(arr["threshold"]), vp(arr["left"]),
+                               vp(arr["right"]), vp(arr["value"])))
+
+
+def tree_unload():
+    _check(lib().csr_tree_unload())
 
 
 def mlp_forward(params, K, X, stream=None):

@@ -687,7 +687,62 @@ csr_status_t autotune(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, hi
 
 using namespace csr;
 
+// Feature-guided classifier (Sec. III-D): a CART tree over the 16 features
+// that predicts the profile-guided classes; walked on the host.
+namespace {
+struct TreeNode {
+    int32_t feature;  // -1 at a leaf
+    double threshold; // go left when f[feature] <= threshold
+    int32_t left, right;
+    int32_t value;    // class mask at a leaf
+};
+std::mutex g_tree_mu;
+std::vector<TreeNode> *const g_tree = new std::vector<TreeNode>;  // empty: no tree
+
+// The class mask the tree predicts for the features f, -1 without a tree.
+// Children always follow their parent, so the walk ends.
+int32_t tree_classes(const double *f) {
+    std::lock_guard<std::mutex> lk(g_tree_mu);
+    if (g_tree->empty()) return -1;
+    size_t k = 0;
+    while ((*g_tree)[k].feature >= 0) {
+        const TreeNode &n = (*g_tree)[k];
+        k = (size_t)(f[n.feature] <= n.threshold ? n.left : n.right);
+    }
+    return (*g_tree)[k].value;
+}
+}  // namespace
+
 extern "C" {
+
+csr_status_t csr_tree_load(int32_t n_nodes, const int32_t *feature, const double *threshold,
+                           const int32_t *left, const int32_t *right, const int32_t *value) {
+    if (n_nodes < 1 || n_nodes > (1 << 20) || !feature || !threshold || !left || !right || !value)
+        return fail(CSR_ERR_INVALID_ARG, "bad tree arrays");
+    std::vector<TreeNode> t((size_t)n_nodes);
+    for (int32_t k = 0; k < n_nodes; ++k) {
+        TreeNode &n = t[(size_t)k];
+        n = TreeNode{feature[k], threshold[k], left[k], right[k], value[k]};
+        if (n.feature < -1 || n.feature >= 16)
+            return fail(CSR_ERR_INVALID_ARG, "tree feature index out of range");
+        if (n.feature >= 0) {
+            if (!std::isfinite(n.threshold)) return fail(CSR_ERR_INVALID_ARG, "non-finite threshold");
+            if (n.left <= k || n.left >= n_nodes || n.right <= k || n.right >= n_nodes)
+                return fail(CSR_ERR_INVALID_ARG, "a child must follow its parent");
+        } else if (n.value < 0 || n.value > 15) {
+            return fail(CSR_ERR_INVALID_ARG, "leaf class mask out of range");
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_tree_mu);
+    g_tree->swap(t);
+    return CSR_OK;
+}
+
+csr_status_t csr_tree_unload(void) {
+    std::lock_guard<std::mutex> lk(g_tree_mu);
+    g_tree->clear();
+    return CSR_OK;
+}
 
 csr_status_t csr_inspect(csr_matrix_t A, csr_features_t *out, void *stream) {
     if (!A || !out) return fail(CSR_ERR_INVALID_ARG, "NULL argument");
@@ -723,7 +778,28 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
     info.classes = -1;
     csr_status_t st = CSR_OK;
     double t_prep = 0.0;
-    switch (mode) {
+    int32_t sel = mode;
+    if (sel == CSR_SEL_TREE) {
+        // features -> decision tree -> bottleneck classes -> Table II
+        // remedies with default parameters (nothing timed); no tree -> the
+        // profile-guided path
+        if ((st = inspect(A, s)) != CSR_OK) return st;
+        const int32_t cls = tree_classes(A->feat.f);
+        if (cls >= 0) {
+            info.classes = cls;
+            const bool has_long = A->feat.f[2] > (double)long_row_tau(A, cfg);
+            const auto tp = Clock::now();
+            st = realize(A, remedies(cls, has_long), cfg, &P, s);
+            t_prep = ms_since(tp);
+            sel = -1;  // decided
+        } else {
+            info.fallback = 1;
+            sel = CSR_SEL_PROFILE;
+        }
+    }
+    switch (sel) {
+    case -1:
+        break;
     case CSR_SEL_PLAIN:
         st = realize(A, 0, cfg, &P, s);
         break;
