@@ -67,6 +67,7 @@ def lib():
             "or_merge_tiles": (i64, [i32, P, i64, i64, P, P]),
             "or_merge_codes": (c_int, [i64, P, P, c_int, P, P]),
             "or_window_codes": (c_int, [i64, P, P, c_int, P, P, P, P]),
+            "or_column_blocks": (None, [i32, P, P, P, i32, i32, P, P, P]),
             "or_long_rows": (i32, [i32, P, i64, P]),
             "or_features": (None, [i32, i32, P, P, P, P]),
         }
@@ -300,6 +301,22 @@ def merge_tiles(rp, L: int, slack: int = 0):
     tj = np.empty(T + 1, dtype=np.int32)
     lib().or_merge_tiles(n, _p(rp), L, slack, _p(ti), _p(tj))
     return ti, tj
+
+
+def column_blocks(rp, col, val, B: int, width: int):
+    """Column blocks (ML remedy on the merge path, Table II): block b holds,
+    row by row in storage order, the nonzeros with column in
+    [b width, (b + 1) width). Returns (rpb of shape (B, n + 1), each counting
+    from 0, colb, valb with the blocks one after the other)."""
+    rp = np.ascontiguousarray(rp, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    n = rp.size - 1
+    rpb = np.zeros((B, n + 1), dtype=np.int32)
+    colb = np.zeros(max(col.size, 1), dtype=np.int32)
+    valb = np.zeros(max(col.size, 1), dtype=np.float64)
+    lib().or_column_blocks(n, _p(rp), _p(col), _p(val), B, width, _p(rpb), _p(colb), _p(valb))
+    return rpb, colb[:col.size], valb[:col.size]
 
 
 def long_rows(rp, tau: int) -> np.ndarray:

@@ -353,6 +353,35 @@ int or_window_codes(int64_t T, const int32_t *tj, const int32_t *col, int maxw,
     return ok;
 }
 
+/* ML remedy composed with the merge path (Table II: x is prefetched into    */
+/* the cache; on a GPU, each pass keeps its x gathers inside one slab that  */
+/* fits a cache): the columns are cut into B blocks of `width` consecutive  */
+/* columns, and block b holds, for every row, the row's nonzeros whose      */
+/* column lies in [b width, (b + 1) width), in storage order. rpb holds B   */
+/* row-pointer arrays of n + 1 entries, each counting from 0 within its     */
+/* block; colb/valb hold the blocks' nonzeros one block after the other.    */
+void or_column_blocks(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                      int32_t B, int32_t width, int32_t *rpb, int32_t *colb, double *valb)
+{
+    int64_t off = 0; /* first nonzero of the current block in colb/valb */
+    for (int32_t b = 0; b < B; ++b) {
+        int32_t *r = rpb + (int64_t)b * (n + 1);
+        int64_t lo = (int64_t)b * width, hi = lo + width, k = 0;
+        r[0] = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            for (int32_t j = rp[i]; j < rp[i + 1]; ++j) {
+                if (col[j] >= lo && col[j] < hi) {
+                    colb[off + k] = col[j];
+                    valb[off + k] = val[j];
+                    ++k;
+                }
+            }
+            r[i + 1] = (int32_t)k;
+        }
+        off += k;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* IMB remedy, decomposition (Sec. III-E, Figs. 5-6): rows with more than    */
 /* tau nonzeros are taken out of the row-parallel pass and computed          */

@@ -453,3 +453,48 @@ def test_spd_generators_symmetric_and_dominant():
         off = np.asarray(abs(A).sum(axis=1)).ravel() - d
         assert np.all(d > off)
         assert np.all(d >= 1.0)
+
+
+# ------------------------------------------------------------ column blocks
+
+@pytest.mark.parametrize("B", [1, 2, 3, 4, 8])
+def test_column_blocks_partition_in_storage_order(B):
+    n, m, rp, col, val = synth.tiny_random(500, 997, 0.02, 31)
+    width = (m + B - 1) // B
+    rpb, colb, valb = oracle.column_blocks(rp, col, val, B, width)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    off = 0
+    got = []
+    for b in range(B):
+        r = rpb[b]
+        assert r[0] == 0 and np.all(np.diff(r) >= 0)
+        k = int(r[-1])
+        cb, vb = colb[off:off + k], valb[off:off + k]
+        assert np.all((cb >= b * width) & (cb < (b + 1) * width))
+        for i in range(n):
+            # the block's part of row i is the row's in-block entries, in order
+            sel = (col[rp[i]:rp[i + 1]] >= b * width) & (col[rp[i]:rp[i + 1]] < (b + 1) * width)
+            assert np.array_equal(cb[r[i]:r[i + 1]], col[rp[i]:rp[i + 1]][sel])
+            assert np.array_equal(vb[r[i]:r[i + 1]], val[rp[i]:rp[i + 1]][sel])
+        got.append(k)
+        off += k
+    assert off == len(col)                      # every nonzero exactly once
+    if B == 1:
+        assert np.array_equal(rpb[0], rp) and np.array_equal(colb, col)
+
+
+def test_column_blocks_sum_to_the_product():
+    """y = sum over blocks of the block products, in block order: bit-exact on
+    dyadic inputs (every partial sum exact)."""
+    n, m, rp, col, val = synth.tiny_random(400, 640, 0.05, 33, dyadic=True)
+    x = synth.dyadic_vector(m, 5)
+    for B in (2, 5):
+        width = (m + B - 1) // B
+        rpb, colb, valb = oracle.column_blocks(rp, col, val, B, width)
+        y = np.zeros(n)
+        off = 0
+        for b in range(B):
+            k = int(rpb[b][-1])
+            y = y + oracle.spmv(rpb[b], colb[off:off + k], valb[off:off + k], x)
+            off += k
+        assert np.array_equal(y, oracle.spmv(rp, col, val, x))
