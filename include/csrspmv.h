@@ -114,6 +114,10 @@ typedef struct {
                                 8): each row-aligned tile stores its distinct columns as
                                 16-bit offsets from its smallest one, each nonzero the 8-bit
                                 rank of its column among them */
+    int32_t column_blocks;   /* > 1: the merge path runs once per column slab of at most
+                                2 MiB of x (ML remedy with MERGE when x outgrows one XCD's
+                                L2 and the rows are short), each pass adding into y */
+    int32_t reserved;
     double p_csr, p_mb, p_ml, p_imb, p_cmp, p_peak;  /* flop/s (PROFILE) */
     double b_max;            /* B/s used for the bounds */
     double t_select_ms;      /* features/probes + decision */
@@ -216,7 +220,11 @@ csr_status_t csr_query(csr_matrix_t A, int32_t *n_rows, int32_t *n_cols, int64_t
  *         bases int32[T] (the smallest column of each tile), 8 window
  *         dictionaries uint16[T][256] (the tile's distinct columns, ascending,
  *         minus its base; zero past the window), 9 window lengths int32[T],
- *         10 window codes uint8[nnz] (rank of the column in its tile's window)
+ *         10 window codes uint8[nnz] (rank of the column in its tile's window),
+ *         11 column-block row pointers int32[B][n_rows + 1] (each from 0),
+ *         12 column-block columns int32[nnz] and 13 values (storage type,
+ *         nnz): the blocks' nonzeros one block after the other, rows in
+ *         order, storage order inside a row
  * Returns CSR_ERR_INVALID_ARG if `bytes` differs from the array's size
  * (*needed receives that size when non-NULL) or the array does not exist.
  * Synchronizes `stream`.

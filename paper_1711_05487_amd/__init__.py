@@ -29,7 +29,7 @@ SELECT = {"plain": SEL_PLAIN, "profile": SEL_PROFILE, "learned": SEL_LEARNED,
 
 (DEBUG_VALUES, DEBUG_CODES, DEBUG_TILE_I, DEBUG_TILE_J, DEBUG_LONG_ROWS, DEBUG_PLAN,
  DEBUG_MERGE_CODES, DEBUG_TILE_BASE, DEBUG_WINDOW_DICT, DEBUG_WINDOW_LEN,
- DEBUG_WINDOW_CODES) = range(11)
+ DEBUG_WINDOW_CODES, DEBUG_CB_ROWPTR, DEBUG_CB_COL, DEBUG_CB_VAL) = range(14)
 
 STATUS = ["CSR_OK", "CSR_ERR_INVALID_ARG", "CSR_ERR_INVALID_MATRIX", "CSR_ERR_OUT_OF_MEMORY",
           "CSR_ERR_DEVICE", "CSR_ERR_UNSUPPORTED", "CSR_ERR_NOT_READY"]
@@ -63,6 +63,7 @@ class PlanInfo(ctypes.Structure):
                 ("merge_items", ctypes.c_int32), ("delta_bits", ctypes.c_int32),
                 ("n_long_rows", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("merge_slack", ctypes.c_int32), ("window_codes", ctypes.c_int32),
+                ("column_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("p_csr", ctypes.c_double), ("p_mb", ctypes.c_double), ("p_ml", ctypes.c_double),
                 ("p_imb", ctypes.c_double), ("p_cmp", ctypes.c_double),
                 ("p_peak", ctypes.c_double), ("b_max", ctypes.c_double),

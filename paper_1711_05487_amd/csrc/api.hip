@@ -140,6 +140,39 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
         if (e != hipSuccess) return e;
     }
     const int32_t skip = P.long_rows ? (int32_t)A->long_tau : INT32_MAX;
+    if ((P.opts & CSR_OPT_MERGE) && P.cblocks > 0) {
+        // column blocks: one pass per slab, each adding into y
+        const int ipt = P.L / kMergeBlock;
+        const bool x32 = x_fits_32(A);
+        const size_t vb = storage_bytes(A->storage);
+        const int32_t n = A->n_rows;
+        hipError_t e = hipSuccess;
+        for (int b = 0; b < P.cblocks && e == hipSuccess; ++b) {
+            const int64_t o = A->cb_nnz_off[b];
+            const void *ab[8] = {A->cb_rp.as<int32_t>() + (size_t)b * (n + 1),
+                                 A->cb_col.as<int32_t>() + o, nullptr,
+                                 A->cb_val.as<char>() + vb * (size_t)o, x, y, nullptr, nullptr};
+            const int32_t *ti = A->cb_tile_i.as<int32_t>() + A->cb_tile_off[b];
+            const int32_t *tj = A->cb_tile_j.as<int32_t>() + A->cb_tile_off[b];
+            hipEvent_t ev = b + 1 == P.cblocks ? after : nullptr;
+            const int64_t T = A->cb_tiles[b];
+            switch (A->storage) {
+            case CSR_VAL_F64:
+                e = launch_merge_s0(ipt, true, x32, false, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
+                                    nullptr, n, T, ev, s, b > 0);
+                break;
+            case CSR_VAL_F32:
+                e = launch_merge_s1(ipt, true, x32, false, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
+                                    nullptr, n, T, ev, s, b > 0);
+                break;
+            default:
+                e = launch_merge_s2(ipt, true, x32, false, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
+                                    nullptr, n, T, ev, s, b > 0);
+                break;
+            }
+        }
+        return e;
+    }
     if (P.opts & CSR_OPT_MERGE) {
         const int ipt = P.L / kMergeBlock;
         const bool x32 = x_fits_32(A);
@@ -421,6 +454,24 @@ csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t by
         if (A->wcode_state == 1) {
             src = A->wcodes.p;
             n = (size_t)A->nnz;
+        }
+        break;
+    case 11:  // column-block row pointers
+        if (A->cb_B > 0) {
+            src = A->cb_rp.p;
+            n = sizeof(int32_t) * (size_t)A->cb_B * (A->n_rows + 1);
+        }
+        break;
+    case 12:  // column-block columns
+        if (A->cb_B > 0) {
+            src = A->cb_col.p;
+            n = sizeof(int32_t) * (size_t)A->nnz;
+        }
+        break;
+    case 13:  // column-block values
+        if (A->cb_B > 0) {
+            src = A->cb_val.p;
+            n = storage_bytes(A->storage) * (size_t)A->nnz;
         }
         break;
     case 5:

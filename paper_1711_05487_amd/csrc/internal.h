@@ -78,6 +78,7 @@ struct Plan {
     int32_t idx = IDX_I32;   // index encoding
     int32_t nt = 0;          // non-temporal val/col stream
     int32_t long_rows = 0;   // decomposition active
+    int32_t cblocks = 0;     // column blocks of the merge path (0: one pass over all columns)
     int32_t variant_id = 0;
 };
 
@@ -106,6 +107,16 @@ struct csr_matrix_s {
     int32_t wcode_state = 0;       // 1 valid, -1 not eligible, 0 not built
     int32_t wcodes_L = 0;          // tile size the window codes were built for
     int64_t wdict_entries = 0;     // sum of the window lengths
+    // column blocks (ML remedy on the merge path): cb_B slabs of cb_width columns
+    int32_t cb_B = 0;              // 0: not built
+    int32_t cb_width = 0;
+    int32_t cb_L = 0;              // tile size of their tile tables
+    csr::DevBuf cb_rp;             // cb_B x (n_rows + 1) row pointers, each from 0
+    csr::DevBuf cb_col, cb_val;    // the blocks' nonzeros, one block after the other (+ padding)
+    csr::DevBuf cb_tile_i, cb_tile_j;   // per block T_b + 1 entries, one block after the other
+    std::vector<int64_t> cb_nnz_off;    // cb_B + 1: first nonzero of each block
+    std::vector<int64_t> cb_tile_off;   // cb_B + 1: first tile-table entry of each block
+    std::vector<int64_t> cb_tiles;      // T_b
     csr::DevBuf carry;             // per-tile carry of the merge-path kernel
     int64_t n_tiles = 0;
     int32_t tiles_L = 0;
@@ -160,6 +171,17 @@ hipError_t launch_merge_encode(const int32_t *col, const int32_t *tile_j, int64_
 hipError_t launch_window_encode(const int32_t *col, const int32_t *tile_j, const int32_t *base,
                                 int64_t n_tiles, uint16_t *dict, int32_t *wlen, uint8_t *codes,
                                 int32_t *max_m, hipStream_t s);
+// Column blocks: cnt[b * n_rows + i] = nonzeros of row i in column block b
+// (columns [b width, (b+1) width)); then every nonzero is copied to its
+// block, rows in order and storage order inside a row, at pos[b] = off[b] +
+// rpb[b * (n_rows + 1) + i] (rpb counting from 0 in each block). B <= 16.
+constexpr int kMaxColBlocks = 16;
+hipError_t launch_colblock_count(const int32_t *rp, const int32_t *col, int32_t n_rows, int32_t B,
+                                 int32_t width, int32_t *cnt, hipStream_t s);
+hipError_t launch_colblock_scatter(const int32_t *rp, const int32_t *col, const void *val,
+                                   int32_t vbytes, int32_t n_rows, int32_t B, int32_t width,
+                                   const int32_t *rpb, const int64_t *off, int32_t *colb,
+                                   void *valb, hipStream_t s);
 // Merge tiles are cut at row ends (slack = longest row + 1) when every row is
 // shorter than this; otherwise slack = 0 and rows may span tiles.
 constexpr int32_t kMergeRowAlignMax = 64;
@@ -167,19 +189,20 @@ constexpr int32_t kMergeRowAlignMax = 64;
 // arr = {rp, col, codes, val, x, y, window dict, window lengths}; L = 64 *
 // ipt; x32: x spans < 4 GiB; fixup: run the cross-tile fixup pass (tiles not
 // row-aligned); idx != IDX_I32: arr[2] holds the merge codes (or the window
-// ranks, IDX_W8, row-aligned tiles only) and tile_base the tile bases
+// ranks, IDX_W8, row-aligned tiles only) and tile_base the tile bases; acc
+// (row-aligned tiles only): y += A x instead of y = A x
 hipError_t launch_merge_s0(int ipt, bool nt, bool x32, bool fixup, int idx,
                            const int32_t *tile_base, int32_t n_cols, const void *const *arr,
                            const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
-                           hipEvent_t after_main, hipStream_t s);
+                           hipEvent_t after_main, hipStream_t s, bool acc = false);
 hipError_t launch_merge_s1(int ipt, bool nt, bool x32, bool fixup, int idx,
                            const int32_t *tile_base, int32_t n_cols, const void *const *arr,
                            const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
-                           hipEvent_t after_main, hipStream_t s);
+                           hipEvent_t after_main, hipStream_t s, bool acc = false);
 hipError_t launch_merge_s2(int ipt, bool nt, bool x32, bool fixup, int idx,
                            const int32_t *tile_base, int32_t n_cols, const void *const *arr,
                            const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
-                           hipEvent_t after_main, hipStream_t s);
+                           hipEvent_t after_main, hipStream_t s, bool acc = false);
 hipError_t launch_fill_row_index(const int32_t *rp, int32_t n_rows, int32_t n_cols, int32_t *out,
                                  hipStream_t s);
 hipError_t launch_convert_values(const double *src, void *dst, int64_t n, int storage,

@@ -42,14 +42,14 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge(
     const X *__restrict__ x, X *__restrict__ y, const int32_t *__restrict__ tile_i,
     const int32_t *__restrict__ tile_j, const int32_t *__restrict__ tile_base,
     A *__restrict__ carry, int32_t n_rows, int32_t n_cols, int64_t per_xcd, int64_t n_tiles,
-    const uint16_t *__restrict__ wdict, const int32_t *__restrict__ wlen) {
+    const uint16_t *__restrict__ wdict, const int32_t *__restrict__ wlen, int32_t acc) {
     using Lds = std::conditional_t<ALN, MergeLdsRows<S, IPT>, MergeLds<S, IPT>>;
     __shared__ Lds lds;
     const int64_t t = xcd_logical_block(per_xcd);
     if (t >= n_tiles) return;
     merge_tile<S, IPT, NT, Lds, X32, IDX, ALN>(t, rp, cols, val, x, y, tile_i, tile_j,
                                                             carry, n_rows, lds, tile_base, n_cols,
-                                                            wdict, wlen);
+                                                            wdict, wlen, acc != 0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_merge_fixup(const int32_t *__restrict__ rp,
@@ -70,6 +70,7 @@ struct MergeArgs {
     int64_t n_tiles;
     bool fixup;
     hipEvent_t after_main;
+    bool acc;
 };
 
 template <int IPT, bool NT, bool X32, int IDX, bool ALN>
@@ -81,7 +82,7 @@ hipError_t go(const MergeArgs &a, hipStream_t s) {
                        0, s, (const int32_t *)a.arr[0], cols, (const V *)a.arr[3],
                        (const X *)a.arr[4], (X *)a.arr[5], a.tile_i, a.tile_j, a.tile_base,
                        (A *)a.carry, a.n_rows, a.n_cols, g.per_xcd, a.n_tiles,
-                       (const uint16_t *)a.arr[6], (const int32_t *)a.arr[7]);
+                       (const uint16_t *)a.arr[6], (const int32_t *)a.arr[7], (int32_t)a.acc);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && a.after_main) e = hipEventRecord(a.after_main, s);
     if (e != hipSuccess || a.n_tiles < 2 || ALN) return e;
@@ -119,9 +120,10 @@ hipError_t CSR_CAT(launch_merge_s, CSR_STORAGE)(int ipt, bool nt, bool x32, bool
                                                 const void *const *arr, const int32_t *tile_i,
                                                 const int32_t *tile_j, void *carry, int32_t n_rows,
                                                 int64_t n_tiles, hipEvent_t after_main,
-                                                hipStream_t s) {
+                                                hipStream_t s, bool acc) {
+    if (acc && fixup) return hipErrorInvalidValue;  // accumulation needs row-aligned tiles
     const MergeArgs a{arr, tile_i, tile_j, tile_base, carry, n_rows, n_cols, n_tiles, fixup,
-                      after_main};
+                      after_main, acc};
     // row-aligned tiles (no fixup) reduce by rows, the others by a
     // segmented scan with carries
     switch (ipt) {

@@ -276,6 +276,39 @@ __global__ __launch_bounds__(kWave) void k_window_encode(const int32_t *__restri
     if (lane == 0 && most > 0) atomicMax(max_m, most);
 }
 
+// Column blocks (ML remedy on the merge path): one thread per row counts,
+// then copies, its nonzeros block by block; per-thread counters in LDS.
+__global__ __launch_bounds__(kBlock) void k_colblock_count(const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ col,
+                                                           int32_t n_rows, int32_t B, int32_t width,
+                                                           int32_t *__restrict__ cnt) {
+    __shared__ int32_t s_cnt[kBlock * kMaxColBlocks];
+    int32_t *c = s_cnt + threadIdx.x * kMaxColBlocks;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (int b = 0; b < B; ++b) c[b] = 0;
+    if (i >= n_rows) return;
+    for (int32_t j = rp[i]; j < rp[i + 1]; ++j) ++c[col[j] / width];
+    for (int b = 0; b < B; ++b) cnt[(int64_t)b * n_rows + i] = c[b];
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_colblock_scatter(
+    const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const T *__restrict__ val,
+    int32_t n_rows, int32_t B, int32_t width, const int32_t *__restrict__ rpb,
+    const int64_t *__restrict__ off, int32_t *__restrict__ colb, T *__restrict__ valb) {
+    __shared__ int64_t s_pos[kBlock * kMaxColBlocks];
+    int64_t *pos = s_pos + threadIdx.x * kMaxColBlocks;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n_rows) return;
+    for (int b = 0; b < B; ++b) pos[b] = off[b] + rpb[(int64_t)b * (n_rows + 1) + i];
+    for (int32_t j = rp[i]; j < rp[i + 1]; ++j) {
+        const int32_t c = col[j];
+        const int64_t p = pos[c / width]++;
+        colb[p] = c;
+        valb[p] = val[j];
+    }
+}
+
 // P_ML probe input (Sec. III-B): a column array holding, for every entry, the
 // index of its own row (clamped to the last column), so the probe reads the
 // same bytes as CSR but x regularly.
@@ -374,6 +407,41 @@ hipError_t launch_window_encode(const int32_t *col, const int32_t *tile_j, const
     const unsigned g = (unsigned)std::min<int64_t>(n_tiles, 256 * 8);
     hipLaunchKernelGGL(k_window_encode, dim3(g), dim3(kWave), 0, s, col, tile_j, base, n_tiles,
                        dict, wlen, codes, max_m);
+    return hipGetLastError();
+}
+
+hipError_t launch_colblock_count(const int32_t *rp, const int32_t *col, int32_t n_rows, int32_t B,
+                                 int32_t width, int32_t *cnt, hipStream_t s) {
+    if (n_rows == 0) return hipSuccess;
+    if (B < 1 || B > kMaxColBlocks || width < 1) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)(((int64_t)n_rows + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_colblock_count, dim3(g), dim3(kBlock), 0, s, rp, col, n_rows, B, width,
+                       cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_colblock_scatter(const int32_t *rp, const int32_t *col, const void *val,
+                                   int32_t vbytes, int32_t n_rows, int32_t B, int32_t width,
+                                   const int32_t *rpb, const int64_t *off, int32_t *colb,
+                                   void *valb, hipStream_t s) {
+    if (n_rows == 0) return hipSuccess;
+    if (B < 1 || B > kMaxColBlocks || width < 1) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)(((int64_t)n_rows + kBlock - 1) / kBlock);
+    switch (vbytes) {
+    case 8:
+        hipLaunchKernelGGL(k_colblock_scatter<uint64_t>, dim3(g), dim3(kBlock), 0, s, rp, col,
+                           (const uint64_t *)val, n_rows, B, width, rpb, off, colb, (uint64_t *)valb);
+        break;
+    case 4:
+        hipLaunchKernelGGL(k_colblock_scatter<uint32_t>, dim3(g), dim3(kBlock), 0, s, rp, col,
+                           (const uint32_t *)val, n_rows, B, width, rpb, off, colb, (uint32_t *)valb);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_colblock_scatter<uint16_t>, dim3(g), dim3(kBlock), 0, s, rp, col,
+                           (const uint16_t *)val, n_rows, B, width, rpb, off, colb, (uint16_t *)valb);
+        break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -541,11 +541,12 @@ __device__ __forceinline__ void merge_gather_rows(const MergeRowRegs<S, IPT, IDX
 // largest g with g * rows <= 64): lane `sub` of the group sums the sub-th
 // contiguous chunk of the row in index order, and the group adds its chunks
 // pairwise. With more rows than lanes, lane l sums rows l, l + 64, ...
-// alone. `re` holds the row ends as MergeTileRegs does.
+// alone. `re` holds the row ends as MergeTileRegs does. With `acc` the row
+// sums are added to y (a column block after the first).
 template <int IPT, class A, class X>
 __device__ __forceinline__ void merge_row_sums(int32_t i0, int32_t i1, int32_t j0,
                                                const int32_t (&re)[IPT], const A *s_prod,
-                                               X *__restrict__ y) {
+                                               X *__restrict__ y, bool acc) {
     constexpr int BS = kMergeBlock;
     const int tid = threadIdx.x;
     const int nre = i1 - i0;  // rows of the tile
@@ -562,7 +563,10 @@ __device__ __forceinline__ void merge_row_sums(int32_t i0, int32_t i1, int32_t j
                     if (tid == 0) prev = wrap;
                 }
                 const int32_t start = r == 0 ? 0 : prev;
-                if (r < nre) yb[r] = (X)lds_run_sum(s_prod, start, end);
+                if (r < nre) {
+                    const A v = lds_run_sum(s_prod, start, end);
+                    yb[r] = acc ? (X)((A)yb[r] + v) : (X)v;
+                }
             }
         }
     } else if (nre > 0) {
@@ -576,7 +580,7 @@ __device__ __forceinline__ void merge_row_sums(int32_t i0, int32_t i1, int32_t j
         const int32_t cb = min(b + sub * chunk, end);
         A v = lds_run_sum(s_prod, cb, min(cb + chunk, end));
         for (int off = (1 << lg) >> 1; off > 0; off >>= 1) v += __shfl_down(v, off);
-        if (sub == 0 && k < nre) yb[k] = (X)v;
+        if (sub == 0 && k < nre) yb[k] = acc ? (X)((A)yb[k] + v) : (X)v;
     }
 }
 
@@ -585,7 +589,8 @@ template <int S, int IPT, class LDS, int IDX>
 __device__ __forceinline__ void merge_finish_rows(const MergeTileRegs<S, IPT, IDX> &R,
                                                   const typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX>::NIT]
                                                                                [MergeTileRegs<S, IPT, IDX>::VEC],
-                                                  typename St<S>::X *__restrict__ y, LDS &lds) {
+                                                  typename St<S>::X *__restrict__ y, LDS &lds,
+                                                  bool acc = false) {
     using A = typename St<S>::A;
     constexpr int VEC = MergeTileRegs<S, IPT, IDX>::VEC, NIT = MergeTileRegs<S, IPT, IDX>::NIT;
     using AV = typename VecOf<A, VEC>::type;
@@ -599,7 +604,7 @@ __device__ __forceinline__ void merge_finish_rows(const MergeTileRegs<S, IPT, ID
         *reinterpret_cast<AV *>(lds.prod + it * STEP + tid * VEC) = pv;
     }
     wave_lds_sync();
-    merge_row_sums<IPT>(R.i0, R.i1, R.j0, R.re, lds.prod, y);
+    merge_row_sums<IPT>(R.i0, R.i1, R.j0, R.re, lds.prod, y, acc);
 }
 
 // Products of a row-aligned tile whose x was gathered in window order
@@ -607,7 +612,8 @@ __device__ __forceinline__ void merge_finish_rows(const MergeTileRegs<S, IPT, ID
 template <int S, int IPT, class LDS, int IDX>
 __device__ __forceinline__ void merge_finish_rows(const MergeRowRegs<S, IPT, IDX> &R,
                                                   const typename St<S>::X (&xv)[IPT],
-                                                  typename St<S>::X *__restrict__ y, LDS &lds) {
+                                                  typename St<S>::X *__restrict__ y, LDS &lds,
+                                                  bool acc = false) {
     using X = typename St<S>::X;
     using A = typename St<S>::A;
     constexpr int VEC = MergeRowRegs<S, IPT, IDX>::VEC, NIT = MergeRowRegs<S, IPT, IDX>::NIT;
@@ -631,7 +637,7 @@ __device__ __forceinline__ void merge_finish_rows(const MergeRowRegs<S, IPT, IDX
         *reinterpret_cast<AV *>(s_prod + it * STEP + tid * VEC) = pv;
     }
     wave_lds_sync();
-    merge_row_sums<IPT>(R.i0, R.i1, R.j0, R.re, s_prod, y);
+    merge_row_sums<IPT>(R.i0, R.i1, R.j0, R.re, s_prod, y, acc);
 }
 
 // One tile, start to end. `cols` is the int32 column array, or the merge
@@ -648,7 +654,8 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
                                            LDS &lds, const int32_t *__restrict__ tile_base = nullptr,
                                            int32_t n_cols = 0,
                                            const uint16_t *__restrict__ wdict = nullptr,
-                                           const int32_t *__restrict__ wlen = nullptr) {
+                                           const int32_t *__restrict__ wlen = nullptr,
+                                           bool acc = false) {
     static_assert(IDX != IDX_W8 || ALN, "window codes need row-aligned tiles");
     if constexpr (IDX == IDX_W8) {
         (void)carry;
@@ -657,7 +664,7 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
         merge_issue<S, IPT, NT, IDX>(t, rp, cols, val, tile_i, tile_j, tile_base, R, wdict, wlen);
         typename St<S>::X xs[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC];
         merge_gather_window<S, IPT>(R, x, n_cols, lds, xs);
-        merge_finish_rows<S, IPT, LDS, IDX>(R, xs, y, lds);
+        merge_finish_rows<S, IPT, LDS, IDX>(R, xs, y, lds, acc);
     } else if constexpr (ALN && IDX != IDX_I32) {
         // codes: one wide load per lane, gathers in window order
         (void)carry;
@@ -666,7 +673,7 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
         merge_issue_rows<S, IPT, NT, IDX>(t, rp, cols, val, tile_i, tile_j, tile_base, R);
         typename St<S>::X xv[IPT];
         merge_gather_rows<S, IPT, X32, IDX>(R, x, n_cols, lds, xv);
-        merge_finish_rows<S, IPT, LDS, IDX>(R, xv, y, lds);
+        merge_finish_rows<S, IPT, LDS, IDX>(R, xv, y, lds, acc);
     } else if constexpr (ALN) {
         (void)carry;
         (void)n_rows;
@@ -674,8 +681,9 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
         merge_issue<S, IPT, NT, IDX>(t, rp, cols, val, tile_i, tile_j, tile_base, R);
         typename St<S>::X xs[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC];
         merge_gather<S, IPT, X32, IDX>(R, x, n_cols, xs);
-        merge_finish_rows<S, IPT, LDS, IDX>(R, xs, y, lds);
+        merge_finish_rows<S, IPT, LDS, IDX>(R, xs, y, lds, acc);
     } else {
+        (void)acc;  // not row-aligned: never a column block
         MergeTileRegs<S, IPT, IDX> R;
         merge_issue<S, IPT, NT, IDX>(t, rp, cols, val, tile_i, tile_j, tile_base, R);
         typename St<S>::X xs[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC];

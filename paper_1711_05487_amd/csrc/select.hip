@@ -57,6 +57,16 @@ double plan_bytes(const csr_matrix_s *A, const Plan &P) {
         if (P.idx != IDX_I32) b += 4.0 * T;
         // window codes: the dictionaries (window entries read) and lengths
         if (P.idx == IDX_W8) b += 2.0 * (double)A->wdict_entries + 4.0 * T;
+        if (P.cblocks > 0) {
+            // column blocks: every pass reads its row pointers and tile table
+            // and writes y (the later ones read it back); the single pass's
+            // row pointers and tile table are not read
+            const double B = (double)P.cblocks;
+            const double xb2 = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
+            b -= 4.0 * (A->n_rows + 1) + 2.0 * 4.0 * (T + 1);
+            b += 4.0 * (A->n_rows + 1) * B + 8.0 * (double)A->cb_tile_off[P.cblocks] +
+                 xb2 * A->n_rows * (2.0 * B - 2.0);
+        }
     }
     if (P.long_rows && A->n_long > 0) {
         const double ab = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
@@ -72,6 +82,7 @@ void fill_info(const csr_matrix_s *A, const Plan &P, csr_plan_info_t *info) {
     info->merge_slack = (P.opts & CSR_OPT_MERGE) ? (int32_t)A->tiles_slack : 0;
     info->delta_bits = P.idx == IDX_D16 ? 16 : (P.idx == IDX_D8 || P.idx == IDX_W8) ? 8 : 32;
     info->window_codes = P.idx == IDX_W8;
+    info->column_blocks = P.cblocks;
     info->n_long_rows = P.long_rows ? A->n_long : 0;
     info->variant_id = catalogue_id(P.opts);
     info->format_bytes = plan_bytes(A, P);
@@ -123,6 +134,7 @@ csr_status_t build_tiles(csr_matrix_s *A, int L, hipStream_t s) {
     A->mcodes_L = 0;  // merge codes belong to the previous tiles
     A->wcodes_L = 0;
     A->wcode_state = 0;
+    A->cb_B = 0;  // column blocks carry their own tile tables
     A->tiles_slack = slack;
     A->tiles_fixup = slack == 0;  // row-aligned tiles leave nothing to fix up
     return CSR_OK;
@@ -195,6 +207,86 @@ csr_status_t build_window_codes(csr_matrix_s *A, hipStream_t s) {
     for (int32_t v : wl) sum += v;
     A->wdict_entries = sum;
     A->wcode_state = 1;
+    return CSR_OK;
+}
+
+// Column blocks (ML remedy composed with the merge path): when x outgrows
+// one XCD's L2 and the rows are short (row-aligned tiles), the columns are
+// cut into slabs of at most kSlabBytes of x and the product runs slab by
+// slab, each pass gathering inside one slab (the L2 keeps it) and adding
+// into y. Worth it only with enough nonzeros per row to pay for the extra y
+// traffic; 0 = one pass over all columns.
+constexpr double kL2Bytes = 4.0 * 1024 * 1024;  // per XCD
+constexpr double kSlabBytes = 2.0 * 1024 * 1024;
+
+int column_blocks_for(const csr_matrix_s *A) {
+    const double xb = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
+    const double x_bytes = xb * A->n_cols;
+    if (x_bytes <= kL2Bytes || A->n_rows == 0 || (double)A->nnz < 4.0 * A->n_rows) return 0;
+    const int B = (int)std::ceil(x_bytes / kSlabBytes);
+    return std::min(B, 8);
+}
+
+csr_status_t build_colblocks(csr_matrix_s *A, int B, int L, hipStream_t s) {
+    if (A->cb_B == B && A->cb_L == L) return CSR_OK;
+    const int32_t n = A->n_rows;
+    const int32_t width = (int32_t)((A->n_cols + (int64_t)B - 1) / B);
+    const size_t vb = storage_bytes(A->storage);
+    csr_status_t st;
+    DevBuf cnt, off;
+    if ((st = cnt.alloc(sizeof(int32_t) * (size_t)B * std::max(n, 1))) != CSR_OK) return st;
+    CSR_HIP(launch_colblock_count(A->rp.as<int32_t>(), A->col.as<int32_t>(), n, B, width,
+                                  cnt.as<int32_t>(), s));
+    std::vector<int32_t> c((size_t)B * n), rpb((size_t)B * (n + 1));
+    if (n > 0)
+        CSR_HIP(hipMemcpyAsync(c.data(), cnt.p, sizeof(int32_t) * c.size(), hipMemcpyDeviceToHost, s));
+    CSR_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> nnz_off((size_t)B + 1, 0);
+    for (int b = 0; b < B; ++b) {
+        int32_t *r = rpb.data() + (size_t)b * (n + 1);
+        int64_t run = 0;
+        r[0] = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            run += c[(size_t)b * n + i];
+            r[i + 1] = (int32_t)run;
+        }
+        nnz_off[b + 1] = nnz_off[b] + run;
+    }
+    if ((st = A->cb_rp.alloc(sizeof(int32_t) * rpb.size())) != CSR_OK) return st;
+    if ((st = A->cb_col.alloc(sizeof(int32_t) * (size_t)A->nnz + kPadBytes)) != CSR_OK) return st;
+    if ((st = A->cb_val.alloc(vb * (size_t)A->nnz + kPadBytes)) != CSR_OK) return st;
+    if ((st = off.alloc(sizeof(int64_t) * B)) != CSR_OK) return st;
+    CSR_HIP(hipMemcpyAsync(A->cb_rp.p, rpb.data(), sizeof(int32_t) * rpb.size(),
+                           hipMemcpyHostToDevice, s));
+    CSR_HIP(hipMemcpyAsync(off.p, nnz_off.data(), sizeof(int64_t) * B, hipMemcpyHostToDevice, s));
+    CSR_HIP(hipMemsetAsync(A->cb_col.as<char>() + sizeof(int32_t) * (size_t)A->nnz, 0, kPadBytes, s));
+    CSR_HIP(hipMemsetAsync(A->cb_val.as<char>() + vb * (size_t)A->nnz, 0, kPadBytes, s));
+    CSR_HIP(launch_colblock_scatter(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->val.p, (int32_t)vb,
+                                    n, B, width, A->cb_rp.as<int32_t>(), off.as<int64_t>(),
+                                    A->cb_col.as<int32_t>(), A->cb_val.p, s));
+    // each block's merge tiles (its rows are no longer than the matrix's, so
+    // the matrix's slack keeps them row-aligned)
+    std::vector<int64_t> tiles((size_t)B), tile_off((size_t)B + 1, 0);
+    const int64_t slack = merge_slack(A, L);
+    for (int b = 0; b < B; ++b) {
+        const int64_t total = (int64_t)n + (nnz_off[b + 1] - nnz_off[b]);
+        tiles[b] = (total + (L - slack) - 1) / (L - slack);
+        tile_off[b + 1] = tile_off[b] + tiles[b] + 1;
+    }
+    if ((st = A->cb_tile_i.alloc(sizeof(int32_t) * (size_t)tile_off[B])) != CSR_OK) return st;
+    if ((st = A->cb_tile_j.alloc(sizeof(int32_t) * (size_t)tile_off[B])) != CSR_OK) return st;
+    for (int b = 0; b < B; ++b)
+        CSR_HIP(launch_merge_partition(A->cb_rp.as<int32_t>() + (size_t)b * (n + 1), n,
+                                       nnz_off[b + 1] - nnz_off[b], L, slack, tiles[b],
+                                       A->cb_tile_i.as<int32_t>() + tile_off[b],
+                                       A->cb_tile_j.as<int32_t>() + tile_off[b], s));
+    CSR_HIP(hipStreamSynchronize(s));
+    A->cb_B = B;
+    A->cb_width = width;
+    A->cb_L = L;
+    A->cb_nnz_off = nnz_off;
+    A->cb_tile_off = tile_off;
+    A->cb_tiles = tiles;
     return CSR_OK;
 }
 
@@ -277,6 +369,14 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
             return fail(CSR_ERR_INVALID_ARG, "merge_items must be 256, 512 or 1024");
         if ((st = build_tiles(A, L, s)) != CSR_OK) return st;
         P.L = L;
+        if ((opts & CSR_OPT_PREFETCH) && !(opts & CSR_OPT_DELTA) && A->tiles_slack > 0) {
+            // ML with the merge path: column blocks when x outgrows the L2
+            const int B = column_blocks_for(A);
+            if (B >= 2) {
+                if ((st = build_colblocks(A, B, L, s)) != CSR_OK) return st;
+                P.cblocks = B;
+            }
+        }
         if (opts & CSR_OPT_DELTA) {
             // MB: tile-base codes when every tile's column range fits 8 or
             // 16 bits (streamed, like the compressed arrays of the remedy);

@@ -36,6 +36,8 @@ def matrix(name: str):
         return synth.uniform_random(1 << 14, 16)
     if name == "unif17":
         return synth.uniform_random(1 << 17, 16)
+    if name == "unif600k":  # x of 4.8 MB: more than one XCD's L2
+        return synth.uniform_random(600_000, 8)
     raise KeyError(name)
 
 

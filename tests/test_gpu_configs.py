@@ -62,6 +62,17 @@ def test_merge_tile_sizes_full_size(name):
     A.close()
 
 
+def test_column_blocks_uniform_full_size():
+    """C3b with PREFETCH|MERGE: 8 MB of x in four slabs, one pass each."""
+    n, m, rp, col, val = matrix("unif20")
+    x = xvec("unif20", m)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    info = A.select("forced", forced_opts=pkg.OPT_MERGE | pkg.OPT_PREFETCH)
+    assert info["column_blocks"] == 4
+    check_f64(spmv(A, x), rp, col, val, x, "unif20 column blocks")
+    A.close()
+
+
 def test_long_row_decomposition_rmat22():
     n, m, rp, col, val = matrix("rmat22")
     x = xvec("rmat22", m)

@@ -229,3 +229,67 @@ def test_window_codes_parity(storage):
         y = A.spmv(xs)
         torch.cuda.synchronize()
         check_reduced(y.cpu().numpy(), rp2, col2, val2, x, storage, f"window codes {storage}")
+
+
+def _dyadic(val, seed):
+    """Small integers (exact products and sums with a dyadic x)."""
+    q = synth.uindex(seed, 0, np.arange(len(val), dtype=np.uint64), 15).astype(np.float64) - 7.0
+    q[q == 0] = 3.0
+    return q
+
+
+@pytest.mark.parametrize("L", [256, 512])
+def test_column_blocks_bit_exact(L):
+    """PREFETCH|MERGE on short rows with x above one XCD's L2: column blocks
+    equal to the oracle's (row pointers, columns, values), and y from one
+    pass per block equals the oracle bit for bit on dyadic inputs."""
+    n, m, rp, col, val = matrix("unif600k")
+    val = _dyadic(val, 41)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    info = A.select("forced", forced_opts=M | pkg.OPT_PREFETCH, merge_items=L)
+    B = info["column_blocks"]
+    assert B == 3  # 4.8 MB of x in slabs of at most 2 MiB
+    width = (m + B - 1) // B
+    rpb, colb, valb = oracle.column_blocks(rp, col, val, B, width)
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_CB_ROWPTR, np.int32), rpb.ravel())
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_CB_COL, np.int32), colb)
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_CB_VAL, np.float64), valb)
+    x = synth.dyadic_vector(m, 42)
+    assert np.array_equal(run(A, x), oracle.spmv(rp, col, val, x))
+    # blocks are deterministic: a second product gives the same bits
+    assert np.array_equal(run(A, x), run(A, x))
+    A.close()
+
+
+def _wide(n_rows=200_000, n_cols=1_500_000, k=8, seed=51):
+    """Rectangular, 8 random columns per row (repeats allowed, summed in
+    storage order): x of 12 MB (f64) or 6 MB (f32)."""
+    idx = np.arange(n_rows * k, dtype=np.uint64)
+    cols = synth.uindex(seed, 0, idx, n_cols).reshape(n_rows, k).astype(np.int64)
+    cols.sort(axis=1)
+    rp = np.arange(0, n_rows * k + 1, k, dtype=np.int32)
+    return n_rows, n_cols, rp, cols.ravel().astype(np.int32), synth.u01(seed, 1, idx)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_column_blocks_parity(storage):
+    n, m, rp, col, val = _wide()
+    x = synth.vector(m, 52)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m, storage=storage)
+    info = A.select("forced", forced_opts=M | pkg.OPT_PREFETCH)
+    assert info["column_blocks"] == (6 if storage == "f64" else 3)
+    if storage == "f64":
+        check_f64(run(A, x), rp, col, val, x, "column blocks")
+    else:
+        xs = torch.from_numpy(oracle.to_f32(x)).cuda()
+        y = A.spmv(xs)
+        torch.cuda.synchronize()
+        check_reduced(y.cpu().numpy(), rp, col, val, x, storage, f"column blocks {storage}")
+    # codes take the single pass
+    assert A.select("forced", forced_opts=M | pkg.OPT_DELTA)["column_blocks"] == 0
+    A.close()
+    # x inside one L2: a single pass
+    n, m, rp, col, val = matrix("unif17")
+    B = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    assert B.select("forced", forced_opts=M | pkg.OPT_PREFETCH)["column_blocks"] == 0
+    B.close()
