@@ -211,11 +211,14 @@ csr_status_t build_window_codes(csr_matrix_s *A, hipStream_t s) {
 }
 
 // Column blocks (ML remedy composed with the merge path): when x outgrows
-// one XCD's L2 and the rows are short (row-aligned tiles), the columns are
-// cut into slabs of at most kSlabBytes of x and the product runs slab by
-// slab, each pass gathering inside one slab (the L2 keeps it) and adding
-// into y. Worth it only with enough nonzeros per row to pay for the extra y
-// traffic; 0 = one pass over all columns.
+// one XCD's L2, the rows are short (row-aligned tiles) and a row's columns
+// spread over more x than a slab holds (the average row bandwidth bw_avg of
+// Table I), the columns are cut into slabs of at most kSlabBytes of x and
+// the product runs slab by slab, each pass gathering inside one slab (the
+// L2 keeps it) and adding into y. Rows whose columns stay close (stencils,
+// bands) already gather from a small window and would only pay the extra y
+// traffic; so would rows with few nonzeros. Needs the features; 0 = one
+// pass over all columns.
 constexpr double kL2Bytes = 4.0 * 1024 * 1024;  // per XCD
 constexpr double kSlabBytes = 2.0 * 1024 * 1024;
 
@@ -223,6 +226,7 @@ int column_blocks_for(const csr_matrix_s *A) {
     const double xb = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
     const double x_bytes = xb * A->n_cols;
     if (x_bytes <= kL2Bytes || A->n_rows == 0 || (double)A->nnz < 4.0 * A->n_rows) return 0;
+    if (!A->has_features || A->feat.f[7] * xb <= kSlabBytes) return 0;
     const int B = (int)std::ceil(x_bytes / kSlabBytes);
     return std::min(B, 8);
 }
@@ -339,6 +343,8 @@ int64_t long_row_tau(const csr_matrix_s *A, const csr_config_t &cfg) {
 
 }  // namespace
 
+csr_status_t inspect(csr_matrix_s *A, hipStream_t s);
+
 // Realize an optimization mask as a concrete plan, building what it needs.
 // Parameters not fixed by cfg take the defaults below; the autotuner varies
 // them.
@@ -371,6 +377,8 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
         P.L = L;
         if ((opts & CSR_OPT_PREFETCH) && !(opts & CSR_OPT_DELTA) && A->tiles_slack > 0) {
             // ML with the merge path: column blocks when x outgrows the L2
+            // and the rows' columns spread over it
+            if (!A->has_features && (st = inspect(A, s)) != CSR_OK) return st;
             const int B = column_blocks_for(A);
             if (B >= 2) {
                 if ((st = build_colblocks(A, B, L, s)) != CSR_OK) return st;
