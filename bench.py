@@ -168,6 +168,9 @@ def main():
                     help="amortization study (Sec. IV-D, Table V; one JSON line per case)")
     ap.add_argument("--amortize-matrices", type=int, default=40,
                     help="held-out suite matrices in the Table V study")
+    ap.add_argument("--irregular", action="store_true",
+                    help="run the irregular configurations' plans (R-MAT 22, uniform 2^20 x 16) "
+                         "a few times each, for counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -178,6 +181,8 @@ def main():
         return suite(args)
     if args.amortize:
         return amortize(args)
+    if args.irregular:
+        return irregular(args)
 
     import torch
     import paper_1711_05487_amd as pkg
@@ -649,6 +654,44 @@ def amortize(args):
                   "n_iters_min": None if nim is None else round(nim, 1)})
             A.close()
         log(f"cg {tag} done")
+
+
+# ---------------------------------------------------------------------------
+# --irregular: the plans of the gather-bound configurations, for counter runs
+# ---------------------------------------------------------------------------
+
+def irregular(args):
+    """R-MAT scale 22 and uniform 2^20 x 16 under plain CSR, the merge path
+    and (uniform) the column-blocked merge path: `args.steps` calls each, one
+    JSON line per plan with the algorithmic bytes of one call."""
+    import torch
+    import paper_1711_05487_amd as pkg
+    import synth
+    torch.cuda.set_device(0)
+    cases = [("C3a", "R-MAT scale 22, edge factor 16", lambda: synth.rmat(22), 303,
+              [("plain", 0), ("merge", pkg.OPT_MERGE), ("prefetch+merge", pkg.OPT_MERGE | pkg.OPT_PREFETCH)]),
+             ("C3b", "uniform random 2^20 x 16", lambda: synth.uniform_random(1 << 20, 16), 403,
+              [("plain", 0), ("merge", pkg.OPT_MERGE),
+               ("prefetch+merge (column blocks)", pkg.OPT_MERGE | pkg.OPT_PREFETCH)])]
+    for tag, desc, gen, xseed, plans in cases:
+        n, m, rp, col, val = gen()
+        x = torch.from_numpy(synth.vector(m, xseed)).cuda()
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+        for name, opts in plans:
+            info = A.select("forced", forced_opts=opts)
+            for _ in range(args.warmup):
+                A.spmv(x, y)
+            torch.cuda.synchronize()
+            for _ in range(args.steps):
+                A.spmv(x, y)
+            torch.cuda.synchronize()
+            k_ms, _, kern = A.time_spmv(x, y, 20)
+            emit({"case": tag, "workload": f"{desc} (N={n:,}, NNZ={len(col):,})", "plan": name,
+                  "kernel": kern, "column_blocks": info["column_blocks"],
+                  "format_bytes": info["format_bytes"], "kernel_ms": round(k_ms, 5),
+                  "calls": args.steps})
+        A.close()
 
 
 if __name__ == "__main__":
