@@ -120,7 +120,8 @@ bool x_fits_32(const csr_matrix_s *A) {
 
 std::string dominant_kernel(const csr_matrix_s *A, const Plan &P) {
     if (P.opts & CSR_OPT_MERGE)
-        return "k_merge<" + std::to_string(P.L / kMergeBlock) + ", " + (P.nt ? "true" : "false") +
+        return "k_merge<" + std::to_string(P.L / kMergeBlock) + ", " +
+               (P.nt && !P.cblocks ? "true" : "false") +
                ", " + (P.idx == IDX_I32 && x_fits_32(A) ? "true" : "false") + ", " +
                std::to_string(P.idx) + ", " + (A->tiles_fixup ? "false" : "true") + ">";
     return "k_rowsplit<" + std::to_string(P.G) + ", " + std::to_string(P.idx) + ", " +
@@ -141,7 +142,9 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
     }
     const int32_t skip = P.long_rows ? (int32_t)A->long_tau : INT32_MAX;
     if ((P.opts & CSR_OPT_MERGE) && P.cblocks > 0) {
-        // column blocks: one pass per slab, each adding into y
+        // column blocks: one pass per slab, each adding into y; the slab's
+        // columns and values are read with ordinary loads (measured faster
+        // than with the streaming hint for these passes)
         const int ipt = P.L / kMergeBlock;
         const bool x32 = x_fits_32(A);
         const size_t vb = storage_bytes(A->storage);
@@ -158,15 +161,15 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
             const int64_t T = A->cb_tiles[b];
             switch (A->storage) {
             case CSR_VAL_F64:
-                e = launch_merge_s0(ipt, true, x32, false, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
+                e = launch_merge_s0(ipt, false, x32, false, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
                                     nullptr, n, T, ev, s, b > 0);
                 break;
             case CSR_VAL_F32:
-                e = launch_merge_s1(ipt, true, x32, false, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
+                e = launch_merge_s1(ipt, false, x32, false, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
                                     nullptr, n, T, ev, s, b > 0);
                 break;
             default:
-                e = launch_merge_s2(ipt, true, x32, false, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
+                e = launch_merge_s2(ipt, false, x32, false, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
                                     nullptr, n, T, ev, s, b > 0);
                 break;
             }
