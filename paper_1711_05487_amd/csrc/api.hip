@@ -430,7 +430,7 @@ csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t by
     case 3: if (A->n_tiles > 0) { src = A->tile_j.p; n = sizeof(int32_t) * (A->n_tiles + 1); } break;
     case 4: if (A->n_long > 0) { src = A->long_list.p; n = sizeof(int32_t) * A->n_long; } break;
     case 6:  // merge codes
-        if (A->mcode_bits == 8 || A->mcode_bits == 16) {
+        if ((A->mcode_bits == 8 || A->mcode_bits == 16) && A->mcodes_encoded) {
             src = A->mcodes.p;
             n = (size_t)A->nnz * (A->mcode_bits / 8);
         }

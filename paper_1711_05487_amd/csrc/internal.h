@@ -101,6 +101,7 @@ struct csr_matrix_s {
     csr::DevBuf mcodes;            // merge codes: per-nonzero offset from its tile's base
     int32_t mcode_bits = 0;        // 8 / 16 when mcodes is valid, 32 = not eligible, 0 = not built
     int32_t mcodes_L = 0;          // tile size the merge codes were built for
+    int32_t mcodes_encoded = 0;    // mcodes holds the codes (not only the bases and width)
     csr::DevBuf wdict;             // window codes: per tile kWindowMax uint16 column offsets
     csr::DevBuf wlen;              // window codes: window entries of each tile, T int32
     csr::DevBuf wcodes;            // window codes: per-nonzero rank in its tile's window (uint8)

@@ -404,7 +404,8 @@ hipError_t launch_window_encode(const int32_t *col, const int32_t *tile_j, const
                                 int64_t n_tiles, uint16_t *dict, int32_t *wlen, uint8_t *codes,
                                 int32_t *max_m, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
-    const unsigned g = (unsigned)std::min<int64_t>(n_tiles, 256 * 8);
+    // 12 KiB of LDS per wave: about a dozen waves per CU
+    const unsigned g = (unsigned)std::min<int64_t>(n_tiles, 256 * 12);
     hipLaunchKernelGGL(k_window_encode, dim3(g), dim3(kWave), 0, s, col, tile_j, base, n_tiles,
                        dict, wlen, codes, max_m);
     return hipGetLastError();

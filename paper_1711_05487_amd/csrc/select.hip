@@ -142,8 +142,22 @@ csr_status_t build_tiles(csr_matrix_s *A, int L, hipStream_t s) {
 
 // Merge codes (MB remedy on the merge path, Table II): the narrowest width
 // (8, else 16 bits) that holds every tile's column range; 32 = not eligible.
-csr_status_t build_merge_codes(csr_matrix_s *A, hipStream_t s) {
-    if (A->mcodes_L == A->tiles_L && A->mcode_bits != 0) return CSR_OK;
+// The tile bases and the width come first; the codes themselves only when
+// `encode` (window codes need the bases and the width check, not the codes).
+csr_status_t build_merge_codes(csr_matrix_s *A, hipStream_t s, bool encode = true) {
+    if (A->mcodes_L == A->tiles_L && A->mcode_bits != 0) {
+        if (!encode || A->mcodes_encoded || A->mcode_bits == 32) return CSR_OK;
+        csr_status_t st;
+        const int bits = A->mcode_bits;
+        if ((st = A->mcodes.alloc((size_t)A->nnz * (bits / 8) + kPadBytes)) != CSR_OK) return st;
+        CSR_HIP(hipMemsetAsync(A->mcodes.as<char>() + (size_t)A->nnz * (bits / 8), 0, kPadBytes,
+                               s));
+        CSR_HIP(launch_merge_encode(A->col.as<int32_t>(), A->tile_j.as<int32_t>(), A->n_tiles,
+                                    A->tile_base.as<int32_t>(), bits, A->mcodes.p, s));
+        CSR_HIP(hipStreamSynchronize(s));
+        A->mcodes_encoded = 1;
+        return CSR_OK;
+    }
     const int64_t T = A->n_tiles;
     csr_status_t st;
     if ((st = A->tile_base.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(T, 1))) != CSR_OK)
@@ -157,13 +171,15 @@ csr_status_t build_merge_codes(csr_matrix_s *A, hipStream_t s) {
     CSR_HIP(hipMemcpyAsync(&r, range.p, sizeof(r), hipMemcpyDeviceToHost, s));
     CSR_HIP(hipStreamSynchronize(s));
     const int bits = r < (1 << 8) ? 8 : r < (1 << 16) ? 16 : 32;
-    if (bits != 32) {
+    A->mcodes_encoded = 0;
+    if (bits != 32 && encode) {
         if ((st = A->mcodes.alloc((size_t)A->nnz * (bits / 8) + kPadBytes)) != CSR_OK) return st;
         CSR_HIP(hipMemsetAsync(A->mcodes.as<char>() + (size_t)A->nnz * (bits / 8), 0, kPadBytes,
                                s));
         CSR_HIP(launch_merge_encode(A->col.as<int32_t>(), A->tile_j.as<int32_t>(), T,
                                     A->tile_base.as<int32_t>(), bits, A->mcodes.p, s));
         CSR_HIP(hipStreamSynchronize(s));
+        A->mcodes_encoded = 1;
     }
     A->mcode_bits = bits;
     A->mcodes_L = A->tiles_L;
@@ -176,7 +192,7 @@ csr_status_t build_merge_codes(csr_matrix_s *A, hipStream_t s) {
 csr_status_t build_window_codes(csr_matrix_s *A, hipStream_t s) {
     if (A->wcodes_L == A->tiles_L && A->wcode_state != 0) return CSR_OK;
     csr_status_t st;
-    if ((st = build_merge_codes(A, s)) != CSR_OK) return st;
+    if ((st = build_merge_codes(A, s, false)) != CSR_OK) return st;
     A->wcodes_L = A->tiles_L;
     A->wcode_state = -1;
     if (A->tiles_slack <= 0 || A->mcode_bits > 16) return CSR_OK;
@@ -390,7 +406,7 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
             // 16 bits (streamed, like the compressed arrays of the remedy);
             // on row-aligned tiles whose ranges need 16 bits, window codes
             // when every tile has at most kWindowMax distinct columns
-            if ((st = build_merge_codes(A, s)) != CSR_OK) return st;
+            if ((st = build_merge_codes(A, s, false)) != CSR_OK) return st;
             if (A->mcode_bits == 16 && A->tiles_slack > 0) {
                 if ((st = build_window_codes(A, s)) != CSR_OK) return st;
             }
@@ -398,6 +414,7 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
                 P.idx = IDX_W8;
                 P.nt = 1;
             } else if (A->mcode_bits == 8 || A->mcode_bits == 16) {
+                if ((st = build_merge_codes(A, s, true)) != CSR_OK) return st;
                 P.idx = A->mcode_bits == 8 ? IDX_D8 : IDX_D16;
                 P.nt = 1;
             }
