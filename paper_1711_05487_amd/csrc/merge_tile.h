@@ -394,7 +394,11 @@ __device__ __forceinline__ void merge_gather_window(const MergeTileRegs<S, IPT, 
     const auto rx = buffer_range(x + R.base, nx * (uint32_t)sizeof(X));
     XV4 w;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = buffer_load<X, false>(rx, (uint32_t)R.dv[k] * (uint32_t)sizeof(X), 0u);
+    for (int k = 0; k < 4; ++k) {
+        // entries past the window read nothing (an offset past the range)
+        const bool in = 4 * (int)threadIdx.x + k < R.wl;
+        w[k] = buffer_load<X, false>(rx, in ? (uint32_t)R.dv[k] * (uint32_t)sizeof(X) : 0x80000000u, 0u);
+    }
     X *s_win = reinterpret_cast<X *>(lds.prod);
     *reinterpret_cast<XV4 *>(s_win + 4 * threadIdx.x) = w;
     wave_lds_sync();
