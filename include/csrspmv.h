@@ -115,8 +115,9 @@ typedef struct {
                                 16-bit offsets from its smallest one, each nonzero the 8-bit
                                 rank of its column among them */
     int32_t column_blocks;   /* > 1: the merge path runs once per column slab of at most
-                                2 MiB of x (ML remedy with MERGE when x outgrows one XCD's
-                                L2 and the rows are short), each pass adding into y */
+                                2 MiB of x, each pass adding into y (merge plans without
+                                codes, when x outgrows one XCD's L2, rows are short and
+                                their columns spread over x) */
     int32_t reserved;
     double p_csr, p_mb, p_ml, p_imb, p_cmp, p_peak;  /* flop/s (PROFILE) */
     double b_max;            /* B/s used for the bounds */

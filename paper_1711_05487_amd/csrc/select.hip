@@ -226,7 +226,8 @@ csr_status_t build_window_codes(csr_matrix_s *A, hipStream_t s) {
     return CSR_OK;
 }
 
-// Column blocks (ML remedy composed with the merge path): when x outgrows
+// Column blocks (the merge path's answer to x gathers that miss the L2, the
+// latency bottleneck of Sec. III-A that the ML remedy targets): when x outgrows
 // one XCD's L2, the rows are short (row-aligned tiles) and a row's columns
 // spread over more x than a slab holds (the average row bandwidth bw_avg of
 // Table I), the columns are cut into slabs of at most kSlabBytes of x and
@@ -391,9 +392,9 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
             return fail(CSR_ERR_INVALID_ARG, "merge_items must be 256, 512 or 1024");
         if ((st = build_tiles(A, L, s)) != CSR_OK) return st;
         P.L = L;
-        if ((opts & CSR_OPT_PREFETCH) && !(opts & CSR_OPT_DELTA) && A->tiles_slack > 0) {
-            // ML with the merge path: column blocks when x outgrows the L2
-            // and the rows' columns spread over it
+        if (!(opts & CSR_OPT_DELTA) && A->tiles_slack > 0) {
+            // the merge path keeps its gathers inside the L2: column blocks
+            // when x outgrows it and the rows' columns spread over it
             if (!A->has_features && (st = inspect(A, s)) != CSR_OK) return st;
             const int B = column_blocks_for(A);
             if (B >= 2) {

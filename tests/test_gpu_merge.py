@@ -240,13 +240,13 @@ def _dyadic(val, seed):
 
 @pytest.mark.parametrize("L", [256, 512])
 def test_column_blocks_bit_exact(L):
-    """PREFETCH|MERGE on short rows with x above one XCD's L2: column blocks
+    """MERGE on short rows spread over an x above one XCD's L2: column blocks
     equal to the oracle's (row pointers, columns, values), and y from one
     pass per block equals the oracle bit for bit on dyadic inputs."""
     n, m, rp, col, val = matrix("unif600k")
     val = _dyadic(val, 41)
     A = pkg.CsrMatrix(rp, col, val, n_cols=m)
-    info = A.select("forced", forced_opts=M | pkg.OPT_PREFETCH, merge_items=L)
+    info = A.select("forced", forced_opts=M, merge_items=L)
     B = info["column_blocks"]
     assert B == 3  # 4.8 MB of x in slabs of at most 2 MiB
     width = (m + B - 1) // B
@@ -288,8 +288,10 @@ def test_column_blocks_parity(storage):
     # codes take the single pass
     assert A.select("forced", forced_opts=M | pkg.OPT_DELTA)["column_blocks"] == 0
     A.close()
-    # x inside one L2: a single pass
-    n, m, rp, col, val = matrix("unif17")
-    B = pkg.CsrMatrix(rp, col, val, n_cols=m)
-    assert B.select("forced", forced_opts=M | pkg.OPT_PREFETCH)["column_blocks"] == 0
-    B.close()
+    # x inside one L2, or rows whose columns stay close: a single pass
+    for name in ("unif17", "st27_128"):
+        n, m, rp, col, val = matrix(name)
+        B = pkg.CsrMatrix(rp, col, val, n_cols=m)
+        assert B.select("forced", forced_opts=M | pkg.OPT_PREFETCH)["column_blocks"] == 0, name
+        assert B.select("forced", forced_opts=M)["column_blocks"] == 0, name
+        B.close()
