@@ -352,7 +352,7 @@ def suite(args):
     emit({"case": "triad", "hbm_gbs": round(triad, 1), "mall_gbs": round(triad_mall, 1),
           "device": torch.cuda.get_device_name(0)})
 
-    configs = [
+    workloads = [
         ("C1", "2-D 5-point Laplacian 100^2", lambda: synth.laplacian2d(100), 101),
         ("C2", "27-point stencil 128^3", lambda: synth.stencil27(128), 203),
         ("C3a", "R-MAT scale 22, edge factor 16", lambda: synth.rmat(22), 303),
@@ -360,7 +360,7 @@ def suite(args):
          lambda: permuted(synth.rmat(22)), 303),
         ("C3b", "uniform random 2^20 x 16", lambda: synth.uniform_random(1 << 20, 16), 403),
     ]
-    for tag, desc, gen, xseed in configs:
+    for tag, desc, gen, xseed in workloads:
         log(f"{tag}: generating {desc}")
         n, m, rp, col, val = gen()
         nnz = len(col)
@@ -418,7 +418,7 @@ def suite(args):
         del chk
 
     # C4: value storage x index format on C1 and C2 (FP32 accumulation for f32/bf16)
-    for tag, desc, gen, xseed in configs[:2]:
+    for tag, desc, gen, xseed in workloads[:2]:
         n, m, rp, col, val = gen()
         x = synth.vector(m, xseed)
         chk = GpuCheck(pkg, rp, col, val, x, m)

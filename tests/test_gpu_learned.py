@@ -1,5 +1,5 @@
-"""The trained learned selector against its judges, on GPU: regret against
-the exhaustive timings on the held-out split (the benchmark spec: within 10% of the
+"""The trained learned selector against the timings that label it, on GPU:
+regret against the exhaustive timings on the held-out split (within 10% of the
 best variant), the gain over the method without the network (plain CSR and
 the profile-guided selector), and the selection cost against one plain
 SpMV. The labels and weights are the committed training set and model
