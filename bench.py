@@ -156,8 +156,8 @@ def cpu_multicore(rp, col, val, x, bytes_per_call, budget_s=4.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--select", default="learned",
                     help="learned (committed MLP), profile, exhaustive or plain")
     ap.add_argument("--grid", type=int, default=128)
