@@ -95,6 +95,11 @@ typedef struct {
     int32_t exhaustive_set;  /* CSR_SEL_EXHAUSTIVE: 0 = the 16-entry catalogue (the "trivial
                                 combined" optimizer of Sec. IV-D), 1 = the baseline and the
                                 5 single remedies ("trivial single") */
+    int32_t dynamic_rows;    /* row-split plans: 0 = static schedule (one block of rows per
+                                workgroup), 1 = dynamic chunks (resident workgroups take
+                                blocks of rows from a counter); the autotuner also tries 1
+                                for imbalanced matrices */
+    int32_t reserved;
 } csr_config_t;
 
 /* What csr_select decided and what it cost. */
@@ -118,7 +123,7 @@ typedef struct {
                                 2 MiB of x, each pass adding into y (merge plans without
                                 codes, when x outgrows one XCD's L2, rows are short and
                                 their columns spread over x) */
-    int32_t reserved;
+    int32_t dynamic_rows;    /* 1: the row-split kernel runs with dynamic chunks */
     double p_csr, p_mb, p_ml, p_imb, p_cmp, p_peak;  /* flop/s (PROFILE) */
     double b_max;            /* B/s used for the bounds */
     double t_select_ms;      /* features/probes + decision */

@@ -54,7 +54,8 @@ class Config(ctypes.Structure):
                 ("forced_opts", ctypes.c_int32), ("rows_per_group", ctypes.c_int32),
                 ("merge_items", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("timing_calls", ctypes.c_int32), ("rows_in_flight", ctypes.c_int32),
-                ("exhaustive_set", ctypes.c_int32)]
+                ("exhaustive_set", ctypes.c_int32), ("dynamic_rows", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -63,7 +64,7 @@ class PlanInfo(ctypes.Structure):
                 ("merge_items", ctypes.c_int32), ("delta_bits", ctypes.c_int32),
                 ("n_long_rows", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("merge_slack", ctypes.c_int32), ("window_codes", ctypes.c_int32),
-                ("column_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("column_blocks", ctypes.c_int32), ("dynamic_rows", ctypes.c_int32),
                 ("p_csr", ctypes.c_double), ("p_mb", ctypes.c_double), ("p_ml", ctypes.c_double),
                 ("p_imb", ctypes.c_double), ("p_cmp", ctypes.c_double),
                 ("p_peak", ctypes.c_double), ("b_max", ctypes.c_double),

@@ -202,6 +202,7 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
                                    A->carry.p, A->n_rows, A->n_tiles, after, s);
         }
     }
+    if (P.dyn) arr[7] = A->dyn_ctr.p;  // dynamic chunks
     hipError_t e;
     switch (A->storage) {
     case CSR_VAL_F64:

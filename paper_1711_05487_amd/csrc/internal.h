@@ -16,6 +16,7 @@ constexpr int kBlock = 256;       // threads per workgroup (4 wave64s)
 constexpr int kMergeBlock = 64;   // merge-path tile workgroup: one wave64
 constexpr int kWave = 64;
 constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies
+constexpr int kMaxResidentGroups = 256 * 8;  // 256-thread workgroups resident at once (256 CUs)
 constexpr size_t kPadBytes = 64;  // tail padding of val/col: vector loads may read past nnz
 
 // IDX_W8: window codes of row-aligned merge tiles (8-bit rank of the column
@@ -79,6 +80,7 @@ struct Plan {
     int32_t nt = 0;          // non-temporal val/col stream
     int32_t long_rows = 0;   // decomposition active
     int32_t cblocks = 0;     // column blocks of the merge path (0: one pass over all columns)
+    int32_t dyn = 0;         // row-split: dynamic chunks instead of the static schedule
     int32_t variant_id = 0;
 };
 
@@ -135,6 +137,7 @@ struct csr_matrix_s {
     int has_features = 0;
     csr_features_t feat{};
     csr::DevBuf scratch_x, scratch_y, scratch_col;  // selection probes
+    csr::DevBuf dyn_ctr;           // the row-split dynamic schedule's two counters (zeroed once)
     csr::DevBuf feat_parts, feat_reuse, feat_long;  // feature-extraction partials, long rows
     double t_inspect_ms = 0.0;
 };
@@ -146,7 +149,8 @@ hipError_t launch_validate(const int32_t *rp, const int32_t *col, int32_t n_rows
                            int32_t n_cols, int64_t nnz, int32_t *d_flags, hipStream_t s);
 hipError_t launch_delta_encode(const int32_t *rp, const int32_t *col, int32_t n_rows, int bits,
                                void *codes, int32_t *d_flags, hipStream_t s);
-// arr = {rp, col, codes, val, x, y, instrumentation records (probe 2)}
+// arr = {rp, col, codes, val, x, y, instrumentation records (probe 2),
+//        dynamic-schedule counters (nullptr: static)}
 hipError_t launch_rowsplit_s0(int G, int idx, bool nt, int U, int R, int probe,
                               const void *const *arr, int32_t skip_above, int32_t n_rows,
                               int32_t n_cols, hipStream_t s);

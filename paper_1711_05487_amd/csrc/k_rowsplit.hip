@@ -32,18 +32,15 @@ using V = typename St<S>::V;
 using X = typename St<S>::X;
 using A = typename St<S>::A;
 
+// Rows of logical block lb (R chunks of 256 / G consecutive rows).
 template <int G, int IDX, bool NT, int U, int R, int PROBE>
-__global__ __launch_bounds__(kBlock) void k_rowsplit(
-    const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-    const void *__restrict__ codes, const V *__restrict__ val, const X *__restrict__ x,
-    X *__restrict__ y, int32_t skip_above, int32_t n_rows, int32_t n_cols, int64_t per_xcd,
-    int64_t nblk, int64_t *__restrict__ rec) {
-    const int64_t lb = xcd_logical_block(per_xcd);
-    if (lb >= nblk) return;
-    int64_t t_start = 0;
-    if constexpr (PROBE == 2) {
-        if (threadIdx.x == 0) t_start = (int64_t)wall_clock64();
-    }
+__device__ __forceinline__ void rowsplit_block(int64_t lb, const int32_t *__restrict__ rp,
+                                               const int32_t *__restrict__ col,
+                                               const void *__restrict__ codes,
+                                               const V *__restrict__ val,
+                                               const X *__restrict__ x, X *__restrict__ y,
+                                               int32_t skip_above, int32_t n_rows,
+                                               int32_t n_cols) {
     constexpr int NG = kBlock / G;
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
@@ -143,27 +140,84 @@ __global__ __launch_bounds__(kBlock) void k_rowsplit(
         t = group_sum<G>(t);
         if (mine[k] && lane == 0) y[row[k]] = (X)t;
     }
-    if constexpr (PROBE == 2) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            rec[3 * lb] = t_start;
-            rec[3 * lb + 1] = (int64_t)wall_clock64();
-            rec[3 * lb + 2] = (int64_t)__smid();
+}
+
+// Static schedule (ctr == nullptr): workgroup b owns logical block
+// xcd_logical_block(b). Dynamic chunks (ctr != nullptr, the "dynamic"
+// schedule of the row-parallel kernel): workgroups take `per_fetch`
+// logical blocks at a time from ctr[0] until none is left; the last
+// workgroup out resets both counters for the next launch, so no host-side
+// reset is needed (and the launch can be captured in a graph). Every row is
+// summed by one lane group in a fixed order: both schedules give the same
+// bits. The P_IMB probe (PROBE == 2) is static.
+template <int G, int IDX, bool NT, int U, int R, int PROBE>
+__global__ __launch_bounds__(kBlock) void k_rowsplit(
+    const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const void *__restrict__ codes, const V *__restrict__ val, const X *__restrict__ x,
+    X *__restrict__ y, int32_t skip_above, int32_t n_rows, int32_t n_cols, int64_t per_xcd,
+    int64_t nblk, int64_t *__restrict__ rec, int32_t *__restrict__ ctr, int32_t per_fetch) {
+    if (PROBE != 0 || ctr == nullptr) {
+        const int64_t lb = xcd_logical_block(per_xcd);
+        if (lb >= nblk) return;
+        int64_t t_start = 0;
+        if constexpr (PROBE == 2) {
+            if (threadIdx.x == 0) t_start = (int64_t)wall_clock64();
         }
+        rowsplit_block<G, IDX, NT, U, R, PROBE>(lb, rp, col, codes, val, x, y, skip_above,
+                                                n_rows, n_cols);
+        if constexpr (PROBE == 2) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                rec[3 * lb] = t_start;
+                rec[3 * lb + 1] = (int64_t)wall_clock64();
+                rec[3 * lb + 2] = (int64_t)__smid();
+            }
+        }
+        return;
+    }
+    __shared__ int32_t s_first;
+    for (;;) {
+        if (threadIdx.x == 0) s_first = atomicAdd(ctr, per_fetch);
+        __syncthreads();
+        const int64_t first = s_first;
+        __syncthreads();  // s_first is written again by the next fetch
+        if (first >= nblk) break;
+        const int64_t last = min(first + (int64_t)per_fetch, nblk);
+        for (int64_t lb = first; lb < last; ++lb)
+            rowsplit_block<G, IDX, NT, U, R, PROBE>(lb, rp, col, codes, val, x, y, skip_above,
+                                                    n_rows, n_cols);
+    }
+    if (threadIdx.x == 0 && atomicAdd(ctr + 1, 1) == (int32_t)gridDim.x - 1) {
+        atomicExch(ctr, 0);
+        atomicExch(ctr + 1, 0);
     }
 }
 
+// arr[7]: the dynamic schedule's two counters (nullptr: static schedule)
 template <int G, int IDX, bool NT, int U, int R, int PROBE>
 hipError_t go(const void *const *arr, int32_t skip_above, int32_t n_rows, int32_t n_cols,
               hipStream_t s) {
     constexpr int NG = kBlock / G;
     const int64_t rows_per_blk = (int64_t)NG * R;
-    const XcdGrid g = xcd_grid((n_rows + rows_per_blk - 1) / rows_per_blk);
-    if (g.nblk == 0) return hipSuccess;
+    const int64_t nblk = (n_rows + rows_per_blk - 1) / rows_per_blk;
+    if (nblk == 0) return hipSuccess;
+    int32_t *ctr = PROBE == 0 ? (int32_t *)arr[7] : nullptr;
+    if (ctr) {
+        // a resident grid (8 workgroups of 256 per CU) fetching ~8 times each
+        const int64_t grid = std::min<int64_t>(nblk, (int64_t)kMaxResidentGroups);
+        const int32_t per_fetch = (int32_t)std::max<int64_t>(1, nblk / (grid * 8));
+        hipLaunchKernelGGL((k_rowsplit<G, IDX, NT, U, R, PROBE>), dim3((unsigned)grid),
+                           dim3(kBlock), 0, s, (const int32_t *)arr[0], (const int32_t *)arr[1],
+                           arr[2], (const V *)arr[3], (const X *)arr[4], (X *)arr[5], skip_above,
+                           n_rows, n_cols, (int64_t)0, nblk, (int64_t *)arr[6], ctr, per_fetch);
+        return hipGetLastError();
+    }
+    const XcdGrid g = xcd_grid(nblk);
     hipLaunchKernelGGL((k_rowsplit<G, IDX, NT, U, R, PROBE>), dim3((unsigned)g.launched),
                        dim3(kBlock), 0, s, (const int32_t *)arr[0], (const int32_t *)arr[1],
                        arr[2], (const V *)arr[3], (const X *)arr[4], (X *)arr[5], skip_above,
-                       n_rows, n_cols, g.per_xcd, g.nblk, (int64_t *)arr[6]);
+                       n_rows, n_cols, g.per_xcd, g.nblk, (int64_t *)arr[6], (int32_t *)nullptr,
+                       (int32_t)1);
     return hipGetLastError();
 }
 
@@ -195,7 +249,7 @@ hipError_t pick(int idx, bool nt, int U, int R, int probe, const void *const *ar
 
 }  // namespace
 
-// arr = {rp, col, codes, val, x, y, instrumentation records}
+// arr = {rp, col, codes, val, x, y, instrumentation records, dynamic counters}
 #define CSR_CAT2(a, b) a##b
 #define CSR_CAT(a, b) CSR_CAT2(a, b)
 hipError_t CSR_CAT(launch_rowsplit_s, CSR_STORAGE)(int G, int idx, bool nt, int U, int R,

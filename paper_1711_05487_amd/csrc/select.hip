@@ -83,6 +83,7 @@ void fill_info(const csr_matrix_s *A, const Plan &P, csr_plan_info_t *info) {
     info->delta_bits = P.idx == IDX_D16 ? 16 : (P.idx == IDX_D8 || P.idx == IDX_W8) ? 8 : 32;
     info->window_codes = P.idx == IDX_W8;
     info->column_blocks = P.cblocks;
+    info->dynamic_rows = P.dyn;
     info->n_long_rows = P.long_rows ? A->n_long : 0;
     info->variant_id = catalogue_id(P.opts);
     info->format_bytes = plan_bytes(A, P);
@@ -382,6 +383,18 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
         P.R = 4;
     }
     if (cfg.rows_per_group > 0) P.G = cfg.rows_per_group;
+    if (cfg.dynamic_rows != 0 && cfg.dynamic_rows != 1)
+        return fail(CSR_ERR_INVALID_ARG, "dynamic_rows must be 0 or 1");
+    if (cfg.dynamic_rows && !(opts & CSR_OPT_MERGE)) {
+        // the row-split kernels' dynamic schedule: two counters, zeroed once
+        // (the kernel leaves them zeroed)
+        if (!A->dyn_ctr.p) {
+            csr_status_t st0;
+            if ((st0 = A->dyn_ctr.alloc(2 * sizeof(int32_t))) != CSR_OK) return st0;
+            CSR_HIP(hipMemsetAsync(A->dyn_ctr.p, 0, 2 * sizeof(int32_t), s));
+        }
+        P.dyn = 1;
+    }
     if (cfg.rows_in_flight > 0) P.R = cfg.rows_in_flight >= 4 ? 4 : cfg.rows_in_flight >= 2 ? 2 : 1;
     csr_status_t st;
     if (opts & CSR_OPT_MERGE) {
@@ -518,7 +531,7 @@ hipError_t launch_probe(const csr_matrix_s *A, int G, int which, const void *x, 
                         hipStream_t s) {
     const void *col = which == 1 ? A->scratch_col.p : A->col.p;
     const int probe = which == 2 ? 1 : 0;
-    const void *arr[7] = {A->rp.p, col, nullptr, A->val.p, x, y, nullptr};
+    const void *arr[8] = {A->rp.p, col, nullptr, A->val.p, x, y, nullptr, nullptr};
     switch (A->storage) {
     case CSR_VAL_F64:
         return launch_rowsplit_s0(G, IDX_I32, false, 1, 1, probe, arr, INT32_MAX, A->n_rows,
@@ -679,8 +692,8 @@ csr_status_t measure_bounds(csr_matrix_s *A, const csr_config_t &cfg, hipStream_
         DevBuf rec;
         if ((st = rec.alloc(sizeof(int64_t) * 3 * (size_t)std::max<int64_t>(nblk, 1))) != CSR_OK)
             return st;
-        const void *arr[7] = {A->rp.p, A->col.p, nullptr, A->val.p, A->scratch_x.p,
-                              A->scratch_y.p, rec.p};
+        const void *arr[8] = {A->rp.p, A->col.p, nullptr, A->val.p, A->scratch_x.p,
+                              A->scratch_y.p, rec.p, nullptr};
         hipError_t e;
         switch (A->storage) {
         case CSR_VAL_F64:
@@ -787,6 +800,17 @@ csr_status_t autotune(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, hi
                 c.rows_in_flight = r;
                 cands.push_back(c);
             }
+        if (opts & CSR_OPT_DECOMP) {
+            // imbalance: the dynamic schedule as well (Sec. IV-A's runtime-chosen
+            // schedule on the row-parallel kernel)
+            for (int g : gs) {
+                csr_config_t c = cfg;
+                c.rows_per_group = g;
+                c.rows_in_flight = 1;
+                c.dynamic_rows = 1;
+                cands.push_back(c);
+            }
+        }
     }
     double best_ms = 1e300;
     size_t best_k = 0;

@@ -208,3 +208,26 @@ def test_deterministic_run_twice():
 def test_triad_plausible():
     bw = pkg.triad(1 << 28, 3)
     assert 1e12 < bw < 9e12
+
+
+@pytest.mark.parametrize("name", ["rmat14", "unif17", "lap100"])
+def test_dynamic_rows_same_bits_as_static(name):
+    """The row-split kernels' dynamic schedule (resident workgroups taking
+    blocks of rows from a counter that the last one resets) sums every row
+    in the same order as the static schedule: the same bits, call after
+    call, and parity with the oracle."""
+    n, m, rp, col, val = matrix(name)
+    x = xvec(name, m)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    for opts in (0, pkg.OPT_UNROLL, pkg.OPT_PREFETCH, pkg.OPT_DECOMP, pkg.OPT_DELTA):
+        A.select("forced", forced_opts=opts, long_row_floor=200)
+        y_static = run(A, x)
+        info = A.select("forced", forced_opts=opts, long_row_floor=200, dynamic_rows=1)
+        assert info["dynamic_rows"] == 1
+        y1, y2 = run(A, x), run(A, x)
+        assert np.array_equal(y1.view(np.uint64), y_static.view(np.uint64)), (name, opts)
+        assert np.array_equal(y2.view(np.uint64), y1.view(np.uint64)), (name, opts)
+    check_f64(y1, rp, col, val, x, f"{name} dynamic rows")
+    with pytest.raises(pkg.CsrError):
+        A.select("forced", forced_opts=0, dynamic_rows=2)
+    A.close()
