@@ -171,6 +171,9 @@ def main():
     ap.add_argument("--irregular", action="store_true",
                     help="run the irregular configurations' plans (R-MAT 22, uniform 2^20 x 16) "
                          "a few times each, for counter runs")
+    ap.add_argument("--partitions", action="store_true",
+                    help="partition-aware ML study: localized irregular stretches and a suite "
+                         "sample under the profile rule with and without partitions")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -183,6 +186,8 @@ def main():
         return amortize(args)
     if args.irregular:
         return irregular(args)
+    if args.partitions:
+        return partitions(args)
 
     import torch
     import paper_1711_05487_amd as pkg
@@ -691,6 +696,57 @@ def irregular(args):
                   "kernel": kern, "column_blocks": info["column_blocks"],
                   "format_bytes": info["format_bytes"], "kernel_ms": round(k_ms, 5),
                   "calls": args.steps})
+        A.close()
+
+
+# --partitions: the partition-aware ML test (proposed with the results of
+# Sec. IV-C) against the whole-matrix test of Fig. 4
+def partitions(args):
+    """Per matrix: the whole-matrix P_ML / P_CSR, the largest partition ratio
+    (256 partitions) and the flagged partitions; the profile-guided plan's
+    kernel time without and with the partition test, with ML forced on and
+    off (the remedy's value), the learned plan's and plain CSR's."""
+    import torch
+    import paper_1711_05487_amd as pkg
+    import synth
+    from paper_1711_05487_amd import learn
+    torch.cuda.set_device(0)
+    learn.install()
+    cases = []
+    for lg in (21, 22):
+        for frac in (1 / 256, 1 / 128, 1 / 64, 1 / 32):
+            cases.append((f"localized 2^{lg} x 16, {frac * 100:.2f}% irregular rows",
+                          lambda lg=lg, frac=frac: synth.localized_irregular(1 << lg, 16, frac, 811)))
+    for i in range(3, 2000, 37):
+        if i % 5 != 0:  # the stencil family has no irregular gathers
+            cases.append((f"suite {i}", lambda i=i: synth.suite_matrix(i)[1]))
+    for name, gen in cases:
+        n, m, rp, col, val = gen()
+        x = torch.from_numpy(synth.vector(m, 3)).cuda()
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+
+        def timed():
+            return round(A.time_spmv(x, y, 30)[0] * 1000, 2)
+        A.select("plain")
+        t_plain = timed()
+        ia = A.select("profile")
+        t_a = timed()
+        ib = A.select("profile", ml_partitions=256)
+        t_b = timed()
+        A.select("profile", t_ml=0.0)
+        t_on = timed()
+        A.select("profile", t_ml=1e9)
+        t_off = timed()
+        A.select("learned")
+        t_l = timed()
+        emit({"matrix": name, "n": n, "nnz": int(rp[-1]),
+              "ml_whole": round(ia["p_ml"] / ia["p_csr"], 3),
+              "ml_part_max": round(ib["ml_part_max"], 3), "parts": ib["ml_partitions"],
+              "flagged": ib["ml_parts_flagged"], "classes": ia["classes"],
+              "classes_partitions": ib["classes"], "us_plain": t_plain, "us_profile": t_a,
+              "us_profile_partitions": t_b, "us_ml_on": t_on, "us_ml_off": t_off,
+              "us_learned": t_l})
         A.close()
 
 

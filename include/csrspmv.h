@@ -99,7 +99,15 @@ typedef struct {
                                 workgroup), 1 = dynamic chunks (resident workgroups take
                                 blocks of rows from a counter); the autotuner also tries 1
                                 for imbalanced matrices */
-    int32_t reserved;
+    int32_t ml_partitions;   /* PROFILE: 0 = the ML test of Fig. 4 on the whole matrix only;
+                                Q in 1..4096 = also the partition-aware ML test (the
+                                extension the paper proposes in Sec. IV-C): the instrumented
+                                baseline and the instrumented P_ML probe are each run 3 times,
+                                every row block keeps its shortest time, the row blocks are
+                                cut into Q contiguous partitions of about nnz/Q nonzeros, and
+                                ML is also set when some partition's summed baseline time
+                                exceeds t_ml_part times its summed probe time */
+    double t_ml_part;        /* partition-aware ML threshold (used when ml_partitions > 0) */
 } csr_config_t;
 
 /* What csr_select decided and what it cost. */
@@ -124,11 +132,14 @@ typedef struct {
                                 codes, when x outgrows one XCD's L2, rows are short and
                                 their columns spread over x) */
     int32_t dynamic_rows;    /* 1: the row-split kernel runs with dynamic chunks */
+    int32_t ml_partitions;   /* non-empty partitions of the partition-aware ML test (0: off) */
+    int32_t ml_parts_flagged;/* partitions whose time ratio exceeded t_ml_part */
     double p_csr, p_mb, p_ml, p_imb, p_cmp, p_peak;  /* flop/s (PROFILE) */
     double b_max;            /* B/s used for the bounds */
     double t_select_ms;      /* features/probes + decision */
     double t_prep_ms;        /* format conversion for the chosen plan */
     double format_bytes;     /* algorithmic bytes of one SpMV with this plan */
+    double ml_part_max;      /* largest partition ratio of the partition-aware ML test */
 } csr_plan_info_t;
 
 /* The 16 features of Sec. III-D, Table I (plus two project-defined ones):
@@ -145,7 +156,8 @@ typedef struct {
 } csr_features_t;
 
 /* Fill *cfg with the defaults (t_ml 1.25, t_imb 1.24, t_mb 0.8,
- * long_row_factor 32, long_row_floor 4096, autotune 1, timing_calls 32). */
+ * long_row_factor 32, long_row_floor 4096, autotune 1, timing_calls 32,
+ * ml_partitions 0, t_ml_part 1.5). */
 void csr_config_default(csr_config_t *cfg);
 
 /*
@@ -230,7 +242,12 @@ csr_status_t csr_query(csr_matrix_t A, int32_t *n_rows, int32_t *n_cols, int64_t
  *         11 column-block row pointers int32[B][n_rows + 1] (each from 0),
  *         12 column-block columns int32[nnz] and 13 values (storage type,
  *         nnz): the blocks' nonzeros one block after the other, rows in
- *         order, storage order inside a row
+ *         order, storage order inside a row; from the last PROFILE selection
+ *         with ml_partitions = Q > 0: 14 partition bounds int32[Q+1] (first
+ *         row block of each partition; a row block is the baseline's
+ *         workgroup of 256/G rows), 15 per-block shortest times int64[2][nblk]
+ *         (baseline, then P_ML probe; 100 MHz ticks), 16 partition ratios
+ *         double[Q] (0 for a partition without blocks)
  * Returns CSR_ERR_INVALID_ARG if `bytes` differs from the array's size
  * (*needed receives that size when non-NULL) or the array does not exist.
  * Synchronizes `stream`.

@@ -392,6 +392,44 @@ def b_for_footprint(bytes_total, b_hbm, b_cache, cache_bytes=MALL_BYTES):
     return b_cache if bytes_total <= cache_bytes else b_hbm
 
 
+def ml_partition_bounds(rp, rows_per_block: int, Q: int) -> np.ndarray:
+    """Partition-aware ML detection, the extension the paper proposes with
+    its Sec. IV-C results (look at the P_ML benchmark per partition instead
+    of over the whole matrix). Reading: the partitions are Q contiguous runs
+    of the baseline's row blocks (rows_per_block rows each) with about nnz/Q
+    nonzeros each, as the static nnz-balanced partitioning of Sec. IV-A.
+    bound[q] is the first block b (0 <= b <= nblk) whose first nonzero index
+    rp[min(b * rows_per_block, N)] is at least floor(q * nnz / Q); bound[Q] is
+    nblk. Linear scan over the blocks."""
+    rp = np.asarray(rp, dtype=np.int64)
+    n = rp.size - 1
+    nnz = int(rp[-1])
+    nblk = -(-n // rows_per_block)
+    first = [int(rp[min(b * rows_per_block, n)]) for b in range(nblk + 1)]
+    out = np.empty(Q + 1, dtype=np.int32)
+    for q in range(Q):
+        target = q * nnz // Q
+        b = 0
+        while b < nblk and first[b] < target:
+            b += 1
+        out[q] = b
+    out[Q] = nblk
+    return out
+
+
+def ml_partition_ratios(t_base, t_probe, bounds) -> np.ndarray:
+    """Per partition: the baseline's summed block times over the P_ML probe's
+    summed block times (the P_ML / P_CSR ratio of Sec. III-B restricted to
+    the partition); 0 for a partition without blocks or without time."""
+    out = np.zeros(len(bounds) - 1)
+    for q in range(len(bounds) - 1):
+        sc = int(np.sum(np.asarray(t_base[bounds[q]:bounds[q + 1]], dtype=np.int64)))
+        sm = int(np.sum(np.asarray(t_probe[bounds[q]:bounds[q + 1]], dtype=np.int64)))
+        if sc > 0 and sm > 0:
+            out[q] = sc / sm
+    return out
+
+
 CLS_MB, CLS_ML, CLS_IMB, CLS_CMP = 1, 2, 4, 8
 
 

@@ -29,7 +29,8 @@ SELECT = {"plain": SEL_PLAIN, "profile": SEL_PROFILE, "learned": SEL_LEARNED,
 
 (DEBUG_VALUES, DEBUG_CODES, DEBUG_TILE_I, DEBUG_TILE_J, DEBUG_LONG_ROWS, DEBUG_PLAN,
  DEBUG_MERGE_CODES, DEBUG_TILE_BASE, DEBUG_WINDOW_DICT, DEBUG_WINDOW_LEN,
- DEBUG_WINDOW_CODES, DEBUG_CB_ROWPTR, DEBUG_CB_COL, DEBUG_CB_VAL) = range(14)
+ DEBUG_WINDOW_CODES, DEBUG_CB_ROWPTR, DEBUG_CB_COL, DEBUG_CB_VAL,
+ DEBUG_MLP_BOUNDS, DEBUG_MLP_TIMES, DEBUG_MLP_RATIOS) = range(17)
 
 STATUS = ["CSR_OK", "CSR_ERR_INVALID_ARG", "CSR_ERR_INVALID_MATRIX", "CSR_ERR_OUT_OF_MEMORY",
           "CSR_ERR_DEVICE", "CSR_ERR_UNSUPPORTED", "CSR_ERR_NOT_READY"]
@@ -55,7 +56,7 @@ class Config(ctypes.Structure):
                 ("merge_items", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("timing_calls", ctypes.c_int32), ("rows_in_flight", ctypes.c_int32),
                 ("exhaustive_set", ctypes.c_int32), ("dynamic_rows", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("ml_partitions", ctypes.c_int32), ("t_ml_part", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -65,11 +66,12 @@ class PlanInfo(ctypes.Structure):
                 ("n_long_rows", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("merge_slack", ctypes.c_int32), ("window_codes", ctypes.c_int32),
                 ("column_blocks", ctypes.c_int32), ("dynamic_rows", ctypes.c_int32),
+                ("ml_partitions", ctypes.c_int32), ("ml_parts_flagged", ctypes.c_int32),
                 ("p_csr", ctypes.c_double), ("p_mb", ctypes.c_double), ("p_ml", ctypes.c_double),
                 ("p_imb", ctypes.c_double), ("p_cmp", ctypes.c_double),
                 ("p_peak", ctypes.c_double), ("b_max", ctypes.c_double),
                 ("t_select_ms", ctypes.c_double), ("t_prep_ms", ctypes.c_double),
-                ("format_bytes", ctypes.c_double)]
+                ("format_bytes", ctypes.c_double), ("ml_part_max", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

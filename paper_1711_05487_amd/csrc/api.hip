@@ -255,6 +255,8 @@ void csr_config_default(csr_config_t *cfg) {
     cfg->merge_items = 0;
     cfg->autotune = 1;
     cfg->timing_calls = 32;
+    cfg->ml_partitions = 0;
+    cfg->t_ml_part = 1.5;
 }
 
 const char *csr_status_str(csr_status_t s) {
@@ -478,6 +480,21 @@ csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t by
             n = storage_bytes(A->storage) * (size_t)A->nnz;
         }
         break;
+    case 14:
+    case 15:
+    case 16: {  // partition-aware ML test (host copies)
+        const void *h = what == 14 ? (const void *)A->mlp_bounds.data()
+                        : what == 15 ? (const void *)A->mlp_times.data()
+                                     : (const void *)A->mlp_ratios.data();
+        const size_t hn = what == 14 ? sizeof(int32_t) * A->mlp_bounds.size()
+                          : what == 15 ? sizeof(int64_t) * A->mlp_times.size()
+                                       : sizeof(double) * A->mlp_ratios.size();
+        if (needed) *needed = hn;
+        if (A->mlp_bounds.empty()) return fail(CSR_ERR_INVALID_ARG, "array not present");
+        if (bytes != hn || !h_dst) return fail(CSR_ERR_INVALID_ARG, "size mismatch");
+        if (hn) std::memcpy(h_dst, h, hn);
+        return CSR_OK;
+    }
     case 5:
         if (needed) *needed = sizeof(csr_plan_info_t);
         if (bytes != sizeof(csr_plan_info_t) || !h_dst) return fail(CSR_ERR_INVALID_ARG, "size");

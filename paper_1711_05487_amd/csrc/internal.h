@@ -137,6 +137,9 @@ struct csr_matrix_s {
     int has_features = 0;
     csr_features_t feat{};
     csr::DevBuf scratch_x, scratch_y, scratch_col;  // selection probes
+    std::vector<int32_t> mlp_bounds;  // partition-aware ML test of the last PROFILE selection
+    std::vector<int64_t> mlp_times;
+    std::vector<double> mlp_ratios;
     csr::DevBuf dyn_ctr;           // the row-split dynamic schedule's two counters (zeroed once)
     csr::DevBuf feat_parts, feat_reuse, feat_long;  // feature-extraction partials, long rows
     double t_inspect_ms = 0.0;

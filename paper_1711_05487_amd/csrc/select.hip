@@ -663,7 +663,52 @@ namespace {
 
 struct Bounds {
     double p_csr, p_mb, p_ml, p_imb, p_cmp, p_peak, b_max;
+    int32_t ml_parts, ml_flagged;  // partition-aware ML test (cfg.ml_partitions > 0)
+    double ml_part_max;
 };
+
+// Contiguous partitions of the baseline's row blocks (NG rows each) with
+// about nnz/Q nonzeros each, the static one-dimensional partitioning of
+// Sec. IV-A applied to blocks: bound[q] is the first block whose first
+// nonzero index is at least floor(q * nnz / Q); bound[0] = 0 and
+// bound[Q] = the number of blocks. Empty partitions (bound[q] = bound[q+1])
+// occur where one block holds more than nnz/Q nonzeros.
+std::vector<int32_t> ml_partition_bounds(const std::vector<int32_t> &rp, int NG, int Q) {
+    const int64_t n = (int64_t)rp.size() - 1, nnz = rp.back();
+    const int64_t nblk = (n + NG - 1) / NG;
+    auto first_nz = [&](int64_t b) { return (int64_t)rp[(size_t)std::min(b * NG, n)]; };
+    std::vector<int32_t> bound((size_t)Q + 1);
+    for (int q = 0; q < Q; ++q) {
+        const int64_t target = (int64_t)q * nnz / Q;
+        int64_t lo = 0, hi = nblk;  // first b in [0, nblk] with first_nz(b) >= target
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (first_nz(mid) >= target) hi = mid;
+            else lo = mid + 1;
+        }
+        bound[q] = (int32_t)lo;
+    }
+    bound[Q] = (int32_t)nblk;
+    return bound;
+}
+
+// Per partition: summed baseline block times over summed probe block times
+// (t[b] baseline, t[nblk + b] probe); 0 for a partition without blocks or
+// without measurable time.
+std::vector<double> ml_partition_ratios(const std::vector<int64_t> &t,
+                                        const std::vector<int32_t> &bound) {
+    const size_t nblk = t.size() / 2;
+    std::vector<double> r(bound.size() - 1, 0.0);
+    for (size_t q = 0; q + 1 < bound.size(); ++q) {
+        int64_t sc = 0, sm = 0;
+        for (int64_t b = bound[q]; b < bound[q + 1]; ++b) {
+            sc += t[b];
+            sm += t[nblk + b];
+        }
+        if (sc > 0 && sm > 0) r[q] = (double)sc / (double)sm;
+    }
+    return r;
+}
 
 csr_status_t measure_bounds(csr_matrix_s *A, const csr_config_t &cfg, hipStream_t s, Bounds *B) {
     const int calls = cfg.timing_calls > 0 ? cfg.timing_calls : 32;
@@ -686,13 +731,14 @@ csr_status_t measure_bounds(csr_matrix_s *A, const csr_config_t &cfg, hipStream_
         return st;
     // P_IMB: per-CU busy spans of the instrumented baseline
     double imb_ratio = 1.0;
-    {
-        const int NG = kBlock / P0.G;
-        const int64_t nblk = (A->n_rows + NG - 1) / NG;
-        DevBuf rec;
-        if ((st = rec.alloc(sizeof(int64_t) * 3 * (size_t)std::max<int64_t>(nblk, 1))) != CSR_OK)
-            return st;
-        const void *arr[8] = {A->rp.p, A->col.p, nullptr, A->val.p, A->scratch_x.p,
+    const int NG = kBlock / P0.G;
+    const int64_t nblk = (A->n_rows + NG - 1) / NG;
+    DevBuf rec;
+    if ((st = rec.alloc(sizeof(int64_t) * 3 * (size_t)std::max<int64_t>(nblk, 1))) != CSR_OK)
+        return st;
+    // one instrumented launch (the baseline on `colp`), records copied to h
+    auto instrumented = [&](const void *colp, std::vector<int64_t> &h) -> csr_status_t {
+        const void *arr[8] = {A->rp.p, colp, nullptr, A->val.p, A->scratch_x.p,
                               A->scratch_y.p, rec.p, nullptr};
         hipError_t e;
         switch (A->storage) {
@@ -710,12 +756,17 @@ csr_status_t measure_bounds(csr_matrix_s *A, const csr_config_t &cfg, hipStream_
             break;
         }
         if (e != hipSuccess) return hip_fail(e, "instrumented baseline");
-        std::vector<int64_t> h(3 * (size_t)nblk);
+        h.assign(3 * (size_t)nblk, 0);
         if (nblk > 0) {
             CSR_HIP(hipMemcpyAsync(h.data(), rec.p, sizeof(int64_t) * h.size(),
                                    hipMemcpyDeviceToHost, s));
         }
         CSR_HIP(hipStreamSynchronize(s));
+        return CSR_OK;
+    };
+    std::vector<int64_t> h;
+    if ((st = instrumented(A->col.p, h)) != CSR_OK) return st;
+    {
         std::map<int64_t, std::pair<int64_t, int64_t>> span;  // cu -> (min start, max end)
         for (int64_t b = 0; b < nblk; ++b) {
             auto it = span.find(h[3 * b + 2]);
@@ -732,6 +783,40 @@ csr_status_t measure_bounds(csr_matrix_s *A, const csr_config_t &cfg, hipStream_
             const size_t m = d.size() / 2;
             const double med = d.size() % 2 ? d[m] : 0.5 * (d[m - 1] + d[m]);
             if (med > 0) imb_ratio = d.back() / med;
+        }
+    }
+    // Partition-aware ML (the extension proposed with the results of
+    // Sec. IV-C): the P_ML comparison repeated on contiguous nnz-balanced
+    // partitions of the row blocks, from per-block times of the instrumented
+    // baseline and of the instrumented P_ML probe (shortest of kMlReps runs).
+    A->mlp_bounds.clear();
+    A->mlp_times.clear();
+    A->mlp_ratios.clear();
+    B->ml_parts = 0;
+    B->ml_flagged = 0;
+    B->ml_part_max = 0.0;
+    if (cfg.ml_partitions > 0 && nblk > 0) {
+        constexpr int kMlReps = 3;
+        std::vector<int64_t> t((size_t)2 * nblk, INT64_MAX);
+        for (int r = 0; r < kMlReps; ++r) {
+            if (r > 0 && (st = instrumented(A->col.p, h)) != CSR_OK) return st;
+            for (int64_t b = 0; b < nblk; ++b) t[b] = std::min(t[b], h[3 * b + 1] - h[3 * b]);
+            if ((st = instrumented(A->scratch_col.p, h)) != CSR_OK) return st;
+            for (int64_t b = 0; b < nblk; ++b)
+                t[nblk + b] = std::min(t[nblk + b], h[3 * b + 1] - h[3 * b]);
+        }
+        std::vector<int32_t> rp_h((size_t)A->n_rows + 1);
+        CSR_HIP(hipMemcpyAsync(rp_h.data(), A->rp.p, sizeof(int32_t) * rp_h.size(),
+                               hipMemcpyDeviceToHost, s));
+        CSR_HIP(hipStreamSynchronize(s));
+        A->mlp_bounds = ml_partition_bounds(rp_h, NG, cfg.ml_partitions);
+        A->mlp_ratios = ml_partition_ratios(t, A->mlp_bounds);
+        A->mlp_times = std::move(t);
+        for (double r : A->mlp_ratios) {
+            if (r <= 0.0) continue;
+            B->ml_parts += 1;
+            if (r > cfg.t_ml_part) B->ml_flagged += 1;
+            B->ml_part_max = std::max(B->ml_part_max, r);
         }
     }
     double b_hbm = 0, b_cache = 0;
@@ -814,21 +899,34 @@ csr_status_t autotune(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, hi
     }
     double best_ms = 1e300;
     size_t best_k = 0;
+    bool best_plain_loads = false;
     for (size_t k = 0; k < cands.size(); ++k) {
         Plan Q;
         csr_status_t st = realize(A, opts, cands[k], &Q, s);
         if (st != CSR_OK) return st;
-        double ms = 0;
-        if ((st = time_plan(A, Q, calls, 2, s, &ms)) != CSR_OK) return st;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best_k = k;
+        // ML's streaming half (non-temporal val/col loads) is timed against
+        // ordinary loads: on this GPU it often costs more than it saves.
+        // Plans whose loads stream regardless (merge codes) or never
+        // (column blocks) have one setting.
+        const bool twin = (opts & CSR_OPT_PREFETCH) && Q.nt && !Q.cblocks &&
+                          !(Q.G == 0 && Q.idx != IDX_I32);
+        for (int plain_loads = 0; plain_loads <= (twin ? 1 : 0); ++plain_loads) {
+            if (plain_loads) Q.nt = 0;
+            double ms = 0;
+            if ((st = time_plan(A, Q, calls, 2, s, &ms)) != CSR_OK) return st;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_k = k;
+                best_plain_loads = plain_loads != 0;
+            }
         }
     }
     // The matrix holds one set of derived tables (tiles, long rows, codes),
     // rebuilt by each candidate: realize the winner again so that its tables
     // are the ones in place (cached per parameter, so this is cheap).
-    return realize(A, opts, cands[best_k], best, s);
+    csr_status_t st = realize(A, opts, cands[best_k], best, s);
+    if (st == CSR_OK && best_plain_loads) best->nt = 0;
+    return st;
 }
 
 }  // namespace
@@ -912,6 +1010,9 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
     csr_config_t cfg;
     if (cfg_in) cfg = *cfg_in;
     else csr_config_default(&cfg);
+    if (cfg.ml_partitions < 0 || cfg.ml_partitions > 4096 ||
+        (cfg.ml_partitions > 0 && !(cfg.t_ml_part > 0.0)))
+        return fail(CSR_ERR_INVALID_ARG, "ml_partitions must be in 0..4096 with t_ml_part > 0");
     int prev = -1;
     (void)hipGetDevice(&prev);
     if (prev != A->device) (void)hipSetDevice(A->device);
@@ -1002,7 +1103,8 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
         Bounds B{};
         if ((st = measure_bounds(A, cfg, s, &B)) != CSR_OK) break;
         if (!A->has_features && (st = inspect(A, s)) != CSR_OK) break;
-        const int32_t cls = classify(B.p_csr, B.p_mb, B.p_ml, B.p_imb, B.p_cmp, B.p_peak, cfg);
+        int32_t cls = classify(B.p_csr, B.p_mb, B.p_ml, B.p_imb, B.p_cmp, B.p_peak, cfg);
+        if (B.ml_flagged > 0) cls |= CSR_CLS_ML;  // partition-aware ML
         const bool has_long = A->feat.f[2] > (double)long_row_tau(A, cfg);
         const int32_t opts = remedies(cls, has_long);
         info.classes = cls;
@@ -1013,6 +1115,9 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
         info.p_cmp = B.p_cmp;
         info.p_peak = B.p_peak;
         info.b_max = B.b_max;
+        info.ml_partitions = B.ml_parts;
+        info.ml_parts_flagged = B.ml_flagged;
+        info.ml_part_max = B.ml_part_max;
         const auto tp = Clock::now();
         if (cfg.autotune) st = autotune(A, opts, cfg, s, &P);
         else st = realize(A, opts, cfg, &P, s);

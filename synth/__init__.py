@@ -353,6 +353,39 @@ def banded_random(n: int, bandwidth: int, per_row: int, seed: int, chunk: int = 
     return n, n, _check_int32(rp), c.astype(np.int32), vals
 
 
+def localized_irregular(n: int, per_row: int, frac: float, seed: int):
+    """Regular rows with an irregular stretch: every row holds exactly
+    `per_row` columns; rows in [n/2, n/2 + frac*n) take distinct uniform
+    random columns over [0, n) (rejection sampling as uniform_random, seed
+    `seed`), the other rows the contiguous window starting at
+    i - per_row/2, shifted to stay inside [0, n). Values U(0,1] by CSR
+    position (seed + 1). The workload of the partition-aware ML test: the
+    irregular gathers are confined to a few contiguous partitions."""
+    r0 = n // 2
+    r1 = min(n, r0 + int(round(frac * n)))
+    rows = np.arange(n, dtype=np.int64)
+    start = np.clip(rows - per_row // 2, 0, n - per_row)
+    col = (start[:, None] + np.arange(per_row)[None, :]).astype(np.int64)
+    if r1 > r0:
+        irr = np.arange(r0, r1, dtype=np.int64)
+        draws = per_row + 8
+        cand = np.empty((irr.size, draws), dtype=np.int64)
+        for k in range(draws):
+            cand[:, k] = _uindex_rows(seed, irr, k, n)
+        picked = _first_distinct(cand, per_row)
+        while picked is None:  # astronomically rare: draw more
+            draws += 8
+            more = np.empty((irr.size, 8), dtype=np.int64)
+            for k in range(8):
+                more[:, k] = _uindex_rows(seed, irr, draws - 8 + k, n)
+            cand = np.concatenate([cand, more], 1)
+            picked = _first_distinct(cand, per_row)
+        col[r0:r1] = np.sort(picked, axis=1)
+    rp = np.arange(n + 1, dtype=np.int64) * per_row
+    val = u01(seed + 1, 0, np.arange(n * per_row, dtype=np.uint64))
+    return n, n, _check_int32(rp), col.reshape(-1).astype(np.int32), val
+
+
 def block_diagonal(n: int, block: int, seed: int):
     """Dense block x block blocks along the diagonal (last block clipped)."""
     rows = np.arange(n, dtype=np.int64)

@@ -203,3 +203,85 @@ def test_every_catalogue_variant_matches_oracle():
         y = A.spmv(torch.from_numpy(x).cuda())
         torch.cuda.synchronize()
         check_f64(y.cpu().numpy(), rp, col, val, x, f"catalogue {opts}")
+
+
+def partition_rows_per_block(n, nblk):
+    ng = [g for g in (4, 8, 16, 32, 64, 128, 256) if -(-n // g) == nblk]
+    assert len(ng) == 1, (n, nblk, ng)
+    return ng[0]
+
+
+def check_partition_records(A, n, rp, Q, t_part):
+    """Bounds bit-exact against the oracle's nnz-balanced partitioning, the
+    ratios exactly the oracle's from the recorded block times, and the plan
+    info's summary consistent with them."""
+    bounds = A.debug_copy(pkg.DEBUG_MLP_BOUNDS, np.int32)
+    times = A.debug_copy(pkg.DEBUG_MLP_TIMES, np.int64)
+    ratios = A.debug_copy(pkg.DEBUG_MLP_RATIOS, np.float64)
+    nblk = times.size // 2
+    NG = partition_rows_per_block(n, nblk)
+    np.testing.assert_array_equal(bounds, oracle.ml_partition_bounds(rp, NG, Q))
+    assert (times >= 0).all()
+    ref = oracle.ml_partition_ratios(times[:nblk], times[nblk:], bounds)
+    np.testing.assert_array_equal(ratios, ref)
+    info = A.info
+    assert info["ml_partitions"] == int((ratios > 0).sum())
+    assert info["ml_parts_flagged"] == int((ratios > t_part).sum())
+    assert info["ml_part_max"] == ratios.max()
+    return bounds, ratios, NG
+
+
+def test_partition_aware_ml_finds_a_local_irregular_stretch():
+    """1/64 of the rows gather at random columns, the rest are banded: the
+    flagged partitions all overlap the irregular stretch, ML is set, and the
+    largest partition ratio exceeds the whole-matrix P_ML / P_CSR."""
+    n, m, rp, col, val = synth.localized_irregular(1 << 21, 16, 1 / 64, 811)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    info = A.select("profile", ml_partitions=256, autotune=0)
+    bounds, ratios, NG = check_partition_records(A, n, rp, 256, 1.5)
+    r0, r1 = n // 2, n // 2 + round(n / 64)
+    flagged = np.nonzero(ratios > 1.5)[0]
+    assert flagged.size > 0, ratios.max()
+    for q in flagged:
+        lo, hi = bounds[q] * NG, min(bounds[q + 1] * NG, n)
+        assert lo < r1 and hi > r0, (q, lo, hi)
+    assert info["classes"] & oracle.CLS_ML
+    assert info["ml_part_max"] > info["p_ml"] / info["p_csr"]
+    y = A.spmv(torch.from_numpy(synth.vector(m, 3)).cuda())
+    check_f64(y.cpu().numpy(), rp, col, val, synth.vector(m, 3), "localized irregular")
+    A.close()
+
+
+def test_partition_aware_ml_quiet_on_banded_rows():
+    n, m, rp, col, val = synth.localized_irregular(1 << 21, 16, 0.0, 811)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    info = A.select("profile", ml_partitions=256, autotune=0)
+    check_partition_records(A, n, rp, 256, 1.5)
+    assert info["ml_parts_flagged"] == 0 and info["ml_part_max"] < 1.5
+    # off by default: no records, and the plan info says so
+    info = A.select("profile", autotune=0)
+    assert info["ml_partitions"] == 0 and info["ml_part_max"] == 0.0
+    with pytest.raises(pkg.CsrError):
+        A.debug_copy(pkg.DEBUG_MLP_BOUNDS, np.int32)
+    A.close()
+
+
+@pytest.mark.parametrize("Q", [1, 7, 4096])
+def test_partition_records_small_and_ragged(Q):
+    """More partitions than row blocks (empty partitions), a single one, and
+    a ragged last block with empty rows."""
+    n, m, rp, col, val = unsorted_with_empty_rows()
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    A.select("profile", ml_partitions=Q, t_ml_part=2.0, autotune=0)
+    check_partition_records(A, n, rp, Q, 2.0)
+    A.close()
+
+
+def test_partition_config_rejected():
+    n, m, rp, col, val = feature_case("tiny")
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    for bad in ({"ml_partitions": 4097}, {"ml_partitions": -1},
+                {"ml_partitions": 8, "t_ml_part": 0.0}):
+        with pytest.raises(pkg.CsrError):
+            A.select("profile", **bad)
+    A.close()
