@@ -31,8 +31,10 @@
 #ifndef CSRSPMV_H
 #define CSRSPMV_H
 
+#ifndef __HIPCC_RTC__  /* the run-time kernel compiler defines these types itself */
 #include <stddef.h>
 #include <stdint.h>
+#endif
 
 #ifdef __cplusplus
 extern "C" {
@@ -108,6 +110,11 @@ typedef struct {
                                 ML is also set when some partition's summed baseline time
                                 exceeds t_ml_part times its summed probe time */
     double t_ml_part;        /* partition-aware ML threshold (used when ml_partitions > 0) */
+    int32_t jit_tiles;       /* 1 = the autotuner also tries merge tiles of 768 and 1536 items,
+                                compiled at run time (merge_items also accepts any multiple of
+                                256 up to 2048; sizes other than 256, 512 and 1024 are compiled
+                                on first use) */
+    int32_t reserved;
 } csr_config_t;
 
 /* What csr_select decided and what it cost. */
@@ -134,6 +141,8 @@ typedef struct {
     int32_t dynamic_rows;    /* 1: the row-split kernel runs with dynamic chunks */
     int32_t ml_partitions;   /* non-empty partitions of the partition-aware ML test (0: off) */
     int32_t ml_parts_flagged;/* partitions whose time ratio exceeded t_ml_part */
+    int32_t jit;             /* 1: the plan's merge kernel was compiled at run time */
+    int32_t reserved;
     double p_csr, p_mb, p_ml, p_imb, p_cmp, p_peak;  /* flop/s (PROFILE) */
     double b_max;            /* B/s used for the bounds */
     double t_select_ms;      /* features/probes + decision */
@@ -157,7 +166,7 @@ typedef struct {
 
 /* Fill *cfg with the defaults (t_ml 1.25, t_imb 1.24, t_mb 0.8,
  * long_row_factor 32, long_row_floor 4096, autotune 1, timing_calls 32,
- * ml_partitions 0, t_ml_part 1.5). */
+ * ml_partitions 0, t_ml_part 1.5, jit_tiles 0). */
 void csr_config_default(csr_config_t *cfg);
 
 /*
@@ -226,6 +235,26 @@ const char *csr_last_error(void);
 /* Basic facts about a handle. */
 csr_status_t csr_query(csr_matrix_t A, int32_t *n_rows, int32_t *n_cols, int64_t *nnz,
                        int32_t *storage, int32_t *rows_sorted);
+
+/*
+ * Run-time specialization (the paper's just-in-time code generation,
+ * Sec. IV-C): compiles the merge-path kernel for value storage `storage`,
+ * tile size `merge_items` (a multiple of 256 from 256 to 2048), index mode
+ * `index_mode` (0 int32 columns, 1 16-bit and 2 8-bit merge codes, 3 window
+ * codes), non-temporal loads (`streaming`, int32 columns only) and row-aligned
+ * tiles (`row_aligned`; required by window codes) with hipRTC for gfx950, from
+ * the kernel sources built into the library, and copies the code object (an
+ * AMDGPU ELF) to host memory `code` of `bytes` bytes (*needed receives its
+ * size; code = NULL only sizes it). Needs no GPU. Launches compile and load
+ * their instances themselves; this entry point exists to inspect what they
+ * run. CSR_ERR_INVALID_ARG for arguments outside these ranges,
+ * CSR_ERR_UNSUPPORTED when codes of that width do not form whole loads at that
+ * tile size or the compilation fails (the compiler log is in
+ * csr_last_error()).
+ */
+csr_status_t csr_jit_compile(int32_t storage, int32_t merge_items, int32_t index_mode,
+                             int32_t streaming, int32_t row_aligned, void *code, size_t bytes,
+                             size_t *needed);
 
 /*
  * Test support: copies an internal device array of the handle to host

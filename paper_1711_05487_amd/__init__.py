@@ -40,7 +40,7 @@ EXPORTS = ("csr_config_default", "csr_create", "csr_destroy", "csr_inspect", "cs
            "csr_spmv", "csr_spmv_batched", "csr_status_str", "csr_last_error", "csr_query",
            "csr_debug_copy", "csr_debug_probe", "csr_triad", "csr_time_spmv", "csr_mlp_load", "csr_mlp_unload",
            "csr_mlp_forward", "csr_mlp_grad", "csr_mlp_train", "csr_mlp_normalize",
-           "csr_tree_load", "csr_tree_unload")
+           "csr_tree_load", "csr_tree_unload", "csr_jit_compile")
 
 
 class CsrError(RuntimeError):
@@ -56,7 +56,8 @@ class Config(ctypes.Structure):
                 ("merge_items", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("timing_calls", ctypes.c_int32), ("rows_in_flight", ctypes.c_int32),
                 ("exhaustive_set", ctypes.c_int32), ("dynamic_rows", ctypes.c_int32),
-                ("ml_partitions", ctypes.c_int32), ("t_ml_part", ctypes.c_double)]
+                ("ml_partitions", ctypes.c_int32), ("t_ml_part", ctypes.c_double),
+                ("jit_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -67,6 +68,7 @@ class PlanInfo(ctypes.Structure):
                 ("merge_slack", ctypes.c_int32), ("window_codes", ctypes.c_int32),
                 ("column_blocks", ctypes.c_int32), ("dynamic_rows", ctypes.c_int32),
                 ("ml_partitions", ctypes.c_int32), ("ml_parts_flagged", ctypes.c_int32),
+                ("jit", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("p_csr", ctypes.c_double), ("p_mb", ctypes.c_double), ("p_ml", ctypes.c_double),
                 ("p_imb", ctypes.c_double), ("p_cmp", ctypes.c_double),
                 ("p_peak", ctypes.c_double), ("b_max", ctypes.c_double),
@@ -120,6 +122,7 @@ def lib():
             "csr_mlp_normalize": (ctypes.c_int, [P, P, P, i64, P, P]),
             "csr_tree_load": (ctypes.c_int, [i32, P, P, P, P, P]),
             "csr_tree_unload": (ctypes.c_int, []),
+            "csr_jit_compile": (ctypes.c_int, [i32, i32, i32, i32, i32, P, sz, ctypes.POINTER(sz)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -352,3 +355,19 @@ def mlp_normalize(F, mu, sigma, stream=None):
     _check(lib().csr_mlp_normalize(_ptr(F), _ptr(mu), _ptr(sigma), F.shape[0], _ptr(out),
                                    _stream(stream)))
     return out
+
+
+STORAGES = {"f64": 0, "f32": 1, "bf16": 2}
+
+
+def jit_compile(storage="f64", merge_items=768, index_mode=0, streaming=True,
+                row_aligned=True) -> bytes:
+    """Compile the merge-path kernel for a tile size (run-time specialization,
+    csr_jit_compile; needs no GPU) and return its code object."""
+    st = STORAGES[storage] if isinstance(storage, str) else int(storage)
+    need = ctypes.c_size_t(0)
+    args = (st, merge_items, index_mode, int(streaming), int(row_aligned))
+    _check(lib().csr_jit_compile(*args, None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib().csr_jit_compile(*args, ctypes.cast(buf, ctypes.c_void_p), need.value, None))
+    return buf.raw

@@ -191,7 +191,8 @@ extern "C" csr_status_t csr_spmv_batched(int32_t count, const csr_matrix_t *h_A,
             std::vector<int> ipt(count);
             for (int k = 0; k < count; ++k) {
                 const Plan &P = h_A[k]->plan;
-                if (P.opts & CSR_OPT_MERGE) ipt[k] = P.L / kMergeBlock;
+                // (tile sizes compiled at run time have no batched instance)
+                if ((P.opts & CSR_OPT_MERGE) && merge_items_prebuilt(P.L)) ipt[k] = P.L / kMergeBlock;
                 else ipt[k] = mode == 0 ? 4 : mode == 1 ? 8 : (nnz[k] < median ? 4 : 8);
             }
             auto cand = std::make_unique<BatchPlan>();

@@ -1,11 +1,14 @@
 // Device-side helpers shared by the SpMV kernels.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 #include <cstdint>
+#include <type_traits>
 
-#include "internal.h"
+#include "kdefs.h"
 
 namespace csr {
 

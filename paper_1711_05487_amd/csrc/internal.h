@@ -9,20 +9,13 @@
 #include <vector>
 
 #include "csrspmv.h"
+#include "kdefs.h"
 
 namespace csr {
 
-constexpr int kBlock = 256;       // threads per workgroup (4 wave64s)
-constexpr int kMergeBlock = 64;   // merge-path tile workgroup: one wave64
 constexpr int kWave = 64;
-constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies
 constexpr int kMaxResidentGroups = 256 * 8;  // 256-thread workgroups resident at once (256 CUs)
 constexpr size_t kPadBytes = 64;  // tail padding of val/col: vector loads may read past nnz
-
-// IDX_W8: window codes of row-aligned merge tiles (8-bit rank of the column
-// among the tile's distinct columns; the tile's window dictionary maps it back)
-enum IdxMode { IDX_I32 = 0, IDX_D16 = 1, IDX_D8 = 2, IDX_W8 = 3 };
-constexpr int kWindowMax = 256;  // window entries per tile (8-bit ranks)
 
 // Error plumbing -------------------------------------------------------------
 void set_error(const std::string &msg);
@@ -63,10 +56,6 @@ struct XcdGrid {
 };
 XcdGrid xcd_grid(int64_t nblk);
 
-__device__ __forceinline__ int64_t xcd_logical_block(int64_t per_xcd) {
-    int64_t b = blockIdx.x;
-    return (b % kNumXcd) * per_xcd + b / kNumXcd;
-}
 
 // Execution plan of one handle -------------------------------------------------
 struct Plan {
@@ -78,6 +67,7 @@ struct Plan {
     int32_t L = 0;           // merge-path items per tile
     int32_t idx = IDX_I32;   // index encoding
     int32_t nt = 0;          // non-temporal val/col stream
+    int32_t jit = 0;         // merge kernel compiled at run time (tile size not prebuilt)
     int32_t long_rows = 0;   // decomposition active
     int32_t cblocks = 0;     // column blocks of the merge path (0: one pass over all columns)
     int32_t dyn = 0;         // row-split: dynamic chunks instead of the static schedule
@@ -220,6 +210,16 @@ hipError_t launch_convert_values(const double *src, void *dst, int64_t n, int st
 hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void *y,
                        hipStream_t s, hipEvent_t before = nullptr, hipEvent_t after = nullptr);
 // Name of the plan's dominant kernel (as in a kernel trace).
+// Merge-path tile sizes: prebuilt (256, 512, 1024) or compiled at run time
+// (any multiple of 256 up to 2048); merge or window codes of code_bytes per
+// nonzero need a lane's codes to form whole loads at tile size L.
+bool merge_items_prebuilt(int64_t L);
+bool merge_items_supported(int64_t L);
+bool merge_codes_fit(int64_t L, int code_bytes);
+// The merge kernel instance compiled at run time (hipRTC) and loaded on
+// `device`; cached for the life of the process.
+csr_status_t jit_merge_kernel(int device, int storage, int ipt, bool nt, bool x32, int idx,
+                              bool aln, hipFunction_t *out);
 // x of this matrix spans < 4 GiB, so gathers may use 32-bit byte offsets
 bool x_fits_32(const csr_matrix_s *A);
 // slack of the row-aligned merge partition at tile size L (0: plain cuts),

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "device.h"
+#include "internal.h"
 
 namespace csr {
 

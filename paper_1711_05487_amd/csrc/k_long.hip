@@ -7,6 +7,7 @@
 //
 // Compiled once per storage type (-DCSR_STORAGE=0/1/2).
 #include "device.h"
+#include "internal.h"
 
 #ifndef CSR_STORAGE
 #error "CSR_STORAGE must be defined"

@@ -22,7 +22,8 @@
 // Every sum has a fixed order, so results are deterministic.
 //
 // Compiled once per storage type (-DCSR_STORAGE=0/1/2).
-#include "merge_tile.h"
+#include "merge_kernel.h"
+#include "internal.h"
 
 #ifndef CSR_STORAGE
 #error "CSR_STORAGE must be defined"
@@ -35,22 +36,6 @@ constexpr int S = CSR_STORAGE;
 using V = typename St<S>::V;
 using X = typename St<S>::X;
 using A = typename St<S>::A;
-
-template <int IPT, bool NT, bool X32, int IDX, bool ALN>
-__global__ __launch_bounds__(kMergeBlock) void k_merge(
-    const int32_t *__restrict__ rp, const void *__restrict__ cols, const V *__restrict__ val,
-    const X *__restrict__ x, X *__restrict__ y, const int32_t *__restrict__ tile_i,
-    const int32_t *__restrict__ tile_j, const int32_t *__restrict__ tile_base,
-    A *__restrict__ carry, int32_t n_rows, int32_t n_cols, int64_t per_xcd, int64_t n_tiles,
-    const uint16_t *__restrict__ wdict, const int32_t *__restrict__ wlen, int32_t acc) {
-    using Lds = std::conditional_t<ALN, MergeLdsRows<S, IPT>, MergeLds<S, IPT>>;
-    __shared__ Lds lds;
-    const int64_t t = xcd_logical_block(per_xcd);
-    if (t >= n_tiles) return;
-    merge_tile<S, IPT, NT, Lds, X32, IDX, ALN>(t, rp, cols, val, x, y, tile_i, tile_j,
-                                                            carry, n_rows, lds, tile_base, n_cols,
-                                                            wdict, wlen, acc != 0);
-}
 
 __global__ __launch_bounds__(kBlock) void k_merge_fixup(const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ tile_i,
@@ -73,6 +58,17 @@ struct MergeArgs {
     bool acc;
 };
 
+// After the main kernel: the caller's event, then (tiles not row-aligned)
+// the fixup pass that adds the carries of rows split across tiles.
+hipError_t after_main(hipError_t e, bool aln, const MergeArgs &a, hipStream_t s) {
+    if (e == hipSuccess && a.after_main) e = hipEventRecord(a.after_main, s);
+    if (e != hipSuccess || a.n_tiles < 2 || aln) return e;
+    const unsigned fb = (unsigned)((a.n_tiles + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_merge_fixup, dim3(fb), dim3(kBlock), 0, s, (const int32_t *)a.arr[0],
+                       a.tile_i, a.tile_j, (const A *)a.carry, (X *)a.arr[5], a.n_rows, a.n_tiles);
+    return hipGetLastError();
+}
+
 template <int IPT, bool NT, bool X32, int IDX, bool ALN>
 hipError_t go(const MergeArgs &a, hipStream_t s) {
     if (a.n_tiles == 0) return hipSuccess;
@@ -83,13 +79,36 @@ hipError_t go(const MergeArgs &a, hipStream_t s) {
                        (const X *)a.arr[4], (X *)a.arr[5], a.tile_i, a.tile_j, a.tile_base,
                        (A *)a.carry, a.n_rows, a.n_cols, g.per_xcd, a.n_tiles,
                        (const uint16_t *)a.arr[6], (const int32_t *)a.arr[7], (int32_t)a.acc);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess && a.after_main) e = hipEventRecord(a.after_main, s);
-    if (e != hipSuccess || a.n_tiles < 2 || ALN) return e;
-    const unsigned fb = (unsigned)((a.n_tiles + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_merge_fixup, dim3(fb), dim3(kBlock), 0, s, (const int32_t *)a.arr[0],
-                       a.tile_i, a.tile_j, (const A *)a.carry, (X *)a.arr[5], a.n_rows, a.n_tiles);
-    return hipGetLastError();
+    return after_main(hipGetLastError(), ALN, a, s);
+}
+
+// Tile sizes outside the prebuilt set: the same kernel template compiled at
+// run time (the fixup pass is the prebuilt one; it does not depend on L).
+hipError_t go_jit(int ipt, bool nt, bool x32, int idx, bool aln, const MergeArgs &a,
+                  hipStream_t s) {
+    if (a.n_tiles == 0) return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    hipFunction_t f;
+    if (jit_merge_kernel(dev, S, ipt, nt, x32, idx, aln, &f) != CSR_OK) return hipErrorInvalidValue;
+    const XcdGrid g = xcd_grid(a.n_tiles);
+    const int32_t *rp = (const int32_t *)a.arr[0];
+    const void *cols = idx == IDX_I32 ? a.arr[1] : a.arr[2];
+    const V *val = (const V *)a.arr[3];
+    const X *x = (const X *)a.arr[4];
+    X *y = (X *)a.arr[5];
+    const int32_t *ti = a.tile_i, *tj = a.tile_j, *tb = a.tile_base;
+    A *carry = (A *)a.carry;
+    int32_t n_rows = a.n_rows, n_cols = a.n_cols, acc = a.acc;
+    int64_t per_xcd = g.per_xcd, n_tiles = a.n_tiles;
+    const uint16_t *wdict = (const uint16_t *)a.arr[6];
+    const int32_t *wlen = (const int32_t *)a.arr[7];
+    void *args[] = {&rp,     &cols,    &val,    &x,     &y,     &ti,   &tj,   &tb,
+                    &carry,  &n_rows,  &n_cols, &per_xcd, &n_tiles, &wdict, &wlen, &acc};
+    e = hipModuleLaunchKernel(f, (unsigned)g.launched, 1, 1, kMergeBlock, 1, 1, 0, s, args,
+                              nullptr);
+    return after_main(e, aln, a, s);
 }
 
 // int32 columns: streaming and 32-bit gathers chosen at run time; merge
@@ -131,7 +150,7 @@ hipError_t CSR_CAT(launch_merge_s, CSR_STORAGE)(int ipt, bool nt, bool x32, bool
     case 8: return fixup ? go_ipt<8, false>(nt, x32, idx, a, s) : go_ipt<8, true>(nt, x32, idx, a, s);
     case 16:
         return fixup ? go_ipt<16, false>(nt, x32, idx, a, s) : go_ipt<16, true>(nt, x32, idx, a, s);
-    default: return hipErrorInvalidValue;
+    default: return go_jit(ipt, nt, x32, idx, !fixup, a, s);
     }
 }
 

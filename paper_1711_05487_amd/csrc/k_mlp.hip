@@ -8,6 +8,7 @@
 // Parameter layout (floats): W1[64][16], b1[64], W2[64][64], b2[64],
 // W3[K][64], b3[K]  (6,288 values for K = 16).
 #include "device.h"
+#include "internal.h"
 
 namespace csr {
 

@@ -3,6 +3,7 @@
 #include <type_traits>
 
 #include "device.h"
+#include "internal.h"
 
 namespace csr {
 namespace {

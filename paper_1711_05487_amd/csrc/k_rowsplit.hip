@@ -19,6 +19,7 @@
 //
 // This file is compiled once per storage type (-DCSR_STORAGE=0/1/2).
 #include "device.h"
+#include "internal.h"
 
 #ifndef CSR_STORAGE
 #error "CSR_STORAGE must be defined"

@@ -1,0 +1,30 @@
+// Constants and helpers shared by the host code and the device code of
+// libcsrspmv. Device-only sources include this header (not internal.h), so
+// the kernels also compile at run time (the run-time compiler has no host
+// standard library).
+#pragma once
+
+#include <cstdint>
+
+#include "csrspmv.h"
+
+namespace csr {
+
+constexpr int kBlock = 256;       // threads per workgroup (4 wave64s)
+constexpr int kMergeBlock = 64;   // merge-path tile workgroup: one wave64
+constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies
+
+// IDX_W8: window codes of row-aligned merge tiles (8-bit rank of the column
+// among the tile's distinct columns; the tile's window dictionary maps it back)
+enum IdxMode { IDX_I32 = 0, IDX_D16 = 1, IDX_D8 = 2, IDX_W8 = 3 };
+constexpr int kWindowMax = 256;  // window entries per tile (8-bit ranks)
+
+// Logical block of this workgroup in a launch of 8 * per_xcd workgroups:
+// workgroups are dispatched to the XCDs round-robin, so logical block
+// l = (b % 8) * per_xcd + b / 8 gives every XCD one contiguous range.
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t per_xcd) {
+    int64_t b = blockIdx.x;
+    return (b % kNumXcd) * per_xcd + b / kNumXcd;
+}
+
+}  // namespace csr

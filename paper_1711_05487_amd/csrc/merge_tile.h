@@ -440,6 +440,7 @@ template <int S, int IPT, int IDX = IDX_I32> struct MergeRowRegs {
     static constexpr int NIT = IPT / VEC;
     static constexpr int CW = IPT * (int)sizeof(C) >= 16 ? 16 / (int)sizeof(C) : IPT;
     static constexpr int NCC = IPT / CW;  // column vectors per lane
+    static_assert(IPT % CW == 0, "a lane's columns are a whole number of vectors");
     using VV = typename VecOfU<V, VEC>::type;
     using CC = typename VecOfU<C, CW>::type;
     int32_t i0, i1, j0, j1;  // the tile's bounds (wave-uniform)

@@ -84,6 +84,7 @@ void fill_info(const csr_matrix_s *A, const Plan &P, csr_plan_info_t *info) {
     info->window_codes = P.idx == IDX_W8;
     info->column_blocks = P.cblocks;
     info->dynamic_rows = P.dyn;
+    info->jit = P.jit;
     info->n_long_rows = P.long_rows ? A->n_long : 0;
     info->variant_id = catalogue_id(P.opts);
     info->format_bytes = plan_bytes(A, P);
@@ -401,8 +402,9 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
         // IMB (GPU counterpart of the runtime-chosen schedule). With DECOMP
         // as well, the merge path already balances long rows.
         const int L = cfg.merge_items > 0 ? cfg.merge_items : 512;
-        if (L != 256 && L != 512 && L != 1024)
-            return fail(CSR_ERR_INVALID_ARG, "merge_items must be 256, 512 or 1024");
+        if (!merge_items_supported(L))
+            return fail(CSR_ERR_INVALID_ARG,
+                        "merge_items must be a multiple of 256 from 256 to 2048");
         if ((st = build_tiles(A, L, s)) != CSR_OK) return st;
         P.L = L;
         if (!(opts & CSR_OPT_DELTA) && A->tiles_slack > 0) {
@@ -420,14 +422,17 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
             // 16 bits (streamed, like the compressed arrays of the remedy);
             // on row-aligned tiles whose ranges need 16 bits, window codes
             // when every tile has at most kWindowMax distinct columns
+            // (codes only at tile sizes where a lane's codes form whole loads)
             if ((st = build_merge_codes(A, s, false)) != CSR_OK) return st;
-            if (A->mcode_bits == 16 && A->tiles_slack > 0) {
+            const bool w8_fits = merge_codes_fit(L, 1);
+            if (A->mcode_bits == 16 && A->tiles_slack > 0 && w8_fits) {
                 if ((st = build_window_codes(A, s)) != CSR_OK) return st;
             }
-            if (A->mcode_bits == 16 && A->wcode_state == 1) {
+            if (A->mcode_bits == 16 && A->wcode_state == 1 && w8_fits) {
                 P.idx = IDX_W8;
                 P.nt = 1;
-            } else if (A->mcode_bits == 8 || A->mcode_bits == 16) {
+            } else if ((A->mcode_bits == 8 || A->mcode_bits == 16) &&
+                       merge_codes_fit(L, A->mcode_bits / 8)) {
                 if ((st = build_merge_codes(A, s, true)) != CSR_OK) return st;
                 P.idx = A->mcode_bits == 8 ? IDX_D8 : IDX_D16;
                 P.nt = 1;
@@ -436,6 +441,18 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
         P.G = 0;
         P.U = 1;
         P.R = 1;
+        if (!merge_items_prebuilt(L)) {
+            // compile (or find) the run-time instance this plan launches, so
+            // that a failed compilation is reported here and not at launch
+            hipFunction_t f;
+            const bool x32 = x_fits_32(A);
+            st = P.cblocks ? jit_merge_kernel(A->device, A->storage, L / kMergeBlock, false, x32,
+                                              IDX_I32, true, &f)
+                           : jit_merge_kernel(A->device, A->storage, L / kMergeBlock, P.nt != 0,
+                                              x32, P.idx, A->tiles_fixup == 0, &f);
+            if (st != CSR_OK) return st;
+            P.jit = 1;
+        }
     } else if (opts & CSR_OPT_DECOMP) {
         if ((st = build_long_rows(A, long_row_tau(A, cfg), s)) != CSR_OK) return st;
         P.long_rows = 1;
@@ -871,7 +888,9 @@ csr_status_t autotune(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, hi
     const double nnz_avg = A->n_rows ? (double)A->nnz / A->n_rows : 0.0;
     const int G0 = default_lanes_per_row(nnz_avg);
     if (opts & CSR_OPT_MERGE) {
-        for (int L : {256, 512, 1024}) {
+        std::vector<int> sizes = {256, 512, 1024};
+        if (cfg.jit_tiles) sizes.insert(sizes.end(), {768, 1536});  // compiled at run time
+        for (int L : sizes) {
             csr_config_t c = cfg;
             c.merge_items = L;
             cands.push_back(c);

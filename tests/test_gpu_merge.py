@@ -183,9 +183,11 @@ def test_reduced_precision(storage):
 
 
 def test_invalid_tile_size_rejected():
+    """Tile sizes are multiples of 256 from 256 to 2048 (other than 256,
+    512 and 1024 compiled at run time)."""
     n, m, rp, col, val = matrix("lap37")
     A = pkg.CsrMatrix(rp, col, val)
-    for L in (128, 768, 2048):
+    for L in (128, 640, 2304, 4096):
         with pytest.raises(pkg.CsrError):
             A.select("forced", forced_opts=M, merge_items=L)
 
