@@ -94,8 +94,9 @@ class GpuCheck:
 
 # the sources of the merge-path kernel and of the encodings it reads: a change
 # to any of them invalidates counter data taken before it
-KERNEL_SOURCES = ("paper_1711_05487_amd/csrc/k_merge.hip", "paper_1711_05487_amd/csrc/merge_tile.h",
-                  "paper_1711_05487_amd/csrc/device.h", "paper_1711_05487_amd/csrc/internal.h",
+KERNEL_SOURCES = ("paper_1711_05487_amd/csrc/k_merge.hip", "paper_1711_05487_amd/csrc/merge_kernel.h",
+                  "paper_1711_05487_amd/csrc/merge_tile.h", "paper_1711_05487_amd/csrc/device.h",
+                  "paper_1711_05487_amd/csrc/kdefs.h", "paper_1711_05487_amd/csrc/internal.h",
                   "paper_1711_05487_amd/csrc/k_prep.hip", "include/csrspmv.h")
 
 
