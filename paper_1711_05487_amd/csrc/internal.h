@@ -243,11 +243,19 @@ int32_t xreuse_samples(int32_t n_rows);
 // G lanes of the sweep); at most this many of them fit in nnz entries.
 int32_t features_long_row(int G);
 int64_t features_long_capacity(int64_t nnz, int G);
-// parts: n_parts + long capacity entries; long_list: long capacity + 1 ints.
-// Synchronizes the stream once (the long rows are sorted on the host).
-hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int64_t nnz,
-                           int G, FeatPart *parts, int32_t n_parts, int32_t *long_list,
-                           int32_t *reuse_out, hipStream_t s);
+// The sweep, its fold into *folded (over the n_parts sweep partials) and the
+// x-reuse samples, enqueued on s; long_list[0] then counts the long rows it
+// left out. parts: n_parts + long capacity entries; long_list: long
+// capacity + 1 ints.
+hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int G,
+                           FeatPart *parts, int32_t n_parts, FeatPart *folded,
+                           int32_t *long_list, int32_t *reuse_out, hipStream_t s);
+// With n_long > 0 long rows (the count launch_features left): their
+// partials, sorted by row, and the fold over all partials into *folded.
+// Synchronizes the stream (the long rows are sorted on the host).
+hipError_t features_long_rows(const int32_t *rp, const int32_t *col, int64_t nnz, int G,
+                              FeatPart *parts, int32_t n_parts, FeatPart *folded,
+                              int32_t *long_list, int32_t n_long, hipStream_t s);
 
 hipError_t launch_long_s0(const int32_t *col, const void *val, const void *x, void *y,
                           const int32_t *chunk_beg, void *part, int64_t n_chunks,

@@ -78,23 +78,34 @@ __device__ __forceinline__ void part_init(FeatPart &p) {
 struct SegStats {
     int32_t mn, mx, miss, grps;
 };
+// The segment is read U entries at a time, all U loads issued before any is
+// used (a segment is short, so one round usually covers it).
 __device__ __forceinline__ SegStats seg_stats(const int32_t *__restrict__ col, int32_t b,
                                               int32_t e, int32_t s0, int32_t s1) {
+    constexpr int U = 4;
     SegStats g{INT32_MAX, INT32_MIN, 0, 0};
     int32_t prev = s0 > b && s0 < e ? col[s0 - 1] : 0;
-    for (int32_t j = s0; j < s1; ++j) {
-        const int32_t c = col[j];
-        g.mn = min(g.mn, c);
-        g.mx = max(g.mx, c);
-        if (j == b) {
-            g.miss += 1;
-            g.grps += 1;
-        } else {
-            const int64_t d = (int64_t)c - prev;
-            g.miss += (d > kFeatE || d < -kFeatE) ? 1 : 0;
-            g.grps += (d != 1) ? 1 : 0;
+    for (int32_t j0 = s0; j0 < s1; j0 += U) {
+        int32_t c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = j0 + u < s1 ? col[j0 + u] : 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t j = j0 + u;
+            if (j < s1) {
+                g.mn = min(g.mn, c[u]);
+                g.mx = max(g.mx, c[u]);
+                if (j == b) {
+                    g.miss += 1;
+                    g.grps += 1;
+                } else {
+                    const int64_t d = (int64_t)c[u] - prev;
+                    g.miss += (d > kFeatE || d < -kFeatE) ? 1 : 0;
+                    g.grps += (d != 1) ? 1 : 0;
+                }
+                prev = c[u];
+            }
         }
-        prev = c;
     }
     return g;
 }
@@ -128,10 +139,17 @@ __global__ __launch_bounds__(kBlock) void k_features(const int32_t *__restrict__
     const int grp = threadIdx.x / G;
     FeatPart p;
     part_init(p);
-    // workgroup b sweeps rows b*NG + grp, then + gridDim*NG, ... (fixed order)
+    // workgroup b sweeps rows b*NG + grp, then + gridDim*NG, ... (fixed order);
+    // the next row's bounds are loaded while this row is reduced
     const int64_t stride = (int64_t)gridDim.x * NG;
-    for (int64_t r = (int64_t)blockIdx.x * NG + grp; r < n_rows; r += stride) {
-        const int32_t b = rp[r], e = rp[r + 1];
+    int64_t r = (int64_t)blockIdx.x * NG + grp;
+    int32_t nb = r < n_rows ? rp[r] : 0, ne = r < n_rows ? rp[r + 1] : 0;
+    for (; r < n_rows; r += stride) {
+        const int32_t b = nb, e = ne;
+        if (r + stride < n_rows) {
+            nb = rp[r + stride];
+            ne = rp[r + stride + 1];
+        }
         const int32_t k = e - b;
         if (k > 64 * G) {  // reduced by its own workgroup later
             if (lane == 0) long_list[1 + atomicAdd(long_list, 1)] = (int32_t)r;
@@ -191,9 +209,11 @@ __global__ __launch_bounds__(kBlock) void k_features_long(const int32_t *__restr
     }
 }
 
-// Fold the per-block partials in block order (one workgroup, fixed tree).
-__global__ __launch_bounds__(kBlock) void k_features_fold(FeatPart *__restrict__ parts,
-                                                          int32_t n_parts) {
+// Fold the per-block partials in block order (one workgroup, fixed tree)
+// into *dst.
+__global__ __launch_bounds__(kBlock) void k_features_fold(const FeatPart *__restrict__ parts,
+                                                          int32_t n_parts,
+                                                          FeatPart *__restrict__ dst) {
     __shared__ FeatPart s[kBlock];
     FeatPart p;
     part_init(p);
@@ -208,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_features_fold(FeatPart *__restrict__
         if ((int)threadIdx.x < w) chan_merge(s[threadIdx.x], s[threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) parts[0] = s[0];
+    if (threadIdx.x == 0) *dst = s[0];
 }
 
 // x-reuse sample s: rows r = 1 + floor(s (N-1) / S) and r-1, first P entries
@@ -272,9 +292,9 @@ int64_t features_long_capacity(int64_t nnz, int G) {
     return nnz / ((int64_t)features_long_row(G) + 1) + 1;
 }
 
-hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int64_t nnz,
-                           int G, FeatPart *parts, int32_t n_parts, int32_t *long_list,
-                           int32_t *reuse_out, hipStream_t s) {
+hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int G,
+                           FeatPart *parts, int32_t n_parts, FeatPart *folded,
+                           int32_t *long_list, int32_t *reuse_out, hipStream_t s) {
     hipError_t e;
     if ((e = hipMemsetAsync(long_list, 0, sizeof(int32_t), s)) != hipSuccess) return e;
     switch (G) {
@@ -287,31 +307,7 @@ hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows
     default: e = go<64>(rp, col, n_rows, parts, n_parts, long_list, s); break;
     }
     if (e != hipSuccess) return e;
-    // long rows: listed in whatever order the sweep met them; sorted here so
-    // that their partials are folded in row order (deterministic features)
-    int32_t n_long = 0;
-    if ((e = hipMemcpyAsync(&n_long, long_list, sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=
-            hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return e;
-    if (n_long < 0 || n_long > features_long_capacity(nnz, G)) return hipErrorInvalidValue;
-    if (n_long > 0) {
-        std::vector<int32_t> rows((size_t)n_long);
-        if ((e = hipMemcpyAsync(rows.data(), long_list + 1, sizeof(int32_t) * rows.size(),
-                                hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess)
-            return e;
-        std::sort(rows.begin(), rows.end());
-        if ((e = hipMemcpyAsync(long_list + 1, rows.data(), sizeof(int32_t) * rows.size(),
-                                hipMemcpyHostToDevice, s)) != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k_features_long, dim3((unsigned)n_long), dim3(kBlock), 0, s, rp, col,
-                           long_list, parts + n_parts);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        // rows lives until the copy has been consumed
-        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_features_fold, dim3(1), dim3(kBlock), 0, s, parts, n_parts + n_long);
+    hipLaunchKernelGGL(k_features_fold, dim3(1), dim3(kBlock), 0, s, parts, n_parts, folded);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int32_t ns = xreuse_samples(n_rows);
     if (ns > 0) {
@@ -319,6 +315,33 @@ hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows
         e = hipGetLastError();
     }
     return e;
+}
+
+hipError_t features_long_rows(const int32_t *rp, const int32_t *col, int64_t nnz, int G,
+                              FeatPart *parts, int32_t n_parts, FeatPart *folded,
+                              int32_t *long_list, int32_t n_long, hipStream_t s) {
+    if (n_long < 0 || n_long > features_long_capacity(nnz, G)) return hipErrorInvalidValue;
+    if (n_long == 0) return hipSuccess;
+    // listed in whatever order the sweep met them; sorted here so that their
+    // partials are folded in row order (deterministic features)
+    hipError_t e;
+    std::vector<int32_t> rows((size_t)n_long);
+    if ((e = hipMemcpyAsync(rows.data(), long_list + 1, sizeof(int32_t) * rows.size(),
+                            hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return e;
+    std::sort(rows.begin(), rows.end());
+    if ((e = hipMemcpyAsync(long_list + 1, rows.data(), sizeof(int32_t) * rows.size(),
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_features_long, dim3((unsigned)n_long), dim3(kBlock), 0, s, rp, col,
+                       long_list, parts + n_parts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_features_fold, dim3(1), dim3(kBlock), 0, s, parts, n_parts + n_long,
+                       folded);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // rows lives until the copy has been consumed
+    return hipStreamSynchronize(s);
 }
 
 }  // namespace csr

@@ -609,25 +609,39 @@ csr_status_t inspect(csr_matrix_s *A, hipStream_t s) {
         const int64_t long_cap = features_long_capacity(A->nnz, G);
         const int32_t n_samp = xreuse_samples(A->n_rows);
         csr_status_t st;
-        if (A->feat_parts.bytes < sizeof(FeatPart) * (size_t)(n_parts + long_cap) &&
-            (st = A->feat_parts.alloc(sizeof(FeatPart) * (size_t)(n_parts + long_cap))) != CSR_OK)
+        // the partials, then the folded result in the last slot
+        const size_t n_slots = (size_t)(n_parts + long_cap) + 1;
+        if (A->feat_parts.bytes < sizeof(FeatPart) * n_slots &&
+            (st = A->feat_parts.alloc(sizeof(FeatPart) * n_slots)) != CSR_OK)
             return st;
+        FeatPart *const folded = A->feat_parts.as<FeatPart>() + (n_slots - 1);
         if (A->feat_long.bytes < sizeof(int32_t) * (size_t)(long_cap + 1) &&
             (st = A->feat_long.alloc(sizeof(int32_t) * (size_t)(long_cap + 1))) != CSR_OK)
             return st;
         if (A->feat_reuse.bytes < sizeof(int32_t) * 2 * (size_t)n_samp + 8 &&
             (st = A->feat_reuse.alloc(sizeof(int32_t) * 2 * (size_t)n_samp + 8)) != CSR_OK)
             return st;
-        CSR_HIP(launch_features(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->n_rows, A->nnz, G,
-                                A->feat_parts.as<FeatPart>(), n_parts, A->feat_long.as<int32_t>(),
-                                A->feat_reuse.as<int32_t>(), s));
+        CSR_HIP(launch_features(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->n_rows, G,
+                                A->feat_parts.as<FeatPart>(), n_parts, folded,
+                                A->feat_long.as<int32_t>(), A->feat_reuse.as<int32_t>(), s));
+        // one round trip when no row was long: the count, the fold and the
+        // x-reuse samples together
         FeatPart p;
+        int32_t n_long = 0;
         std::vector<int32_t> reuse(2 * (size_t)n_samp);
-        CSR_HIP(hipMemcpyAsync(&p, A->feat_parts.p, sizeof(p), hipMemcpyDeviceToHost, s));
+        CSR_HIP(hipMemcpyAsync(&n_long, A->feat_long.p, sizeof(n_long), hipMemcpyDeviceToHost, s));
+        CSR_HIP(hipMemcpyAsync(&p, folded, sizeof(p), hipMemcpyDeviceToHost, s));
         if (n_samp > 0)
             CSR_HIP(hipMemcpyAsync(reuse.data(), A->feat_reuse.p, sizeof(int32_t) * reuse.size(),
                                    hipMemcpyDeviceToHost, s));
         CSR_HIP(hipStreamSynchronize(s));
+        if (n_long != 0) {
+            CSR_HIP(features_long_rows(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->nnz, G,
+                                       A->feat_parts.as<FeatPart>(), n_parts, folded,
+                                       A->feat_long.as<int32_t>(), n_long, s));
+            CSR_HIP(hipMemcpyAsync(&p, folded, sizeof(p), hipMemcpyDeviceToHost, s));
+            CSR_HIP(hipStreamSynchronize(s));
+        }
         int64_t shared = 0, distinct = 0;
         for (int32_t q = 0; q < n_samp; ++q) {
             shared += reuse[2 * q];
