@@ -337,6 +337,7 @@ csr_status_t csr_create(csr_matrix_t *out, int32_t n_rows, int32_t n_cols, int64
     STEP(launch_convert_values(d_val, A->val.p, nnz, storage, s));
     STEP(hipStreamSynchronize(s));
 #undef STEP
+    if ((st = feature_buffers(A)) != CSR_OK) return bail(st);
     csr_config_t cfg;
     csr_config_default(&cfg);
     if ((st = realize(A, 0, cfg, &A->plan, s)) != CSR_OK) return bail(st);

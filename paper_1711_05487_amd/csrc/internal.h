@@ -243,6 +243,8 @@ int32_t xreuse_samples(int32_t n_rows);
 // G lanes of the sweep); at most this many of them fit in nnz entries.
 int32_t features_long_row(int G);
 int64_t features_long_capacity(int64_t nnz, int G);
+// Allocate the feature sweep's workspace of a handle (no-op when present).
+csr_status_t feature_buffers(csr_matrix_s *A);
 // The sweep, its fold into *folded (over the n_parts sweep partials) and the
 // x-reuse samples, enqueued on s; long_list[0] then counts the long rows it
 // left out. parts: n_parts + long capacity entries; long_list: long

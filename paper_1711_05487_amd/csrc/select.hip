@@ -596,6 +596,31 @@ csr_status_t device_bandwidth(int device, hipStream_t s, double *hbm, double *ca
 // --------------------------------------------------------------------------
 // Features (Sec. III-D, Table I)
 // --------------------------------------------------------------------------
+// The feature sweep's workspace (partials, long-row list, x-reuse samples),
+// sized from the matrix's shape; allocated with the handle so that an
+// inspection launches and reads back only.
+csr_status_t feature_buffers(csr_matrix_s *A) {
+    if (A->n_rows == 0) return CSR_OK;
+    const double nnz_avg = (double)A->nnz / A->n_rows;
+    const int G0 = default_lanes_per_row(nnz_avg);
+    const int G = G0 >= 4 ? G0 / 4 : 1;
+    const size_t n_slots = (size_t)(features_partials(A->n_rows, G) +
+                                    features_long_capacity(A->nnz, G)) + 1;
+    const size_t n_long = (size_t)features_long_capacity(A->nnz, G) + 1;
+    const size_t n_reuse = 2 * (size_t)xreuse_samples(A->n_rows) + 8;
+    csr_status_t st;
+    if (A->feat_parts.bytes < sizeof(FeatPart) * n_slots &&
+        (st = A->feat_parts.alloc(sizeof(FeatPart) * n_slots)) != CSR_OK)
+        return st;
+    if (A->feat_long.bytes < sizeof(int32_t) * n_long &&
+        (st = A->feat_long.alloc(sizeof(int32_t) * n_long)) != CSR_OK)
+        return st;
+    if (A->feat_reuse.bytes < sizeof(int32_t) * n_reuse &&
+        (st = A->feat_reuse.alloc(sizeof(int32_t) * n_reuse)) != CSR_OK)
+        return st;
+    return CSR_OK;
+}
+
 csr_status_t inspect(csr_matrix_s *A, hipStream_t s) {
     const auto t0 = Clock::now();
     csr_features_t F{};
@@ -609,18 +634,10 @@ csr_status_t inspect(csr_matrix_s *A, hipStream_t s) {
         const int64_t long_cap = features_long_capacity(A->nnz, G);
         const int32_t n_samp = xreuse_samples(A->n_rows);
         csr_status_t st;
+        if ((st = feature_buffers(A)) != CSR_OK) return st;  // allocated by csr_create
         // the partials, then the folded result in the last slot
         const size_t n_slots = (size_t)(n_parts + long_cap) + 1;
-        if (A->feat_parts.bytes < sizeof(FeatPart) * n_slots &&
-            (st = A->feat_parts.alloc(sizeof(FeatPart) * n_slots)) != CSR_OK)
-            return st;
         FeatPart *const folded = A->feat_parts.as<FeatPart>() + (n_slots - 1);
-        if (A->feat_long.bytes < sizeof(int32_t) * (size_t)(long_cap + 1) &&
-            (st = A->feat_long.alloc(sizeof(int32_t) * (size_t)(long_cap + 1))) != CSR_OK)
-            return st;
-        if (A->feat_reuse.bytes < sizeof(int32_t) * 2 * (size_t)n_samp + 8 &&
-            (st = A->feat_reuse.alloc(sizeof(int32_t) * 2 * (size_t)n_samp + 8)) != CSR_OK)
-            return st;
         CSR_HIP(launch_features(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->n_rows, G,
                                 A->feat_parts.as<FeatPart>(), n_parts, folded,
                                 A->feat_long.as<int32_t>(), A->feat_reuse.as<int32_t>(), s));
