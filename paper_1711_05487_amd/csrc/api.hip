@@ -55,6 +55,19 @@ csr_status_t hip_fail(hipError_t e, const char *what) {
     return e == hipErrorOutOfMemory ? CSR_ERR_OUT_OF_MEMORY : CSR_ERR_DEVICE;
 }
 
+csr_status_t HostBuf::alloc(size_t n) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    const hipError_t e = hipHostMalloc(&p, n ? n : 64, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return hip_fail(e, "hipHostMalloc");
+    }
+    bytes = n ? n : 64;
+    return CSR_OK;
+}
+
 csr_status_t DevBuf::alloc(size_t n) {
     release();
     if (n == 0) n = 256;  // keep a valid, aligned pointer for empty arrays

@@ -45,6 +45,20 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Pinned host memory owned by a handle (freed in the destructor): staging
+// for small device-to-host reads that are waited on at once.
+struct HostBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+    ~HostBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+    csr_status_t alloc(size_t n);
+};
+
 // Grid shape of a static-partition launch: `nblk` logical workgroups, padded to
 // a multiple of 8 so that logical block l = (b % 8) * per_xcd + b / 8 gives
 // every XCD one contiguous range of logical blocks (workgroups are dispatched
@@ -132,6 +146,7 @@ struct csr_matrix_s {
     std::vector<double> mlp_ratios;
     csr::DevBuf dyn_ctr;           // the row-split dynamic schedule's two counters (zeroed once)
     csr::DevBuf feat_parts, feat_reuse, feat_long;  // feature-extraction partials, long rows
+    csr::HostBuf feat_host;        // pinned copy of feat_reuse (the sweep's results)
     double t_inspect_ms = 0.0;
 };
 
@@ -245,19 +260,22 @@ int32_t features_long_row(int G);
 int64_t features_long_capacity(int64_t nnz, int G);
 // Allocate the feature sweep's workspace of a handle (no-op when present).
 csr_status_t feature_buffers(csr_matrix_s *A);
-// The sweep, its fold into *folded (over the n_parts sweep partials) and the
-// x-reuse samples, enqueued on s; long_list[0] then counts the long rows it
-// left out. parts: n_parts + long capacity entries; long_list: long
-// capacity + 1 ints.
+// The sweep's results, read back in one copy: the folded partials, the
+// number of long rows, then (at kFeatHeader bytes) the x-reuse samples.
+constexpr size_t kFeatHeader = 128;
+static_assert(sizeof(FeatPart) + sizeof(int32_t) <= kFeatHeader, "feature header");
+// The sweep, its fold and the x-reuse samples, enqueued on s; `out` receives
+// the results laid out as above (the long rows are not in the fold yet).
+// parts: n_parts + long capacity entries; long_list: long capacity + 1 ints.
 hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int G,
-                           FeatPart *parts, int32_t n_parts, FeatPart *folded,
-                           int32_t *long_list, int32_t *reuse_out, hipStream_t s);
+                           FeatPart *parts, int32_t n_parts, int32_t *long_list, void *out,
+                           hipStream_t s);
 // With n_long > 0 long rows (the count launch_features left): their
-// partials, sorted by row, and the fold over all partials into *folded.
+// partials, sorted by row, and the fold over all partials into `out`.
 // Synchronizes the stream (the long rows are sorted on the host).
 hipError_t features_long_rows(const int32_t *rp, const int32_t *col, int64_t nnz, int G,
-                              FeatPart *parts, int32_t n_parts, FeatPart *folded,
-                              int32_t *long_list, int32_t n_long, hipStream_t s);
+                              FeatPart *parts, int32_t n_parts, int32_t *long_list,
+                              int32_t n_long, void *out, hipStream_t s);
 
 hipError_t launch_long_s0(const int32_t *col, const void *val, const void *x, void *y,
                           const int32_t *chunk_beg, void *part, int64_t n_chunks,

@@ -210,10 +210,11 @@ __global__ __launch_bounds__(kBlock) void k_features_long(const int32_t *__restr
 }
 
 // Fold the per-block partials in block order (one workgroup, fixed tree)
-// into *dst.
+// into the results header: the fold, then the long-row count.
 __global__ __launch_bounds__(kBlock) void k_features_fold(const FeatPart *__restrict__ parts,
                                                           int32_t n_parts,
-                                                          FeatPart *__restrict__ dst) {
+                                                          const int32_t *__restrict__ long_list,
+                                                          char *__restrict__ out) {
     __shared__ FeatPart s[kBlock];
     FeatPart p;
     part_init(p);
@@ -228,7 +229,10 @@ __global__ __launch_bounds__(kBlock) void k_features_fold(const FeatPart *__rest
         if ((int)threadIdx.x < w) chan_merge(s[threadIdx.x], s[threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *dst = s[0];
+    if (threadIdx.x == 0) {
+        *reinterpret_cast<FeatPart *>(out) = s[0];
+        *reinterpret_cast<int32_t *>(out + sizeof(FeatPart)) = long_list[0];
+    }
 }
 
 // x-reuse sample s: rows r = 1 + floor(s (N-1) / S) and r-1, first P entries
@@ -293,8 +297,10 @@ int64_t features_long_capacity(int64_t nnz, int G) {
 }
 
 hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int G,
-                           FeatPart *parts, int32_t n_parts, FeatPart *folded,
-                           int32_t *long_list, int32_t *reuse_out, hipStream_t s) {
+                           FeatPart *parts, int32_t n_parts, int32_t *long_list, void *out,
+                           hipStream_t s) {
+    char *const out_b = static_cast<char *>(out);
+    int32_t *const reuse_out = reinterpret_cast<int32_t *>(out_b + kFeatHeader);
     hipError_t e;
     if ((e = hipMemsetAsync(long_list, 0, sizeof(int32_t), s)) != hipSuccess) return e;
     switch (G) {
@@ -307,7 +313,8 @@ hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows
     default: e = go<64>(rp, col, n_rows, parts, n_parts, long_list, s); break;
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_features_fold, dim3(1), dim3(kBlock), 0, s, parts, n_parts, folded);
+    hipLaunchKernelGGL(k_features_fold, dim3(1), dim3(kBlock), 0, s, parts, n_parts,
+                       (const int32_t *)long_list, out_b);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int32_t ns = xreuse_samples(n_rows);
     if (ns > 0) {
@@ -318,8 +325,8 @@ hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows
 }
 
 hipError_t features_long_rows(const int32_t *rp, const int32_t *col, int64_t nnz, int G,
-                              FeatPart *parts, int32_t n_parts, FeatPart *folded,
-                              int32_t *long_list, int32_t n_long, hipStream_t s) {
+                              FeatPart *parts, int32_t n_parts, int32_t *long_list,
+                              int32_t n_long, void *out, hipStream_t s) {
     if (n_long < 0 || n_long > features_long_capacity(nnz, G)) return hipErrorInvalidValue;
     if (n_long == 0) return hipSuccess;
     // listed in whatever order the sweep met them; sorted here so that their
@@ -338,7 +345,7 @@ hipError_t features_long_rows(const int32_t *rp, const int32_t *col, int64_t nnz
                        long_list, parts + n_parts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_features_fold, dim3(1), dim3(kBlock), 0, s, parts, n_parts + n_long,
-                       folded);
+                       (const int32_t *)long_list, static_cast<char *>(out));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // rows lives until the copy has been consumed
     return hipStreamSynchronize(s);

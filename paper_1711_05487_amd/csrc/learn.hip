@@ -13,6 +13,7 @@ namespace {
 
 struct Model {
     DevBuf params, mu, sigma, feat, pick;
+    HostBuf io;  // pinned staging: 16 features in, the pick out
     int K = 0;
     bool ready = false;
 };
@@ -38,11 +39,15 @@ csr_status_t learned_pick(csr_matrix_s *A, hipStream_t s, int32_t *variant) {
     Model &M = g_models[A->device];
     for (int i = 0; i < 16; ++i)
         if (!std::isfinite(A->feat.f[i])) return fail(CSR_ERR_NOT_READY, "non-finite feature");
-    CSR_HIP(hipMemcpyAsync(M.feat.p, A->feat.f, sizeof(double) * 16, hipMemcpyHostToDevice, s));
+    double *const hf = static_cast<double *>(M.io.p);
+    int32_t *const hp = reinterpret_cast<int32_t *>(hf + 16);
+    std::memcpy(hf, A->feat.f, sizeof(double) * 16);
+    CSR_HIP(hipMemcpyAsync(M.feat.p, hf, sizeof(double) * 16, hipMemcpyHostToDevice, s));
     CSR_HIP(launch_mlp_select(M.params.as<float>(), M.K, M.feat.as<double>(), M.mu.as<double>(),
                               M.sigma.as<double>(), M.pick.as<int32_t>(), s));
-    CSR_HIP(hipMemcpyAsync(variant, M.pick.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    CSR_HIP(hipMemcpyAsync(hp, M.pick.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     CSR_HIP(hipStreamSynchronize(s));
+    *variant = *hp;
     return CSR_OK;
 }
 
@@ -74,6 +79,8 @@ csr_status_t csr_mlp_load(const float *h_params, int32_t K, const double *h_mu,
     if ((st = M.sigma.alloc(sizeof(double) * 16)) != CSR_OK) return st;
     if ((st = M.feat.alloc(sizeof(double) * 16)) != CSR_OK) return st;
     if ((st = M.pick.alloc(sizeof(int32_t))) != CSR_OK) return st;
+    if (!M.io.p && (st = M.io.alloc(sizeof(double) * 16 + sizeof(int32_t) * 2)) != CSR_OK)
+        return st;
     CSR_HIP(hipMemcpy(M.params.p, h_params, sizeof(float) * n, hipMemcpyHostToDevice));
     CSR_HIP(hipMemcpy(M.mu.p, h_mu, sizeof(double) * 16, hipMemcpyHostToDevice));
     CSR_HIP(hipMemcpy(M.sigma.p, h_sigma, sizeof(double) * 16, hipMemcpyHostToDevice));

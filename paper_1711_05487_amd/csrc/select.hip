@@ -605,9 +605,9 @@ csr_status_t feature_buffers(csr_matrix_s *A) {
     const int G0 = default_lanes_per_row(nnz_avg);
     const int G = G0 >= 4 ? G0 / 4 : 1;
     const size_t n_slots = (size_t)(features_partials(A->n_rows, G) +
-                                    features_long_capacity(A->nnz, G)) + 1;
+                                    features_long_capacity(A->nnz, G));
     const size_t n_long = (size_t)features_long_capacity(A->nnz, G) + 1;
-    const size_t n_reuse = 2 * (size_t)xreuse_samples(A->n_rows) + 8;
+    const size_t n_out = kFeatHeader + sizeof(int32_t) * 2 * (size_t)xreuse_samples(A->n_rows);
     csr_status_t st;
     if (A->feat_parts.bytes < sizeof(FeatPart) * n_slots &&
         (st = A->feat_parts.alloc(sizeof(FeatPart) * n_slots)) != CSR_OK)
@@ -615,9 +615,8 @@ csr_status_t feature_buffers(csr_matrix_s *A) {
     if (A->feat_long.bytes < sizeof(int32_t) * n_long &&
         (st = A->feat_long.alloc(sizeof(int32_t) * n_long)) != CSR_OK)
         return st;
-    if (A->feat_reuse.bytes < sizeof(int32_t) * n_reuse &&
-        (st = A->feat_reuse.alloc(sizeof(int32_t) * n_reuse)) != CSR_OK)
-        return st;
+    if (A->feat_reuse.bytes < n_out && (st = A->feat_reuse.alloc(n_out)) != CSR_OK) return st;
+    if (A->feat_host.bytes < n_out && (st = A->feat_host.alloc(n_out)) != CSR_OK) return st;
     return CSR_OK;
 }
 
@@ -631,33 +630,32 @@ csr_status_t inspect(csr_matrix_s *A, hipStream_t s) {
         const int G0 = default_lanes_per_row(nnz_avg);
         const int G = G0 >= 4 ? G0 / 4 : 1;  // contiguous segments of about 4 entries per lane
         const int32_t n_parts = features_partials(A->n_rows, G);
-        const int64_t long_cap = features_long_capacity(A->nnz, G);
         const int32_t n_samp = xreuse_samples(A->n_rows);
         csr_status_t st;
         if ((st = feature_buffers(A)) != CSR_OK) return st;  // allocated by csr_create
-        // the partials, then the folded result in the last slot
-        const size_t n_slots = (size_t)(n_parts + long_cap) + 1;
-        FeatPart *const folded = A->feat_parts.as<FeatPart>() + (n_slots - 1);
         CSR_HIP(launch_features(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->n_rows, G,
-                                A->feat_parts.as<FeatPart>(), n_parts, folded,
-                                A->feat_long.as<int32_t>(), A->feat_reuse.as<int32_t>(), s));
-        // one round trip when no row was long: the count, the fold and the
-        // x-reuse samples together
+                                A->feat_parts.as<FeatPart>(), n_parts, A->feat_long.as<int32_t>(),
+                                A->feat_reuse.p, s));
+        // one round trip when no row was long: the fold, the long-row count
+        // and the x-reuse samples in one copy to pinned memory
+        const size_t out_bytes = kFeatHeader + sizeof(int32_t) * 2 * (size_t)n_samp;
+        const char *const h = static_cast<const char *>(A->feat_host.p);
+        CSR_HIP(hipMemcpyAsync(A->feat_host.p, A->feat_reuse.p, out_bytes, hipMemcpyDeviceToHost, s));
+        CSR_HIP(hipStreamSynchronize(s));
         FeatPart p;
         int32_t n_long = 0;
+        std::memcpy(&p, h, sizeof(p));
+        std::memcpy(&n_long, h + sizeof(FeatPart), sizeof(n_long));
         std::vector<int32_t> reuse(2 * (size_t)n_samp);
-        CSR_HIP(hipMemcpyAsync(&n_long, A->feat_long.p, sizeof(n_long), hipMemcpyDeviceToHost, s));
-        CSR_HIP(hipMemcpyAsync(&p, folded, sizeof(p), hipMemcpyDeviceToHost, s));
-        if (n_samp > 0)
-            CSR_HIP(hipMemcpyAsync(reuse.data(), A->feat_reuse.p, sizeof(int32_t) * reuse.size(),
-                                   hipMemcpyDeviceToHost, s));
-        CSR_HIP(hipStreamSynchronize(s));
+        if (n_samp > 0) std::memcpy(reuse.data(), h + kFeatHeader, sizeof(int32_t) * reuse.size());
         if (n_long != 0) {
             CSR_HIP(features_long_rows(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->nnz, G,
-                                       A->feat_parts.as<FeatPart>(), n_parts, folded,
-                                       A->feat_long.as<int32_t>(), n_long, s));
-            CSR_HIP(hipMemcpyAsync(&p, folded, sizeof(p), hipMemcpyDeviceToHost, s));
+                                       A->feat_parts.as<FeatPart>(), n_parts,
+                                       A->feat_long.as<int32_t>(), n_long, A->feat_reuse.p, s));
+            CSR_HIP(hipMemcpyAsync(A->feat_host.p, A->feat_reuse.p, sizeof(p),
+                                   hipMemcpyDeviceToHost, s));
             CSR_HIP(hipStreamSynchronize(s));
+            std::memcpy(&p, h, sizeof(p));
         }
         int64_t shared = 0, distinct = 0;
         for (int32_t q = 0; q < n_samp; ++q) {
