@@ -455,6 +455,27 @@ def test_spd_generators_symmetric_and_dominant():
         assert np.all(d >= 1.0)
 
 
+def test_localized_irregular_generator():
+    """The partition study's matrices: 16 sorted distinct columns in every
+    row; outside the stretch [n/2, n/2 + f n) each row is the contiguous
+    window starting at i - 8 (shifted inside [0, n)), inside it the columns
+    are spread (not one window)."""
+    n = 4096
+    for frac in (0.0, 1 / 64, 1 / 4):
+        n_, m, rp, col, val = synth.localized_irregular(n, 16, frac, 811)
+        assert n_ == m == n and np.array_equal(rp, np.arange(n + 1) * 16)
+        c = col.reshape(n, 16).astype(np.int64)
+        assert np.all(np.diff(c, axis=1) > 0) and c.min() >= 0 and c.max() < n
+        r0, r1 = n // 2, n // 2 + round(frac * n)
+        start = np.clip(np.arange(n) - 8, 0, n - 16)
+        regular = np.ones(n, dtype=bool)
+        regular[r0:r1] = False
+        assert np.array_equal(c[regular], (start[:, None] + np.arange(16))[regular])
+        if r1 > r0:
+            assert np.all(c[r0:r1, -1] - c[r0:r1, 0] > 16)
+        assert np.all((val > 0) & (val <= 1))
+
+
 # ------------------------------------------------------------ column blocks
 
 @pytest.mark.parametrize("B", [1, 2, 3, 4, 8])
