@@ -50,11 +50,14 @@ def test_training_reproduces_committed_model():
     assert np.array_equal(mu, mu0) and np.array_equal(sd, sd0)
 
 
-def test_learned_selection_cost_below_one_plain_spmv():
+@pytest.mark.parametrize("name", ["st27_128", "unif20", "rmat22"])
+def test_learned_selection_cost_below_one_plain_spmv(name):
+    """Features + inference + decision (t_select_ms, the median of five
+    selections) below one plain SpMV on the configurations with NNZ >= 10^6."""
     learn.install()
-    n, m, rp, col, val = matrix("st27_128")
-    A = pkg.CsrMatrix(rp, col, val)
-    x = torch.from_numpy(xvec("st27_128", m)).cuda()
+    n, m, rp, col, val = matrix(name)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    x = torch.from_numpy(xvec(name, m)).cuda()
     y = torch.empty(n, dtype=torch.float64, device="cuda")
     A.select("plain")
     A.spmv(x, y)
@@ -72,11 +75,12 @@ def test_learned_selection_cost_below_one_plain_spmv():
         info = A.select("learned")
         assert info["fallback"] == 0
         costs.append(info["t_select_ms"])
-    print("t_select_ms", costs, "t_plain_ms", t_plain, "variant", info["variant_id"])
-    assert min(costs) < t_plain
+    print(name, "t_select_ms", costs, "t_plain_ms", t_plain, "variant", info["variant_id"])
+    assert float(np.median(costs)) < t_plain
     y = A.spmv(x)
     torch.cuda.synchronize()
-    check_f64(y.cpu().numpy(), rp, col, val, x.cpu().numpy(), "learned st27")
+    check_f64(y.cpu().numpy(), rp, col, val, x.cpu().numpy(), f"learned {name}")
+    A.close()
 
 
 def test_learned_selection_parity_on_config_matrices():
