@@ -22,6 +22,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -100,10 +101,23 @@ KERNEL_SOURCES = ("paper_1711_05487_amd/csrc/k_merge.hip", "paper_1711_05487_amd
                   "paper_1711_05487_amd/csrc/k_prep.hip", "include/csrspmv.h")
 
 
-def kernel_source_sha():
+def code_text(src: str) -> str:
+    """C/C++ source with comments removed and whitespace runs collapsed, so
+    that edits to comments alone leave the hash unchanged (string literals
+    in these sources hold no comment markers)."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
+def kernel_source_sha(texts=None):
+    """Hash of the code (not the comments) of KERNEL_SOURCES, or of the given
+    texts in that order."""
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if texts is None:
+        texts = [open(os.path.join(ROOT, f)).read() for f in KERNEL_SOURCES]
+    for t in texts:
+        h.update(code_text(t).encode())
     return h.hexdigest()[:16]
 
 

@@ -90,7 +90,9 @@ typedef struct {
     int32_t long_row_floor;
     int32_t forced_opts;     /* CSR_SEL_FORCED: mask of CSR_OPT_* */
     int32_t rows_per_group;  /* 0 = auto: lanes per row G in {1,2,4,...,64} */
-    int32_t merge_items;     /* 0 = auto: merge-path items per tile L (256, 512 or 1024) */
+    int32_t merge_items;     /* 0 = auto (512): merge-path items per tile L, a multiple of 256
+                                up to 2048 (256, 512 and 1024 prebuilt, the others compiled
+                                at run time on first use) */
     int32_t autotune;        /* 1 = time a small parameter grid for the chosen remedies */
     int32_t timing_calls;    /* SpMV calls per timing run inside selection (default 32) */
     int32_t rows_in_flight;  /* 0 = auto: rows per lane group loaded at once (1, 2 or 4) */
