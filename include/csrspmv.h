@@ -240,7 +240,7 @@ csr_status_t csr_query(csr_matrix_t A, int32_t *n_rows, int32_t *n_cols, int64_t
 
 /*
  * Run-time specialization (the paper's just-in-time code generation,
- * Sec. IV-C): compiles the merge-path kernel for value storage `storage`,
+ * Sec. IV-D): compiles the merge-path kernel for value storage `storage`,
  * tile size `merge_items` (a multiple of 256 from 256 to 2048), index mode
  * `index_mode` (0 int32 columns, 1 16-bit and 2 8-bit merge codes, 3 window
  * codes), non-temporal loads (`streaming`, int32 columns only) and row-aligned

@@ -1,6 +1,6 @@
 // Run-time specialization of the merge-path kernel: the counterpart of the
 // paper's just-in-time code generation for the selected optimizations
-// (Sec. IV-C). The library holds k_merge for tile sizes L = 256, 512 and
+// (Sec. IV-D). The library holds k_merge for tile sizes L = 256, 512 and
 // 1024 ahead of time; any other L = 64 * IPT (IPT a multiple of 4 up to 32)
 // is compiled on first use with hipRTC from the same headers (embedded at
 // build time), with the same code-generation flags, and the module is kept

@@ -1,5 +1,5 @@
 """GPU parity of the merge-path kernel compiled at run time (the paper's
-just-in-time code generation, Sec. IV-C) for tile sizes outside the
+just-in-time code generation, Sec. IV-D) for tile sizes outside the
 prebuilt 256, 512 and 1024: tile tables and codes bit-exact against the
 oracle, y bit-exact on dyadic inputs and within the FP64 / reduced-precision
 bounds otherwise, on row-aligned tiles, tiles with carries (long rows),

@@ -1,5 +1,5 @@
 """Run-time specialization of the merge-path kernel (the paper's
-just-in-time code generation, Sec. IV-C) on the host: csr_jit_compile needs
+just-in-time code generation, Sec. IV-D) on the host: csr_jit_compile needs
 no GPU. The compiled instance of a prebuilt tile size is instruction for
 instruction the library's own kernel, run-time sizes compile without packed
 FP32 instructions, and instances that cannot exist are refused.
