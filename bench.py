@@ -160,10 +160,10 @@ def cpu_multicore(rp, col, val, x, bytes_per_call, budget_s=4.0):
     """The OpenMP CSR baseline (Sec. IV-A: contiguous nnz-balanced row blocks,
     one per thread) on all host threads OpenMP is given: context beside the
     single-threaded oracle, never the target."""
-    from oracle import omp
-    sec, th = omp.time_spmv(rp, col, val, x, 4)
+    import cpu_omp
+    sec, th = cpu_omp.time_spmv(rp, col, val, x, 4)
     calls = max(4, min(2048, int(budget_s / max(sec / 4, 1e-6))))
-    sec, th = omp.time_spmv(rp, col, val, x, calls)
+    sec, th = cpu_omp.time_spmv(rp, col, val, x, calls)
     return {"value": round(bytes_per_call * calls / sec / 1e9, 3), "unit": "GB/s", "threads": th,
             "kind": "openmp csr", "sample": f"{calls} full SpMV calls ({sec:.1f} s)"}
 

@@ -1,4 +1,5 @@
-"""Multi-core CPU baseline (OpenMP CSR, Sec. IV-A): measurement infrastructure.
+"""Multi-core CPU baseline (OpenMP CSR, Sec. IV-A): measurement infrastructure,
+not an oracle and not part of the GPU library (it shares no code with either).
 
 Only bench.py and the tests load it. Rows are split into contiguous blocks of
 equal nonzero counts, one per thread; the thread count is OpenMP's default

@@ -3,8 +3,8 @@
  * kernels run with OpenMP on all cores, rows split into contiguous blocks of
  * equal nonzero counts, one block per thread, threads placed close).
  *
- * MEASUREMENT INFRASTRUCTURE, like the oracle beside it: only the benchmark
- * and the test suite load it, and the GPU library shares no code with it.
+ * MEASUREMENT INFRASTRUCTURE: only the benchmark and the test suite load
+ * it; it shares no code with the GPU library or with the oracle.
  * Each row is summed in storage order from +0.0, as in the oracle; the
  * compiler may fuse multiply and add here, so results agree with the oracle
  * to rounding, not bit for bit.

@@ -4,14 +4,12 @@ TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the
 benchmark's CPU-baseline leg may import this package. The GPU library never
 calls it, and it shares no code with the GPU library (`paper_1711_05487_amd`).
 
-Two halves:
+Two parts:
 
 * ``csr_oracle.c`` (plain C, ``gcc -O2 -ffp-contract=off``), loaded with ctypes:
   SpMV in storage order, |A||x|, the Dot2 accurate reference, dense matvec,
   CSR validation, FP32/BF16 rounding, delta codes, merge-path tiles, long-row
   list and the matrix features.
-* ``csr_omp.c`` / ``omp.py``: the multi-core OpenMP CSR baseline that the
-  benchmark reports beside the single-threaded oracle (measurement only).
 * Pure Python/numpy here: the per-class bounds, the profile-guided rule, the
   class-to-optimization map, the amortization count, the reduced-precision
   error report, feature normalization and the FP64 MLP with its gradients and
