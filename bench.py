@@ -137,23 +137,45 @@ def traffic_from_profiles(kernel, workload, launches_bytes):
         return None
 
 
-def cpu_baseline(rp, col, val, x, bytes_per_call, budget_s=12.0):
+def cpu_baseline(rp, col, val, x, bytes_per_call, budget_s=12.0, runs=5):
     """The oracle as it stands (single-threaded C, storage-order FP64), timed on
-    the host over whole-matrix calls until ~budget_s seconds have passed."""
+    the host: `runs` runs of whole-matrix calls of about budget_s / runs
+    seconds each, summarized as the harmonic mean of the per-run rates
+    (Sec. IV-A). Also returns the oracle's y for the parity check of the GPU
+    result."""
     import oracle
-    oracle.spmv(rp, col, val, x)  # warm
-    t0 = time.perf_counter()
-    calls = 0
-    while True:
-        oracle.spmv(rp, col, val, x)
-        calls += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or calls >= 4096:
-            break
-    gbs = bytes_per_call * calls / el / 1e9
-    return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{calls} full SpMV calls of the same 27-point 128^3 FP64 matrix "
-                      f"({el:.1f} s, single thread)"}
+    y = oracle.spmv(rp, col, val, x)  # warm; kept for the parity check
+    rates, calls_total, el_total = [], 0, 0.0
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        calls = 0
+        while True:
+            oracle.spmv(rp, col, val, x)
+            calls += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s / runs or calls >= 1024:
+                break
+        rates.append(bytes_per_call * calls / el / 1e9)
+        calls_total += calls
+        el_total += el
+    gbs = len(rates) / sum(1.0 / r for r in rates)
+    rec = {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+           "sample": f"{runs} runs, {calls_total} full SpMV calls of the same 27-point 128^3 FP64 "
+                     f"matrix ({el_total:.1f} s, single thread), harmonic mean of the run rates"}
+    return rec, y
+
+
+def oracle_parity(y_gpu, y_oracle, rp, col, val, x):
+    """The GPU result against the oracle's storage-order FP64 product from the
+    CPU-baseline leg: both lie within gamma_n (|A||x|)_i of the exact product
+    (n <= 27 here, gamma_n < 3e-15), so 1e-12 (|A||x|)_i bounds their gap."""
+    import oracle
+    ab = oracle.absax(rp, col, val, x)
+    d = np.abs(np.asarray(y_gpu, dtype=np.float64) - y_oracle)
+    nz = ab > 0
+    ok = bool(np.all(d <= 1e-12 * ab)) and bool(np.all(d[~nz] == 0))
+    rel = float(np.max(d[nz] / ab[nz])) if nz.any() else 0.0
+    return {"ok": ok, "max_rel": rel, "bar": "1e-12 (|A||x|)_i per row, against the oracle"}
 
 
 def cpu_multicore(rp, col, val, x, bytes_per_call, budget_s=4.0):
@@ -267,8 +289,9 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
     fmt_bytes = info["format_bytes"]
     gbs = fmt_bytes / (ms * 1e-3) / 1e9
-    # dominant kernel alone: HIP events recorded on the launch stream around it
-    k_ms, call_ms, kernel = A.time_spmv(xd, yd, max(args.steps, 20))
+    # the dominant kernel's mean duration from HIP events on its launch
+    # stream: one event pair around 200 back-to-back calls of a one-kernel plan
+    k_ms, call_ms, kernel = A.time_spmv(xd, yd, 200)
     achieved = fmt_bytes / (k_ms * 1e-3) / 1e9
     t_sel_proto = harmonic_runs(A, xd, yd, 5, 128)
     t_pre = info["t_select_ms"] + info["t_prep_ms"]
@@ -321,7 +344,13 @@ def main():
     }
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(rp, col, val, x, plain["format_bytes"])
+        out["cpu_baseline"], y_or = cpu_baseline(rp, col, val, x, plain["format_bytes"])
+        A.spmv(xd, yd)
+        torch.cuda.synchronize()
+        par = oracle_parity(yd.cpu().numpy(), y_or, rp, col, val, x)
+        out["config"]["parity_oracle"] = par
+        ok = ok and par["ok"]
+        out["config"]["parity_ok"] = ok
         log("cpu baseline (openmp)")
         out["cpu_multicore"] = cpu_multicore(rp, col, val, x, plain["format_bytes"])
     print(json.dumps(out), flush=True)
@@ -465,7 +494,7 @@ def suite(args):
                       "opts": [nm for bit, nm in pkg.OPT_NAMES.items() if info["opts"] & bit],
                       "ms": round(t, 5), "kernel_ms": round(k_ms, 5), "format_bytes": fb,
                       "gbs": round(fb / (t * 1e-3) / 1e9, 1),
-                      "max_rel_err": mx, "p99_rel_err": p99})
+                      "max_rel_err_vs_gpu_f64": mx, "p99_rel_err_vs_gpu_f64": p99})
             A.close()
         del chk
 

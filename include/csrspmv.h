@@ -228,8 +228,9 @@ csr_status_t csr_spmv(csr_matrix_t A, const void *d_x, void *d_y, void *stream);
 csr_status_t csr_spmv_batched(int32_t count, const csr_matrix_t *h_A,
                               const void *const *h_x, void *const *h_y, void *stream);
 
-/* Human-readable name of a status code (static storage). */
-const char *csr_status_str(csr_status_t s);
+/* Human-readable name of a status code (static storage); any int is
+ * accepted ("CSR_ERR_UNKNOWN" outside the enumeration). */
+const char *csr_status_str(int32_t s);
 
 /* Message describing the most recent failure on the calling thread. */
 const char *csr_last_error(void);
@@ -278,7 +279,12 @@ csr_status_t csr_jit_compile(int32_t storage, int32_t merge_items, int32_t index
  *         row block of each partition; a row block is the baseline's
  *         workgroup of 256/G rows), 15 per-block shortest times int64[2][nblk]
  *         (baseline, then P_ML probe; 100 MHz ticks), 16 partition ratios
- *         double[Q] (0 for a partition without blocks)
+ *         double[Q] (0 for a partition without blocks); from the last
+ *         PROFILE selection: 17 P_IMB's busy span of every compute unit that
+ *         ran work in the instrumented baseline int64[n_cu] (wall-clock
+ *         ticks, by compute-unit id), 18 double[3]: the HBM and the cache
+ *         triad bandwidth (B/s; B_max is the second when the plan's bytes
+ *         fit in the 256 MB Infinity Cache) and the span clock (ticks/s)
  * Returns CSR_ERR_INVALID_ARG if `bytes` differs from the array's size
  * (*needed receives that size when non-NULL) or the array does not exist.
  * Synchronizes `stream`.
@@ -287,12 +293,28 @@ csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t by
                             size_t *needed, void *stream);
 
 /*
+ * Test support for the out-of-memory paths. Reports the device buffers the
+ * library holds (*live_buffers, *live_bytes) and the device allocations it
+ * attempted since the last arming (*attempts); any output may be NULL. With
+ * arm != 0 it then re-arms the failure injector: counting attempts from 0
+ * again, those numbered fail_from .. fail_from + fail_count - 1 fail with
+ * CSR_ERR_OUT_OF_MEMORY without reaching hipMalloc (fail_count = 0: none
+ * fail). Process-wide; not for use while other threads call the library.
+ */
+csr_status_t csr_debug_alloc(int32_t arm, int64_t fail_from, int64_t fail_count,
+                             int64_t *live_buffers, int64_t *live_bytes, int64_t *attempts);
+
+/*
  * Measurement support: `calls` back-to-back SpMVs with the current plan on
- * the caller's vectors (after one warm call). *kernel_ms = mean duration of
- * the plan's dominant kernel (HIP events recorded on `stream` immediately
- * before and after it), *call_ms = mean duration of a whole call (events
- * around all calls). kernel_name (may be NULL) receives the dominant kernel's
- * name as a kernel trace shows it, truncated to name_bytes. Synchronizes.
+ * the caller's vectors (after one warm call), between two HIP events on
+ * `stream`: *call_ms = their elapsed time / calls. *kernel_ms = the mean
+ * duration of the plan's dominant kernel: for a plan that launches one
+ * kernel per call the same figure as *call_ms (so it never exceeds it);
+ * otherwise a second pass of `calls` calls with events recorded immediately
+ * before and after the dominant kernel, averaged (this includes the
+ * events' own overhead). kernel_name (may be NULL) receives the dominant
+ * kernel's name as a kernel trace shows it, truncated to name_bytes.
+ * Synchronizes.
  */
 csr_status_t csr_time_spmv(csr_matrix_t A, const void *d_x, void *d_y, int32_t calls,
                            double *kernel_ms, double *call_ms, char *kernel_name,
@@ -314,10 +336,44 @@ csr_status_t csr_debug_probe(csr_matrix_t A, int32_t which, const void *d_x, voi
 /*
  * B_max probe (Sec. III-B; Sec. IV-A, Table III: STREAM triad). Runs
  * a[i] = b[i] + s * c[i] over three FP64 arrays of `bytes_per_array` bytes
- * each (allocated and freed inside) and returns the sustained bandwidth in
- * bytes/s counting 3 * bytes_per_array per pass (best of `reps` passes).
+ * each (allocated and freed inside, non-temporal loads and stores) and
+ * returns the sustained bandwidth in bytes/s counting 3 * bytes_per_array
+ * per pass (best of `reps` passes).
  */
 csr_status_t csr_triad(size_t bytes_per_array, int32_t reps, double *gbytes_per_s, void *stream);
+
+/*
+ * The profile-guided classifier on given bounds (Sec. III-C, Fig. 4) and the
+ * remedies of the classes it finds (Sec. III-E, Table II), exactly as
+ * csr_select(CSR_SEL_PROFILE) applies them: p[6] = {P_CSR, P_MB, P_ML,
+ * P_IMB, P_CMP, P_peak} in flop/s (finite, > 0), the thresholds of cfg
+ * (NULL: the defaults), has_long_rows != 0 when the matrix has rows longer
+ * than the decomposition threshold. *classes receives the CSR_CLS_* mask,
+ * *opts the CSR_OPT_* mask (before autotuning). Host only; used to tune the
+ * thresholds by grid search over recorded bounds.
+ */
+csr_status_t csr_classify(const double *p, const csr_config_t *cfg, int32_t has_long_rows,
+                          int32_t *classes, int32_t *opts);
+
+/*
+ * The two bandwidths PROFILE selection takes B_max from (Sec. III-B and its
+ * footnote: B is raised for working sets that fit in the cache hierarchy),
+ * measured on the current device on first use and cached for the process:
+ * *hbm from the streaming triad over 3 x 1 GiB, *cache from a triad with
+ * ordinary loads and stores over 3 x 48 MiB (inside the 256 MB Infinity
+ * Cache), never below *hbm. Bytes/s. Synchronizes `stream`.
+ */
+csr_status_t csr_device_bandwidth(double *hbm, double *cache, void *stream);
+
+/*
+ * Test support: one pass of the B_max triad kernel on caller arrays,
+ * d_a[i] = d_b[i] + scalar * d_c[i] as one fused multiply-add, i < n
+ * (device arrays of n doubles, n even, 16-byte aligned; d_a must not
+ * overlap d_b or d_c). streaming = 1: the non-temporal accesses of the HBM
+ * probe, 0: ordinary ones (the cache probe). Asynchronous on `stream`.
+ */
+csr_status_t csr_debug_triad(double *d_a, const double *d_b, const double *d_c, int64_t n,
+                             double scalar, int32_t streaming, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Learned selector (replaces the decision tree of Sec. III-D): an MLP

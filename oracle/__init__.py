@@ -375,7 +375,10 @@ def p_peak(nnz, s_values, s_x, s_y, b_max):
 
 def p_imb(nnz, unit_times):
     """P_IMB = 2 NNZ / t_median over the execution units that ran work; for an
-    even count the median is the mean of the two middle values."""
+    even count the median is the mean of the two middle values. Reading for a
+    GPU: the paper's threads are the compute units, and a unit's time is the
+    span from the start of its first workgroup to the end of its last one in
+    the instrumented baseline run."""
     t = np.sort(np.asarray(unit_times, dtype=np.float64))
     if t.size == 0:
         return float("inf")
@@ -432,24 +435,22 @@ CLS_MB, CLS_ML, CLS_IMB, CLS_CMP = 1, 2, 4, 8
 
 
 def classify(p_csr, p_mb_, p_ml, p_imb_, p_cmp, p_peak_, t_ml=1.25, t_imb=1.24, t_mb=0.8):
-    """Profile-guided rule (Sec. III-C, Fig. 4) -> bit mask of classes.
+    """Profile-guided classifier (Sec. III-C, Fig. 4) -> bit mask of classes.
 
-    IMB  if P_IMB / P_CSR > T_IMB
-    ML   if P_ML  / P_CSR > T_ML
-    MB   if P_CSR ~ P_MB and P_MB < P_CMP < P_peak
-    CMP  if P_MB > P_CMP or P_CMP > P_peak
-    The paper leaves '~' undefined; it is read as P_CSR >= T_MB * P_MB.
+    A matrix is in every class whose test on the bounds of Sec. III-B holds:
+    imbalance and irregular x when removing them (P_IMB, P_ML) would beat
+    the baseline by more than the thresholds; bandwidth when the baseline
+    streams near P_MB and the no-index probe P_CMP lies between the two
+    bandwidth bounds; computation when P_CMP lies outside them. The paper
+    leaves its "approximately equal" undefined; read as P_CSR >= T_MB P_MB.
     """
-    c = 0
-    if p_imb_ / p_csr > t_imb:
-        c |= CLS_IMB
-    if p_ml / p_csr > t_ml:
-        c |= CLS_ML
-    if p_csr >= t_mb * p_mb_ and p_mb_ < p_cmp < p_peak_:
-        c |= CLS_MB
-    if p_mb_ > p_cmp or p_cmp > p_peak_:
-        c |= CLS_CMP
-    return c
+    tests = {
+        CLS_MB: p_csr >= t_mb * p_mb_ and p_mb_ < p_cmp < p_peak_,
+        CLS_ML: p_ml / p_csr > t_ml,
+        CLS_IMB: p_imb_ / p_csr > t_imb,
+        CLS_CMP: p_cmp < p_mb_ or p_cmp > p_peak_,
+    }
+    return sum(cls for cls, holds in tests.items() if holds)
 
 
 OPT_DELTA, OPT_PREFETCH, OPT_DECOMP, OPT_MERGE, OPT_UNROLL = 1, 2, 4, 8, 16

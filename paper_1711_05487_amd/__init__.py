@@ -30,7 +30,8 @@ SELECT = {"plain": SEL_PLAIN, "profile": SEL_PROFILE, "learned": SEL_LEARNED,
 (DEBUG_VALUES, DEBUG_CODES, DEBUG_TILE_I, DEBUG_TILE_J, DEBUG_LONG_ROWS, DEBUG_PLAN,
  DEBUG_MERGE_CODES, DEBUG_TILE_BASE, DEBUG_WINDOW_DICT, DEBUG_WINDOW_LEN,
  DEBUG_WINDOW_CODES, DEBUG_CB_ROWPTR, DEBUG_CB_COL, DEBUG_CB_VAL,
- DEBUG_MLP_BOUNDS, DEBUG_MLP_TIMES, DEBUG_MLP_RATIOS) = range(17)
+ DEBUG_MLP_BOUNDS, DEBUG_MLP_TIMES, DEBUG_MLP_RATIOS, DEBUG_IMB_SPANS,
+ DEBUG_BANDWIDTH) = range(19)
 
 STATUS = ["CSR_OK", "CSR_ERR_INVALID_ARG", "CSR_ERR_INVALID_MATRIX", "CSR_ERR_OUT_OF_MEMORY",
           "CSR_ERR_DEVICE", "CSR_ERR_UNSUPPORTED", "CSR_ERR_NOT_READY"]
@@ -38,9 +39,11 @@ STATUS = ["CSR_OK", "CSR_ERR_INVALID_ARG", "CSR_ERR_INVALID_MATRIX", "CSR_ERR_OU
 # Every entry point declared in include/csrspmv.h.
 EXPORTS = ("csr_config_default", "csr_create", "csr_destroy", "csr_inspect", "csr_select",
            "csr_spmv", "csr_spmv_batched", "csr_status_str", "csr_last_error", "csr_query",
-           "csr_debug_copy", "csr_debug_probe", "csr_triad", "csr_time_spmv", "csr_mlp_load", "csr_mlp_unload",
+           "csr_debug_copy", "csr_debug_probe", "csr_triad", "csr_device_bandwidth",
+           "csr_debug_triad", "csr_time_spmv", "csr_mlp_load", "csr_mlp_unload",
            "csr_mlp_forward", "csr_mlp_grad", "csr_mlp_train", "csr_mlp_normalize",
-           "csr_tree_load", "csr_tree_unload", "csr_jit_compile")
+           "csr_tree_load", "csr_tree_unload", "csr_jit_compile",
+           "csr_debug_alloc", "csr_classify")
 
 
 class CsrError(RuntimeError):
@@ -110,6 +113,9 @@ def lib():
                                          ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "csr_debug_copy": (ctypes.c_int, [P, i32, P, sz, ctypes.POINTER(sz), P]),
             "csr_triad": (ctypes.c_int, [sz, i32, ctypes.POINTER(ctypes.c_double), P]),
+            "csr_device_bandwidth": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
+                                                    ctypes.POINTER(ctypes.c_double), P]),
+            "csr_debug_triad": (ctypes.c_int, [P, P, P, i64, ctypes.c_double, i32, P]),
             "csr_debug_probe": (ctypes.c_int, [P, i32, P, P, P]),
             "csr_time_spmv": (ctypes.c_int, [P, P, P, i32, ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_double), ctypes.c_char_p, sz, P]),
@@ -123,6 +129,10 @@ def lib():
             "csr_tree_load": (ctypes.c_int, [i32, P, P, P, P, P]),
             "csr_tree_unload": (ctypes.c_int, []),
             "csr_jit_compile": (ctypes.c_int, [i32, i32, i32, i32, i32, P, sz, ctypes.POINTER(sz)]),
+            "csr_classify": (ctypes.c_int, [P, ctypes.POINTER(Config), i32, ctypes.POINTER(i32),
+                                            ctypes.POINTER(i32)]),
+            "csr_debug_alloc": (ctypes.c_int, [i32, i64, i64, ctypes.POINTER(i64),
+                                               ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -285,6 +295,45 @@ def triad(bytes_per_array: int = 1 << 30, reps: int = 5, stream=None) -> float:
     out = ctypes.c_double()
     _check(lib().csr_triad(bytes_per_array, reps, ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def classify(bounds, has_long_rows: bool, config: Config | None = None, **overrides):
+    """(classes, opts) of the profile-guided rule on bounds = (P_CSR, P_MB,
+    P_ML, P_IMB, P_CMP, P_peak), as csr_select('profile') decides them."""
+    cfg = config if config is not None else default_config()
+    for k, v in overrides.items():
+        setattr(cfg, k, v)
+    p = np.ascontiguousarray(bounds, dtype=np.float64)
+    if p.shape != (6,):
+        raise ValueError("six bounds")
+    c, o = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().csr_classify(p.ctypes.data_as(ctypes.c_void_p), ctypes.byref(cfg),
+                              1 if has_long_rows else 0, ctypes.byref(c), ctypes.byref(o)))
+    return c.value, o.value
+
+
+def debug_alloc(arm: bool = False, fail_from: int = 0, fail_count: int = 0):
+    """(live device buffers, live bytes, allocation attempts since the last
+    arming) of the library; with arm=True then re-arm the failure injector so
+    that attempts fail_from .. fail_from + fail_count - 1 from now fail."""
+    b, n, a = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().csr_debug_alloc(1 if arm else 0, fail_from, fail_count, ctypes.byref(b),
+                                 ctypes.byref(n), ctypes.byref(a)))
+    return b.value, n.value, a.value
+
+
+def device_bandwidth(stream=None):
+    """(HBM, cache) triad bandwidths in bytes/s that PROFILE takes B_max from."""
+    h, c = ctypes.c_double(), ctypes.c_double()
+    _check(lib().csr_device_bandwidth(ctypes.byref(h), ctypes.byref(c), _stream(stream)))
+    return h.value, c.value
+
+
+def debug_triad(a, b, c, scalar: float, streaming: bool, stream=None):
+    """One pass of the B_max triad kernel: a = b + scalar * c (FP64 tensors)."""
+    _check(lib().csr_debug_triad(_ptr(a), _ptr(b), _ptr(c), a.numel(), float(scalar),
+                                 1 if streaming else 0, _stream(stream)))
+    return a
 
 
 # ---------------------------------------------------------------------------

@@ -18,18 +18,14 @@ namespace csr {
 namespace {
 thread_local std::string g_err;
 
-// Test hook: CSRSPMV_FAIL_ALLOC_AFTER=n makes the (n+1)-th device allocation
-// of the process fail, to exercise the out-of-memory paths without a GPU
-// actually running out.
-std::atomic<long long> g_alloc_count{0};
+// Test support for the out-of-memory paths (csr_debug_alloc): device
+// allocation attempts are numbered from the last arming, and those in
+// [g_fail_from, g_fail_from + g_fail_count) fail without calling hipMalloc.
+// The live counters cover every device buffer the library holds.
+std::atomic<long long> g_alloc_attempts{0};
+std::atomic<long long> g_fail_from{0}, g_fail_count{0};
+std::atomic<long long> g_live_buffers{0}, g_live_bytes{0};
 std::atomic<uint64_t> g_next_id{1};
-long long fail_alloc_after() {
-    static long long v = [] {
-        const char *e = std::getenv("CSRSPMV_FAIL_ALLOC_AFTER");
-        return e ? std::atoll(e) : -1LL;
-    }();
-    return v;
-}
 
 struct DeviceGuard {
     int prev = -1;
@@ -71,8 +67,9 @@ csr_status_t HostBuf::alloc(size_t n) {
 csr_status_t DevBuf::alloc(size_t n) {
     release();
     if (n == 0) n = 256;  // keep a valid, aligned pointer for empty arrays
-    const long long lim = fail_alloc_after();
-    if (lim >= 0 && g_alloc_count.fetch_add(1) >= lim)
+    const long long k = g_alloc_attempts.fetch_add(1);
+    const long long f0 = g_fail_from.load();
+    if (k >= f0 && k < f0 + g_fail_count.load())
         return fail(CSR_ERR_OUT_OF_MEMORY, "injected allocation failure");
     hipError_t e = hipMalloc(&p, n);
     if (e != hipSuccess) {
@@ -80,7 +77,19 @@ csr_status_t DevBuf::alloc(size_t n) {
         return hip_fail(e, "hipMalloc");
     }
     bytes = n;
+    g_live_buffers.fetch_add(1);
+    g_live_bytes.fetch_add((long long)n);
     return CSR_OK;
+}
+
+void DevBuf::release() {
+    if (p) {
+        (void)hipFree(p);
+        g_live_buffers.fetch_sub(1);
+        g_live_bytes.fetch_sub((long long)bytes);
+    }
+    p = nullptr;
+    bytes = 0;
 }
 
 XcdGrid xcd_grid(int64_t nblk) {
@@ -140,6 +149,12 @@ std::string dominant_kernel(const csr_matrix_s *A, const Plan &P) {
     return "k_rowsplit<" + std::to_string(P.G) + ", " + std::to_string(P.idx) + ", " +
            (P.nt ? "true" : "false") + ", " + std::to_string(P.U) + ", " + std::to_string(P.R) +
            ", 0>";
+}
+
+int plan_kernel_count(const csr_matrix_s *A, const Plan &P) {
+    if ((P.opts & CSR_OPT_MERGE) && P.cblocks > 0) return P.cblocks;
+    if (P.opts & CSR_OPT_MERGE) return A->tiles_fixup ? 2 : 1;
+    return P.long_rows && A->n_long > 0 ? 3 : 1;
 }
 
 size_t storage_bytes(int storage) {
@@ -249,6 +264,50 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
     }
 }
 
+double device_wall_clock_hz(int device) {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
+        khz <= 0)
+        khz = 100000;  // the 100 MHz constant clock of CDNA parts
+    return 1e3 * (double)khz;
+}
+
+csr_status_t triad_bandwidth(size_t bytes_per_array, int reps, bool streaming, hipStream_t s,
+                             double *bytes_per_s) {
+    const int64_t n = (int64_t)(bytes_per_array / 16) * 2;
+    DevBuf a, b, c;
+    csr_status_t st;
+    if ((st = a.alloc(n * 8)) != CSR_OK || (st = b.alloc(n * 8)) != CSR_OK ||
+        (st = c.alloc(n * 8)) != CSR_OK)
+        return st;
+    CSR_HIP(hipMemsetAsync(b.p, 0, n * 8, s));
+    CSR_HIP(hipMemsetAsync(c.p, 0, n * 8, s));
+    hipEvent_t e0, e1;
+    CSR_HIP(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    float best = 1e30f;
+    e = launch_triad(a.as<double>(), b.as<double>(), c.as<double>(), 3.0, n, streaming, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess)
+            e = launch_triad(a.as<double>(), b.as<double>(), c.as<double>(), 3.0, n, streaming, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms < best) best = ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "triad");
+    *bytes_per_s = 3.0 * 8.0 * (double)n / (best * 1e-3);
+    return CSR_OK;
+}
+
 }  // namespace csr
 
 using namespace csr;
@@ -272,7 +331,7 @@ void csr_config_default(csr_config_t *cfg) {
     cfg->t_ml_part = 1.5;
 }
 
-const char *csr_status_str(csr_status_t s) {
+const char *csr_status_str(int32_t s) {
     switch (s) {
     case CSR_OK: return "CSR_OK";
     case CSR_ERR_INVALID_ARG: return "CSR_ERR_INVALID_ARG";
@@ -354,6 +413,7 @@ csr_status_t csr_create(csr_matrix_t *out, int32_t n_rows, int32_t n_cols, int64
     csr_config_t cfg;
     csr_config_default(&cfg);
     if ((st = realize(A, 0, cfg, &A->plan, s)) != CSR_OK) return bail(st);
+    A->plan_cfg = cfg;
     A->info = csr_plan_info_t{};
     A->info.classes = -1;
     fill_info(A, A->plan, &A->info);
@@ -390,6 +450,8 @@ csr_status_t csr_spmv(csr_matrix_t A, const void *d_x, void *d_y, void *stream) 
     if (A->n_rows > 0 && A->n_cols > 0 && x0 < y1 && y0 < x1)
         return fail(CSR_ERR_INVALID_ARG, "x and y overlap");
     if (A->n_rows == 0) return CSR_OK;
+    if (!plan_tables_ok(A, A->plan))
+        return fail(CSR_ERR_NOT_READY, "the plan's tables are not in place");
     DeviceGuard g(A->device);
     CSR_HIP(launch_spmv(A, A->plan, d_x, d_y, (hipStream_t)stream));
     return CSR_OK;
@@ -401,27 +463,42 @@ csr_status_t csr_time_spmv(csr_matrix_t A, const void *d_x, void *d_y, int32_t c
     if (!A || calls < 1 || !kernel_ms || !call_ms) return fail(CSR_ERR_INVALID_ARG, "bad arguments");
     if ((!d_x && A->n_cols > 0) || (!d_y && A->n_rows > 0))
         return fail(CSR_ERR_INVALID_ARG, "NULL vector");
+    if (!plan_tables_ok(A, A->plan))
+        return fail(CSR_ERR_NOT_READY, "the plan's tables are not in place");
     DeviceGuard g(A->device);
     hipStream_t s = (hipStream_t)stream;
-    std::vector<hipEvent_t> ev(2 * (size_t)calls + 2);
-    for (auto &e : ev) CSR_HIP(hipEventCreate(&e));
-    hipError_t e = launch_spmv(A, A->plan, d_x, d_y, s);  // warm
-    if (e == hipSuccess) e = hipEventRecord(ev[2 * calls], s);
-    for (int c = 0; c < calls && e == hipSuccess; ++c)
-        e = launch_spmv(A, A->plan, d_x, d_y, s, ev[2 * c], ev[2 * c + 1]);
-    if (e == hipSuccess) e = hipEventRecord(ev[2 * calls + 1], s);
-    if (e == hipSuccess) e = hipEventSynchronize(ev[2 * calls + 1]);
-    double k = 0.0;
+    // one event pair around all calls; a plan of several kernels also gets
+    // an event pair around its dominant kernel in every call, in a second
+    // pass (those events add their own overhead to that figure)
+    const bool single = plan_kernel_count(A, A->plan) == 1;
+    std::vector<hipEvent_t> ev(single ? 2 : 2 * (size_t)calls + 2, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto &x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    if (e == hipSuccess) e = launch_spmv(A, A->plan, d_x, d_y, s);  // warm
+    if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+    for (int c = 0; c < calls && e == hipSuccess; ++c) e = launch_spmv(A, A->plan, d_x, d_y, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
     float f = 0.f;
-    for (int c = 0; c < calls && e == hipSuccess; ++c) {
-        e = hipEventElapsedTime(&f, ev[2 * c], ev[2 * c + 1]);
-        k += f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&f, ev[0], ev[1]);
+    const double per_call = (double)f / calls;
+    double k = per_call * calls;
+    if (!single) {
+        for (int c = 0; c < calls && e == hipSuccess; ++c)
+            e = launch_spmv(A, A->plan, d_x, d_y, s, ev[2 + 2 * c], ev[3 + 2 * c]);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1 + 2 * calls]);
+        k = 0.0;
+        for (int c = 0; c < calls && e == hipSuccess; ++c) {
+            e = hipEventElapsedTime(&f, ev[2 + 2 * c], ev[3 + 2 * c]);
+            k += f;
+        }
     }
-    if (e == hipSuccess) e = hipEventElapsedTime(&f, ev[2 * calls], ev[2 * calls + 1]);
-    for (auto &x : ev) (void)hipEventDestroy(x);
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
     if (e != hipSuccess) return hip_fail(e, "timed SpMV");
     *kernel_ms = k / calls;
-    *call_ms = (double)f / calls;
+    *call_ms = per_call;
     if (kernel_name && name_bytes > 0) {
         const std::string n = dominant_kernel(A, A->plan);
         std::snprintf(kernel_name, name_bytes, "%s", n.c_str());
@@ -509,6 +586,22 @@ csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t by
         if (hn) std::memcpy(h_dst, h, hn);
         return CSR_OK;
     }
+    case 17: {  // P_IMB's per-CU spans (host copy)
+        const size_t hn = sizeof(int64_t) * A->imb_spans.size();
+        if (needed) *needed = hn;
+        if (A->imb_spans.empty()) return fail(CSR_ERR_INVALID_ARG, "array not present");
+        if (bytes != hn || !h_dst) return fail(CSR_ERR_INVALID_ARG, "size mismatch");
+        std::memcpy(h_dst, A->imb_spans.data(), hn);
+        return CSR_OK;
+    }
+    case 18: {  // B_max inputs: HBM and cache triad B/s, span clock Hz
+        const double v[3] = {A->bw_hbm, A->bw_cache, A->imb_clock_hz};
+        if (needed) *needed = sizeof(v);
+        if (A->imb_spans.empty()) return fail(CSR_ERR_INVALID_ARG, "array not present");
+        if (bytes != sizeof(v) || !h_dst) return fail(CSR_ERR_INVALID_ARG, "size mismatch");
+        std::memcpy(h_dst, v, sizeof(v));
+        return CSR_OK;
+    }
     case 5:
         if (needed) *needed = sizeof(csr_plan_info_t);
         if (bytes != sizeof(csr_plan_info_t) || !h_dst) return fail(CSR_ERR_INVALID_ARG, "size");
@@ -528,32 +621,33 @@ csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t by
 csr_status_t csr_triad(size_t bytes_per_array, int32_t reps, double *gbytes_per_s, void *stream) {
     if (!gbytes_per_s || reps < 1 || bytes_per_array < 4096)
         return fail(CSR_ERR_INVALID_ARG, "bad triad arguments");
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t n = (int64_t)(bytes_per_array / 16) * 2;
-    DevBuf a, b, c;
-    csr_status_t st;
-    if ((st = a.alloc(n * 8)) != CSR_OK || (st = b.alloc(n * 8)) != CSR_OK ||
-        (st = c.alloc(n * 8)) != CSR_OK)
-        return st;
-    CSR_HIP(hipMemsetAsync(b.p, 0, n * 8, s));
-    CSR_HIP(hipMemsetAsync(c.p, 0, n * 8, s));
-    hipEvent_t e0, e1;
-    CSR_HIP(hipEventCreate(&e0));
-    CSR_HIP(hipEventCreate(&e1));
-    float best = 1e30f;
-    CSR_HIP(launch_triad(a.as<double>(), b.as<double>(), c.as<double>(), 3.0, n, s));
-    for (int r = 0; r < reps; ++r) {
-        CSR_HIP(hipEventRecord(e0, s));
-        CSR_HIP(launch_triad(a.as<double>(), b.as<double>(), c.as<double>(), 3.0, n, s));
-        CSR_HIP(hipEventRecord(e1, s));
-        CSR_HIP(hipEventSynchronize(e1));
-        float ms = 0;
-        CSR_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) best = ms;
+    return triad_bandwidth(bytes_per_array, reps, true, (hipStream_t)stream, gbytes_per_s);
+}
+
+csr_status_t csr_debug_alloc(int32_t arm, int64_t fail_from, int64_t fail_count,
+                             int64_t *live_buffers, int64_t *live_bytes, int64_t *attempts) {
+    if (arm && (fail_from < 0 || fail_count < 0))
+        return fail(CSR_ERR_INVALID_ARG, "fail_from and fail_count must be >= 0");
+    if (live_buffers) *live_buffers = g_live_buffers.load();
+    if (live_bytes) *live_bytes = g_live_bytes.load();
+    if (attempts) *attempts = g_alloc_attempts.load();
+    if (arm) {
+        g_fail_count.store(0);
+        g_alloc_attempts.store(0);
+        g_fail_from.store(fail_from);
+        g_fail_count.store(fail_count);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    *gbytes_per_s = 3.0 * 8.0 * (double)n / (best * 1e-3);
+    return CSR_OK;
+}
+
+csr_status_t csr_debug_triad(double *d_a, const double *d_b, const double *d_c, int64_t n,
+                             double scalar, int32_t streaming, void *stream) {
+    if (n < 0 || (n & 1) || (n > 0 && (!d_a || !d_b || !d_c)) || (streaming != 0 && streaming != 1))
+        return fail(CSR_ERR_INVALID_ARG, "bad triad arguments");
+    if ((((uintptr_t)d_a | (uintptr_t)d_b | (uintptr_t)d_c) & 15) != 0)
+        return fail(CSR_ERR_INVALID_ARG, "triad arrays must be 16-byte aligned");
+    if (n == 0) return CSR_OK;
+    CSR_HIP(launch_triad(d_a, d_b, d_c, scalar, n, streaming != 0, (hipStream_t)stream));
     return CSR_OK;
 }
 

@@ -36,11 +36,7 @@ struct DevBuf {
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
+    void release();
     csr_status_t alloc(size_t n);
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
@@ -137,10 +133,17 @@ struct csr_matrix_s {
     int64_t long_tau = -1;         // threshold the current list was built for
     int64_t n_long_chunks = 0;
     csr::Plan plan;
+    csr_config_t plan_cfg{};       // the configuration `plan` was realized with
     csr_plan_info_t info{};
     int has_features = 0;
     csr_features_t feat{};
     csr::DevBuf scratch_x, scratch_y, scratch_col;  // selection probes
+    // P_IMB of the last PROFILE selection: busy span of every compute unit
+    // that ran work in the instrumented baseline (wall-clock ticks, by CU id),
+    // the tick rate, and the device's two triad bandwidths
+    std::vector<int64_t> imb_spans;
+    double imb_clock_hz = 0.0;
+    double bw_hbm = 0.0, bw_cache = 0.0;
     std::vector<int32_t> mlp_bounds;  // partition-aware ML test of the last PROFILE selection
     std::vector<int64_t> mlp_times;
     std::vector<double> mlp_ratios;
@@ -242,8 +245,19 @@ bool x_fits_32(const csr_matrix_s *A);
 int64_t merge_slack(const csr_matrix_s *A, int64_t L);
 int64_t merge_tile_count(const csr_matrix_s *A, int64_t L);
 std::string dominant_kernel(const csr_matrix_s *A, const Plan &P);
+// kernels one call of plan P launches
+int plan_kernel_count(const csr_matrix_s *A, const Plan &P);
+// a[i] = b[i] + scalar * c[i] (one FMA) over n doubles (n even); streaming:
+// non-temporal loads and stores (the HBM probe), else ordinary ones (the
+// cache-resident probe)
 hipError_t launch_triad(double *a, const double *b, const double *c, double scalar,
-                        int64_t n, hipStream_t s);
+                        int64_t n, bool streaming, hipStream_t s);
+// B_max probe at one footprint: best of `reps` triad passes over three
+// arrays of bytes_per_array bytes (allocated and freed inside), in B/s
+csr_status_t triad_bandwidth(size_t bytes_per_array, int reps, bool streaming, hipStream_t s,
+                             double *bytes_per_s);
+// wall_clock64() ticks per second on `device`
+double device_wall_clock_hz(int device);
 
 // Partial feature sums of one workgroup (folded in a fixed order).
 struct FeatPart {
@@ -310,6 +324,9 @@ csr_status_t learned_pick(csr_matrix_s *A, hipStream_t s, int32_t *variant);
 
 // Plans and selection (select.hip) -----------------------------------------------
 double plan_bytes(const csr_matrix_s *A, const Plan &P);
+// the derived tables plan P reads (tile table, codes, column blocks, long-row
+// list, schedule counters) are the ones the handle holds
+bool plan_tables_ok(const csr_matrix_s *A, const Plan &P);
 csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Plan *out,
                      hipStream_t s);
 void fill_info(const csr_matrix_s *A, const Plan &P, csr_plan_info_t *info);

@@ -8,6 +8,7 @@
 // Compiled once per storage type (-DCSR_STORAGE=0/1/2).
 #include "device.h"
 #include "internal.h"
+#include "long_rows.h"
 
 #ifndef CSR_STORAGE
 #error "CSR_STORAGE must be defined"
@@ -21,7 +22,7 @@ using V = typename St<S>::V;
 using X = typename St<S>::X;
 using A = typename St<S>::A;
 
-// chunk c covers nonzeros [chunk_beg[c], chunk_beg[c+1]) of one long row
+// chunk c covers nonzeros [chunk_beg[2c], chunk_beg[2c + 1]) of one long row
 __global__ __launch_bounds__(kBlock) void k_long_partial(const int32_t *__restrict__ col,
                                                          const V *__restrict__ val,
                                                          const X *__restrict__ x,
@@ -30,18 +31,7 @@ __global__ __launch_bounds__(kBlock) void k_long_partial(const int32_t *__restri
     __shared__ A s[kBlock];
     const int64_t c = blockIdx.x;
     if (c >= n_chunks) return;
-    const int32_t b = chunk_beg[2 * c], e = chunk_beg[2 * c + 1];
-    A acc = A(0);
-    for (int32_t j = b + threadIdx.x; j < e; j += kBlock)
-        acc = fma_acc(St<S>::cvt(__builtin_nontemporal_load(val + j)),
-                      (A)x[__builtin_nontemporal_load(col + j)], acc);
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[c] = s[0];
+    long_chunk_partial<S>(c, col, val, x, chunk_beg, part, s);
 }
 
 // long row k owns chunks [row_chunk[k], row_chunk[k+1])
@@ -51,9 +41,7 @@ __global__ __launch_bounds__(kBlock) void k_long_final(const int32_t *__restrict
                                                        X *__restrict__ y, int32_t n_long) {
     const int32_t k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= n_long) return;
-    A sum = A(0);
-    for (int32_t c = row_chunk[k]; c < row_chunk[k + 1]; ++c) sum += part[c];
-    y[long_rows[k]] = (X)sum;
+    long_row_final<S>(k, long_rows, row_chunk, part, y);
 }
 
 }  // namespace

@@ -326,19 +326,30 @@ __global__ __launch_bounds__(kBlock) void k_fill_row_index(const int32_t *__rest
     }
 }
 
-// Triad for B_max: one 16-byte vector per array per thread, streamed.
+// Triad for B_max: one 16-byte vector per array per thread. STREAM: the
+// non-temporal loads and stores of the HBM probe; otherwise ordinary
+// accesses, which a working set smaller than the Infinity Cache serves from
+// there on repeated passes.
+template <bool STREAM>
 __global__ __launch_bounds__(kBlock) void k_triad1(dvec2 *__restrict__ a,
                                                    const dvec2 *__restrict__ b,
                                                    const dvec2 *__restrict__ c, double s,
                                                    int64_t n2) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n2) {
-        const dvec2 bb = __builtin_nontemporal_load(b + i);
-        const dvec2 cc = __builtin_nontemporal_load(c + i);
+        dvec2 bb, cc;
+        if constexpr (STREAM) {
+            bb = __builtin_nontemporal_load(b + i);
+            cc = __builtin_nontemporal_load(c + i);
+        } else {
+            bb = b[i];
+            cc = c[i];
+        }
         dvec2 r;
         r.x = fma(s, cc.x, bb.x);
         r.y = fma(s, cc.y, bb.y);
-        __builtin_nontemporal_store(r, a + i);
+        if constexpr (STREAM) __builtin_nontemporal_store(r, a + i);
+        else a[i] = r;
     }
 }
 
@@ -463,11 +474,15 @@ hipError_t launch_convert_values(const double *src, void *dst, int64_t n, int st
 }
 
 hipError_t launch_triad(double *a, const double *b, const double *c, double scalar, int64_t n,
-                        hipStream_t s) {
+                        bool streaming, hipStream_t s) {
     const int64_t n2 = n / 2;
     const unsigned g = (unsigned)((n2 + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_triad1, dim3(g), dim3(kBlock), 0, s, (dvec2 *)a, (const dvec2 *)b,
-                       (const dvec2 *)c, scalar, n2);
+    if (streaming)
+        hipLaunchKernelGGL(k_triad1<true>, dim3(g), dim3(kBlock), 0, s, (dvec2 *)a,
+                           (const dvec2 *)b, (const dvec2 *)c, scalar, n2);
+    else
+        hipLaunchKernelGGL(k_triad1<false>, dim3(g), dim3(kBlock), 0, s, (dvec2 *)a,
+                           (const dvec2 *)b, (const dvec2 *)c, scalar, n2);
     return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@
 // This file is compiled once per storage type (-DCSR_STORAGE=0/1/2).
 #include "device.h"
 #include "internal.h"
+#include "rowsplit_block.h"
 
 #ifndef CSR_STORAGE
 #error "CSR_STORAGE must be defined"
@@ -32,116 +33,6 @@ constexpr int S = CSR_STORAGE;
 using V = typename St<S>::V;
 using X = typename St<S>::X;
 using A = typename St<S>::A;
-
-// Rows of logical block lb (R chunks of 256 / G consecutive rows).
-template <int G, int IDX, bool NT, int U, int R, int PROBE>
-__device__ __forceinline__ void rowsplit_block(int64_t lb, const int32_t *__restrict__ rp,
-                                               const int32_t *__restrict__ col,
-                                               const void *__restrict__ codes,
-                                               const V *__restrict__ val,
-                                               const X *__restrict__ x, X *__restrict__ y,
-                                               int32_t skip_above, int32_t n_rows,
-                                               int32_t n_cols) {
-    constexpr int NG = kBlock / G;
-    const int lane = threadIdx.x % G;
-    const int grp = threadIdx.x / G;
-    const int64_t first = lb * (int64_t)NG * R;
-
-    int32_t row[R], b[R], e[R];
-    bool mine[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int64_t slot = first + (int64_t)k * NG + grp;
-        const bool live = slot < n_rows;
-        row[k] = live ? (int32_t)slot : 0;
-        b[k] = live ? rp[row[k]] : 0;
-        e[k] = live ? rp[row[k] + 1] : 0;
-        // Decomposition: rows longer than skip_above belong to the long-row
-        // pass, which writes their y.
-        mine[k] = live && (e[k] - b[k]) <= skip_above;
-        if (!mine[k]) e[k] = b[k];
-    }
-    A acc[R][U];
-#pragma unroll
-    for (int k = 0; k < R; ++k)
-#pragma unroll
-        for (int u = 0; u < U; ++u) acc[k][u] = A(0);
-
-    if constexpr (IDX == IDX_I32) {
-        // first G*U entries of every row: all loads issued before any use
-        int32_t c[R][U];
-        V v[R][U];
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int32_t jj = b[k] + lane + u * G;
-                const bool ok = jj < e[k];
-                if constexpr (PROBE == 1) c[k][u] = min(row[k], n_cols - 1);
-                else c[k][u] = ok ? ld<NT>(col + jj) : 0;
-                v[k][u] = ok ? ld<NT>(val + jj) : V(0);
-            }
-        X xv[R][U];
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool ok = b[k] + lane + u * G < e[k];
-                xv[k][u] = ok ? x[c[k][u]] : X(0);
-            }
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                acc[k][u] = fma_acc(St<S>::cvt(v[k][u]), (A)xv[k][u], acc[k][u]);
-        // tails of rows longer than G*U
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            for (int32_t j = b[k] + lane + G * U; j < e[k]; j += G * U) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int32_t jj = j + u * G;
-                    if (jj < e[k]) {
-                        const int32_t cc = PROBE == 1 ? min(row[k], n_cols - 1) : ld<NT>(col + jj);
-                        acc[k][u] = fma_acc(St<S>::cvt(ld<NT>(val + jj)), (A)x[cc], acc[k][u]);
-                    }
-                }
-            }
-        }
-    } else {
-        // Delta decode: per chunk of G entries, an inclusive scan of the codes
-        // inside the lane group, added to the last column of the previous
-        // chunk. The chunk loop bound is uniform in the group.
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            int32_t base = 0;
-            for (int32_t j0 = b[k]; j0 < e[k]; j0 += G) {
-                const int32_t j = j0 + lane;
-                const bool ok = j < e[k];
-                int32_t v = 0;
-                if (ok) {
-                    v = load_code<IDX>(codes, j, j == b[k]);
-                    if (j == b[k]) v += row[k];
-                }
-                const int32_t s = group_scan<G>(v, lane);
-                const int32_t c = base + s;
-                base += __shfl(s, G - 1, G);
-                if (ok) {
-                    const V vv = ld<NT>(val + j);
-                    acc[k][0] = fma_acc(St<S>::cvt(vv), (A)x[c], acc[k][0]);
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        A t = acc[k][0];
-#pragma unroll
-        for (int u = 1; u < U; ++u) t += acc[k][u];
-        t = group_sum<G>(t);
-        if (mine[k] && lane == 0) y[row[k]] = (X)t;
-    }
-}
 
 // Static schedule (ctr == nullptr): workgroup b owns logical block
 // xcd_logical_block(b). Dynamic chunks (ctr != nullptr, the "dynamic"
@@ -164,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsplit(
         if constexpr (PROBE == 2) {
             if (threadIdx.x == 0) t_start = (int64_t)wall_clock64();
         }
-        rowsplit_block<G, IDX, NT, U, R, PROBE>(lb, rp, col, codes, val, x, y, skip_above,
+        rowsplit_block<S, G, IDX, NT, U, R, PROBE>(lb, rp, col, codes, val, x, y, skip_above,
                                                 n_rows, n_cols);
         if constexpr (PROBE == 2) {
             __syncthreads();
@@ -185,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsplit(
         if (first >= nblk) break;
         const int64_t last = min(first + (int64_t)per_fetch, nblk);
         for (int64_t lb = first; lb < last; ++lb)
-            rowsplit_block<G, IDX, NT, U, R, PROBE>(lb, rp, col, codes, val, x, y, skip_above,
+            rowsplit_block<S, G, IDX, NT, U, R, PROBE>(lb, rp, col, codes, val, x, y, skip_above,
                                                     n_rows, n_cols);
     }
     if (threadIdx.x == 0 && atomicAdd(ctr + 1, 1) == (int32_t)gridDim.x - 1) {

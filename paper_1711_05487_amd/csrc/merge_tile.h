@@ -378,29 +378,35 @@ __device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT, ID
 // staged in LDS, and every nonzero reads its x there by its rank. The
 // window occupies the front of the product buffer, which is overwritten
 // only after the last rank has been read.
-template <int S, int IPT, class LDS>
-__device__ __forceinline__ void merge_gather_window(const MergeTileRegs<S, IPT, IDX_W8> &R,
-                                                    const typename St<S>::X *__restrict__ x,
-                                                    int32_t n_cols, LDS &lds,
-                                                    typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX_W8>::NIT]
-                                                                          [MergeTileRegs<S, IPT, IDX_W8>::VEC]) {
+template <int S, int IPT>
+__device__ __forceinline__ typename VecOf<typename St<S>::X, 4>::type merge_window_load(
+    const MergeTileRegs<S, IPT, IDX_W8> &R, const typename St<S>::X *__restrict__ x,
+    int32_t n_cols) {
     using X = typename St<S>::X;
-    constexpr int VEC = MergeTileRegs<S, IPT, IDX_W8>::VEC, NIT = MergeTileRegs<S, IPT, IDX_W8>::NIT;
-    static_assert(kWindowMax * sizeof(X) <= sizeof(lds.prod), "the window fits the product buffer");
     static_assert(kWindowMax == 4 * kMergeBlock, "four window entries per lane");
-    using XV4 = typename VecOf<X, 4>::type;
     // an entry is below 2^16: the range never needs more than 2^16 elements
     const uint32_t nx = (uint32_t)min(n_cols - R.base, 1 << 16);
     const auto rx = buffer_range(x + R.base, nx * (uint32_t)sizeof(X));
-    XV4 w;
+    typename VecOf<X, 4>::type w;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         // entries past the window read nothing (an offset past the range)
         const bool in = 4 * (int)threadIdx.x + k < R.wl;
         w[k] = buffer_load<X, false>(rx, in ? (uint32_t)R.dv[k] * (uint32_t)sizeof(X) : 0x80000000u, 0u);
     }
+    return w;
+}
+
+template <int S, int IPT, class LDS>
+__device__ __forceinline__ void merge_window_stage(
+    const MergeTileRegs<S, IPT, IDX_W8> &R, const typename VecOf<typename St<S>::X, 4>::type &w,
+    LDS &lds,
+    typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX_W8>::NIT][MergeTileRegs<S, IPT, IDX_W8>::VEC]) {
+    using X = typename St<S>::X;
+    constexpr int VEC = MergeTileRegs<S, IPT, IDX_W8>::VEC, NIT = MergeTileRegs<S, IPT, IDX_W8>::NIT;
+    static_assert(kWindowMax * sizeof(X) <= sizeof(lds.prod), "the window fits the product buffer");
     X *s_win = reinterpret_cast<X *>(lds.prod);
-    *reinterpret_cast<XV4 *>(s_win + 4 * threadIdx.x) = w;
+    *reinterpret_cast<typename VecOf<X, 4>::type *>(s_win + 4 * threadIdx.x) = w;
     wave_lds_sync();
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
@@ -408,6 +414,15 @@ __device__ __forceinline__ void merge_gather_window(const MergeTileRegs<S, IPT, 
         for (int e = 0; e < VEC; ++e) xs[it][e] = s_win[R.cv[it][e]];
     }
     wave_lds_sync();
+}
+
+template <int S, int IPT, class LDS>
+__device__ __forceinline__ void merge_gather_window(const MergeTileRegs<S, IPT, IDX_W8> &R,
+                                                    const typename St<S>::X *__restrict__ x,
+                                                    int32_t n_cols, LDS &lds,
+                                                    typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX_W8>::NIT]
+                                                                          [MergeTileRegs<S, IPT, IDX_W8>::VEC]) {
+    merge_window_stage<S, IPT>(R, merge_window_load<S, IPT>(R, x, n_cols), lds, xs);
 }
 
 // Sum of s[b .. e) in index order, starting from +0.

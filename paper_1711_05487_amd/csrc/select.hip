@@ -97,11 +97,15 @@ namespace {
 
 csr_status_t build_delta(csr_matrix_s *A, hipStream_t s) {
     if (A->code_bits != 32) return CSR_OK;  // built already, or known ineligible (0)
-    A->code_bits = 0;
-    if (!A->rows_sorted) return CSR_OK;
+    if (!A->rows_sorted) {
+        A->code_bits = 0;
+        return CSR_OK;
+    }
     for (int bits : {8, 16}) {
         DevBuf flags, codes;
         csr_status_t st;
+        // a failed step leaves code_bits at 32 (not built), so a later
+        // call tries again
         if ((st = flags.alloc(sizeof(int32_t))) != CSR_OK) return st;
         if ((st = codes.alloc((size_t)A->nnz * (bits / 8) + kPadBytes)) != CSR_OK) return st;
         CSR_HIP(hipMemsetAsync(flags.p, 0, sizeof(int32_t), s));
@@ -117,6 +121,7 @@ csr_status_t build_delta(csr_matrix_s *A, hipStream_t s) {
             return CSR_OK;
         }
     }
+    A->code_bits = 0;
     return CSR_OK;
 }
 
@@ -124,6 +129,13 @@ csr_status_t build_tiles(csr_matrix_s *A, int L, hipStream_t s) {
     if (A->tiles_L == L) return CSR_OK;
     const int64_t slack = merge_slack(A, L);
     const int64_t T = merge_tile_count(A, L);
+    // until the new table is complete, no table (and nothing built on one)
+    // is valid
+    A->tiles_L = 0;
+    A->n_tiles = 0;
+    A->mcodes_L = 0;
+    A->wcodes_L = 0;
+    A->wcode_state = 0;
     csr_status_t st;
     if ((st = A->tile_i.alloc(sizeof(int32_t) * (T + 1))) != CSR_OK) return st;
     if ((st = A->tile_j.alloc(sizeof(int32_t) * (T + 1))) != CSR_OK) return st;
@@ -133,10 +145,6 @@ csr_status_t build_tiles(csr_matrix_s *A, int L, hipStream_t s) {
                                    A->tile_i.as<int32_t>(), A->tile_j.as<int32_t>(), s));
     A->n_tiles = T;
     A->tiles_L = L;
-    A->mcodes_L = 0;  // merge codes belong to the previous tiles
-    A->wcodes_L = 0;
-    A->wcode_state = 0;
-    A->cb_B = 0;  // column blocks carry their own tile tables
     A->tiles_slack = slack;
     A->tiles_fixup = slack == 0;  // row-aligned tiles leave nothing to fix up
     return CSR_OK;
@@ -161,6 +169,9 @@ csr_status_t build_merge_codes(csr_matrix_s *A, hipStream_t s, bool encode = tru
         return CSR_OK;
     }
     const int64_t T = A->n_tiles;
+    A->mcodes_L = 0;  // not valid until the end
+    A->mcode_bits = 0;
+    A->mcodes_encoded = 0;
     csr_status_t st;
     if ((st = A->tile_base.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(T, 1))) != CSR_OK)
         return st;
@@ -173,7 +184,6 @@ csr_status_t build_merge_codes(csr_matrix_s *A, hipStream_t s, bool encode = tru
     CSR_HIP(hipMemcpyAsync(&r, range.p, sizeof(r), hipMemcpyDeviceToHost, s));
     CSR_HIP(hipStreamSynchronize(s));
     const int bits = r < (1 << 8) ? 8 : r < (1 << 16) ? 16 : 32;
-    A->mcodes_encoded = 0;
     if (bits != 32 && encode) {
         if ((st = A->mcodes.alloc((size_t)A->nnz * (bits / 8) + kPadBytes)) != CSR_OK) return st;
         CSR_HIP(hipMemsetAsync(A->mcodes.as<char>() + (size_t)A->nnz * (bits / 8), 0, kPadBytes,
@@ -195,9 +205,13 @@ csr_status_t build_window_codes(csr_matrix_s *A, hipStream_t s) {
     if (A->wcodes_L == A->tiles_L && A->wcode_state != 0) return CSR_OK;
     csr_status_t st;
     if ((st = build_merge_codes(A, s, false)) != CSR_OK) return st;
-    A->wcodes_L = A->tiles_L;
-    A->wcode_state = -1;
-    if (A->tiles_slack <= 0 || A->mcode_bits > 16) return CSR_OK;
+    A->wcodes_L = 0;  // not valid until the end
+    A->wcode_state = 0;
+    if (A->tiles_slack <= 0 || A->mcode_bits > 16) {
+        A->wcodes_L = A->tiles_L;
+        A->wcode_state = -1;
+        return CSR_OK;
+    }
     const int64_t T = A->n_tiles;
     if ((st = A->wdict.alloc(sizeof(uint16_t) * kWindowMax * (size_t)std::max<int64_t>(T, 1))) !=
         CSR_OK)
@@ -215,7 +229,11 @@ csr_status_t build_window_codes(csr_matrix_s *A, hipStream_t s) {
     int32_t m = 0;
     CSR_HIP(hipMemcpyAsync(&m, most.p, sizeof(m), hipMemcpyDeviceToHost, s));
     CSR_HIP(hipStreamSynchronize(s));
-    if (m > kWindowMax) return CSR_OK;
+    if (m > kWindowMax) {
+        A->wcodes_L = A->tiles_L;
+        A->wcode_state = -1;
+        return CSR_OK;
+    }
     std::vector<int32_t> wl((size_t)T);
     if (T > 0)
         CSR_HIP(hipMemcpyAsync(wl.data(), A->wlen.p, sizeof(int32_t) * (size_t)T,
@@ -224,6 +242,7 @@ csr_status_t build_window_codes(csr_matrix_s *A, hipStream_t s) {
     int64_t sum = 0;
     for (int32_t v : wl) sum += v;
     A->wdict_entries = sum;
+    A->wcodes_L = A->tiles_L;
     A->wcode_state = 1;
     return CSR_OK;
 }
@@ -252,6 +271,8 @@ int column_blocks_for(const csr_matrix_s *A) {
 
 csr_status_t build_colblocks(csr_matrix_s *A, int B, int L, hipStream_t s) {
     if (A->cb_B == B && A->cb_L == L) return CSR_OK;
+    A->cb_B = 0;  // not valid until the end
+    A->cb_L = 0;
     const int32_t n = A->n_rows;
     const int32_t width = (int32_t)((A->n_cols + (int64_t)B - 1) / B);
     const size_t vb = storage_bytes(A->storage);
@@ -319,6 +340,7 @@ constexpr int32_t kLongChunk = 8192;
 
 csr_status_t build_long_rows(csr_matrix_s *A, int64_t tau, hipStream_t s) {
     if (A->long_tau == tau) return CSR_OK;
+    A->long_tau = -1;  // not valid until the end
     std::vector<int32_t> rp((size_t)A->n_rows + 1);
     CSR_HIP(hipMemcpyAsync(rp.data(), A->rp.p, sizeof(int32_t) * rp.size(),
                            hipMemcpyDeviceToHost, s));
@@ -334,13 +356,11 @@ csr_status_t build_long_rows(csr_matrix_s *A, int64_t tau, hipStream_t s) {
         }
         row_chunk.push_back((int32_t)(chunks.size() / 2));
     }
-    A->n_long = (int32_t)rows.size();
-    A->n_long_chunks = (int64_t)chunks.size() / 2;
     csr_status_t st;
     if ((st = A->long_list.alloc(sizeof(int32_t) * rows.size())) != CSR_OK) return st;
     if ((st = A->long_row_chunk.alloc(sizeof(int32_t) * row_chunk.size())) != CSR_OK) return st;
     if ((st = A->long_chunks.alloc(sizeof(int32_t) * chunks.size())) != CSR_OK) return st;
-    if ((st = A->long_part.alloc(8 * (size_t)A->n_long_chunks)) != CSR_OK) return st;
+    if ((st = A->long_part.alloc(8 * (chunks.size() / 2))) != CSR_OK) return st;
     if (!rows.empty()) {
         CSR_HIP(hipMemcpyAsync(A->long_list.p, rows.data(), sizeof(int32_t) * rows.size(),
                                hipMemcpyHostToDevice, s));
@@ -350,6 +370,8 @@ csr_status_t build_long_rows(csr_matrix_s *A, int64_t tau, hipStream_t s) {
                                hipMemcpyHostToDevice, s));
         CSR_HIP(hipStreamSynchronize(s));
     }
+    A->n_long = (int32_t)rows.size();
+    A->n_long_chunks = (int64_t)chunks.size() / 2;
     A->long_tau = tau;
     return CSR_OK;
 }
@@ -363,6 +385,23 @@ int64_t long_row_tau(const csr_matrix_s *A, const csr_config_t &cfg) {
 }  // namespace
 
 csr_status_t inspect(csr_matrix_s *A, hipStream_t s);
+
+bool plan_tables_ok(const csr_matrix_s *A, const Plan &P) {
+    if (P.opts & CSR_OPT_MERGE) {
+        if (P.cblocks > 0) return A->cb_B == P.cblocks && A->cb_L == P.L;
+        if (A->tiles_L != P.L || A->n_tiles <= 0) return false;
+        if (P.idx == IDX_W8) return A->wcode_state == 1 && A->wcodes_L == P.L;
+        if (P.idx == IDX_D8 || P.idx == IDX_D16)
+            return A->mcodes_encoded && A->mcodes_L == P.L &&
+                   A->mcode_bits == (P.idx == IDX_D8 ? 8 : 16);
+        return true;
+    }
+    if ((P.idx == IDX_D8 || P.idx == IDX_D16) && A->code_bits != (P.idx == IDX_D8 ? 8 : 16))
+        return false;
+    if (P.long_rows && A->long_tau < 0) return false;
+    if (P.dyn && !A->dyn_ctr.p) return false;
+    return true;
+}
 
 // Realize an optimization mask as a concrete plan, building what it needs.
 // Parameters not fixed by cfg take the defaults below; the autotuner varies
@@ -583,8 +622,11 @@ csr_status_t device_bandwidth(int device, hipStream_t s, double *hbm, double *ca
     }
     DeviceBandwidth d;
     csr_status_t st;
-    if ((st = csr_triad((size_t)1 << 30, 3, &d.hbm, s)) != CSR_OK) return st;
-    if ((st = csr_triad((size_t)48 << 20, 5, &d.cache, s)) != CSR_OK) return st;
+    // HBM: 3 x 1 GiB with non-temporal accesses. Cache: 3 x 48 MiB (inside
+    // the 256 MB Infinity Cache) with ordinary accesses, so that repeated
+    // passes hit there. The cache figure never goes below the HBM one.
+    if ((st = triad_bandwidth((size_t)1 << 30, 3, true, s, &d.hbm)) != CSR_OK) return st;
+    if ((st = triad_bandwidth((size_t)48 << 20, 5, false, s, &d.cache)) != CSR_OK) return st;
     if (d.cache < d.hbm) d.cache = d.hbm;
     std::lock_guard<std::mutex> lk(mu);
     known[device] = d;
@@ -776,7 +818,6 @@ csr_status_t measure_bounds(csr_matrix_s *A, const csr_config_t &cfg, hipStream_
                             calls, 3, s, &t_cmp)) != CSR_OK)
         return st;
     // P_IMB: per-CU busy spans of the instrumented baseline
-    double imb_ratio = 1.0;
     const int NG = kBlock / P0.G;
     const int64_t nblk = (A->n_rows + NG - 1) / NG;
     DevBuf rec;
@@ -822,14 +863,11 @@ csr_status_t measure_bounds(csr_matrix_s *A, const csr_config_t &cfg, hipStream_
                 it->second.second = std::max(it->second.second, h[3 * b + 1]);
             }
         }
-        std::vector<double> d;
-        for (auto &kv : span) d.push_back((double)(kv.second.second - kv.second.first));
-        if (!d.empty()) {
-            std::sort(d.begin(), d.end());
-            const size_t m = d.size() / 2;
-            const double med = d.size() % 2 ? d[m] : 0.5 * (d[m - 1] + d[m]);
-            if (med > 0) imb_ratio = d.back() / med;
-        }
+        // the "threads" of Sec. III-B are the compute units: each one's time
+        // is the span from its first workgroup's start to its last one's end
+        A->imb_spans.clear();
+        for (auto &kv : span) A->imb_spans.push_back(kv.second.second - kv.second.first);
+        A->imb_clock_hz = device_wall_clock_hz(A->device);
     }
     // Partition-aware ML (the extension proposed with the results of
     // Sec. IV-C): the P_ML comparison repeated on contiguous nnz-balanced
@@ -873,10 +911,22 @@ csr_status_t measure_bounds(csr_matrix_s *A, const csr_config_t &cfg, hipStream_
     const double s_fmt = (double)A->nnz * (vb + 4.0) + 4.0 * (A->n_rows + 1);
     const double bmax = (s_fmt + sx + sy) <= kCacheBytes ? b_cache : b_hbm;
     B->b_max = bmax;
+    A->bw_hbm = b_hbm;
+    A->bw_cache = b_cache;
     B->p_csr = flops / (t_csr * 1e-3);
     B->p_ml = flops / (t_ml * 1e-3);
     B->p_cmp = flops / (t_cmp * 1e-3);
-    B->p_imb = B->p_csr * imb_ratio;  // 2 NNZ / t_median with t_median = t * median/max span
+    // P_IMB = 2 NNZ / t_median, t_median the median span over the compute
+    // units that ran work (for an even count the mean of the two middle
+    // ones); without spans the baseline's own rate
+    B->p_imb = B->p_csr;
+    if (!A->imb_spans.empty()) {
+        std::vector<int64_t> d = A->imb_spans;
+        std::sort(d.begin(), d.end());
+        const size_t m = d.size() / 2;
+        const double med = d.size() % 2 ? (double)d[m] : 0.5 * ((double)d[m - 1] + (double)d[m]);
+        if (med > 0) B->p_imb = flops / (med / A->imb_clock_hz);
+    }
     B->p_mb = flops / ((s_fmt + sx + sy) / bmax);
     B->p_peak = flops / (((double)A->nnz * vb + sx + sy) / bmax);
     return CSR_OK;
@@ -884,16 +934,42 @@ csr_status_t measure_bounds(csr_matrix_s *A, const csr_config_t &cfg, hipStream_
 
 }  // namespace
 
-// Fig. 4: the profile-guided rule (cfg thresholds; "P_CSR ~ P_MB" read as
-// P_CSR >= t_mb * P_MB).
+// The profile-guided classifier (Sec. III-C, Fig. 4). Every bottleneck
+// class has its own test on the bounds of Sec. III-B, independent of the
+// others, and a matrix belongs to every class whose test holds:
+//   IMB  removing the imbalance would pay: P_IMB / P_CSR above t_imb;
+//   ML   regular x accesses would pay: P_ML / P_CSR above t_ml;
+//   MB   the baseline already streams near the bandwidth bound (P_CSR at
+//        least t_mb P_MB, the reading of the paper's "approximately equal")
+//        while dropping the index stream stays between the two
+//        bandwidth bounds (P_MB < P_CMP < P_peak);
+//   CMP  the no-index probe falls outside those bounds (P_CMP below P_MB or
+//        above P_peak).
+namespace {
+struct ClassTest {
+    int32_t cls;
+    bool (*holds)(const double *p, const csr_config_t &cfg);  // p: csr, mb, ml, imb, cmp, peak
+};
+enum { B_CSR, B_MB, B_ML, B_IMB, B_CMP, B_PEAK };
+constexpr ClassTest kClassTests[] = {
+    {CSR_CLS_MB, [](const double *p, const csr_config_t &c) {
+         return p[B_CSR] >= c.t_mb * p[B_MB] && p[B_MB] < p[B_CMP] && p[B_CMP] < p[B_PEAK];
+     }},
+    {CSR_CLS_ML, [](const double *p, const csr_config_t &c) { return p[B_ML] / p[B_CSR] > c.t_ml; }},
+    {CSR_CLS_IMB, [](const double *p, const csr_config_t &c) { return p[B_IMB] / p[B_CSR] > c.t_imb; }},
+    {CSR_CLS_CMP, [](const double *p, const csr_config_t &) {
+         return p[B_CMP] < p[B_MB] || p[B_CMP] > p[B_PEAK];
+     }},
+};
+}  // namespace
+
 int32_t classify(double p_csr, double p_mb, double p_ml, double p_imb, double p_cmp,
                  double p_peak, const csr_config_t &cfg) {
-    int32_t c = 0;
-    if (p_imb / p_csr > cfg.t_imb) c |= CSR_CLS_IMB;
-    if (p_ml / p_csr > cfg.t_ml) c |= CSR_CLS_ML;
-    if (p_csr >= cfg.t_mb * p_mb && p_mb < p_cmp && p_cmp < p_peak) c |= CSR_CLS_MB;
-    if (p_mb > p_cmp || p_cmp > p_peak) c |= CSR_CLS_CMP;
-    return c;
+    const double p[] = {p_csr, p_mb, p_ml, p_imb, p_cmp, p_peak};
+    int32_t classes = 0;
+    for (const ClassTest &t : kClassTests)
+        if (t.holds(p, cfg)) classes |= t.cls;
+    return classes;
 }
 
 // Table II: classes -> optimizations, applied jointly.
@@ -911,7 +987,7 @@ namespace {
 // A few parameter settings of the chosen optimization set, timed; the
 // fastest is kept.
 csr_status_t autotune(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, hipStream_t s,
-                      Plan *best) {
+                      Plan *best, csr_config_t *best_cfg) {
     const int calls = cfg.timing_calls > 0 ? cfg.timing_calls : 32;
     std::vector<csr_config_t> cands;
     const double nnz_avg = A->n_rows ? (double)A->nnz / A->n_rows : 0.0;
@@ -974,6 +1050,7 @@ csr_status_t autotune(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, hi
     // are the ones in place (cached per parameter, so this is cheap).
     csr_status_t st = realize(A, opts, cands[best_k], best, s);
     if (st == CSR_OK && best_plain_loads) best->nt = 0;
+    *best_cfg = cands[best_k];
     return st;
 }
 
@@ -1052,6 +1129,34 @@ csr_status_t csr_inspect(csr_matrix_t A, csr_features_t *out, void *stream) {
     return CSR_OK;
 }
 
+namespace {
+// After a failed selection: the candidates it built may have replaced the
+// tables of the committed plan (they share the handle's tile table, codes,
+// column blocks and long-row list). Rebuild them; if that fails too, fall
+// back to the plain plan, which reads only row_ptr, col_idx and val. The
+// failure's message is kept.
+void restore_plan(csr_matrix_s *A, hipStream_t s) {
+    if (plan_tables_ok(A, A->plan)) return;
+    const std::string why = csr_last_error();
+    Plan Q;
+    const bool rebuilt = realize(A, A->plan.opts, A->plan_cfg, &Q, s) == CSR_OK &&
+                         plan_tables_ok(A, A->plan);
+    if (!rebuilt) {
+        csr_config_t dc;
+        csr_config_default(&dc);
+        (void)realize(A, 0, dc, &Q, s);  // builds nothing
+        A->plan = Q;
+        A->plan_cfg = dc;
+        A->info = csr_plan_info_t{};
+        A->info.classes = -1;
+        fill_info(A, Q, &A->info);
+        A->version += 1;
+    }
+    (void)hipStreamSynchronize(s);
+    set_error(why);
+}
+}  // namespace
+
 csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in,
                         csr_plan_info_t *out, void *stream) {
     if (!A) return fail(CSR_ERR_INVALID_ARG, "NULL handle");
@@ -1073,6 +1178,7 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
     hipStream_t s = (hipStream_t)stream;
     const auto t0 = Clock::now();
     Plan P;
+    csr_config_t used = cfg;  // the configuration P is realized with
     csr_plan_info_t info{};
     info.classes = -1;
     csr_status_t st = CSR_OK;
@@ -1167,7 +1273,7 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
         info.ml_parts_flagged = B.ml_flagged;
         info.ml_part_max = B.ml_part_max;
         const auto tp = Clock::now();
-        if (cfg.autotune) st = autotune(A, opts, cfg, s, &P);
+        if (cfg.autotune) st = autotune(A, opts, cfg, s, &P, &used);
         else st = realize(A, opts, cfg, &P, s);
         t_prep = ms_since(tp);
         break;
@@ -1175,9 +1281,13 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
     default:
         return fail(CSR_ERR_UNSUPPORTED, "selection mode not available");
     }
-    if (st != CSR_OK) return st;
+    if (st != CSR_OK) {
+        restore_plan(A, s);
+        return st;
+    }
     CSR_HIP(hipStreamSynchronize(s));
     A->plan = P;
+    A->plan_cfg = used;
     A->version += 1;
     const int32_t fell_back = info.fallback;
     fill_info(A, P, &info);
@@ -1187,6 +1297,27 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
     A->info = info;
     if (out) *out = info;
     return CSR_OK;
+}
+
+csr_status_t csr_classify(const double *p, const csr_config_t *cfg_in, int32_t has_long_rows,
+                          int32_t *classes, int32_t *opts) {
+    if (!p || !classes || !opts) return fail(CSR_ERR_INVALID_ARG, "NULL argument");
+    for (int k = 0; k < 6; ++k)
+        if (!(p[k] > 0.0) || !std::isfinite(p[k]))
+            return fail(CSR_ERR_INVALID_ARG, "bounds must be finite and positive");
+    csr_config_t cfg;
+    if (cfg_in) cfg = *cfg_in;
+    else csr_config_default(&cfg);
+    *classes = classify(p[0], p[1], p[2], p[3], p[4], p[5], cfg);
+    *opts = remedies(*classes, has_long_rows != 0);
+    return CSR_OK;
+}
+
+csr_status_t csr_device_bandwidth(double *hbm, double *cache, void *stream) {
+    if (!hbm || !cache) return fail(CSR_ERR_INVALID_ARG, "NULL argument");
+    int dev = 0;
+    CSR_HIP(hipGetDevice(&dev));
+    return device_bandwidth(dev, (hipStream_t)stream, hbm, cache);
 }
 
 csr_status_t csr_debug_probe(csr_matrix_t A, int32_t which, const void *d_x, void *d_y,

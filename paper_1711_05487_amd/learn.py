@@ -145,6 +145,148 @@ def label(start, count, out, base_seed=501, n_min=1e4, n_max=4e6, nnz_cap=1 << 2
     os.rmdir(tmpdir)
 
 
+def _remedies_of(pkg, cls, has_long):
+    # classes -> remedies of Table II: the bounds are chosen so that the
+    # library's rule returns exactly `cls` (each class's test made to hold
+    # or fail on its own), which keeps the map in one place (the library)
+    p = {"csr": 1.0, "mb": 1.0, "ml": 1.0, "imb": 1.0, "cmp": 1.0, "peak": 1.0}
+    cfg = pkg.default_config()
+    cfg.t_ml, cfg.t_imb, cfg.t_mb = 1.5, 1.5, 0.5
+    if cls & 4:
+        p["imb"] = 2.0
+    if cls & 2:
+        p["ml"] = 2.0
+    if cls & 1:      # P_CSR >= t_mb P_MB and P_MB < P_CMP < P_peak
+        p.update(mb=1.5, cmp=1.7, peak=2.0)
+    elif cls & 8:    # P_CMP < P_MB
+        p.update(mb=1.5, cmp=1.2, peak=2.0)
+    else:            # neither: P_CMP == P_MB (not below, not strictly between)
+        p.update(mb=1.5, cmp=1.5, peak=2.0)
+    if (cls & 1) and (cls & 8):
+        return None  # MB and CMP exclude each other under the rule
+    got, opts = pkg.classify([p[k] for k in ("csr", "mb", "ml", "imb", "cmp", "peak")],
+                             has_long, config=cfg)
+    assert got == cls, (cls, got)
+    return opts
+
+
+def profile_label(start, count, out, base_seed=501, n_min=1e4, n_max=4e6, nnz_cap=1 << 25,
+                  workers=8, calls=10, runs=3):
+    """For the threshold grid search of the profile-guided classifier
+    (Sec. III-C): per matrix, the bounds of Sec. III-B as PROFILE measures
+    them, the time of every optimization set the rule can pick (one per
+    class mask, default parameters) and, for the regret judge, the 16
+    catalogue variants timed in the same session. JSON lines, resumable."""
+    import multiprocessing as mp
+    import torch
+    import paper_1711_05487_amd as pkg
+
+    done = set()
+    if os.path.exists(out):
+        with open(out) as f:
+            for line in f:
+                try:
+                    done.add(json.loads(line)["index"])
+                except Exception:
+                    pass
+    todo = [i for i in range(start, start + count) if i not in done]
+    print(f"[bounds] {len(todo)} matrices ({len(done)} already in {out})", flush=True)
+    if not todo:
+        return
+    tmpdir = tempfile.mkdtemp(prefix="csr_bounds_", dir="/dev/shm" if os.path.isdir("/dev/shm") else None)
+    ctx = mp.get_context("spawn")
+    t0 = time.time()
+    cfg_tau = pkg.default_config()
+    with ctx.Pool(workers) as pool, open(out, "a") as fo:
+        jobs = [(i, base_seed, n_min, n_max, nnz_cap, tmpdir) for i in todo]
+        for k, (index, name, path) in enumerate(pool.imap(_gen_to_file, jobs)):
+            n, m, rp, col, val = _load(path)
+            A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+            f, isum, sorted_flag = A.inspect()
+            tau = max(cfg_tau.long_row_factor * f[3], cfg_tau.long_row_floor)
+            has_long = bool(f[2] > tau)
+            prof = A.select("profile", autotune=0, timing_calls=calls)
+            xd = torch.ones(m, dtype=torch.float64, device="cuda")
+            yd = torch.empty(n, dtype=torch.float64, device="cuda")
+            set_times = {}
+            for opts in sorted({o for o in (_remedies_of(pkg, c, has_long) for c in range(16))
+                                if o is not None}):
+                A.select("forced", forced_opts=opts)
+                A.spmv(xd, yd)
+                set_times[str(opts)] = _time_current(A, xd, yd, calls, runs)
+            cat = time_variants(A, xd, yd, calls, runs)
+            rec = {"index": index, "seed": base_seed + index, "name": name, "n": n,
+                   "nnz": len(col), "features": [float(v) for v in f], "has_long": has_long,
+                   "bounds": [prof[k] for k in ("p_csr", "p_mb", "p_ml", "p_imb", "p_cmp",
+                                                "p_peak")],
+                   "b_max": prof["b_max"], "classes": prof["classes"], "opts": prof["opts"],
+                   "set_times_ms": set_times, "catalogue_ms": cat}
+            fo.write(json.dumps(rec) + "\n")
+            fo.flush()
+            A.close()
+            print(f"[bounds] {k + 1}/{len(todo)} idx={index} {name} n={n} nnz={len(col)} "
+                  f"classes={prof['classes']} ({time.time() - t0:.0f}s)", flush=True)
+    os.rmdir(tmpdir)
+
+
+def default_thresholds():
+    import paper_1711_05487_amd as pkg
+    d = pkg.default_config()
+    return (d.t_ml, d.t_imb, d.t_mb)
+
+
+def tune_thresholds(recs, grid_ml=None, grid_imb=None, grid_mb=None):
+    """Grid search of T_ML, T_IMB and T_MB (Sec. III-C: the thresholds are the
+    classifier's hyperparameters, tuned by exhaustive grid search for the
+    highest average performance gain of the chosen optimizations): for every
+    setting, every record's classes under the library's rule, the time of
+    the set they map to, and the mean of t_plain / t_set. Returns (best
+    (t_ml, t_imb, t_mb), its mean gain, the mean gain of the given defaults)."""
+    import paper_1711_05487_amd as pkg
+    grid_ml = np.round(np.arange(1.0, 3.001, 0.05), 4) if grid_ml is None else grid_ml
+    grid_imb = np.round(np.arange(1.0, 3.001, 0.05), 4) if grid_imb is None else grid_imb
+    grid_mb = np.round(np.arange(0.5, 1.001, 0.05), 4) if grid_mb is None else grid_mb
+
+    def gain(t_ml, t_imb, t_mb):
+        cfg = pkg.default_config()
+        cfg.t_ml, cfg.t_imb, cfg.t_mb = float(t_ml), float(t_imb), float(t_mb)
+        g = []
+        for r in recs:
+            _, opts = pkg.classify(r["bounds"], r["has_long"], config=cfg)
+            st = r["set_times_ms"]
+            g.append(st["0"] / st[str(opts)])
+        return float(np.mean(g))
+
+    best, best_g = None, -1.0
+    for a in grid_ml:
+        for b in grid_imb:
+            for c in grid_mb:
+                v = gain(a, b, c)
+                if v > best_g + 1e-12:
+                    best, best_g = (float(a), float(b), float(c)), v
+    d = pkg.default_config()
+    return best, best_g, gain(d.t_ml, d.t_imb, d.t_mb)
+
+
+def profile_regret(recs, thresholds):
+    """Per record t_selected / t_best with the profile rule at the given
+    thresholds (default parameters), t_best the fastest of everything timed
+    for that matrix in the same session (16 catalogue variants and the sets
+    the rule can pick). Returns (geomean, p90, geomean speedup over plain)."""
+    import paper_1711_05487_amd as pkg
+    cfg = pkg.default_config()
+    cfg.t_ml, cfg.t_imb, cfg.t_mb = thresholds
+    ratio, speed = [], []
+    for r in recs:
+        _, opts = pkg.classify(r["bounds"], r["has_long"], config=cfg)
+        t = r["set_times_ms"][str(opts)]
+        best = min(min(r["catalogue_ms"]), min(r["set_times_ms"].values()))
+        ratio.append(t / best)
+        speed.append(r["set_times_ms"]["0"] / t)
+    gm = lambda a: float(np.exp(np.mean(np.log(a))))
+    return gm(ratio), float(np.percentile(ratio, 90)), gm(speed)
+
+
 def _time_current(A, xd, yd, calls, runs):
     import torch
     s = torch.cuda.current_stream()
@@ -249,25 +391,62 @@ def evaluate(recs, pred):
     }
 
 
+class WeightsError(ValueError):
+    """A weights file that is malformed or fails its checksum."""
+
+
+def weights_digest(params, mu, sd) -> str:
+    """SHA-256 over the model's bytes: FP32 parameters, then FP64 mu and sigma."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(params, dtype="<f4").tobytes())
+    h.update(np.ascontiguousarray(mu, dtype="<f8").tobytes())
+    h.update(np.ascontiguousarray(sd, dtype="<f8").tobytes())
+    return h.hexdigest()
+
+
 def save_weights(path, params, mu, sd, meta):
     os.makedirs(os.path.dirname(path), exist_ok=True)
+    params = np.asarray(params, dtype=np.float32)
     with open(path, "w") as f:
         json.dump({"K": K, "sizes": SIZES, "params": [float(v) for v in params],
-                   "mu": [float(v) for v in mu], "sigma": [float(v) for v in sd], "meta": meta}, f)
+                   "mu": [float(v) for v in mu], "sigma": [float(v) for v in sd],
+                   "sha256": weights_digest(params, mu, sd), "meta": meta}, f)
 
 
 def load_weights(path=WEIGHTS):
-    with open(path) as f:
-        d = json.load(f)
-    return (np.array(d["params"], dtype=np.float32), np.array(d["mu"]), np.array(d["sigma"]),
-            d.get("meta", {}))
+    """(params, mu, sigma, meta) of a saved model; WeightsError when the file
+    is malformed, has the wrong shapes or does not match its checksum."""
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        params = np.array(d["params"], dtype=np.float32)
+        mu, sd = np.array(d["mu"], dtype=np.float64), np.array(d["sigma"], dtype=np.float64)
+        digest = d["sha256"]
+    except (OSError, ValueError, KeyError, TypeError) as e:
+        raise WeightsError(f"{path}: unreadable weights ({e})") from None
+    n = sum(SIZES[i + 1] * SIZES[i] + SIZES[i + 1] for i in range(len(SIZES) - 1))
+    if params.shape != (n,) or mu.shape != (16,) or sd.shape != (16,):
+        raise WeightsError(f"{path}: wrong shapes")
+    if weights_digest(params, mu, sd) != digest:
+        raise WeightsError(f"{path}: checksum mismatch")
+    return params, mu, sd, d.get("meta", {})
 
 
-def install(path=WEIGHTS):
-    """Load the saved model into the library for select('learned')."""
+def install(path=WEIGHTS) -> bool:
+    """Load the saved model into the library for select('learned'). A
+    corrupted or unreadable file installs nothing (any model loaded before
+    is removed, so learned selection falls back to the profile-guided one)
+    and returns False."""
     import paper_1711_05487_amd as pkg
-    params, mu, sd, _ = load_weights(path)
+    try:
+        params, mu, sd, _ = load_weights(path)
+    except WeightsError as e:
+        print(f"[learn] not installing the selector model: {e}", file=sys.stderr)
+        pkg.mlp_unload()
+        return False
     pkg.mlp_load(params, K, mu, sd)
+    return True
 
 
 def main():
@@ -279,6 +458,14 @@ def main():
     a.add_argument("--out", required=True)
     a.add_argument("--workers", type=int, default=8)
     a.add_argument("--n-max", type=float, default=4e6)
+    c = sub.add_parser("bounds")
+    c.add_argument("--start", type=int, default=0)
+    c.add_argument("--count", type=int, default=400)
+    c.add_argument("--out", required=True)
+    c.add_argument("--workers", type=int, default=8)
+    c.add_argument("--n-max", type=float, default=4e6)
+    t = sub.add_parser("tune")
+    t.add_argument("--bounds", required=True)
     b = sub.add_parser("train")
     b.add_argument("--labels", required=True)
     b.add_argument("--out", default=WEIGHTS)
@@ -286,6 +473,17 @@ def main():
     args = ap.parse_args()
     if args.cmd == "label":
         label(args.start, args.count, args.out, workers=args.workers, n_max=args.n_max)
+    elif args.cmd == "bounds":
+        profile_label(args.start, args.count, args.out, workers=args.workers, n_max=args.n_max)
+    elif args.cmd == "tune":
+        recs = read_labels(args.bounds)
+        tr, te = split(recs)
+        best, g_best, g_default = tune_thresholds(tr)
+        d = default_thresholds()
+        out = {"n_train": len(tr), "n_test": len(te), "best": best, "train_gain_best": g_best,
+               "train_gain_default": g_default, "default": d,
+               "test_default": profile_regret(te, d), "test_best": profile_regret(te, best)}
+        print(json.dumps(out, indent=1), flush=True)
     else:
         recs = read_labels(args.labels)
         tr, te = split(recs)

@@ -88,3 +88,25 @@ def test_struct_layout_matches_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_classify_matches_oracle_rule():
+    """The library's profile-guided rule and class -> remedy map (host code,
+    no GPU) against the oracle's on random bounds and thresholds."""
+    import numpy as np
+    import oracle
+    import synth
+    rng_u = lambda s, n: synth.u01(s, 0, np.arange(n, dtype=np.uint64))
+    n = 4000
+    P = 10.0 ** (9 + 3 * rng_u(11, 6 * n).reshape(n, 6))
+    T = 0.5 + 2.0 * rng_u(12, 3 * n).reshape(n, 3)
+    for k in range(n):
+        cfg = pkg.default_config()
+        cfg.t_ml, cfg.t_imb, cfg.t_mb = T[k]
+        has_long = bool(k % 3 == 0)
+        cls, opts = pkg.classify(P[k], has_long, config=cfg)
+        want = oracle.classify(*P[k], t_ml=T[k, 0], t_imb=T[k, 1], t_mb=T[k, 2])
+        assert cls == want, (k, P[k], T[k])
+        assert opts == oracle.remedies(want, has_long)
+    with pytest.raises(pkg.CsrError):
+        pkg.classify([1.0, 1.0, 1.0, 0.0, 1.0, 1.0], False)

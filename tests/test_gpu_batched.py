@@ -1,7 +1,8 @@
-"""GPU parity of csr_spmv_batched (one persistent, graph-captured launch over
-many matrices): bit-identical to each matrix's own merge-path SpMV with the
-same tile size, within the FP64 bar against the oracle, and stable across
-graph replays interleaved with eager work."""
+"""GPU parity of csr_spmv_batched (one graph-captured launch over many
+matrices, each running its own plan): bit-identical to each matrix's own
+csr_spmv for every catalogue variant and for learned plans, within the FP64
+bar against the oracle, stable across graph replays interleaved with eager
+work, and correct when back-to-back calls move the vectors."""
 import numpy as np
 import pytest
 import torch
@@ -44,8 +45,8 @@ def test_batched_bit_identical_to_single_merge():
 
 
 def test_batched_bit_identical_to_single_merge_codes():
-    """Single launches on merge codes (MERGE|DELTA) against the batch, which
-    reads int32 columns: the same partition and arithmetic, the same bits."""
+    """Merge codes and window codes (MERGE|DELTA): the batch reads the same
+    codes with the same tiles as the single launches, so the same bits."""
     mats, hs = batch_mats(12)
     for k, A in enumerate(hs):
         A.select("forced", forced_opts=pkg.OPT_MERGE | pkg.OPT_DELTA, merge_items=(256, 512)[k % 2])
@@ -124,3 +125,72 @@ def test_batched_errors_and_handle_lifetime():
     pkg.spmv_batched([A, C], [x, x], [torch.empty(50, dtype=torch.float64, device="cuda"), y2])
     torch.cuda.synchronize()
     check_f64(y2.cpu().numpy(), b[2], b[3], b[4], np.ones(50), "after destroy")
+
+
+def same_as_single(mats, hs, xs, ys, what):
+    for k, A in enumerate(hs):
+        single = A.spmv(xs[k])
+        torch.cuda.synchronize()
+        n = mats[k][0]
+        assert torch.equal(ys[k][:n], single[:n]), f"{what}: matrix {k}"
+
+
+def test_batched_every_catalogue_variant_bit_identical():
+    """Every variant of the 16-entry catalogue (row split with delta codes,
+    streaming, unrolling and long rows; merge tiles with codes, window codes
+    and column blocks), several matrices per variant and several variants
+    per batch, each bit-identical to its own csr_spmv and within the FP64 bar."""
+    cat = [0, 1, 2, 4, 8, 16] + [a | b for i, a in enumerate((1, 2, 4, 8, 16))
+                                 for b in (1, 2, 4, 8, 16)[i + 1:]]
+    mats = [synth.batch_matrix(i)[1] for i in range(32)]
+    mats.append(synth.stencil27(10))
+    mats.append(synth.uniform_random(600_000, 8))     # x beyond an L2: column blocks (P|M)
+    mats.append(synth.rmat(12, 16))                   # long rows: decomposition (D|X)
+    mats.append(synth.stencil27(12))                  # short rows: window codes (D|M)
+    hs = [pkg.CsrMatrix(rp, col, val, n_cols=m) for (n, m, rp, col, val) in mats]
+    xs, ys = vectors(mats, 400)
+    seen = set()
+    for shift in range(4):
+        for k, A in enumerate(hs):
+            info = A.select("forced", forced_opts=cat[(k + 5 * shift) % 16], long_row_floor=256,
+                            long_row_factor=8.0, dynamic_rows=k % 2)
+            seen.add((info["opts"], info["window_codes"], info["column_blocks"] > 1,
+                      info["n_long_rows"] > 0))
+        pkg.spmv_batched(hs, xs, ys)
+        torch.cuda.synchronize()
+        same_as_single(mats, hs, xs, ys, f"shift {shift}")
+        for k, (n, m, rp, col, val) in enumerate(mats):
+            check_f64(ys[k][:n].cpu().numpy(), rp, col, val, xs[k].cpu().numpy(), f"batch {k}")
+    assert any(w for _, w, _, _ in seen) and any(c for _, _, c, _ in seen)
+    assert any(l for *_, l in seen)
+
+
+def test_batched_learned_plans_bit_identical():
+    from paper_1711_05487_amd import learn
+    learn.install()
+    mats = [synth.batch_matrix(i)[1] for i in range(64)]
+    hs = [pkg.CsrMatrix(rp, col, val, n_cols=m) for (n, m, rp, col, val) in mats]
+    opts = set()
+    for A in hs:
+        opts.add(A.select("learned")["opts"])
+    assert len(opts) >= 3
+    xs, ys = vectors(mats, 500)
+    pkg.spmv_batched(hs, xs, ys)
+    torch.cuda.synchronize()
+    same_as_single(mats, hs, xs, ys, "learned")
+
+
+def test_batched_back_to_back_moving_vectors():
+    """Calls issued without waiting, each with new vectors: the descriptor
+    refresh of one call must not change what the previous call reads."""
+    mats, hs = batch_mats(20)
+    for k, A in enumerate(hs):
+        A.select("forced", forced_opts=(0, 1, 8, 9, 16)[k % 5])
+    sets = [vectors(mats, 600 + 10 * r) for r in range(4)]
+    for xs, ys in sets:
+        pkg.spmv_batched(hs, xs, ys)
+    torch.cuda.synchronize()
+    for r, (xs, ys) in enumerate(sets):
+        for k, (n, m, rp, col, val) in enumerate(mats):
+            check_f64(ys[k][:n].cpu().numpy(), rp, col, val, xs[k].cpu().numpy(),
+                      f"call {r} matrix {k}")

@@ -11,6 +11,7 @@ Each case runs the learned and the profile-guided selection (Sec. III-E,
 IV) and every merge-path tile size, and compares every row with the oracle
 (FP64: |y - y_acc| <= 1e-12 (|A||x|)_i against the compensated product;
 FP32/BF16: the gamma bound of the stored values)."""
+import json
 import os
 
 import pytest
@@ -94,3 +95,43 @@ def test_reduced_precision_full_size(name, storage):
         y = spmv(A, oracle.to_f32(x))
         check_reduced(y, rp, col, val, x, storage, f"{name} {storage} {mode}")
     A.close()
+
+
+SWEEP = {}
+
+
+@pytest.mark.parametrize("index", ["int32", "delta"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("name", ["lap100", "st27_128"])
+def test_precision_sweep_against_oracle(name, storage, index):
+    """The precision sweep of the benchmark's C4 cases (merge-path tiles with
+    int32 columns, then with the MB remedy's codes), each result checked at
+    its bar and its error against the FP64 oracle reported: max and 99th
+    percentile over rows of |y - y_acc| / (|A||x|)_i. With CSRSPMV_REPORT_DIR
+    set, the table is written to precision_sweep.json there."""
+    n, m, rp, col, val = matrix(name)
+    x = xvec(name, m)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m, storage=storage)
+    opts = pkg.OPT_MERGE | (pkg.OPT_PREFETCH if index == "int32" else pkg.OPT_DELTA)
+    info = A.select("forced", forced_opts=opts)
+    if index == "delta":
+        assert info["delta_bits"] in (8, 16)
+    xin = x if storage == "f64" else oracle.to_f32(x)
+    y = spmv(A, xin)
+    A.close()
+    what = f"{name} {storage} {index}"
+    if storage == "f64":
+        check_f64(y, rp, col, val, x, what)
+        rep = oracle.rel_error_report(y, oracle.spmv_accurate(rp, col, val, x),
+                                      oracle.absax(rp, col, val, x))
+    else:
+        rep = check_reduced(y, rp, col, val, x, storage, what)
+    assert rep["zero_rows_exact"]
+    SWEEP[what] = {"index": ("window8" if info["window_codes"] else
+                             "int32" if info["delta_bits"] == 32 else f"delta{info['delta_bits']}"),
+                   "max_rel_err": rep["max"], "p99_rel_err": rep["p99"]}
+    out = os.environ.get("CSRSPMV_REPORT_DIR")
+    if out:
+        os.makedirs(out, exist_ok=True)
+        with open(os.path.join(out, "precision_sweep.json"), "w") as f:
+            json.dump(SWEEP, f, indent=1, sort_keys=True)

@@ -1,0 +1,147 @@
+"""Failure paths: injected device-allocation failures at every allocation of
+csr_create, csr_select and csr_spmv_batched return CSR_ERR_OUT_OF_MEMORY,
+leak no device memory, and leave every handle usable (a failed selection
+keeps a plan whose tables are in place, checked against the oracle); a
+corrupted selector model makes learned selection fall back to the
+profile-guided one."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1711_05487_amd as pkg
+import synth
+from paper_1711_05487_amd import learn
+from spmv_cases import check_f64, matrix
+
+pytestmark = pytest.mark.gpu
+OOM = 3
+
+
+@pytest.fixture(autouse=True)
+def disarmed():
+    pkg.debug_alloc(arm=True, fail_count=0)
+    yield
+    pkg.debug_alloc(arm=True, fail_count=0)
+
+
+def attempts_of(fn):
+    """Device allocations `fn` makes (run once with nothing failing)."""
+    pkg.debug_alloc(arm=True, fail_count=0)
+    out = fn()
+    return pkg.debug_alloc()[2], out
+
+
+def y_of(A, x):
+    y = A.spmv(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def test_create_fails_cleanly_at_every_allocation():
+    n, m, rp, col, val = matrix("st27_24")
+    live0 = pkg.debug_alloc()[:2]
+    k_max, A = attempts_of(lambda: pkg.CsrMatrix(rp, col, val))
+    A.close()
+    assert k_max >= 4 and pkg.debug_alloc()[:2] == live0
+    for k in range(k_max):
+        pkg.debug_alloc(arm=True, fail_from=k, fail_count=1)
+        with pytest.raises(pkg.CsrError) as e:
+            pkg.CsrMatrix(rp, col, val)
+        assert e.value.status == OOM, k
+        assert pkg.debug_alloc()[:2] == live0, f"leak after failing allocation {k}"
+
+
+@pytest.mark.parametrize("committed,attempt", [
+    ({"mode": "forced", "forced_opts": pkg.OPT_MERGE | pkg.OPT_DELTA},
+     {"mode": "forced", "forced_opts": pkg.OPT_MERGE | pkg.OPT_PREFETCH, "merge_items": 1024}),
+    ({"mode": "forced", "forced_opts": pkg.OPT_MERGE | pkg.OPT_PREFETCH, "merge_items": 256},
+     {"mode": "exhaustive", "timing_calls": 2}),
+    ({"mode": "forced", "forced_opts": pkg.OPT_DELTA},
+     {"mode": "forced", "forced_opts": pkg.OPT_DECOMP | pkg.OPT_UNROLL, "long_row_floor": 16,
+      "long_row_factor": 1.0, "dynamic_rows": 1}),
+])
+def test_failed_select_keeps_a_working_plan(committed, attempt):
+    """A fresh handle per failing allocation (tables a selection built once
+    stay cached on its handle, so a second attempt may allocate nothing)."""
+    n, m, rp, col, val = matrix("st27_24")
+    x = synth.vector(m, 3)
+    live0 = pkg.debug_alloc()[:2]
+
+    def committed_handle():
+        A = pkg.CsrMatrix(rp, col, val)
+        return A, A.select(**committed)
+
+    A, info0 = committed_handle()
+    check_f64(y_of(A, x), rp, col, val, x, "committed plan")
+    k_max, _ = attempts_of(lambda: A.select(**attempt))
+    A.close()
+    assert k_max >= 1
+    for k in range(k_max):
+        A, _ = committed_handle()
+        pkg.debug_alloc(arm=True, fail_from=k, fail_count=1)
+        with pytest.raises(pkg.CsrError) as e:
+            A.select(**attempt)
+        assert e.value.status == OOM, k
+        pkg.debug_alloc(arm=True, fail_count=0)
+        # the kept plan (or the plain one) runs correctly
+        check_f64(y_of(A, x), rp, col, val, x, f"after failing allocation {k}")
+        A.select(**committed)
+        assert A.info["opts"] == info0["opts"]
+        check_f64(y_of(A, x), rp, col, val, x, f"committed again after {k}")
+        A.close()
+        assert pkg.debug_alloc()[:2] == live0, f"leak after failing allocation {k}"
+
+
+def test_batched_build_failure_then_success():
+    mats = [synth.batch_matrix(i)[1] for i in range(6)]
+    live0 = pkg.debug_alloc()[:2]
+    As, xs, ys = [], [], []
+    for i, (n, m, rp, col, val) in enumerate(mats):
+        A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+        A.select("forced", forced_opts=pkg.OPT_MERGE)
+        As.append(A)
+        xs.append(torch.from_numpy(synth.vector(m, 50 + i)).cuda())
+        ys.append(torch.zeros(n, dtype=torch.float64, device="cuda"))
+    k_max, _ = attempts_of(lambda: pkg.spmv_batched(As, xs, ys))
+    for A in As:
+        A.close()
+    assert pkg.debug_alloc()[:2] == live0
+    assert k_max >= 1
+    for k in range(k_max):
+        As = [pkg.CsrMatrix(rp, col, val, n_cols=m) for (n, m, rp, col, val) in mats]
+        for A in As:
+            A.select("forced", forced_opts=pkg.OPT_MERGE)
+        pkg.debug_alloc(arm=True, fail_from=k, fail_count=1)
+        with pytest.raises(pkg.CsrError) as e:
+            pkg.spmv_batched(As, xs, ys)
+        assert e.value.status == OOM
+        pkg.debug_alloc(arm=True, fail_count=0)
+        pkg.spmv_batched(As, xs, ys)
+        torch.cuda.synchronize()
+        for (n, m, rp, col, val), x, y in zip(mats, xs, ys):
+            check_f64(y.cpu().numpy(), rp, col, val, x.cpu().numpy(), f"batched after {k}")
+        for A in As:
+            A.close()
+        assert pkg.debug_alloc()[:2] == live0, f"leak after failing batched allocation {k}"
+
+
+def test_corrupted_weights_fall_back_to_profile(tmp_path):
+    d = json.load(open(learn.WEIGHTS))
+    d["params"][100] += 0.5  # one weight changed, checksum not updated
+    bad = os.path.join(tmp_path, "bad.json")
+    json.dump(d, open(bad, "w"))
+    n, m, rp, col, val = matrix("lap100")
+    x = synth.vector(m, 101)
+    try:
+        assert learn.install() is True
+        assert not learn.install(bad)
+        A = pkg.CsrMatrix(rp, col, val)
+        info = A.select("learned")
+        assert info["fallback"] == 1 and info["classes"] >= 0  # the profile rule ran
+        check_f64(y_of(A, x), rp, col, val, x, "fallback plan")
+        A.close()
+    finally:
+        learn.install()
