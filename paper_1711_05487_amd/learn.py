@@ -464,6 +464,7 @@ def main():
     c.add_argument("--out", required=True)
     c.add_argument("--workers", type=int, default=8)
     c.add_argument("--n-max", type=float, default=4e6)
+    c.add_argument("--calls", type=int, default=32)
     t = sub.add_parser("tune")
     t.add_argument("--bounds", required=True)
     b = sub.add_parser("train")
@@ -474,7 +475,8 @@ def main():
     if args.cmd == "label":
         label(args.start, args.count, args.out, workers=args.workers, n_max=args.n_max)
     elif args.cmd == "bounds":
-        profile_label(args.start, args.count, args.out, workers=args.workers, n_max=args.n_max)
+        profile_label(args.start, args.count, args.out, workers=args.workers, n_max=args.n_max,
+                      calls=args.calls)
     elif args.cmd == "tune":
         recs = read_labels(args.bounds)
         tr, te = split(recs)

@@ -94,3 +94,31 @@ def test_learned_selection_parity_on_config_matrices():
         y = A.spmv(torch.from_numpy(x).cuda())
         torch.cuda.synchronize()
         check_f64(y.cpu().numpy(), rp, col, val, x, f"learned {name}")
+
+
+def test_regret_same_session_on_held_out_sample():
+    """The regret judge re-timed now (the profiling selector's exhaustive
+    timing as the reference, Sec. IV-D): on 24 held-out matrices of the suite
+    (N <= 2^20, to keep generation short), the learned plan and all 16
+    catalogue variants are timed in this session with the same protocol,
+    and the geometric mean of t_learned / t_best stays within 10%."""
+    import synth
+    learn.install()
+    te = [r for r in held_out() if r["n"] <= (1 << 20)]
+    te = te[:: max(1, len(te) // 24)][:24]
+    ratios = []
+    for r in te:
+        name, (n, m, rp, col, val) = synth.suite_matrix(r["index"])
+        A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+        x = torch.ones(m, dtype=torch.float64, device="cuda")
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        times = learn.time_variants(A, x, y, calls=32, runs=3)
+        info = A.select("learned")
+        assert info["fallback"] == 0
+        A.spmv(x, y)
+        t_sel = learn._time_current(A, x, y, 32, 3)
+        ratios.append(t_sel / min(times))
+        A.close()
+    gm = float(np.exp(np.mean(np.log(ratios))))
+    print("same-session t_learned / t_best:", gm, "p90", float(np.percentile(ratios, 90)), len(ratios))
+    assert gm <= 1.10

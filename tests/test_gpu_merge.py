@@ -299,27 +299,27 @@ def test_column_blocks_parity(storage):
         B.close()
 
 
-def tridiagonal(n, seed):
-    """1-D three-point matrix: about 170 rows per 512-item tile (more rows
-    than lanes) and a narrow window."""
+def far_bidiagonal(n, seed, offset=1000):
+    """a_ii and a_i,i+offset: about 127 rows per 256-item tile (more rows than
+    lanes), a column range above 2^8 (16-bit codes) and at most 256 distinct
+    columns per tile (window codes)."""
     i = np.arange(n)
-    rows = np.concatenate([i, i[1:], i[:-1]])
-    cols = np.concatenate([i, i[1:] - 1, i[:-1] + 1])
+    rows = np.concatenate([i, i[:-offset]])
+    cols = np.concatenate([i, i[:-offset] + offset])
     vals = _dyadic(np.zeros(rows.size), seed)
     return synth.from_coo(rows, cols, vals, n, n)
 
 
-@pytest.mark.parametrize("L", [256, 512])
-def test_window_codes_many_rows_per_tile(L):
-    """Window-coded tiles holding more rows than lanes (a three-point
-    matrix: about 85 or 170 rows per tile): with dyadic values and x, the
-    same bits as int32 columns on the same tiles and as the oracle."""
-    n, m, rp, col, val = tridiagonal(300_001, 12)
+def test_window_codes_many_rows_per_tile():
+    """Window-coded tiles holding more rows than lanes: with dyadic values
+    and x, the same bits as int32 columns on the same tiles and as the
+    oracle."""
+    n, m, rp, col, val = far_bidiagonal(300_001, 12)
     x = synth.dyadic_vector(m, 14)
     A = pkg.CsrMatrix(rp, col, val, n_cols=m)
-    info = A.select("forced", forced_opts=M | pkg.OPT_DELTA, merge_items=L)
+    info = A.select("forced", forced_opts=M | pkg.OPT_DELTA, merge_items=256)
     assert info["window_codes"] == 1
     y_w = run(A, x)
-    y_i = run(A, x, M | pkg.OPT_PREFETCH, L)
+    y_i = run(A, x, M | pkg.OPT_PREFETCH, 256)
     assert np.array_equal(y_w.view(np.uint64), y_i.view(np.uint64))
     assert np.array_equal(y_w, oracle.spmv(rp, col, val, x))
