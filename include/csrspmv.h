@@ -228,6 +228,30 @@ csr_status_t csr_spmv(csr_matrix_t A, const void *d_x, void *d_y, void *stream);
 csr_status_t csr_spmv_batched(int32_t count, const csr_matrix_t *h_A,
                               const void *const *h_x, void *const *h_y, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): y = A x
+ * for an FP64 CSR matrix given directly as device arrays, with no handle,
+ * no allocation and no memset. It runs the kernel of csr_spmv's plain plan
+ * with dynamic row chunks (the result is bit-identical to csr_spmv after
+ * csr_select(CSR_SEL_FORCED, forced_opts = 0, dynamic_rows = 1)); the
+ * chunk counters live in a 256-byte device array of the library, one per
+ * GPU, held until the process ends and cleared by a kernel at the start of
+ * every call.
+ *   d_row_ptr int32[n_rows + 1], d_col_idx int32[nnz], d_val double[nnz],
+ *   d_x double[n_cols], d_y double[n_rows]: device, owned by the caller.
+ * The arrays must form a valid CSR matrix (what csr_create checks); this
+ * call does not check them. Every input size csr_create accepts fits the
+ * fixed array (it holds two counters whatever the size). Calls that overlap
+ * on one GPU (e.g. on two streams) share the array and race: order them.
+ * Asynchronous on `stream`. Errors: CSR_ERR_INVALID_ARG (negative sizes,
+ * NULL arrays, x and y overlapping), CSR_ERR_UNSUPPORTED (nnz >= 2^31),
+ * CSR_ERR_DEVICE.
+ */
+csr_status_t csr_spmv_noalloc(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                              const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                              const double *d_val, const double *d_x, double *d_y, void *stream);
+
 /* Human-readable name of a status code (static storage); any int is
  * accepted ("CSR_ERR_UNKNOWN" outside the enumeration). */
 const char *csr_status_str(int32_t s);

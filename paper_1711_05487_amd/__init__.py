@@ -42,7 +42,7 @@ EXPORTS = ("csr_config_default", "csr_create", "csr_destroy", "csr_inspect", "cs
            "csr_debug_copy", "csr_debug_probe", "csr_triad", "csr_device_bandwidth",
            "csr_debug_triad", "csr_time_spmv", "csr_mlp_load", "csr_mlp_unload",
            "csr_mlp_forward", "csr_mlp_grad", "csr_mlp_train", "csr_mlp_normalize",
-           "csr_tree_load", "csr_tree_unload", "csr_jit_compile",
+           "csr_tree_load", "csr_tree_unload", "csr_jit_compile", "csr_spmv_noalloc",
            "csr_debug_alloc", "csr_classify")
 
 
@@ -129,6 +129,7 @@ def lib():
             "csr_tree_load": (ctypes.c_int, [i32, P, P, P, P, P]),
             "csr_tree_unload": (ctypes.c_int, []),
             "csr_jit_compile": (ctypes.c_int, [i32, i32, i32, i32, i32, P, sz, ctypes.POINTER(sz)]),
+            "csr_spmv_noalloc": (ctypes.c_int, [i32, i32, i64, P, P, P, P, P, P]),
             "csr_classify": (ctypes.c_int, [P, ctypes.POINTER(Config), i32, ctypes.POINTER(i32),
                                             ctypes.POINTER(i32)]),
             "csr_debug_alloc": (ctypes.c_int, [i32, i64, i64, ctypes.POINTER(i64),
@@ -280,6 +281,14 @@ class CsrMatrix:
                                ctypes.byref(d), ctypes.byref(e)))
         return {"n_rows": a.value, "n_cols": b.value, "nnz": n.value, "storage": d.value,
                 "rows_sorted": e.value}
+
+
+def spmv_noalloc(n_rows: int, n_cols: int, row_ptr, col_idx, val, x, y, stream=None):
+    """y = A x on device CSR tensors (int32 row_ptr/col_idx, float64 val, x,
+    y) without a handle and without allocating (csr_spmv_noalloc)."""
+    _check(lib().csr_spmv_noalloc(n_rows, n_cols, col_idx.numel(), _ptr(row_ptr), _ptr(col_idx),
+                                  _ptr(val), _ptr(x), _ptr(y), _stream(stream)))
+    return y
 
 
 def spmv_batched(mats, xs, ys, stream=None):

@@ -43,6 +43,9 @@ CHILD = textwrap.dedent(r'''
     assert L.csr_debug_copy(None, 0, None, 0, None, None) == 1
     assert L.csr_spmv_batched(-1, None, None, None, None) == 1
     assert L.csr_spmv_batched(0, None, None, None, None) == 0
+    assert L.csr_spmv_noalloc(-1, 4, i64(0), P(8), None, None, P(8), P(64), None) == 1
+    assert L.csr_spmv_noalloc(4, 4, i64(4), P(8), P(8), P(8), P(4096), P(4096 + 8), None) == 1
+    assert L.csr_spmv_noalloc(0, 0, i64(0), P(8), None, None, None, None, None) == 0
     assert L.csr_triad(sz(16), 1, None, None) == 1
     assert L.csr_debug_triad(P(16), P(32), P(48), i64(3), ctypes.c_double(1.0), 0, None) == 1
     assert L.csr_debug_triad(P(16), P(32), P(48), i64(4), ctypes.c_double(1.0), 2, None) == 1
