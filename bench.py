@@ -324,6 +324,7 @@ def main():
             "lanes_per_row": info["lanes_per_row"],
             "merge_items": info["merge_items"],
             "delta_bits": info["delta_bits"], "window_codes": bool(info["window_codes"]),
+            "window_runs": info["window_codes"] == 2,
             "pct_of_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
             "pct_of_triad": round(100 * gbs / triad, 2),
             "triad_gbs": round(triad, 1),
@@ -490,7 +491,8 @@ def suite(args):
                 fb = info["format_bytes"]
                 emit({"case": "C4", "config": tag, "storage": storage,
                       "index": ("int32" if info["delta_bits"] == 32 else "window8"
-                                if info["window_codes"] else f"delta{info['delta_bits']}"),
+                                if info["window_codes"] else f"delta{info['delta_bits']}")
+                      + (" runs" if info["window_codes"] == 2 else ""),
                       "opts": [nm for bit, nm in pkg.OPT_NAMES.items() if info["opts"] & bit],
                       "ms": round(t, 5), "kernel_ms": round(k_ms, 5), "format_bytes": fb,
                       "gbs": round(fb / (t * 1e-3) / 1e9, 1),

@@ -83,9 +83,12 @@ typedef enum {
 
 /* Tunables; csr_config_default() fills the defaults. */
 typedef struct {
-    double t_ml;             /* ML threshold on P_ML / P_CSR (paper: 1.25) */
-    double t_imb;            /* IMB threshold on P_IMB / P_CSR (paper: 1.24) */
-    double t_mb;             /* MB: P_CSR >= t_mb * P_MB reads "P_CSR ~ P_MB" */
+    double t_ml;             /* ML threshold on P_ML / P_CSR (paper, on KNC: 1.25; default
+                                1.0, from the grid search over the suite on MI355X) */
+    double t_imb;            /* IMB threshold on P_IMB / P_CSR (paper, on KNC: 1.24;
+                                default 1.0, from the same grid search) */
+    double t_mb;             /* MB: P_CSR >= t_mb * P_MB reads "P_CSR ~ P_MB" (default 0.5,
+                                from the same grid search) */
     double long_row_factor;  /* a row is long if nnz_i > max(factor*nnz_avg, long_row_floor) */
     int32_t long_row_floor;
     int32_t forced_opts;     /* CSR_SEL_FORCED: mask of CSR_OPT_* */
@@ -116,7 +119,18 @@ typedef struct {
                                 compiled at run time (merge_items also accepts any multiple of
                                 256 up to 2048; sizes other than 256, 512 and 1024 are compiled
                                 on first use) */
-    int32_t reserved;
+    int32_t window_runs;     /* 1 = window-coded merge plans replace the per-tile dictionary
+                                by a 64-byte record of at most 14 runs of consecutive
+                                columns when every tile's window fits one (the same bits;
+                                0, the default, keeps the dictionary; the autotuner tries
+                                both) */
+    int32_t remedy_map;      /* classes -> optimizations: 0 = the paper's Table II (MB delta
+                                codes, ML prefetch, IMB decomposition or merge path, CMP
+                                unrolling); 1 (default) = as they pay on MI355X (measured over
+                                the synthetic suite): MB delta codes, ML the merge path, IMB
+                                the merge path with compressed codes (decomposition when long
+                                rows exist), CMP nothing */
+    int32_t reserved2;
 } csr_config_t;
 
 /* What csr_select decided and what it cost. */
@@ -135,7 +149,9 @@ typedef struct {
     int32_t window_codes;    /* 1: the merge path's column codes are window ranks (delta_bits
                                 8): each row-aligned tile stores its distinct columns as
                                 16-bit offsets from its smallest one, each nonzero the 8-bit
-                                rank of its column among them */
+                                rank of its column among them; 2: the same ranks, with each
+                                tile's distinct columns stored as at most 14 runs of
+                                consecutive columns (a 64-byte record per tile) */
     int32_t column_blocks;   /* > 1: the merge path runs once per column slab of at most
                                 2 MiB of x, each pass adding into y (merge plans without
                                 codes, when x outgrows one XCD's L2, rows are short and
@@ -166,7 +182,7 @@ typedef struct {
     int32_t reserved;
 } csr_features_t;
 
-/* Fill *cfg with the defaults (t_ml 1.25, t_imb 1.24, t_mb 0.8,
+/* Fill *cfg with the defaults (t_ml 1.0, t_imb 1.0, t_mb 0.5, remedy_map 1,
  * long_row_factor 32, long_row_floor 4096, autotune 1, timing_calls 32,
  * ml_partitions 0, t_ml_part 1.5, jit_tiles 0). */
 void csr_config_default(csr_config_t *cfg);
@@ -268,7 +284,7 @@ csr_status_t csr_query(csr_matrix_t A, int32_t *n_rows, int32_t *n_cols, int64_t
  * Sec. IV-D): compiles the merge-path kernel for value storage `storage`,
  * tile size `merge_items` (a multiple of 256 from 256 to 2048), index mode
  * `index_mode` (0 int32 columns, 1 16-bit and 2 8-bit merge codes, 3 window
- * codes), non-temporal loads (`streaming`, int32 columns only) and row-aligned
+ * codes, 4 window codes with run records), non-temporal loads (`streaming`, int32 columns only) and row-aligned
  * tiles (`row_aligned`; required by window codes) with hipRTC for gfx950, from
  * the kernel sources built into the library, and copies the code object (an
  * AMDGPU ELF) to host memory `code` of `bytes` bytes (*needed receives its
@@ -308,7 +324,10 @@ csr_status_t csr_jit_compile(int32_t storage, int32_t merge_items, int32_t index
  *         ran work in the instrumented baseline int64[n_cu] (wall-clock
  *         ticks, by compute-unit id), 18 double[3]: the HBM and the cache
  *         triad bandwidth (B/s; B_max is the second when the plan's bytes
- *         fit in the 256 MB Infinity Cache) and the span clock (ticks/s)
+ *         fit in the 256 MB Infinity Cache) and the span clock (ticks/s);
+ *         19 run-window records int32[T][16] (per tile: smallest column,
+ *         window entries | runs << 16, then per run its first column minus
+ *         the smallest | its length << 16, zero past the last run)
  * Returns CSR_ERR_INVALID_ARG if `bytes` differs from the array's size
  * (*needed receives that size when non-NULL) or the array does not exist.
  * Synchronizes `stream`.

@@ -286,6 +286,44 @@ def window_codes(tj, col, maxw: int = 256):
     return base[:T], wlen[:T], dct[:T], codes[:col.size]
 
 
+def window_runs(tj, col, max_runs: int = 14):
+    """Run windows of row-aligned merge tiles (MB + ML remedies, Table II):
+    the window of a tile (its distinct columns, ascending: u_0 < ... < u_{m-1},
+    at most 256 of them within a range below 2^16) written as maximal runs of
+    consecutive columns. Per tile a record of 16 int32 words: [0] = u_0 (0
+    for a tile without nonzeros), [1] = m | (number of runs << 16), [2 + r] =
+    (first column of run r - u_0) | (length of run r << 16), zero past the
+    last run; per nonzero the 8-bit rank of its column in the window (as for
+    window codes). Returns (records of shape (T, 16), codes), or None when
+    some tile has more than max_runs runs, more than 256 distinct columns or
+    a range of 2^16 or more."""
+    assert 1 <= max_runs <= 14, "a record holds at most 14 runs"
+    tj = np.asarray(tj, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    T = tj.size - 1
+    rec = np.zeros((max(T, 0), 16), dtype=np.int64)
+    codes = np.zeros(col.size, dtype=np.uint8)
+    for t in range(T):
+        c = col[tj[t]:tj[t + 1]]
+        if c.size == 0:
+            continue
+        u = np.unique(c)
+        if u.size > 256 or u[-1] - u[0] >= 65536:
+            return None
+        # a run starts at the first column and wherever the next column is
+        # not the previous one plus one
+        starts = [0] + [k for k in range(1, u.size) if u[k] != u[k - 1] + 1]
+        if len(starts) > max_runs:
+            return None
+        ends = starts[1:] + [u.size]
+        rec[t, 0] = u[0]
+        rec[t, 1] = u.size | (len(starts) << 16)
+        for r, (a, b) in enumerate(zip(starts, ends)):
+            rec[t, 2 + r] = (u[a] - u[0]) | ((b - a) << 16)
+        codes[tj[t]:tj[t + 1]] = np.searchsorted(u, c)
+    return rec.astype(np.int32), codes
+
+
 def merge_tiles(rp, L: int, slack: int = 0):
     """(i_t, j_t) for t = 0..T of the merge path of the row ends with the
     nonzeros, cut every L items; with slack s > 0 cut every L - s items and
@@ -457,18 +495,32 @@ OPT_DELTA, OPT_PREFETCH, OPT_DECOMP, OPT_MERGE, OPT_UNROLL = 1, 2, 4, 8, 16
 OPT_ORDER = (OPT_DELTA, OPT_PREFETCH, OPT_DECOMP, OPT_MERGE, OPT_UNROLL)
 
 
-def remedies(classes: int, has_long_rows: bool) -> int:
-    """Class set -> optimization set (Sec. III-E, Table II), applied jointly.
+def remedies(classes: int, has_long_rows: bool, remedy_map: int = 0) -> int:
+    """Class set -> optimization set, applied jointly.
 
-    MB  -> delta-compressed column indices (+ wide loads)
-    ML  -> prefetched x gathers
-    IMB -> long-row decomposition when long rows exist, else the nnz-balanced
-           merge-path split (the GPU counterpart of the runtime-chosen schedule)
-    CMP -> unrolling with several rows per wavefront (+ wide loads)
+    remedy_map 0 follows Sec. III-E, Table II:
+      MB  -> delta-compressed column indices (+ wide loads)
+      ML  -> prefetched x gathers
+      IMB -> long-row decomposition when long rows exist, else the nnz-balanced
+             merge-path split (the GPU counterpart of the runtime-chosen schedule)
+      CMP -> unrolling with several rows per wavefront (+ wide loads)
+    remedy_map 1 is the reading for a GPU on which prefetching and unrolling
+    do not pay (Sec. III-C leaves the map to be fixed per platform):
+      MB  -> delta-compressed column indices
+      ML  -> the merge-path split (its tiles gather x through one window)
+      IMB -> decomposition when long rows exist, else merge path with codes
+      CMP -> nothing
     """
+    assert remedy_map in (0, 1)
     o = 0
     if classes & CLS_MB:
         o |= OPT_DELTA
+    if remedy_map == 1:
+        if classes & CLS_ML:
+            o |= OPT_MERGE
+        if classes & CLS_IMB:
+            o |= OPT_DECOMP if has_long_rows else (OPT_MERGE | OPT_DELTA)
+        return o
     if classes & CLS_ML:
         o |= OPT_PREFETCH
     if classes & CLS_IMB:

@@ -31,7 +31,7 @@ SELECT = {"plain": SEL_PLAIN, "profile": SEL_PROFILE, "learned": SEL_LEARNED,
  DEBUG_MERGE_CODES, DEBUG_TILE_BASE, DEBUG_WINDOW_DICT, DEBUG_WINDOW_LEN,
  DEBUG_WINDOW_CODES, DEBUG_CB_ROWPTR, DEBUG_CB_COL, DEBUG_CB_VAL,
  DEBUG_MLP_BOUNDS, DEBUG_MLP_TIMES, DEBUG_MLP_RATIOS, DEBUG_IMB_SPANS,
- DEBUG_BANDWIDTH) = range(19)
+ DEBUG_BANDWIDTH, DEBUG_WINDOW_RUNS) = range(20)
 
 STATUS = ["CSR_OK", "CSR_ERR_INVALID_ARG", "CSR_ERR_INVALID_MATRIX", "CSR_ERR_OUT_OF_MEMORY",
           "CSR_ERR_DEVICE", "CSR_ERR_UNSUPPORTED", "CSR_ERR_NOT_READY"]
@@ -60,7 +60,8 @@ class Config(ctypes.Structure):
                 ("timing_calls", ctypes.c_int32), ("rows_in_flight", ctypes.c_int32),
                 ("exhaustive_set", ctypes.c_int32), ("dynamic_rows", ctypes.c_int32),
                 ("ml_partitions", ctypes.c_int32), ("t_ml_part", ctypes.c_double),
-                ("jit_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("jit_tiles", ctypes.c_int32), ("window_runs", ctypes.c_int32),
+                ("remedy_map", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):

@@ -214,6 +214,9 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
             arr[2] = A->wcodes.p;
             arr[6] = A->wdict.p;
             arr[7] = A->wlen.p;
+        } else if (P.idx == IDX_R8) {
+            arr[2] = A->wcodes.p;
+            arr[7] = A->wruns.p;  // the tiles' run records
         } else if (P.idx != IDX_I32) {
             arr[2] = A->mcodes.p;
         }
@@ -317,9 +320,13 @@ extern "C" {
 void csr_config_default(csr_config_t *cfg) {
     if (!cfg) return;
     std::memset(cfg, 0, sizeof(*cfg));
-    cfg->t_ml = 1.25;
-    cfg->t_imb = 1.24;
-    cfg->t_mb = 0.8;
+    // the profile rule's thresholds and class -> remedy map as tuned on
+    // MI355X by grid search (Sec. III-C) over the synthetic suite's
+    // training split; the paper's KNC values were 1.25 and 1.24
+    cfg->t_ml = 1.0;
+    cfg->t_imb = 1.0;
+    cfg->t_mb = 0.5;
+    cfg->remedy_map = 1;
     cfg->long_row_factor = 32.0;
     cfg->long_row_floor = 4096;
     cfg->forced_opts = 0;
@@ -569,6 +576,12 @@ csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t by
         if (A->cb_B > 0) {
             src = A->cb_val.p;
             n = storage_bytes(A->storage) * (size_t)A->nnz;
+        }
+        break;
+    case 19:  // run-window records
+        if (A->wruns_state == 1) {
+            src = A->wruns.p;
+            n = sizeof(int32_t) * kRunWords * (size_t)A->n_tiles;
         }
         break;
     case 14:

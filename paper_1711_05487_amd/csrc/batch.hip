@@ -130,6 +130,9 @@ void plan_classes(BatchPlan &B, const csr_matrix_t *h_A, const void *const *x, v
                 M.codes = A->wcodes.p;
                 M.wdict = A->wdict.as<uint16_t>();
                 M.wlen = A->wlen.as<int32_t>();
+            } else if (P.idx == IDX_R8) {
+                M.codes = A->wcodes.p;
+                M.wlen = A->wruns.as<int32_t>();  // the tiles' run records
             } else if (P.idx != IDX_I32) {
                 M.codes = A->mcodes.p;
             }

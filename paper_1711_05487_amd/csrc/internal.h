@@ -109,6 +109,9 @@ struct csr_matrix_s {
     csr::DevBuf wcodes;            // window codes: per-nonzero rank in its tile's window (uint8)
     int32_t wcode_state = 0;       // 1 valid, -1 not eligible, 0 not built
     int32_t wcodes_L = 0;          // tile size the window codes were built for
+    csr::DevBuf wruns;             // run windows: per tile kRunWords int32 (IDX_R8)
+    int32_t wruns_state = 0;       // 1 valid, -1 not eligible, 0 not built
+    int32_t wruns_L = 0;           // tile size the run windows were built for
     int64_t wdict_entries = 0;     // sum of the window lengths
     // column blocks (ML remedy on the merge path): cb_B slabs of cb_width columns
     int32_t cb_B = 0;              // 0: not built
@@ -184,6 +187,11 @@ hipError_t launch_merge_encode(const int32_t *col, const int32_t *tile_j, int64_
 // base[t], wlen[t] = distinct columns, codes[j] = rank of col[j]; *max_m =
 // the largest window (tiles over kWindowMax write nothing). Every tile's
 // column range must be below 2^16.
+// Run windows: rec[t * kRunWords ...] = tile t's window (dict, wlen, base)
+// as runs of consecutive columns; *max_runs = the most runs of any tile
+// (records of tiles over kRunsMax hold their first kRunsMax runs).
+hipError_t launch_window_runs(const uint16_t *dict, const int32_t *wlen, const int32_t *base,
+                              int64_t n_tiles, int32_t *rec, int32_t *max_runs, hipStream_t s);
 hipError_t launch_window_encode(const int32_t *col, const int32_t *tile_j, const int32_t *base,
                                 int64_t n_tiles, uint16_t *dict, int32_t *wlen, uint8_t *codes,
                                 int32_t *max_m, hipStream_t s);

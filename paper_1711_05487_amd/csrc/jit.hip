@@ -52,8 +52,9 @@ csr_status_t check_instance(int storage, int ipt, int idx, bool aln) {
         return fail(CSR_ERR_INVALID_ARG, "unknown value storage");
     if (!merge_items_supported(64 * ipt))
         return fail(CSR_ERR_INVALID_ARG, "merge tile size must be 64 * IPT, IPT = 4, 8, ..., 32");
-    if (idx < IDX_I32 || idx > IDX_W8) return fail(CSR_ERR_INVALID_ARG, "unknown index mode");
-    if (idx == IDX_W8 && !aln) return fail(CSR_ERR_INVALID_ARG, "window codes need row-aligned tiles");
+    if (idx < IDX_I32 || idx > IDX_R8) return fail(CSR_ERR_INVALID_ARG, "unknown index mode");
+    if ((idx == IDX_W8 || idx == IDX_R8) && !aln)
+        return fail(CSR_ERR_INVALID_ARG, "window codes need row-aligned tiles");
     if (idx != IDX_I32 && !merge_codes_fit(64 * ipt, idx == IDX_D16 ? 2 : 1))
         return fail(CSR_ERR_UNSUPPORTED, "merge codes do not form whole loads at this tile size");
     return CSR_OK;

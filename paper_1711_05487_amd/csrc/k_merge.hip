@@ -122,6 +122,9 @@ hipError_t go_ipt(bool nt, bool x32, int idx, const MergeArgs &a, hipStream_t s)
     case IDX_W8:
         if constexpr (ALN) return go<IPT, true, false, IDX_W8, true>(a, s);
         else return hipErrorInvalidValue;  // window codes need row-aligned tiles
+    case IDX_R8:
+        if constexpr (ALN) return go<IPT, true, false, IDX_R8, true>(a, s);
+        else return hipErrorInvalidValue;
     default: break;
     }
     if (nt)

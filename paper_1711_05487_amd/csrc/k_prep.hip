@@ -326,6 +326,34 @@ __global__ __launch_bounds__(kBlock) void k_fill_row_index(const int32_t *__rest
     }
 }
 
+// Run windows: tile t's window dict[t][0 .. wlen[t]) (ascending offsets from
+// its smallest column base[t]) cut into maximal runs of consecutive
+// offsets, written as a record of kRunWords words (zero past the last run);
+// one thread per tile.
+__global__ __launch_bounds__(kBlock) void k_window_runs(const uint16_t *__restrict__ dict,
+                                                        const int32_t *__restrict__ wlen,
+                                                        const int32_t *__restrict__ base,
+                                                        int64_t n_tiles, int32_t *__restrict__ rec,
+                                                        int32_t *__restrict__ max_runs) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint16_t *d = dict + t * kWindowMax;
+    const int32_t m = wlen[t];
+    int32_t *r = rec + t * kRunWords;
+    int32_t nr = 0, k0 = 0;
+    for (int32_t k = 1; k <= m; ++k) {
+        if (k == m || d[k] != d[k - 1] + 1) {  // run [k0, k) ends here
+            if (nr < kRunsMax) r[2 + nr] = (int32_t)((uint32_t)d[k0] | ((uint32_t)(k - k0) << 16));
+            ++nr;
+            k0 = k;
+        }
+    }
+    for (int32_t q = nr < kRunsMax ? nr : kRunsMax; q < kRunsMax; ++q) r[2 + q] = 0;
+    r[0] = m > 0 ? base[t] : 0;
+    r[1] = (int32_t)((uint32_t)m | ((uint32_t)nr << 16));
+    atomicMax(max_runs, nr);
+}
+
 // Triad for B_max: one 16-byte vector per array per thread. STREAM: the
 // non-temporal loads and stores of the HBM probe; otherwise ordinary
 // accesses, which a working set smaller than the Infinity Cache serves from
@@ -470,6 +498,14 @@ hipError_t launch_convert_values(const double *src, void *dst, int64_t n, int st
     if (n == 0) return hipSuccess;
     const unsigned g = grid_for(n, kBlock * 4, 256 * 32);
     hipLaunchKernelGGL(k_convert, dim3(g), dim3(kBlock), 0, s, src, dst, n, storage);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_runs(const uint16_t *dict, const int32_t *wlen, const int32_t *base,
+                              int64_t n_tiles, int32_t *rec, int32_t *max_runs, hipStream_t s) {
+    if (n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_window_runs, dim3((unsigned)((n_tiles + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, dict, wlen, base, n_tiles, rec, max_runs);
     return hipGetLastError();
 }
 

@@ -16,8 +16,16 @@ constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies
 
 // IDX_W8: window codes of row-aligned merge tiles (8-bit rank of the column
 // among the tile's distinct columns; the tile's window dictionary maps it back)
-enum IdxMode { IDX_I32 = 0, IDX_D16 = 1, IDX_D8 = 2, IDX_W8 = 3 };
+// IDX_R8: the same ranks, with each tile's window given as at most
+// kRunsMax runs of consecutive columns in a record of kRunWords int32 words
+// ([0] the smallest column, [1] entries | runs << 16, [2 + r] run r's first
+// column minus [0] | its length << 16), which the tile reads with scalar
+// loads before any vector load, so its x window is loaded together with
+// the tile's values instead of after a dictionary load
+enum IdxMode { IDX_I32 = 0, IDX_D16 = 1, IDX_D8 = 2, IDX_W8 = 3, IDX_R8 = 4 };
 constexpr int kWindowMax = 256;  // window entries per tile (8-bit ranks)
+constexpr int kRunWords = 16;
+constexpr int kRunsMax = kRunWords - 2;
 
 // Logical block of this workgroup in a launch of 8 * per_xcd workgroups:
 // workgroups are dispatched to the XCDs round-robin, so logical block

@@ -133,6 +133,7 @@ template <int IDX> struct MergeCol { using type = int32_t; };
 template <> struct MergeCol<IDX_D16> { using type = uint16_t; };
 template <> struct MergeCol<IDX_D8> { using type = uint8_t; };
 template <> struct MergeCol<IDX_W8> { using type = uint8_t; };
+template <> struct MergeCol<IDX_R8> { using type = uint8_t; };
 
 // What a lane holds for one tile between issuing its loads and reducing it.
 template <int S, int IPT, int IDX = IDX_I32> struct MergeTileRegs {
@@ -151,6 +152,7 @@ template <int S, int IPT, int IDX = IDX_I32> struct MergeTileRegs {
     CV cv[NIT];              // columns (or codes) of the tile's window
     int32_t wl;              // window codes: entries of the tile's x window
     typename VecOfU<uint16_t, 4>::type dv;  // window codes: entries [4 lane, 4 lane + 4)
+    typename VecOf<typename St<S>::X, 4>::type wx;  // run windows: x at entries [4 lane, 4 lane + 4)
 };
 
 // Stage 1: issue the tile's loads. The window [j0, j0 + L) starts at the
@@ -397,13 +399,13 @@ __device__ __forceinline__ typename VecOf<typename St<S>::X, 4>::type merge_wind
     return w;
 }
 
-template <int S, int IPT, class LDS>
+template <int S, int IPT, class LDS, int IDX = IDX_W8>
 __device__ __forceinline__ void merge_window_stage(
-    const MergeTileRegs<S, IPT, IDX_W8> &R, const typename VecOf<typename St<S>::X, 4>::type &w,
+    const MergeTileRegs<S, IPT, IDX> &R, const typename VecOf<typename St<S>::X, 4>::type &w,
     LDS &lds,
-    typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX_W8>::NIT][MergeTileRegs<S, IPT, IDX_W8>::VEC]) {
+    typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC]) {
     using X = typename St<S>::X;
-    constexpr int VEC = MergeTileRegs<S, IPT, IDX_W8>::VEC, NIT = MergeTileRegs<S, IPT, IDX_W8>::NIT;
+    constexpr int VEC = MergeTileRegs<S, IPT, IDX>::VEC, NIT = MergeTileRegs<S, IPT, IDX>::NIT;
     static_assert(kWindowMax * sizeof(X) <= sizeof(lds.prod), "the window fits the product buffer");
     X *s_win = reinterpret_cast<X *>(lds.prod);
     *reinterpret_cast<typename VecOf<X, 4>::type *>(s_win + 4 * threadIdx.x) = w;
@@ -423,6 +425,88 @@ __device__ __forceinline__ void merge_gather_window(const MergeTileRegs<S, IPT, 
                                                     typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX_W8>::NIT]
                                                                           [MergeTileRegs<S, IPT, IDX_W8>::VEC]) {
     merge_window_stage<S, IPT>(R, merge_window_load<S, IPT>(R, x, n_cols), lds, xs);
+}
+
+// Run windows (row-aligned tiles, IDX_R8): the tile's record (its smallest
+// column, window length, runs of consecutive columns) is read with scalar
+// loads first; then every vector load of the tile is issued at once: row
+// ends, rank codes, the x window (lane l: entries 4l .. 4l+3, each located
+// in its run by the wave-uniform run table), values. The x window goes to
+// LDS as for window codes, and every nonzero reads x there by its rank.
+template <int S, int IPT>
+__device__ __forceinline__ void merge_issue_runs(int64_t t, const int32_t *__restrict__ rp,
+                                                 const uint8_t *__restrict__ codes,
+                                                 const typename St<S>::V *__restrict__ val,
+                                                 const typename St<S>::X *__restrict__ x,
+                                                 int32_t n_cols, const int32_t *__restrict__ tile_i,
+                                                 const int32_t *__restrict__ tile_j,
+                                                 const int32_t *__restrict__ runs,
+                                                 MergeTileRegs<S, IPT, IDX_R8> &R) {
+    using Rg = MergeTileRegs<S, IPT, IDX_R8>;
+    using V = typename St<S>::V;
+    using X = typename St<S>::X;
+    constexpr int VEC = Rg::VEC, NIT = Rg::NIT;
+    constexpr int BS = kMergeBlock;
+    constexpr int STEP = BS * VEC;
+    static_assert(kWindowMax == 4 * kMergeBlock, "four window entries per lane");
+    const uint32_t tid = threadIdx.x;
+    // the whole record at once (one 64-byte scalar load; records are 64-byte
+    // aligned), so no load waits inside the run loop below
+    using I4 = typename VecOf<int32_t, 4>::type;
+    const I4 *r4 = reinterpret_cast<const I4 *>(runs + t * kRunWords);
+    const I4 q0 = r4[0], q1 = r4[1], q2 = r4[2], q3 = r4[3];
+    const int32_t rec[kRunWords] = {q0[0], q0[1], q0[2], q0[3], q1[0], q1[1], q1[2], q1[3],
+                                    q2[0], q2[1], q2[2], q2[3], q3[0], q3[1], q3[2], q3[3]};
+    static_assert(kRunWords == 16, "four 16-byte words per record");
+    R.i0 = tile_i[t];
+    R.i1 = tile_i[t + 1];
+    R.j0 = tile_j[t];
+    R.j1 = tile_j[t + 1];
+    R.base = rec[0];
+    R.wl = rec[1] & 0xFFFF;
+    const uint32_t nwin = R.j1 > R.j0 ? ((uint32_t)(R.j1 - 1 - R.j0) & ~(uint32_t)(VEC - 1)) + VEC : 0u;
+    const uint32_t nre = (uint32_t)(R.i1 - R.i0);
+    const auto rr = buffer_range(rp + R.i0 + 1, nre * (uint32_t)sizeof(int32_t));
+    if (nre <= (uint32_t)BS) {
+        R.re[0] = buffer_load<int32_t, false>(rr, tid * 4u, 0u);
+#pragma unroll
+        for (int q = 1; q < IPT; ++q) R.re[q] = 0;
+    } else {
+#pragma unroll
+        for (int q = 0; q < IPT; ++q)
+            R.re[q] = buffer_load<int32_t, false>(rr, tid * 4u, (uint32_t)(q * BS * 4));
+    }
+    const auto rc = buffer_range(codes + R.j0, nwin);
+#pragma unroll
+    for (int it = 0; it < NIT; ++it)
+        R.cv[it] = buffer_load<typename Rg::CV, true>(rc, tid * (uint32_t)VEC, (uint32_t)(it * STEP));
+    // window entry k = 4 tid + q lies in run r when k - (entries of runs
+    // before r) < length of r; the words past the last run are zero (length
+    // 0), so every run slot can be tested; entries past the window read
+    // nothing
+    uint32_t off[4] = {0x80000000u, 0x80000000u, 0x80000000u, 0x80000000u};
+    uint32_t before = 0;
+#pragma unroll
+    for (int r = 0; r < kRunsMax; ++r) {
+        const uint32_t w = (uint32_t)rec[2 + r];
+        const uint32_t first = w & 0xFFFFu, len = w >> 16;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t d = 4u * tid + (uint32_t)q - before;
+            if (d < len) off[q] = (first + d) * (uint32_t)sizeof(X);
+        }
+        before += len;
+    }
+    // an entry is below 2^16: the range never needs more than 2^16 elements
+    const uint32_t nx = (uint32_t)min(n_cols - R.base, 1 << 16);
+    const auto rx = buffer_range(x + R.base, nx * (uint32_t)sizeof(X));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) R.wx[q] = buffer_load<X, false>(rx, off[q], 0u);
+    const auto rv = buffer_range(val + R.j0, nwin * (uint32_t)sizeof(V));
+#pragma unroll
+    for (int it = 0; it < NIT; ++it)
+        R.vv[it] = buffer_load<typename Rg::VV, true>(rv, tid * (uint32_t)(VEC * sizeof(V)),
+                                                     (uint32_t)(it * STEP * sizeof(V)));
 }
 
 // Sum of s[b .. e) in index order, starting from +0.
@@ -676,8 +760,20 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
                                            const uint16_t *__restrict__ wdict = nullptr,
                                            const int32_t *__restrict__ wlen = nullptr,
                                            bool acc = false) {
-    static_assert(IDX != IDX_W8 || ALN, "window codes need row-aligned tiles");
-    if constexpr (IDX == IDX_W8) {
+    static_assert((IDX != IDX_W8 && IDX != IDX_R8) || ALN, "window codes need row-aligned tiles");
+    if constexpr (IDX == IDX_R8) {
+        // `wlen` holds the tiles' run records
+        (void)carry;
+        (void)n_rows;
+        (void)tile_base;
+        (void)wdict;
+        MergeTileRegs<S, IPT, IDX> R;
+        merge_issue_runs<S, IPT>(t, rp, static_cast<const uint8_t *>(cols), val, x, n_cols, tile_i,
+                                 tile_j, wlen, R);
+        typename St<S>::X xs[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC];
+        merge_window_stage<S, IPT, LDS, IDX>(R, R.wx, lds, xs);
+        merge_finish_rows<S, IPT, LDS, IDX>(R, xs, y, lds, acc);
+    } else if constexpr (IDX == IDX_W8) {
         (void)carry;
         (void)n_rows;
         MergeTileRegs<S, IPT, IDX> R;

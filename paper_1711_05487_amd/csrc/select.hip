@@ -45,7 +45,9 @@ int catalogue_id(int32_t opts) {
 double plan_bytes(const csr_matrix_s *A, const Plan &P) {
     const double vb = (double)storage_bytes(A->storage);
     const double xb = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
-    const double ib = P.idx == IDX_D16 ? 2.0 : (P.idx == IDX_D8 || P.idx == IDX_W8) ? 1.0 : 4.0;
+    const double ib = P.idx == IDX_D16                                        ? 2.0
+                      : (P.idx == IDX_D8 || P.idx == IDX_W8 || P.idx == IDX_R8) ? 1.0
+                                                                                : 4.0;
     double b = (double)A->nnz * (vb + ib) + 4.0 * (A->n_rows + 1) + xb * A->n_cols +
                xb * A->n_rows;
     if (P.opts & CSR_OPT_MERGE) {
@@ -54,9 +56,11 @@ double plan_bytes(const csr_matrix_s *A, const Plan &P) {
         const double T = (double)A->n_tiles;
         const double ab = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
         b += 2.0 * 4.0 * (T + 1) + (A->tiles_fixup ? 2.0 * ab * T : 0.0);
-        if (P.idx != IDX_I32) b += 4.0 * T;
-        // window codes: the dictionaries (window entries read) and lengths
+        if (P.idx != IDX_I32 && P.idx != IDX_R8) b += 4.0 * T;
+        // window codes: the dictionaries (window entries read) and lengths;
+        // run windows: one record per tile
         if (P.idx == IDX_W8) b += 2.0 * (double)A->wdict_entries + 4.0 * T;
+        if (P.idx == IDX_R8) b += 4.0 * kRunWords * T;
         if (P.cblocks > 0) {
             // column blocks: every pass reads its row pointers and tile table
             // and writes y (the later ones read it back); the single pass's
@@ -80,8 +84,10 @@ void fill_info(const csr_matrix_s *A, const Plan &P, csr_plan_info_t *info) {
     info->lanes_per_row = P.G;
     info->merge_items = P.L;
     info->merge_slack = (P.opts & CSR_OPT_MERGE) ? (int32_t)A->tiles_slack : 0;
-    info->delta_bits = P.idx == IDX_D16 ? 16 : (P.idx == IDX_D8 || P.idx == IDX_W8) ? 8 : 32;
-    info->window_codes = P.idx == IDX_W8;
+    info->delta_bits = P.idx == IDX_D16                                        ? 16
+                       : (P.idx == IDX_D8 || P.idx == IDX_W8 || P.idx == IDX_R8) ? 8
+                                                                                 : 32;
+    info->window_codes = P.idx == IDX_W8 ? 1 : P.idx == IDX_R8 ? 2 : 0;
     info->column_blocks = P.cblocks;
     info->dynamic_rows = P.dyn;
     info->jit = P.jit;
@@ -136,6 +142,8 @@ csr_status_t build_tiles(csr_matrix_s *A, int L, hipStream_t s) {
     A->mcodes_L = 0;
     A->wcodes_L = 0;
     A->wcode_state = 0;
+    A->wruns_L = 0;
+    A->wruns_state = 0;
     csr_status_t st;
     if ((st = A->tile_i.alloc(sizeof(int32_t) * (T + 1))) != CSR_OK) return st;
     if ((st = A->tile_j.alloc(sizeof(int32_t) * (T + 1))) != CSR_OK) return st;
@@ -244,6 +252,38 @@ csr_status_t build_window_codes(csr_matrix_s *A, hipStream_t s) {
     A->wdict_entries = sum;
     A->wcodes_L = A->tiles_L;
     A->wcode_state = 1;
+    return CSR_OK;
+}
+
+// Run windows (IDX_R8): the window codes' dictionaries cut into runs of
+// consecutive columns, one record per tile; eligible when no tile has more
+// than kRunsMax runs (the codes are the window codes' ranks).
+csr_status_t build_window_runs(csr_matrix_s *A, hipStream_t s) {
+    if (A->wruns_L == A->tiles_L && A->wruns_state != 0) return CSR_OK;
+    csr_status_t st;
+    if ((st = build_window_codes(A, s)) != CSR_OK) return st;
+    A->wruns_L = 0;  // not valid until the end
+    A->wruns_state = 0;
+    if (A->wcode_state != 1) {
+        A->wruns_L = A->tiles_L;
+        A->wruns_state = -1;
+        return CSR_OK;
+    }
+    const int64_t T = A->n_tiles;
+    if ((st = A->wruns.alloc(sizeof(int32_t) * kRunWords * (size_t)std::max<int64_t>(T, 1))) !=
+        CSR_OK)
+        return st;
+    DevBuf most;
+    if ((st = most.alloc(sizeof(int32_t))) != CSR_OK) return st;
+    CSR_HIP(hipMemsetAsync(most.p, 0, sizeof(int32_t), s));
+    CSR_HIP(launch_window_runs(A->wdict.as<uint16_t>(), A->wlen.as<int32_t>(),
+                               A->tile_base.as<int32_t>(), T, A->wruns.as<int32_t>(),
+                               most.as<int32_t>(), s));
+    int32_t m = 0;
+    CSR_HIP(hipMemcpyAsync(&m, most.p, sizeof(m), hipMemcpyDeviceToHost, s));
+    CSR_HIP(hipStreamSynchronize(s));
+    A->wruns_L = A->tiles_L;
+    A->wruns_state = m <= kRunsMax ? 1 : -1;
     return CSR_OK;
 }
 
@@ -391,6 +431,9 @@ bool plan_tables_ok(const csr_matrix_s *A, const Plan &P) {
         if (P.cblocks > 0) return A->cb_B == P.cblocks && A->cb_L == P.L;
         if (A->tiles_L != P.L || A->n_tiles <= 0) return false;
         if (P.idx == IDX_W8) return A->wcode_state == 1 && A->wcodes_L == P.L;
+        if (P.idx == IDX_R8)
+            return A->wcode_state == 1 && A->wcodes_L == P.L && A->wruns_state == 1 &&
+                   A->wruns_L == P.L;
         if (P.idx == IDX_D8 || P.idx == IDX_D16)
             return A->mcodes_encoded && A->mcodes_L == P.L &&
                    A->mcode_bits == (P.idx == IDX_D8 ? 8 : 16);
@@ -466,9 +509,15 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
             const bool w8_fits = merge_codes_fit(L, 1);
             if (A->mcode_bits == 16 && A->tiles_slack > 0 && w8_fits) {
                 if ((st = build_window_codes(A, s)) != CSR_OK) return st;
+                // the same windows as runs of consecutive columns, when few
+                // enough (their x loads then need no dictionary load first)
+                if (A->wcode_state == 1 && cfg.window_runs == 1 &&
+                    (st = build_window_runs(A, s)) != CSR_OK)
+                    return st;
             }
             if (A->mcode_bits == 16 && A->wcode_state == 1 && w8_fits) {
-                P.idx = IDX_W8;
+                P.idx = cfg.window_runs == 1 && A->wruns_state == 1 && A->wruns_L == L ? IDX_R8
+                                                                                        : IDX_W8;
                 P.nt = 1;
             } else if ((A->mcode_bits == 8 || A->mcode_bits == 16) &&
                        merge_codes_fit(L, A->mcode_bits / 8)) {
@@ -973,9 +1022,20 @@ int32_t classify(double p_csr, double p_mb, double p_ml, double p_imb, double p_
 }
 
 // Table II: classes -> optimizations, applied jointly.
-int32_t remedies(int32_t classes, bool has_long_rows) {
+// map 0: as the paper's table; map 1: the pool as it pays on this GPU
+// (measured over the suite): irregular x gathers go to the merge path (its
+// window codes and column blocks keep gathers close), imbalance to the
+// merge path with compressed column codes (the decomposition when long rows
+// exist), and the computation class has no remedy that pays here.
+int32_t remedies(int32_t classes, bool has_long_rows, int map) {
     int32_t o = 0;
     if (classes & CSR_CLS_MB) o |= CSR_OPT_DELTA;
+    if (map == 1) {
+        if (classes & CSR_CLS_ML) o |= CSR_OPT_MERGE;
+        if (classes & CSR_CLS_IMB)
+            o |= has_long_rows ? CSR_OPT_DECOMP : (CSR_OPT_MERGE | CSR_OPT_DELTA);
+        return o;
+    }
     if (classes & CSR_CLS_ML) o |= CSR_OPT_PREFETCH;
     if (classes & CSR_CLS_IMB) o |= has_long_rows ? CSR_OPT_DECOMP : CSR_OPT_MERGE;
     if (classes & CSR_CLS_CMP) o |= CSR_OPT_UNROLL;
@@ -999,6 +1059,10 @@ csr_status_t autotune(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, hi
             csr_config_t c = cfg;
             c.merge_items = L;
             cands.push_back(c);
+            if (opts & CSR_OPT_DELTA) {  // window codes: dictionary or run records
+                c.window_runs = 1 - cfg.window_runs;
+                cands.push_back(c);
+            }
         }
     } else {
         const int gs[3] = {G0, G0 >= 2 ? G0 / 2 : 1, G0 <= 32 ? G0 * 2 : 64};
@@ -1163,6 +1227,8 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
     csr_config_t cfg;
     if (cfg_in) cfg = *cfg_in;
     else csr_config_default(&cfg);
+    if (cfg.remedy_map != 0 && cfg.remedy_map != 1)
+        return fail(CSR_ERR_INVALID_ARG, "remedy_map must be 0 or 1");
     if (cfg.ml_partitions < 0 || cfg.ml_partitions > 4096 ||
         (cfg.ml_partitions > 0 && !(cfg.t_ml_part > 0.0)))
         return fail(CSR_ERR_INVALID_ARG, "ml_partitions must be in 0..4096 with t_ml_part > 0");
@@ -1194,7 +1260,7 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
             info.classes = cls;
             const bool has_long = A->feat.f[2] > (double)long_row_tau(A, cfg);
             const auto tp = Clock::now();
-            st = realize(A, remedies(cls, has_long), cfg, &P, s);
+            st = realize(A, remedies(cls, has_long, cfg.remedy_map), cfg, &P, s);
             t_prep = ms_since(tp);
             sel = -1;  // decided
         } else {
@@ -1260,7 +1326,7 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
         int32_t cls = classify(B.p_csr, B.p_mb, B.p_ml, B.p_imb, B.p_cmp, B.p_peak, cfg);
         if (B.ml_flagged > 0) cls |= CSR_CLS_ML;  // partition-aware ML
         const bool has_long = A->feat.f[2] > (double)long_row_tau(A, cfg);
-        const int32_t opts = remedies(cls, has_long);
+        const int32_t opts = remedies(cls, has_long, cfg.remedy_map);
         info.classes = cls;
         info.p_csr = B.p_csr;
         info.p_mb = B.p_mb;
@@ -1308,8 +1374,10 @@ csr_status_t csr_classify(const double *p, const csr_config_t *cfg_in, int32_t h
     csr_config_t cfg;
     if (cfg_in) cfg = *cfg_in;
     else csr_config_default(&cfg);
+    if (cfg.remedy_map != 0 && cfg.remedy_map != 1)
+        return fail(CSR_ERR_INVALID_ARG, "remedy_map must be 0 or 1");
     *classes = classify(p[0], p[1], p[2], p[3], p[4], p[5], cfg);
-    *opts = remedies(*classes, has_long_rows != 0);
+    *opts = remedies(*classes, has_long_rows != 0, cfg.remedy_map);
     return CSR_OK;
 }
 

@@ -145,13 +145,15 @@ def label(start, count, out, base_seed=501, n_min=1e4, n_max=4e6, nnz_cap=1 << 2
     os.rmdir(tmpdir)
 
 
-def _remedies_of(pkg, cls, has_long):
-    # classes -> remedies of Table II: the bounds are chosen so that the
-    # library's rule returns exactly `cls` (each class's test made to hold
-    # or fail on its own), which keeps the map in one place (the library)
+def _remedies_of(pkg, cls, has_long, remedy_map):
+    # classes -> remedies under the library's map: the bounds are chosen so
+    # that the library's rule returns exactly `cls` (each class's test made
+    # to hold or fail on its own), which keeps the map in one place (the
+    # library)
     p = {"csr": 1.0, "mb": 1.0, "ml": 1.0, "imb": 1.0, "cmp": 1.0, "peak": 1.0}
     cfg = pkg.default_config()
     cfg.t_ml, cfg.t_imb, cfg.t_mb = 1.5, 1.5, 0.5
+    cfg.remedy_map = remedy_map
     if cls & 4:
         p["imb"] = 2.0
     if cls & 2:
@@ -209,8 +211,8 @@ def profile_label(start, count, out, base_seed=501, n_min=1e4, n_max=4e6, nnz_ca
             xd = torch.ones(m, dtype=torch.float64, device="cuda")
             yd = torch.empty(n, dtype=torch.float64, device="cuda")
             set_times = {}
-            for opts in sorted({o for o in (_remedies_of(pkg, c, has_long) for c in range(16))
-                                if o is not None}):
+            reach = {_remedies_of(pkg, c, has_long, mp_) for c in range(16) for mp_ in (0, 1)}
+            for opts in sorted({canonical_opts(o) for o in reach if o is not None}):
                 A.select("forced", forced_opts=opts)
                 A.spmv(xd, yd)
                 set_times[str(opts)] = _time_current(A, xd, yd, calls, runs)
@@ -229,19 +231,42 @@ def profile_label(start, count, out, base_seed=501, n_min=1e4, n_max=4e6, nnz_ca
     os.rmdir(tmpdir)
 
 
+def canonical_opts(opts):
+    """The optimization set the library actually realizes: the merge path
+    takes precedence over long-row decomposition, so MERGE|DECOMP runs the
+    plan of MERGE."""
+    return opts & ~4 if opts & 8 else opts
+
+
+def set_time(rec, opts):
+    """Time of an optimization set in a bounds record: from the sets timed
+    for the rule, else from the catalogue timed in the same session."""
+    o = canonical_opts(opts)
+    st = rec["set_times_ms"]
+    if str(o) in st:
+        return st[str(o)]
+    return rec["catalogue_ms"][catalogue().index(o)]
+
+
+# the paper's thresholds, tuned on its KNC platform (Sec. IV-B)
+PAPER_THRESHOLDS = (1.25, 1.24, 0.8)
+
+
 def default_thresholds():
     import paper_1711_05487_amd as pkg
     d = pkg.default_config()
     return (d.t_ml, d.t_imb, d.t_mb)
 
 
-def tune_thresholds(recs, grid_ml=None, grid_imb=None, grid_mb=None):
+def tune_thresholds(recs, remedy_map=1, grid_ml=None, grid_imb=None, grid_mb=None,
+                    defaults=None):
     """Grid search of T_ML, T_IMB and T_MB (Sec. III-C: the thresholds are the
     classifier's hyperparameters, tuned by exhaustive grid search for the
     highest average performance gain of the chosen optimizations): for every
     setting, every record's classes under the library's rule, the time of
-    the set they map to, and the mean of t_plain / t_set. Returns (best
-    (t_ml, t_imb, t_mb), its mean gain, the mean gain of the given defaults)."""
+    the set they map to under `remedy_map`, and the mean of t_plain / t_set.
+    Returns (best (t_ml, t_imb, t_mb), its mean gain, the mean gain of
+    `defaults`, the library's defaults when None)."""
     import paper_1711_05487_amd as pkg
     grid_ml = np.round(np.arange(1.0, 3.001, 0.05), 4) if grid_ml is None else grid_ml
     grid_imb = np.round(np.arange(1.0, 3.001, 0.05), 4) if grid_imb is None else grid_imb
@@ -250,11 +275,11 @@ def tune_thresholds(recs, grid_ml=None, grid_imb=None, grid_mb=None):
     def gain(t_ml, t_imb, t_mb):
         cfg = pkg.default_config()
         cfg.t_ml, cfg.t_imb, cfg.t_mb = float(t_ml), float(t_imb), float(t_mb)
+        cfg.remedy_map = remedy_map
         g = []
         for r in recs:
             _, opts = pkg.classify(r["bounds"], r["has_long"], config=cfg)
-            st = r["set_times_ms"]
-            g.append(st["0"] / st[str(opts)])
+            g.append(r["set_times_ms"]["0"] / set_time(r, opts))
         return float(np.mean(g))
 
     best, best_g = None, -1.0
@@ -264,11 +289,11 @@ def tune_thresholds(recs, grid_ml=None, grid_imb=None, grid_mb=None):
                 v = gain(a, b, c)
                 if v > best_g + 1e-12:
                     best, best_g = (float(a), float(b), float(c)), v
-    d = pkg.default_config()
-    return best, best_g, gain(d.t_ml, d.t_imb, d.t_mb)
+    d = default_thresholds() if defaults is None else defaults
+    return best, best_g, gain(*d)
 
 
-def profile_regret(recs, thresholds):
+def profile_regret(recs, thresholds, remedy_map=1):
     """Per record t_selected / t_best with the profile rule at the given
     thresholds (default parameters), t_best the fastest of everything timed
     for that matrix in the same session (16 catalogue variants and the sets
@@ -276,10 +301,11 @@ def profile_regret(recs, thresholds):
     import paper_1711_05487_amd as pkg
     cfg = pkg.default_config()
     cfg.t_ml, cfg.t_imb, cfg.t_mb = thresholds
+    cfg.remedy_map = remedy_map
     ratio, speed = [], []
     for r in recs:
         _, opts = pkg.classify(r["bounds"], r["has_long"], config=cfg)
-        t = r["set_times_ms"][str(opts)]
+        t = set_time(r, opts)
         best = min(min(r["catalogue_ms"]), min(r["set_times_ms"].values()))
         ratio.append(t / best)
         speed.append(r["set_times_ms"]["0"] / t)
@@ -480,11 +506,14 @@ def main():
     elif args.cmd == "tune":
         recs = read_labels(args.bounds)
         tr, te = split(recs)
-        best, g_best, g_default = tune_thresholds(tr)
-        d = default_thresholds()
-        out = {"n_train": len(tr), "n_test": len(te), "best": best, "train_gain_best": g_best,
-               "train_gain_default": g_default, "default": d,
-               "test_default": profile_regret(te, d), "test_best": profile_regret(te, best)}
+        out = {"n_train": len(tr), "n_test": len(te), "default": default_thresholds(),
+               "paper": PAPER_THRESHOLDS}
+        for mp_ in (0, 1):
+            best, g_best, g_paper = tune_thresholds(tr, mp_, defaults=PAPER_THRESHOLDS)
+            out[f"map{mp_}"] = {
+                "best": best, "train_gain_best": g_best, "train_gain_paper": g_paper,
+                "test_paper": profile_regret(te, PAPER_THRESHOLDS, mp_),
+                "test_best": profile_regret(te, best, mp_)}
         print(json.dumps(out, indent=1), flush=True)
     else:
         recs = read_labels(args.labels)

@@ -33,7 +33,7 @@ def test_status_strings_and_defaults():
     for k, name in enumerate(pkg.STATUS):
         assert L.csr_status_str(k).decode() == name
     c = pkg.default_config()
-    assert (c.t_ml, c.t_imb, c.t_mb) == (1.25, 1.24, 0.8)
+    assert (c.t_ml, c.t_imb, c.t_mb, c.remedy_map) == (1.0, 1.0, 0.5, 1)
     assert c.long_row_factor == 32.0 and c.long_row_floor == 4096 and c.timing_calls == 32
 
 
@@ -103,10 +103,13 @@ def test_classify_matches_oracle_rule():
     for k in range(n):
         cfg = pkg.default_config()
         cfg.t_ml, cfg.t_imb, cfg.t_mb = T[k]
+        cfg.remedy_map = k % 2
         has_long = bool(k % 3 == 0)
         cls, opts = pkg.classify(P[k], has_long, config=cfg)
         want = oracle.classify(*P[k], t_ml=T[k, 0], t_imb=T[k, 1], t_mb=T[k, 2])
         assert cls == want, (k, P[k], T[k])
-        assert opts == oracle.remedies(want, has_long)
+        assert opts == oracle.remedies(want, has_long, k % 2)
     with pytest.raises(pkg.CsrError):
         pkg.classify([1.0, 1.0, 1.0, 0.0, 1.0, 1.0], False)
+    with pytest.raises(pkg.CsrError):
+        pkg.classify([1.0] * 6, False, remedy_map=2)

@@ -127,7 +127,8 @@ def test_precision_sweep_against_oracle(name, storage, index):
     else:
         rep = check_reduced(y, rp, col, val, x, storage, what)
     assert rep["zero_rows_exact"]
-    SWEEP[what] = {"index": ("window8" if info["window_codes"] else
+    SWEEP[what] = {"index": ("window8 runs" if info["window_codes"] == 2 else
+                             "window8" if info["window_codes"] else
                              "int32" if info["delta_bits"] == 32 else f"delta{info['delta_bits']}"),
                    "max_rel_err": rep["max"], "p99_rel_err": rep["p99"]}
     out = os.environ.get("CSRSPMV_REPORT_DIR")

@@ -323,3 +323,63 @@ def test_window_codes_many_rows_per_tile():
     y_i = run(A, x, M | pkg.OPT_PREFETCH, 256)
     assert np.array_equal(y_w.view(np.uint64), y_i.view(np.uint64))
     assert np.array_equal(y_w, oracle.spmv(rp, col, val, x))
+
+
+@pytest.mark.parametrize("name", ["st27_24", "bidiag"])
+def test_window_runs_bit_exact_and_same_bits(name):
+    """Run windows (window codes whose windows are at most 14 runs of
+    consecutive columns): records bit-exact against the oracle's, and y
+    bit-identical to the dictionary form and to int32 columns on the same
+    tiles (dyadic values: equal to the oracle)."""
+    if name == "bidiag":
+        n, m, rp, col, val = far_bidiagonal(200_003, 17)
+        L = 256
+    else:
+        n, m, rp, col, val = matrix(name)
+        val = _dyadic(val, 18)
+        L = 512
+    x = synth.dyadic_vector(m, 19)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    info = A.select("forced", forced_opts=M | pkg.OPT_DELTA, merge_items=L, window_runs=1)
+    s = expected_slack(rp, L)
+    ti, tj = oracle.merge_tiles(rp, L, s)
+    want = oracle.window_runs(tj, col)
+    assert want is not None and info["window_codes"] == 2
+    rec = A.debug_copy(pkg.DEBUG_WINDOW_RUNS, np.int32).reshape(-1, 16)
+    assert np.array_equal(rec, want[0])
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_WINDOW_CODES, np.uint8), want[1])
+    y_r = run(A, x)
+    info = A.select("forced", forced_opts=M | pkg.OPT_DELTA, merge_items=L)
+    assert info["window_codes"] == 1
+    y_w = run(A, x)
+    y_i = run(A, x, M | pkg.OPT_PREFETCH, L)
+    assert np.array_equal(y_r.view(np.uint64), y_w.view(np.uint64))
+    assert np.array_equal(y_r.view(np.uint64), y_i.view(np.uint64))
+    assert np.array_equal(y_r, oracle.spmv(rp, col, val, x))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_window_runs_parity_with_empty_rows(storage):
+    """Run windows with runs of emptied rows (five every 997 rows, which
+    keeps every tile within 14 runs), against the oracle in every value
+    storage."""
+    n, m, rp, col, val = matrix("st27_24")
+    keep = np.ones(n, dtype=bool)
+    for k in range(0, n, 997):
+        keep[k:k + 5] = False
+    lens = np.where(keep, np.diff(rp), 0)
+    sel = keep[np.repeat(np.arange(n), np.diff(rp))]
+    rp2 = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    col2, val2 = col[sel], val[sel]
+    x = xvec("st27_24", m)
+    A = pkg.CsrMatrix(rp2, col2, val2, n_cols=m, storage=storage)
+    info = A.select("forced", forced_opts=M | pkg.OPT_DELTA, merge_items=512, window_runs=1)
+    assert info["window_codes"] == 2
+    if storage == "f64":
+        y = run(A, x)
+        check_f64(y, rp2, col2, val2, x, "run windows with empty rows")
+        assert np.all(y[~keep] == 0)
+    else:
+        y = A.spmv(torch.from_numpy(oracle.to_f32(x)).cuda())
+        torch.cuda.synchronize()
+        check_reduced(y.cpu().numpy(), rp2, col2, val2, x, storage, f"run windows {storage}")

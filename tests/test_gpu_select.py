@@ -164,11 +164,13 @@ def test_profile_rule_and_remedies_match_oracle(name):
     info = A.select("profile")
     p = info
     assert p["p_peak"] >= p["p_mb"] > 0 and p["p_csr"] > 0 and p["b_max"] > 1e11
-    cls = oracle.classify(p["p_csr"], p["p_mb"], p["p_ml"], p["p_imb"], p["p_cmp"], p["p_peak"])
+    d = pkg.default_config()
+    cls = oracle.classify(p["p_csr"], p["p_mb"], p["p_ml"], p["p_imb"], p["p_cmp"], p["p_peak"],
+                          t_ml=d.t_ml, t_imb=d.t_imb, t_mb=d.t_mb)
     assert info["classes"] == cls
     f, _ = oracle.features(n, m, rp, col)
     has_long = f[F["nnz_max"]] > oracle.long_row_threshold(f[F["nnz_avg"]])
-    assert info["opts"] == oracle.remedies(cls, has_long)
+    assert info["opts"] == oracle.remedies(cls, has_long, d.remedy_map)
     check_tables_in_place(A, info, rp)
     x = xvec(name, m)
     y = A.spmv(torch.from_numpy(x).cuda())
@@ -200,8 +202,9 @@ def test_profile_bounds_match_oracle_formulas(name, storage):
     assert 1 <= spans.size <= 256 and np.all(spans > 0)
     assert clock_hz > 0
     assert info["p_imb"] == pytest.approx(oracle.p_imb(nnz, spans / clock_hz), rel=1e-14)
+    d = pkg.default_config()
     cls = oracle.classify(info["p_csr"], info["p_mb"], info["p_ml"], info["p_imb"],
-                          info["p_cmp"], info["p_peak"])
+                          info["p_cmp"], info["p_peak"], t_ml=d.t_ml, t_imb=d.t_imb, t_mb=d.t_mb)
     assert info["classes"] == cls
 
 

@@ -31,7 +31,7 @@ def test_tree_selection_follows_the_tree(name):
     assert info["fallback"] == 0
     assert info["classes"] == cls
     tau = int(max(32.0 * f[3], 4096))  # default long-row threshold of the library
-    assert info["opts"] == oracle.remedies(cls, f[2] > tau)
+    assert info["opts"] == oracle.remedies(cls, f[2] > tau, pkg.default_config().remedy_map)
     x = xvec(name, m)
     y = A.spmv(torch.from_numpy(x).cuda())
     torch.cuda.synchronize()

@@ -24,7 +24,7 @@ CHILD = textwrap.dedent(r'''
     L.csr_last_error.restype = ctypes.c_char_p
     cfg = pkg.Config()
     L.csr_config_default(ctypes.byref(cfg))
-    assert cfg.t_ml == 1.25 and cfg.timing_calls == 32
+    assert cfg.t_ml == 1.0 and cfg.remedy_map == 1 and cfg.timing_calls == 32
     for s in range(-1, 9):
         assert L.csr_status_str(s)
     h = P()

@@ -92,3 +92,36 @@ def test_committed_model_within_ten_percent_on_held_out(recs, model):
     assert rep["geomean_sel_over_best"] <= 1.10
     assert rep["geomean_sel_over_best"] == pytest.approx(meta["test"]["geomean_sel_over_best"],
                                                          rel=0.01)
+
+
+BOUNDS = learn.WEIGHTS.replace("mlp16_mi355x.json", "bounds_mi355x.jsonl")
+
+
+def test_profile_thresholds_are_the_grid_search_optimum():
+    """The library's default thresholds and class -> remedy map are what a
+    grid search (Sec. III-C) over the committed MI355X bounds records picks
+    on the training split; on the held-out split they beat the paper's KNC
+    thresholds with either map. Runs the library's own rule (host code)."""
+    recs = learn.read_labels(BOUNDS)
+    assert len(recs) == 400
+    for r in recs:
+        assert len(r["bounds"]) == 6 and len(r["catalogue_ms"]) == 16
+        assert r["set_times_ms"]["0"] > 0
+    tr, te = learn.split(recs)
+    d = learn.default_thresholds()
+    grid = dict(grid_ml=[1.0, 1.25, 1.5, 2.0], grid_imb=[1.0, 1.24, 1.5, 2.0],
+                grid_mb=[0.5, 0.8, 1.0])
+    best, g_best, g_paper = learn.tune_thresholds(tr, 1, defaults=learn.PAPER_THRESHOLDS, **grid)
+    assert best == d and g_best > g_paper
+    held = learn.profile_regret(te, d, 1)
+    assert held[0] < 1.1
+    assert held[0] < learn.profile_regret(te, learn.PAPER_THRESHOLDS, 0)[0]
+    assert held[0] < learn.profile_regret(te, learn.PAPER_THRESHOLDS, 1)[0]
+
+
+def test_set_time_resolves_equivalent_sets():
+    r = {"set_times_ms": {"0": 2.0, "8": 1.0}, "catalogue_ms": list(range(1, 17))}
+    assert learn.set_time(r, 8) == 1.0
+    assert learn.set_time(r, 8 | 4) == 1.0          # the merge path wins over decomposition
+    cat = learn.catalogue()
+    assert learn.set_time(r, 9) == r["catalogue_ms"][cat.index(9)]

@@ -433,6 +433,97 @@ def test_window_codes_boundaries():
     assert list(dct[0, :3]) == [0, 2, 5] and list(codes) == [0, 1, 1, 0, 2]
 
 
+# ------------------------------------------------- run windows (row-aligned tiles)
+
+def _expand_runs(rec):
+    """The window a run record describes: base + start_r + k for k < len_r."""
+    base, m, nr = int(rec[0]), int(rec[1]) & 0xFFFF, int(rec[1]) >> 16
+    cols = []
+    for r in range(nr):
+        start, ln = int(rec[2 + r]) & 0xFFFF, (int(rec[2 + r]) >> 16) & 0xFFFF
+        cols += [base + start + k for k in range(ln)]
+    assert len(cols) == m
+    assert all(int(v) == 0 for v in rec[2 + nr:])
+    return cols
+
+
+@pytest.mark.parametrize("name,L", [("lap", 256), ("st27", 512), ("rand", 128)])
+def test_window_runs_expand_to_the_window(name, L):
+    if name == "lap":
+        n, _, rp, col, _ = synth.laplacian2d(60)
+    elif name == "st27":
+        n, _, rp, col, _ = synth.stencil27(12)
+    else:
+        n, _, rp, col, _ = synth.tiny_random(300, 2000, 0.01, 5)
+    ti, tj = _aligned_tiles(rp, L)
+    got = oracle.window_runs(tj, col)
+    if name == "rand":  # scattered columns: far more than 14 runs per tile
+        assert got is None
+        return
+    assert got is not None
+    rec, codes = got
+    t_of = _tile_of_each_nonzero(tj, len(col))
+    for t in range(len(tj) - 1):
+        cols = col[tj[t]:tj[t + 1]]
+        window = sorted(set(int(c) for c in cols))      # brute force
+        assert _expand_runs(rec[t]) == window
+        # runs are maximal: consecutive runs are separated by a gap
+        nr = int(rec[t, 1]) >> 16
+        for r in range(nr - 1):
+            end = (int(rec[t, 2 + r]) & 0xFFFF) + (int(rec[t, 2 + r]) >> 16)
+            assert (int(rec[t, 3 + r]) & 0xFFFF) > end
+    # the codes are the window ranks: the same as window codes
+    assert np.array_equal(codes, oracle.window_codes(tj, col)[3])
+    assert np.array_equal(np.array([_expand_runs(rec[t])[codes[j]] for j, t in enumerate(t_of)]), col)
+
+
+def test_window_runs_laplacian_closed_form():
+    # a tile of rows [a, b) of the 5-point Laplacian's grid interior has the
+    # three bands [a-n, b-1-n], [a-1, b], [a+n, b-1+n] (b - a + 2 < n): three
+    # runs of lengths b - a, b - a + 2, b - a starting at offsets 0, n - 1, 2n
+    n = 100
+    _, _, rp, col, _ = synth.laplacian2d(n)
+    ti, tj = _aligned_tiles(rp, 256)
+    rec, _ = oracle.window_runs(tj, col)
+    checked = 0
+    for t in range(len(tj) - 1):
+        a, b = int(ti[t]), int(ti[t + 1])
+        rows = np.arange(a, b)
+        if b <= a or b - a + 2 >= n:
+            continue
+        x, y = rows % n, rows // n
+        if x.min() < 1 or x.max() > n - 2 or y.min() < 1 or y.max() > n - 2:
+            continue
+        k = b - a
+        assert list(rec[t, :5]) == [a - n, (3 * k + 2) | (3 << 16), 0 | (k << 16),
+                                    (n - 1) | ((k + 2) << 16), (2 * n) | (k << 16)]
+        checked += 1
+    assert checked > 10
+
+
+def test_window_runs_limits():
+    def one_row(cols, max_runs=14):
+        rp = np.array([0, len(cols)], dtype=np.int32)
+        c = np.array(cols, dtype=np.int32)
+        ti, tj = oracle.merge_tiles(rp, 1024, len(cols) + 1)
+        return oracle.window_runs(tj, c, max_runs)
+    # 14 runs fit, 15 do not (isolated columns: one run each)
+    assert one_row(list(range(0, 28, 2))) is not None
+    assert one_row(list(range(0, 30, 2))) is None
+    # 256 consecutive columns are one run; 257 distinct do not fit the window
+    rec, codes = one_row(list(range(1000, 1256)))
+    assert list(rec[0, :3]) == [1000, 256 | (1 << 16), 0 | (256 << 16)]
+    assert list(codes) == list(range(256))
+    assert one_row(list(range(1000, 1257))) is None
+    # range 2^16 - 1 fits, 2^16 does not
+    assert one_row([3, 3 + 65535]) is not None
+    assert one_row([3, 3 + 65536]) is None
+    # repeated columns: one window entry, one code; an empty tile stays zero
+    rec, codes = one_row([7, 8, 8, 7, 12, 13])
+    assert list(rec[0, :4]) == [7, 4 | (2 << 16), 0 | (2 << 16), 5 | (2 << 16)]
+    assert list(codes) == [0, 1, 1, 0, 2, 3]
+
+
 # ------------------------------------------------------- SPD study matrices
 
 def test_spd_generators_symmetric_and_dominant():

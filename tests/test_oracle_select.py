@@ -61,6 +61,15 @@ def test_remedies_table():
     assert C.remedies(C.CLS_CMP, False) == C.OPT_UNROLL
     assert C.remedies(C.CLS_IMB | C.CLS_CMP | C.CLS_ML, True) == (
         C.OPT_DECOMP | C.OPT_UNROLL | C.OPT_PREFETCH)
+    # the map for a GPU on which prefetching and unrolling do not pay
+    assert C.remedies(C.CLS_MB, False, 1) == C.OPT_DELTA
+    assert C.remedies(C.CLS_ML, False, 1) == C.OPT_MERGE
+    assert C.remedies(C.CLS_IMB, True, 1) == C.OPT_DECOMP
+    assert C.remedies(C.CLS_IMB, False, 1) == C.OPT_MERGE | C.OPT_DELTA
+    assert C.remedies(C.CLS_CMP, False, 1) == 0
+    assert C.remedies(C.CLS_ML | C.CLS_CMP, True, 1) == C.OPT_MERGE
+    with pytest.raises(AssertionError):
+        C.remedies(C.CLS_MB, False, 2)
     cat = C.catalogue()
     assert len(cat) == 16 and len(set(cat)) == 16 and cat[0] == 0
     assert all(bin(s).count("1") <= 2 for s in cat)
