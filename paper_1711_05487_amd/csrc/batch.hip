@@ -5,7 +5,8 @@
 // long-row pass of decomposition plans; each column-block pass of a merge
 // plan on its own, so that the passes of one matrix run in order); each class
 // is one persistent kernel over the concatenated items of its matrices, and
-// the classes are captured once into a HIP graph that later calls replay. A
+// the classes are captured once into a HIP graph that later calls replay
+// (the classes of one pass as parallel branches). A
 // plan without a batched instance (a merge tile size compiled at run time)
 // has its own launches captured in the same graph.
 #include <algorithm>
@@ -248,23 +249,75 @@ csr_status_t upload(BatchPlan &B, hipStream_t s) {
     return CSR_OK;
 }
 
+// Streams and events of one capture, released on every path.
+struct CaptureRes {
+    hipStream_t cs = nullptr;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;
+    ~CaptureRes() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        for (hipStream_t s : side) (void)hipStreamDestroy(s);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+    hipError_t event(hipEvent_t *out) {
+        hipError_t e = hipEventCreateWithFlags(out, hipEventDisableTiming);
+        if (e == hipSuccess) ev.push_back(*out);
+        return e;
+    }
+};
+
+// The classes of one column-block pass touch disjoint rows (every matrix
+// is in one class per pass; a decomposition plan's row blocks skip the
+// long rows its long-row class writes), so they are captured as parallel
+// branches (fork on an event, one side stream per class up to
+// kCaptureStreams, join before the next pass); small classes then share
+// the GPU instead of running one after another.
+constexpr int kCaptureStreams = 8;
+
+hipError_t capture_runs(const BatchPlan &B, CaptureRes &R) {
+    hipError_t e = hipSuccess;
+    size_t q = 0;
+    while (q < B.runs.size() && e == hipSuccess) {
+        const int pass = std::get<0>(B.runs[q].key);
+        size_t q1 = q;
+        while (q1 < B.runs.size() && std::get<0>(B.runs[q1].key) == pass) ++q1;
+        hipEvent_t fork;
+        if ((e = R.event(&fork)) != hipSuccess || (e = hipEventRecord(fork, R.cs)) != hipSuccess)
+            break;
+        const int nside = (int)std::min<size_t>(q1 - q, (size_t)kCaptureStreams);
+        for (int k = 0; k < nside && e == hipSuccess; ++k)
+            e = hipStreamWaitEvent(R.side[k], fork, 0);
+        for (size_t r = q; r < q1 && e == hipSuccess; ++r)
+            e = launch_run(B, B.runs[r], R.side[(r - q) % nside]);
+        for (int k = 0; k < nside && e == hipSuccess; ++k) {
+            hipEvent_t done;
+            if ((e = R.event(&done)) == hipSuccess && (e = hipEventRecord(done, R.side[k])) == hipSuccess)
+                e = hipStreamWaitEvent(R.cs, done, 0);
+        }
+        q = q1;
+    }
+    return e;
+}
+
 csr_status_t capture(BatchPlan &B) {
     if (B.exec) (void)hipGraphExecDestroy(B.exec);
     if (B.graph) (void)hipGraphDestroy(B.graph);
     B.exec = nullptr;
     B.graph = nullptr;
-    hipStream_t cs;
-    CSR_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    CaptureRes R;
+    CSR_HIP(hipStreamCreateWithFlags(&R.cs, hipStreamNonBlocking));
+    for (int k = 0; k < kCaptureStreams; ++k) {
+        hipStream_t s2;
+        CSR_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        R.side.push_back(s2);
+    }
+    hipError_t e = hipStreamBeginCapture(R.cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = hipSuccess;
-        for (const ClassRun &r : B.runs)
-            if (le == hipSuccess) le = launch_run(B, r, cs);
-        e = hipStreamEndCapture(cs, &B.graph);
+        const hipError_t le = capture_runs(B, R);
+        e = hipStreamEndCapture(R.cs, &B.graph);
         if (le != hipSuccess) e = le;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0);
-    (void)hipStreamDestroy(cs);
     if (e != hipSuccess) return hip_fail(e, "graph capture");
     return CSR_OK;
 }

@@ -151,8 +151,8 @@ template <int S, int IPT, int IDX = IDX_I32> struct MergeTileRegs {
     VV vv[NIT];              // values of the tile's window
     CV cv[NIT];              // columns (or codes) of the tile's window
     int32_t wl;              // window codes: entries of the tile's x window
-    typename VecOfU<uint16_t, 4>::type dv;  // window codes: entries [4 lane, 4 lane + 4)
-    typename VecOf<typename St<S>::X, 4>::type wx;  // run windows: x at entries [4 lane, 4 lane + 4)
+    uint16_t dv[4];          // window codes: entries lane + 64 k, k < 4
+    typename VecOf<typename St<S>::X, 4>::type wx;  // run windows: x at entries lane + 64 k
 };
 
 // Stage 1: issue the tile's loads. The window [j0, j0 + L) starts at the
@@ -204,12 +204,13 @@ __device__ __forceinline__ void merge_issue(int64_t t, const int32_t *__restrict
             R.re[q] = buffer_load<int32_t, false>(rr, tid * 4u, (uint32_t)(q * BS * 4));
     }
     if constexpr (IDX == IDX_W8) {
-        // the window's dictionary entries, read as whole 4-entry vectors (a
-        // vector crossing the range end would read zeros; the dictionary
-        // row is zero past the window anyway)
+        // the window's dictionary entries lane + 64 k: each load reads 64
+        // consecutive entries (entries past the window read zero)
         R.wl = wlen[t];
-        const auto rd = buffer_range(wdict + t * kWindowMax, (uint32_t)((R.wl + 3) & ~3) * 2u);
-        R.dv = buffer_load<typename VecOfU<uint16_t, 4>::type, NT>(rd, tid * 8u, 0u);
+        const auto rd = buffer_range(wdict + t * kWindowMax, (uint32_t)R.wl * 2u);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            R.dv[k] = buffer_load<uint16_t, NT>(rd, tid * 2u, (uint32_t)(k * kMergeBlock * 2));
     }
     const auto rc = buffer_range(static_cast<const C *>(cols) + R.j0, nwin * (uint32_t)sizeof(C));
     const auto rv = buffer_range(val + R.j0, nwin * (uint32_t)sizeof(V));
@@ -375,11 +376,12 @@ __device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT, ID
 }
 
 // Window codes (row-aligned tiles): the tile's x window (its distinct
-// columns, at most kWindowMax) is read with one load per lane and entry
-// block (lane l: entries 4l .. 4l+3, consecutive columns on banded rows),
-// staged in LDS, and every nonzero reads its x there by its rank. The
-// window occupies the front of the product buffer, which is overwritten
-// only after the last rank has been read.
+// columns, at most kWindowMax) is read with four loads per lane (lane l:
+// entries l + 64 k, so that one load covers 64 consecutive entries, which
+// are consecutive columns on banded rows and share few cache lines), staged
+// in LDS, and every nonzero reads its x there by its rank. The window
+// occupies the front of the product buffer, which is overwritten only after
+// the last rank has been read.
 template <int S, int IPT>
 __device__ __forceinline__ typename VecOf<typename St<S>::X, 4>::type merge_window_load(
     const MergeTileRegs<S, IPT, IDX_W8> &R, const typename St<S>::X *__restrict__ x,
@@ -393,7 +395,7 @@ __device__ __forceinline__ typename VecOf<typename St<S>::X, 4>::type merge_wind
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         // entries past the window read nothing (an offset past the range)
-        const bool in = 4 * (int)threadIdx.x + k < R.wl;
+        const bool in = (int)threadIdx.x + k * kMergeBlock < R.wl;
         w[k] = buffer_load<X, false>(rx, in ? (uint32_t)R.dv[k] * (uint32_t)sizeof(X) : 0x80000000u, 0u);
     }
     return w;
@@ -408,7 +410,8 @@ __device__ __forceinline__ void merge_window_stage(
     constexpr int VEC = MergeTileRegs<S, IPT, IDX>::VEC, NIT = MergeTileRegs<S, IPT, IDX>::NIT;
     static_assert(kWindowMax * sizeof(X) <= sizeof(lds.prod), "the window fits the product buffer");
     X *s_win = reinterpret_cast<X *>(lds.prod);
-    *reinterpret_cast<typename VecOf<X, 4>::type *>(s_win + 4 * threadIdx.x) = w;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s_win[threadIdx.x + k * kMergeBlock] = w[k];
     wave_lds_sync();
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
@@ -430,8 +433,8 @@ __device__ __forceinline__ void merge_gather_window(const MergeTileRegs<S, IPT, 
 // Run windows (row-aligned tiles, IDX_R8): the tile's record (its smallest
 // column, window length, runs of consecutive columns) is read with scalar
 // loads first; then every vector load of the tile is issued at once: row
-// ends, rank codes, the x window (lane l: entries 4l .. 4l+3, each located
-// in its run by the wave-uniform run table), values. The x window goes to
+// ends, rank codes, the x window (lane l: entries l + 64 k, each located in
+// its run by the wave-uniform run table), values. The x window goes to
 // LDS as for window codes, and every nonzero reads x there by its rank.
 template <int S, int IPT>
 __device__ __forceinline__ void merge_issue_runs(int64_t t, const int32_t *__restrict__ rp,
@@ -480,7 +483,7 @@ __device__ __forceinline__ void merge_issue_runs(int64_t t, const int32_t *__res
 #pragma unroll
     for (int it = 0; it < NIT; ++it)
         R.cv[it] = buffer_load<typename Rg::CV, true>(rc, tid * (uint32_t)VEC, (uint32_t)(it * STEP));
-    // window entry k = 4 tid + q lies in run r when k - (entries of runs
+    // window entry k = tid + 64 q lies in run r when k - (entries of runs
     // before r) < length of r; the words past the last run are zero (length
     // 0), so every run slot can be tested; entries past the window read
     // nothing
@@ -492,7 +495,7 @@ __device__ __forceinline__ void merge_issue_runs(int64_t t, const int32_t *__res
         const uint32_t first = w & 0xFFFFu, len = w >> 16;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const uint32_t d = 4u * tid + (uint32_t)q - before;
+            const uint32_t d = tid + (uint32_t)(q * BS) - before;
             if (d < len) off[q] = (first + d) * (uint32_t)sizeof(X);
         }
         before += len;

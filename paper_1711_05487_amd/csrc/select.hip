@@ -489,16 +489,6 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
                         "merge_items must be a multiple of 256 from 256 to 2048");
         if ((st = build_tiles(A, L, s)) != CSR_OK) return st;
         P.L = L;
-        if (!(opts & CSR_OPT_DELTA) && A->tiles_slack > 0) {
-            // the merge path keeps its gathers inside the L2: column blocks
-            // when x outgrows it and the rows' columns spread over it
-            if (!A->has_features && (st = inspect(A, s)) != CSR_OK) return st;
-            const int B = column_blocks_for(A);
-            if (B >= 2) {
-                if ((st = build_colblocks(A, B, L, s)) != CSR_OK) return st;
-                P.cblocks = B;
-            }
-        }
         if (opts & CSR_OPT_DELTA) {
             // MB: tile-base codes when every tile's column range fits 8 or
             // 16 bits (streamed, like the compressed arrays of the remedy);
@@ -524,6 +514,18 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
                 if ((st = build_merge_codes(A, s, true)) != CSR_OK) return st;
                 P.idx = A->mcode_bits == 8 ? IDX_D8 : IDX_D16;
                 P.nt = 1;
+            }
+        }
+        if (P.idx == IDX_I32 && A->tiles_slack > 0) {
+            // int32 columns (no codes asked for, or the matrix is not
+            // eligible for them): the merge path keeps its gathers inside
+            // the L2, with column blocks when x outgrows it and the rows'
+            // columns spread over it
+            if (!A->has_features && (st = inspect(A, s)) != CSR_OK) return st;
+            const int B = column_blocks_for(A);
+            if (B >= 2) {
+                if ((st = build_colblocks(A, B, L, s)) != CSR_OK) return st;
+                P.cblocks = B;
             }
         }
         P.G = 0;

@@ -287,8 +287,13 @@ def test_column_blocks_parity(storage):
         y = A.spmv(xs)
         torch.cuda.synchronize()
         check_reduced(y.cpu().numpy(), rp, col, val, x, storage, f"column blocks {storage}")
-    # codes take the single pass
-    assert A.select("forced", forced_opts=M | pkg.OPT_DELTA)["column_blocks"] == 0
+    # codes take the single pass; without eligible codes (these rows' column
+    # ranges need 32 bits) MERGE|DELTA keeps the column blocks
+    info = A.select("forced", forced_opts=M | pkg.OPT_DELTA)
+    assert info["delta_bits"] == 32
+    assert info["column_blocks"] == (6 if storage == "f64" else 3)
+    if storage == "f64":
+        check_f64(run(A, x), rp, col, val, x, "column blocks, codes not eligible")
     A.close()
     # x inside one L2, or rows whose columns stay close: a single pass
     for name in ("unif17", "st27_128"):

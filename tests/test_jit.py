@@ -36,7 +36,8 @@ def kernel_lines(path):
         lines = [re.sub(r"<[^>]*>", "", l.split("//")[0]).strip() for l in block.split("\n")[1:]]
         lines = [l for l in lines if l and not l.startswith(";")]
         # zero words after the last branch are padding between functions
-        while lines and lines[-1] == "v_cndmask_b32_e32 v0, s0, v0, vcc":
+        # (disassembled as v_cndmask, or elided as "...")
+        while lines and lines[-1] in ("v_cndmask_b32_e32 v0, s0, v0, vcc", "..."):
             lines.pop()
         out[head] = lines
     return out
