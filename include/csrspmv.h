@@ -127,9 +127,9 @@ typedef struct {
     int32_t remedy_map;      /* classes -> optimizations: 0 = the paper's Table II (MB delta
                                 codes, ML prefetch, IMB decomposition or merge path, CMP
                                 unrolling); 1 (default) = as they pay on MI355X (measured over
-                                the synthetic suite): MB delta codes, ML the merge path, IMB
-                                the merge path with compressed codes (decomposition when long
-                                rows exist), CMP nothing */
+                                the synthetic suite): MB delta codes, ML and IMB the merge
+                                path with compressed codes (IMB: decomposition when long rows
+                                exist), CMP nothing */
     int32_t reserved2;
 } csr_config_t;
 

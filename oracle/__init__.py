@@ -507,7 +507,8 @@ def remedies(classes: int, has_long_rows: bool, remedy_map: int = 0) -> int:
     remedy_map 1 is the reading for a GPU on which prefetching and unrolling
     do not pay (Sec. III-C leaves the map to be fixed per platform):
       MB  -> delta-compressed column indices
-      ML  -> the merge-path split (its tiles gather x through one window)
+      ML  -> the merge-path split with its codes (window-coded tiles gather
+             x through one window brought into fast memory first)
       IMB -> decomposition when long rows exist, else merge path with codes
       CMP -> nothing
     """
@@ -517,7 +518,7 @@ def remedies(classes: int, has_long_rows: bool, remedy_map: int = 0) -> int:
         o |= OPT_DELTA
     if remedy_map == 1:
         if classes & CLS_ML:
-            o |= OPT_MERGE
+            o |= OPT_MERGE | OPT_DELTA
         if classes & CLS_IMB:
             o |= OPT_DECOMP if has_long_rows else (OPT_MERGE | OPT_DELTA)
         return o

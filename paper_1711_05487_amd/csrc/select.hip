@@ -1033,7 +1033,7 @@ int32_t remedies(int32_t classes, bool has_long_rows, int map) {
     int32_t o = 0;
     if (classes & CSR_CLS_MB) o |= CSR_OPT_DELTA;
     if (map == 1) {
-        if (classes & CSR_CLS_ML) o |= CSR_OPT_MERGE;
+        if (classes & CSR_CLS_ML) o |= CSR_OPT_MERGE | CSR_OPT_DELTA;
         if (classes & CSR_CLS_IMB)
             o |= has_long_rows ? CSR_OPT_DECOMP : (CSR_OPT_MERGE | CSR_OPT_DELTA);
         return o;

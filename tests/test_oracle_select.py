@@ -63,11 +63,12 @@ def test_remedies_table():
         C.OPT_DECOMP | C.OPT_UNROLL | C.OPT_PREFETCH)
     # the map for a GPU on which prefetching and unrolling do not pay
     assert C.remedies(C.CLS_MB, False, 1) == C.OPT_DELTA
-    assert C.remedies(C.CLS_ML, False, 1) == C.OPT_MERGE
+    assert C.remedies(C.CLS_ML, False, 1) == C.OPT_MERGE | C.OPT_DELTA
     assert C.remedies(C.CLS_IMB, True, 1) == C.OPT_DECOMP
     assert C.remedies(C.CLS_IMB, False, 1) == C.OPT_MERGE | C.OPT_DELTA
     assert C.remedies(C.CLS_CMP, False, 1) == 0
-    assert C.remedies(C.CLS_ML | C.CLS_CMP, True, 1) == C.OPT_MERGE
+    assert C.remedies(C.CLS_ML | C.CLS_CMP, True, 1) == C.OPT_MERGE | C.OPT_DELTA
+    assert C.remedies(C.CLS_ML | C.CLS_IMB, True, 1) == C.OPT_MERGE | C.OPT_DELTA | C.OPT_DECOMP
     with pytest.raises(AssertionError):
         C.remedies(C.CLS_MB, False, 2)
     cat = C.catalogue()
