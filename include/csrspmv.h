@@ -130,7 +130,11 @@ typedef struct {
                                 the synthetic suite): MB delta codes, ML and IMB the merge
                                 path with compressed codes (IMB: decomposition when long rows
                                 exist), CMP nothing */
-    int32_t reserved2;
+    int32_t split_row_blocks; /* 1 = column blocks (x above one XCD's L2, rows whose columns
+                                spread over it) also on merge tiles that are not row-aligned,
+                                each pass carrying its split rows through the fixup; 0
+                                (default) = only on row-aligned tiles. The autotuner times
+                                both where they apply */
 } csr_config_t;
 
 /* What csr_select decided and what it cost. */

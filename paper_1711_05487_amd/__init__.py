@@ -61,7 +61,7 @@ class Config(ctypes.Structure):
                 ("exhaustive_set", ctypes.c_int32), ("dynamic_rows", ctypes.c_int32),
                 ("ml_partitions", ctypes.c_int32), ("t_ml_part", ctypes.c_double),
                 ("jit_tiles", ctypes.c_int32), ("window_runs", ctypes.c_int32),
-                ("remedy_map", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("remedy_map", ctypes.c_int32), ("split_row_blocks", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):

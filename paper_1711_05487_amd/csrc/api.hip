@@ -170,11 +170,14 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
     }
     const int32_t skip = P.long_rows ? (int32_t)A->long_tau : INT32_MAX;
     if ((P.opts & CSR_OPT_MERGE) && P.cblocks > 0) {
-        // column blocks: one pass per slab, each adding into y; the slab's
-        // columns and values are read with ordinary loads (measured faster
-        // than with the streaming hint for these passes)
+        // column blocks: one pass per slab, each adding into y (tiles that
+        // are not row-aligned: the pass's fixup adds its carries before the
+        // next pass); the slab's columns and values are read with ordinary
+        // loads (measured faster than with the streaming hint for these
+        // passes)
         const int ipt = P.L / kMergeBlock;
         const bool x32 = x_fits_32(A);
+        const bool fix = A->tiles_fixup != 0;
         const size_t vb = storage_bytes(A->storage);
         const int32_t n = A->n_rows;
         hipError_t e = hipSuccess;
@@ -189,16 +192,16 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
             const int64_t T = A->cb_tiles[b];
             switch (A->storage) {
             case CSR_VAL_F64:
-                e = launch_merge_s0(ipt, false, x32, false, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
-                                    nullptr, n, T, ev, s, b > 0);
+                e = launch_merge_s0(ipt, false, x32, fix, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
+                                    A->carry.p, n, T, ev, s, b > 0);
                 break;
             case CSR_VAL_F32:
-                e = launch_merge_s1(ipt, false, x32, false, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
-                                    nullptr, n, T, ev, s, b > 0);
+                e = launch_merge_s1(ipt, false, x32, fix, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
+                                    A->carry.p, n, T, ev, s, b > 0);
                 break;
             default:
-                e = launch_merge_s2(ipt, false, x32, false, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
-                                    nullptr, n, T, ev, s, b > 0);
+                e = launch_merge_s2(ipt, false, x32, fix, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
+                                    A->carry.p, n, T, ev, s, b > 0);
                 break;
             }
         }

@@ -119,8 +119,10 @@ void plan_classes(BatchPlan &B, const csr_matrix_t *h_A, const void *const *x, v
                 M.tile_i = A->cb_tile_i.as<int32_t>() + A->cb_tile_off[b];
                 M.tile_j = A->cb_tile_j.as<int32_t>() + A->cb_tile_off[b];
                 M.acc = b > 0;
-                add(ClassKey{b, K_MERGE, P.L / kMergeBlock, IDX_I32, 0, x32, 1, 0, 0}, M, k,
-                    A->cb_tiles[b], 0);
+                M.carry = A->carry.p;  // tiles not row-aligned: the pass's carries
+                add(ClassKey{b, K_MERGE, P.L / kMergeBlock, IDX_I32, 0, x32, A->tiles_fixup == 0, 0,
+                             0},
+                    M, k, A->cb_tiles[b], 0);
             }
         } else if ((P.opts & CSR_OPT_MERGE) && merge_items_prebuilt(P.L)) {
             BatchMat M = base_desc(A, x[k], y[k]);

@@ -143,7 +143,6 @@ hipError_t CSR_CAT(launch_merge_s, CSR_STORAGE)(int ipt, bool nt, bool x32, bool
                                                 const int32_t *tile_j, void *carry, int32_t n_rows,
                                                 int64_t n_tiles, hipEvent_t after_main,
                                                 hipStream_t s, bool acc) {
-    if (acc && fixup) return hipErrorInvalidValue;  // accumulation needs row-aligned tiles
     const MergeArgs a{arr, tile_i, tile_j, tile_base, carry, n_rows, n_cols, n_tiles, fixup,
                       after_main, acc};
     // row-aligned tiles (no fixup) reduce by rows, the others by a

@@ -264,14 +264,17 @@ __device__ __forceinline__ void merge_gather(const MergeTileRegs<S, IPT, IDX> &R
     }
 }
 
-// Stage 3: products, segmented scan, rows and carry.
+// Stage 3: products, segmented scan, rows and carry. With `acc` (a column
+// block after the first) the tile's part of each row ending in it is added
+// to y, and a row without nonzeros here keeps y; the fixup pass then adds
+// the carries as without `acc`.
 template <int S, int IPT, class LDS, int IDX = IDX_I32>
 __device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT, IDX> &R,
                                              const typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX>::NIT]
                                                                           [MergeTileRegs<S, IPT, IDX>::VEC],
                                              typename St<S>::X *__restrict__ y,
                                              typename St<S>::A *__restrict__ carry,
-                                             int32_t n_rows, LDS &lds) {
+                                             int32_t n_rows, LDS &lds, bool acc = false) {
     using X = typename St<S>::X;
     using A = typename St<S>::A;
     constexpr int VEC = MergeTileRegs<S, IPT, IDX>::VEC, NIT = MergeTileRegs<S, IPT, IDX>::NIT;
@@ -367,7 +370,10 @@ __device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT, ID
             }
             const int32_t start = r == 0 ? 0 : prev;
             const A sum = s_prod[off + max(re[q] - 1, 0)];
-            if (r < nre) yb[r] = re[q] > start ? (X)sum : X(0);
+            if (r < nre) {
+                if (re[q] > start) yb[r] = acc ? (X)((A)yb[r] + sum) : (X)sum;
+                else if (!acc) yb[r] = X(0);
+            }
         }
     }
     // the segment open at the tile end leaves a carry for later tiles
@@ -802,12 +808,11 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
         merge_gather<S, IPT, X32, IDX>(R, x, n_cols, xs);
         merge_finish_rows<S, IPT, LDS, IDX>(R, xs, y, lds, acc);
     } else {
-        (void)acc;  // not row-aligned: never a column block
         MergeTileRegs<S, IPT, IDX> R;
         merge_issue<S, IPT, NT, IDX>(t, rp, cols, val, tile_i, tile_j, tile_base, R);
         typename St<S>::X xs[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC];
         merge_gather<S, IPT, X32, IDX>(R, x, n_cols, xs);
-        merge_finish<S, IPT, LDS, IDX>(t, R, xs, y, carry, n_rows, lds);
+        merge_finish<S, IPT, LDS, IDX>(t, R, xs, y, carry, n_rows, lds, acc);
     }
 }
 

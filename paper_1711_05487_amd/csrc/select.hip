@@ -70,6 +70,8 @@ double plan_bytes(const csr_matrix_s *A, const Plan &P) {
             b -= 4.0 * (A->n_rows + 1) + 2.0 * 4.0 * (T + 1);
             b += 4.0 * (A->n_rows + 1) * B + 8.0 * (double)A->cb_tile_off[P.cblocks] +
                  xb2 * A->n_rows * (2.0 * B - 2.0);
+            if (A->tiles_fixup)  // every pass's carries, not the single pass's
+                b += 2.0 * ab * ((double)A->cb_tile_off[P.cblocks] - B - T);
         }
     }
     if (P.long_rows && A->n_long > 0) {
@@ -516,11 +518,14 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
                 P.nt = 1;
             }
         }
-        if (P.idx == IDX_I32 && A->tiles_slack > 0) {
+        if (P.idx == IDX_I32 && (A->tiles_slack > 0 || cfg.split_row_blocks == 1)) {
             // int32 columns (no codes asked for, or the matrix is not
             // eligible for them): the merge path keeps its gathers inside
             // the L2, with column blocks when x outgrows it and the rows'
-            // columns spread over it
+            // columns spread over it (on tiles that are not row-aligned,
+            // on request: every pass then carries its split rows through
+            // the fixup and walks every row end again, which pays only
+            // where the gathers miss)
             if (!A->has_features && (st = inspect(A, s)) != CSR_OK) return st;
             const int B = column_blocks_for(A);
             if (B >= 2) {
@@ -537,7 +542,7 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
             hipFunction_t f;
             const bool x32 = x_fits_32(A);
             st = P.cblocks ? jit_merge_kernel(A->device, A->storage, L / kMergeBlock, false, x32,
-                                              IDX_I32, true, &f)
+                                              IDX_I32, A->tiles_fixup == 0, &f)
                            : jit_merge_kernel(A->device, A->storage, L / kMergeBlock, P.nt != 0,
                                               x32, P.idx, A->tiles_fixup == 0, &f);
             if (st != CSR_OK) return st;
@@ -1057,12 +1062,24 @@ csr_status_t autotune(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, hi
     if (opts & CSR_OPT_MERGE) {
         std::vector<int> sizes = {256, 512, 1024};
         if (cfg.jit_tiles) sizes.insert(sizes.end(), {768, 1536});  // compiled at run time
+        // column blocks on tiles that are not row-aligned: timed both ways
+        // where they would apply
+        if (!A->has_features) {
+            csr_status_t st0 = inspect(A, s);
+            if (st0 != CSR_OK) return st0;
+        }
+        const bool split_blocks = column_blocks_for(A) >= 2;
         for (int L : sizes) {
             csr_config_t c = cfg;
             c.merge_items = L;
             cands.push_back(c);
             if (opts & CSR_OPT_DELTA) {  // window codes: dictionary or run records
-                c.window_runs = 1 - cfg.window_runs;
+                csr_config_t w = c;
+                w.window_runs = 1 - cfg.window_runs;
+                cands.push_back(w);
+            }
+            if (split_blocks && merge_slack(A, L) == 0) {
+                c.split_row_blocks = 1 - cfg.split_row_blocks;
                 cands.push_back(c);
             }
         }
@@ -1231,6 +1248,8 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
     else csr_config_default(&cfg);
     if (cfg.remedy_map != 0 && cfg.remedy_map != 1)
         return fail(CSR_ERR_INVALID_ARG, "remedy_map must be 0 or 1");
+    if (cfg.split_row_blocks != 0 && cfg.split_row_blocks != 1)
+        return fail(CSR_ERR_INVALID_ARG, "split_row_blocks must be 0 or 1");
     if (cfg.ml_partitions < 0 || cfg.ml_partitions > 4096 ||
         (cfg.ml_partitions > 0 && !(cfg.t_ml_part > 0.0)))
         return fail(CSR_ERR_INVALID_ARG, "ml_partitions must be in 0..4096 with t_ml_part > 0");

@@ -194,3 +194,30 @@ def test_batched_back_to_back_moving_vectors():
         for k, (n, m, rp, col, val) in enumerate(mats):
             check_f64(ys[k][:n].cpu().numpy(), rp, col, val, xs[k].cpu().numpy(),
                       f"call {r} matrix {k}")
+
+
+def test_batched_column_blocks_with_split_rows():
+    """Column-blocked merge plans on tiles that are not row-aligned (R-MAT
+    scale 21: every pass with its carries and fixup) beside row-aligned
+    column blocks and small plans: bit-identical to each matrix's own
+    csr_spmv, within the FP64 bar, and the same on a replay."""
+    mats = [synth.rmat(21, 16), synth.uniform_random(600_000, 8)]
+    mats += [synth.batch_matrix(i)[1] for i in range(6)]
+    hs = [pkg.CsrMatrix(rp, col, val, n_cols=m) for (n, m, rp, col, val) in mats]
+    for k, A in enumerate(hs):
+        info = A.select("forced", forced_opts=pkg.OPT_MERGE, split_row_blocks=1)
+        if k == 0:
+            assert info["column_blocks"] == 8 and info["merge_slack"] == 0
+        if k == 1:
+            assert info["column_blocks"] == 3 and info["merge_slack"] > 0
+    xs, ys = vectors(mats, 700)
+    pkg.spmv_batched(hs, xs, ys)
+    torch.cuda.synchronize()
+    first = [y.clone() for y in ys]
+    same_as_single(mats, hs, xs, ys, "split-row column blocks")
+    for k, (n, m, rp, col, val) in enumerate(mats):
+        check_f64(first[k][:n].cpu().numpy(), rp, col, val, xs[k].cpu().numpy(), f"batch {k}")
+    pkg.spmv_batched(hs, xs, ys)
+    torch.cuda.synchronize()
+    for k, (n, *_ ) in enumerate(mats):
+        assert torch.equal(ys[k][:n], first[k][:n]), k

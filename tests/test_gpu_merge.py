@@ -263,6 +263,45 @@ def test_column_blocks_bit_exact(L):
     A.close()
 
 
+@pytest.fixture(scope="module")
+def rmat21():
+    return synth.rmat(21, 16)
+
+
+def test_column_blocks_with_split_rows(rmat21):
+    """Skewed rows (R-MAT scale 21: rows of thousands of nonzeros, so the
+    tiles are not row-aligned and rows span tiles) over an x above one XCD's
+    L2: one pass per column block, each with its carries; blocks equal to the
+    oracle's, y bit-exact on dyadic inputs and deterministic, and within the
+    FP64 bar on the generator's values."""
+    n, m, rp, col, val = rmat21
+    dv = _dyadic(val, 43)
+    A = pkg.CsrMatrix(rp, col, dv, n_cols=m)
+    # off by default on tiles that are not row-aligned
+    assert A.select("forced", forced_opts=M, merge_items=512)["column_blocks"] == 0
+    for opts in (M, M | pkg.OPT_DELTA):  # no eligible codes: the same blocks
+        info = A.select("forced", forced_opts=opts, merge_items=512, split_row_blocks=1)
+        assert info["merge_slack"] == 0 and info["delta_bits"] == 32
+        assert info["column_blocks"] == 8  # 16 MB of x in slabs of at most 2 MiB
+    B = 8
+    width = (m + B - 1) // B
+    rpb, colb, valb = oracle.column_blocks(rp, col, dv, B, width)
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_CB_ROWPTR, np.int32), rpb.ravel())
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_CB_COL, np.int32), colb)
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_CB_VAL, np.float64), valb)
+    x = synth.dyadic_vector(m, 44)
+    y = run(A, x)
+    assert np.array_equal(y, oracle.spmv(rp, col, dv, x))
+    assert np.array_equal(run(A, x), y)
+    A.close()
+    xr = synth.vector(m, 45)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    assert A.select("forced", forced_opts=M, merge_items=1024,
+                    split_row_blocks=1)["column_blocks"] == 8
+    check_f64(run(A, xr), rp, col, val, xr, "rmat21 column blocks")
+    A.close()
+
+
 def _wide(n_rows=200_000, n_cols=1_500_000, k=8, seed=51):
     """Rectangular, 8 random columns per row (repeats allowed, summed in
     storage order): x of 12 MB (f64) or 6 MB (f32)."""
