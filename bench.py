@@ -719,18 +719,24 @@ def irregular(args):
     import paper_1711_05487_amd as pkg
     import synth
     torch.cuda.set_device(0)
-    cases = [("C3a", "R-MAT scale 22, edge factor 16", lambda: synth.rmat(22), 303,
-              [("plain", 0), ("merge", pkg.OPT_MERGE), ("prefetch+merge", pkg.OPT_MERGE | pkg.OPT_PREFETCH)]),
+    M, P = pkg.OPT_MERGE, pkg.OPT_PREFETCH
+    one = {"split_row_blocks": 0}  # tiles with split rows: a single pass
+    rmat_plans = [("plain", 0, {}), ("merge, one pass", M, one),
+                  ("prefetch+merge, one pass", M | P, one),
+                  ("merge (column blocks over row lists)", M, {})]
+    cases = [("C3a", "R-MAT scale 22, edge factor 16", lambda: synth.rmat(22), 303, rmat_plans),
+             ("C3a-perm", "R-MAT scale 22, seeded symmetric permutation",
+              lambda: permuted(synth.rmat(22)), 303, rmat_plans),
              ("C3b", "uniform random 2^20 x 16", lambda: synth.uniform_random(1 << 20, 16), 403,
-              [("plain", 0), ("merge", pkg.OPT_MERGE),
-               ("prefetch+merge (column blocks)", pkg.OPT_MERGE | pkg.OPT_PREFETCH)])]
+              [("plain", 0, {}), ("merge", M, {}),
+               ("prefetch+merge (column blocks)", M | P, {})])]
     for tag, desc, gen, xseed, plans in cases:
         n, m, rp, col, val = gen()
         x = torch.from_numpy(synth.vector(m, xseed)).cuda()
         y = torch.empty(n, dtype=torch.float64, device="cuda")
         A = pkg.CsrMatrix(rp, col, val, n_cols=m)
-        for name, opts in plans:
-            info = A.select("forced", forced_opts=opts)
+        for name, opts, over in plans:
+            info = A.select("forced", forced_opts=opts, **over)
             for _ in range(args.warmup):
                 A.spmv(x, y)
             torch.cuda.synchronize()

@@ -130,11 +130,12 @@ typedef struct {
                                 the synthetic suite): MB delta codes, ML and IMB the merge
                                 path with compressed codes (IMB: decomposition when long rows
                                 exist), CMP nothing */
-    int32_t split_row_blocks; /* 1 = column blocks (x above one XCD's L2, rows whose columns
-                                spread over it) also on merge tiles that are not row-aligned,
-                                each pass carrying its split rows through the fixup; 0
-                                (default) = only on row-aligned tiles. The autotuner times
-                                both where they apply */
+    int32_t split_row_blocks; /* 1 (default) = column blocks (x above one XCD's L2, rows
+                                whose columns spread over it) also on merge tiles that are
+                                not row-aligned: each block carries its split rows through
+                                the fixup, and the blocks after the first walk only the rows
+                                with nonzeros in them; 0 = only on row-aligned tiles. The
+                                autotuner times both where they apply */
 } csr_config_t;
 
 /* What csr_select decided and what it cost. */
@@ -186,7 +187,7 @@ typedef struct {
     int32_t reserved;
 } csr_features_t;
 
-/* Fill *cfg with the defaults (t_ml 1.0, t_imb 1.0, t_mb 0.5, remedy_map 1,
+/* Fill *cfg with the defaults (t_ml 1.0, t_imb 1.0, t_mb 0.5, remedy_map 1, split_row_blocks 1,
  * long_row_factor 32, long_row_floor 4096, autotune 1, timing_calls 32,
  * ml_partitions 0, t_ml_part 1.5, jit_tiles 0). */
 void csr_config_default(csr_config_t *cfg);
@@ -331,7 +332,11 @@ csr_status_t csr_jit_compile(int32_t storage, int32_t merge_items, int32_t index
  *         fit in the 256 MB Infinity Cache) and the span clock (ticks/s);
  *         19 run-window records int32[T][16] (per tile: smallest column,
  *         window entries | runs << 16, then per run its first column minus
- *         the smallest | its length << 16, zero past the last run)
+ *         the smallest | its length << 16, zero past the last run);
+ *         column blocks on tiles that are not row-aligned, blocks 1 .. B-1
+ *         one after the other: 20 the rows with nonzeros in the block,
+ *         ascending, int32, and 21 their row pointers int32[n_b + 1] (each
+ *         from 0)
  * Returns CSR_ERR_INVALID_ARG if `bytes` differs from the array's size
  * (*needed receives that size when non-NULL) or the array does not exist.
  * Synchronizes `stream`.

@@ -355,6 +355,21 @@ def column_blocks(rp, col, val, B: int, width: int):
     return rpb, colb[:col.size], valb[:col.size]
 
 
+def column_block_rows(rpb):
+    """Row lists of column blocks 1 .. B-1 (blocks of split rows walk only
+    the rows with nonzeros in them): per block the rows i with
+    rpb[b, i+1] > rpb[b, i], ascending, and their row pointers from 0.
+    Returns (rows, rowptr), the blocks one after the other."""
+    rows, ptr = [], []
+    for b in range(1, rpb.shape[0]):
+        cnt = np.diff(rpb[b].astype(np.int64))
+        r = np.nonzero(cnt)[0]
+        rows.append(r.astype(np.int32))
+        ptr.append(np.concatenate([[0], np.cumsum(cnt[r])]).astype(np.int32))
+    cat = lambda a: np.concatenate(a) if a else np.zeros(0, dtype=np.int32)
+    return cat(rows), cat(ptr)
+
+
 def long_rows(rp, tau: int) -> np.ndarray:
     rp = np.ascontiguousarray(rp, dtype=np.int32)
     out = np.empty(max(rp.size - 1, 1), dtype=np.int32)

@@ -31,7 +31,7 @@ SELECT = {"plain": SEL_PLAIN, "profile": SEL_PROFILE, "learned": SEL_LEARNED,
  DEBUG_MERGE_CODES, DEBUG_TILE_BASE, DEBUG_WINDOW_DICT, DEBUG_WINDOW_LEN,
  DEBUG_WINDOW_CODES, DEBUG_CB_ROWPTR, DEBUG_CB_COL, DEBUG_CB_VAL,
  DEBUG_MLP_BOUNDS, DEBUG_MLP_TIMES, DEBUG_MLP_RATIOS, DEBUG_IMB_SPANS,
- DEBUG_BANDWIDTH, DEBUG_WINDOW_RUNS) = range(20)
+ DEBUG_BANDWIDTH, DEBUG_WINDOW_RUNS, DEBUG_CB_ROWS, DEBUG_CB_ROWLIST_PTR) = range(22)
 
 STATUS = ["CSR_OK", "CSR_ERR_INVALID_ARG", "CSR_ERR_INVALID_MATRIX", "CSR_ERR_OUT_OF_MEMORY",
           "CSR_ERR_DEVICE", "CSR_ERR_UNSUPPORTED", "CSR_ERR_NOT_READY"]

@@ -183,9 +183,14 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
         hipError_t e = hipSuccess;
         for (int b = 0; b < P.cblocks && e == hipSuccess; ++b) {
             const int64_t o = A->cb_nnz_off[b];
-            const void *ab[8] = {A->cb_rp.as<int32_t>() + (size_t)b * (n + 1),
+            // split rows: the blocks after the first run over their row lists
+            const bool list = A->cb_split && b > 0;
+            const void *ab[8] = {list ? A->cb_rrp.as<int32_t>() + A->cb_rrp_off[b]
+                                      : A->cb_rp.as<int32_t>() + (size_t)b * (n + 1),
                                  A->cb_col.as<int32_t>() + o, nullptr,
                                  A->cb_val.as<char>() + vb * (size_t)o, x, y, nullptr, nullptr};
+            const int32_t *rid = list ? A->cb_rid.as<int32_t>() + A->cb_rid_off[b] : nullptr;
+            const int32_t nb = list ? (int32_t)A->cb_rows[b] : n;
             const int32_t *ti = A->cb_tile_i.as<int32_t>() + A->cb_tile_off[b];
             const int32_t *tj = A->cb_tile_j.as<int32_t>() + A->cb_tile_off[b];
             hipEvent_t ev = b + 1 == P.cblocks ? after : nullptr;
@@ -193,15 +198,15 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
             switch (A->storage) {
             case CSR_VAL_F64:
                 e = launch_merge_s0(ipt, false, x32, fix, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
-                                    A->carry.p, n, T, ev, s, b > 0);
+                                    A->carry.p, nb, T, ev, s, b > 0, rid);
                 break;
             case CSR_VAL_F32:
                 e = launch_merge_s1(ipt, false, x32, fix, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
-                                    A->carry.p, n, T, ev, s, b > 0);
+                                    A->carry.p, nb, T, ev, s, b > 0, rid);
                 break;
             default:
                 e = launch_merge_s2(ipt, false, x32, fix, IDX_I32, nullptr, A->n_cols, ab, ti, tj,
-                                    A->carry.p, n, T, ev, s, b > 0);
+                                    A->carry.p, nb, T, ev, s, b > 0, rid);
                 break;
             }
         }
@@ -330,6 +335,7 @@ void csr_config_default(csr_config_t *cfg) {
     cfg->t_imb = 1.0;
     cfg->t_mb = 0.5;
     cfg->remedy_map = 1;
+    cfg->split_row_blocks = 1;
     cfg->long_row_factor = 32.0;
     cfg->long_row_floor = 4096;
     cfg->forced_opts = 0;
@@ -585,6 +591,18 @@ csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t by
         if (A->wruns_state == 1) {
             src = A->wruns.p;
             n = sizeof(int32_t) * kRunWords * (size_t)A->n_tiles;
+        }
+        break;
+    case 20:  // column blocks over row lists: the rows of blocks 1 .. B-1
+        if (A->cb_B > 0 && A->cb_split) {
+            src = A->cb_rid.p;
+            n = sizeof(int32_t) * (size_t)A->cb_rid_off[A->cb_B];
+        }
+        break;
+    case 21:  // ... and their row pointers
+        if (A->cb_B > 0 && A->cb_split) {
+            src = A->cb_rrp.p;
+            n = sizeof(int32_t) * (size_t)A->cb_rrp_off[A->cb_B];
         }
         break;
     case 14:

@@ -31,6 +31,7 @@ struct BatchMat {
     int32_t n_cols;
     int32_t skip_above;         // row split: longer rows belong to the long-row pass
     int32_t acc;                // merge path, column blocks after the first: y += A x
+    const int32_t *rowid;       // merge path, a column block over its rows: y's row of each
     int64_t item_base;          // first item of this matrix in its class's queue
     int64_t item_base2;         // long-row pass: first long row in the second queue
 };

@@ -114,6 +114,11 @@ void plan_classes(BatchPlan &B, const csr_matrix_t *h_A, const void *const *x, v
                 BatchMat M = base_desc(A, x[k], y[k]);
                 const int64_t o = A->cb_nnz_off[b];
                 M.rp = A->cb_rp.as<int32_t>() + (size_t)b * (A->n_rows + 1);
+                if (A->cb_split && b > 0) {  // split rows: the block's row list
+                    M.rp = A->cb_rrp.as<int32_t>() + A->cb_rrp_off[b];
+                    M.rowid = A->cb_rid.as<int32_t>() + A->cb_rid_off[b];
+                    M.n_rows = (int32_t)A->cb_rows[b];
+                }
                 M.col = A->cb_col.as<int32_t>() + o;
                 M.val = A->cb_val.as<char>() + vb * (size_t)o;
                 M.tile_i = A->cb_tile_i.as<int32_t>() + A->cb_tile_off[b];

@@ -123,6 +123,14 @@ struct csr_matrix_s {
     std::vector<int64_t> cb_nnz_off;    // cb_B + 1: first nonzero of each block
     std::vector<int64_t> cb_tile_off;   // cb_B + 1: first tile-table entry of each block
     std::vector<int64_t> cb_tiles;      // T_b
+    // tiles that are not row-aligned: blocks b >= 1 run over the rows with
+    // nonzeros in them (block 0 over every row, so that it writes all of y)
+    int32_t cb_split = 0;
+    csr::DevBuf cb_rid;                 // those rows, block after block
+    csr::DevBuf cb_rrp;                 // their row pointers (n_b + 1 each, from 0)
+    std::vector<int64_t> cb_rows;       // n_b (block 0: n_rows)
+    std::vector<int64_t> cb_rid_off;    // first row-list entry of each block (block 0: unused)
+    std::vector<int64_t> cb_rrp_off;    // first row pointer of each block (block 0: unused)
     csr::DevBuf carry;             // per-tile carry of the merge-path kernel
     int64_t n_tiles = 0;
     int32_t tiles_L = 0;
@@ -218,15 +226,18 @@ constexpr int32_t kMergeRowAlignMax = 64;
 hipError_t launch_merge_s0(int ipt, bool nt, bool x32, bool fixup, int idx,
                            const int32_t *tile_base, int32_t n_cols, const void *const *arr,
                            const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
-                           hipEvent_t after_main, hipStream_t s, bool acc = false);
+                           hipEvent_t after_main, hipStream_t s, bool acc = false,
+                           const int32_t *rowid = nullptr);
 hipError_t launch_merge_s1(int ipt, bool nt, bool x32, bool fixup, int idx,
                            const int32_t *tile_base, int32_t n_cols, const void *const *arr,
                            const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
-                           hipEvent_t after_main, hipStream_t s, bool acc = false);
+                           hipEvent_t after_main, hipStream_t s, bool acc = false,
+                           const int32_t *rowid = nullptr);
 hipError_t launch_merge_s2(int ipt, bool nt, bool x32, bool fixup, int idx,
                            const int32_t *tile_base, int32_t n_cols, const void *const *arr,
                            const int32_t *tile_i, const int32_t *tile_j, void *carry, int32_t n_rows, int64_t n_tiles,
-                           hipEvent_t after_main, hipStream_t s, bool acc = false);
+                           hipEvent_t after_main, hipStream_t s, bool acc = false,
+                           const int32_t *rowid = nullptr);
 hipError_t launch_fill_row_index(const int32_t *rp, int32_t n_rows, int32_t n_cols, int32_t *out,
                                  hipStream_t s);
 hipError_t launch_convert_values(const double *src, void *dst, int64_t n, int storage,

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(kMergeBlock) void k_bmerge(const BatchMat *__restri
         merge_tile<S, IPT, NT, Lds, X32, IDX, ALN>(
             g - M.item_base, M.rp, cols, (const V *)M.val, (const X *)M.x, (X *)M.y, M.tile_i,
             M.tile_j, (A *)M.carry, M.n_rows, lds, M.tile_base, M.n_cols, M.wdict, M.wlen,
-            M.acc != 0);
+            M.acc != 0, M.rowid);
         wave_lds_sync();  // LDS is reused by the next item
     }
 }
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_bmerge_fixup(const BatchMat *__restr
     if (g >= n_items) return;
     const BatchMat &M = mats[item_mat[g]];
     merge_fixup_tile<S>(g - M.item_base, M.rp, M.tile_i, M.tile_j, (const A *)M.carry, (X *)M.y,
-                        M.n_rows);
+                        M.n_rows, M.rowid);
 }
 
 __global__ __launch_bounds__(kBlock) void k_blong_partial(const BatchMat *__restrict__ mats,

@@ -42,9 +42,10 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup(const int32_t *__restric
                                                         const int32_t *__restrict__ tile_j,
                                                         const A *__restrict__ carry,
                                                         X *__restrict__ y, int32_t n_rows,
-                                                        int64_t n_tiles) {
+                                                        int64_t n_tiles,
+                                                        const int32_t *__restrict__ rowid) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (t < n_tiles) merge_fixup_tile<S>(t, rp, tile_i, tile_j, carry, y, n_rows);
+    if (t < n_tiles) merge_fixup_tile<S>(t, rp, tile_i, tile_j, carry, y, n_rows, rowid);
 }
 
 struct MergeArgs {
@@ -56,6 +57,7 @@ struct MergeArgs {
     bool fixup;
     hipEvent_t after_main;
     bool acc;
+    const int32_t *rowid;  // rows as a list (column block over its rows), or null
 };
 
 // After the main kernel: the caller's event, then (tiles not row-aligned)
@@ -65,7 +67,8 @@ hipError_t after_main(hipError_t e, bool aln, const MergeArgs &a, hipStream_t s)
     if (e != hipSuccess || a.n_tiles < 2 || aln) return e;
     const unsigned fb = (unsigned)((a.n_tiles + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_merge_fixup, dim3(fb), dim3(kBlock), 0, s, (const int32_t *)a.arr[0],
-                       a.tile_i, a.tile_j, (const A *)a.carry, (X *)a.arr[5], a.n_rows, a.n_tiles);
+                       a.tile_i, a.tile_j, (const A *)a.carry, (X *)a.arr[5], a.n_rows, a.n_tiles,
+                       a.rowid);
     return hipGetLastError();
 }
 
@@ -78,7 +81,8 @@ hipError_t go(const MergeArgs &a, hipStream_t s) {
                        0, s, (const int32_t *)a.arr[0], cols, (const V *)a.arr[3],
                        (const X *)a.arr[4], (X *)a.arr[5], a.tile_i, a.tile_j, a.tile_base,
                        (A *)a.carry, a.n_rows, a.n_cols, g.per_xcd, a.n_tiles,
-                       (const uint16_t *)a.arr[6], (const int32_t *)a.arr[7], (int32_t)a.acc);
+                       (const uint16_t *)a.arr[6], (const int32_t *)a.arr[7], (int32_t)a.acc,
+                       a.rowid);
     return after_main(hipGetLastError(), ALN, a, s);
 }
 
@@ -104,8 +108,10 @@ hipError_t go_jit(int ipt, bool nt, bool x32, int idx, bool aln, const MergeArgs
     int64_t per_xcd = g.per_xcd, n_tiles = a.n_tiles;
     const uint16_t *wdict = (const uint16_t *)a.arr[6];
     const int32_t *wlen = (const int32_t *)a.arr[7];
+    const int32_t *rowid = a.rowid;
     void *args[] = {&rp,     &cols,    &val,    &x,     &y,     &ti,   &tj,   &tb,
-                    &carry,  &n_rows,  &n_cols, &per_xcd, &n_tiles, &wdict, &wlen, &acc};
+                    &carry,  &n_rows,  &n_cols, &per_xcd, &n_tiles, &wdict, &wlen, &acc,
+                    &rowid};
     e = hipModuleLaunchKernel(f, (unsigned)g.launched, 1, 1, kMergeBlock, 1, 1, 0, s, args,
                               nullptr);
     return after_main(e, aln, a, s);
@@ -142,9 +148,10 @@ hipError_t CSR_CAT(launch_merge_s, CSR_STORAGE)(int ipt, bool nt, bool x32, bool
                                                 const void *const *arr, const int32_t *tile_i,
                                                 const int32_t *tile_j, void *carry, int32_t n_rows,
                                                 int64_t n_tiles, hipEvent_t after_main,
-                                                hipStream_t s, bool acc) {
+                                                hipStream_t s, bool acc, const int32_t *rowid) {
+    if (rowid && !fixup) return hipErrorInvalidValue;  // row lists only on split rows
     const MergeArgs a{arr, tile_i, tile_j, tile_base, carry, n_rows, n_cols, n_tiles, fixup,
-                      after_main, acc};
+                      after_main, acc, rowid};
     // row-aligned tiles (no fixup) reduce by rows, the others by a
     // segmented scan with carries
     switch (ipt) {

@@ -25,7 +25,8 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge(
     const int32_t *__restrict__ tile_i, const int32_t *__restrict__ tile_j,
     const int32_t *__restrict__ tile_base, typename St<CSR_STORAGE>::A *__restrict__ carry,
     int32_t n_rows, int32_t n_cols, int64_t per_xcd, int64_t n_tiles,
-    const uint16_t *__restrict__ wdict, const int32_t *__restrict__ wlen, int32_t acc) {
+    const uint16_t *__restrict__ wdict, const int32_t *__restrict__ wlen, int32_t acc,
+    const int32_t *__restrict__ rowid) {
     constexpr int S = CSR_STORAGE;
     using Lds = std::conditional_t<ALN, MergeLdsRows<S, IPT>, MergeLds<S, IPT>>;
     __shared__ Lds lds;
@@ -33,7 +34,7 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge(
     if (t >= n_tiles) return;
     merge_tile<S, IPT, NT, Lds, X32, IDX, ALN>(t, rp, cols, val, x, y, tile_i, tile_j, carry,
                                                 n_rows, lds, tile_base, n_cols, wdict, wlen,
-                                                acc != 0);
+                                                acc != 0, rowid);
 }
 
 #ifndef __HIPCC_RTC__

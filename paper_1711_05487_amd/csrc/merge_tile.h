@@ -267,14 +267,17 @@ __device__ __forceinline__ void merge_gather(const MergeTileRegs<S, IPT, IDX> &R
 // Stage 3: products, segmented scan, rows and carry. With `acc` (a column
 // block after the first) the tile's part of each row ending in it is added
 // to y, and a row without nonzeros here keeps y; the fixup pass then adds
-// the carries as without `acc`.
+// the carries as without `acc`. With `rowid` the rows are a list (a column
+// block over the rows with nonzeros in it): row r of the list is y's row
+// rowid[r].
 template <int S, int IPT, class LDS, int IDX = IDX_I32>
 __device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT, IDX> &R,
                                              const typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX>::NIT]
                                                                           [MergeTileRegs<S, IPT, IDX>::VEC],
                                              typename St<S>::X *__restrict__ y,
                                              typename St<S>::A *__restrict__ carry,
-                                             int32_t n_rows, LDS &lds, bool acc = false) {
+                                             int32_t n_rows, LDS &lds, bool acc = false,
+                                             const int32_t *__restrict__ rowid = nullptr) {
     using X = typename St<S>::X;
     using A = typename St<S>::A;
     constexpr int VEC = MergeTileRegs<S, IPT, IDX>::VEC, NIT = MergeTileRegs<S, IPT, IDX>::NIT;
@@ -358,7 +361,6 @@ __device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT, ID
 
     // 4. rows: y = segment sum at the row's last nonzero, 0 for a row with no
     //    nonzeros in this tile
-    X *yb = y + i0;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         if (q * BS < nre) {
@@ -371,8 +373,9 @@ __device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT, ID
             const int32_t start = r == 0 ? 0 : prev;
             const A sum = s_prod[off + max(re[q] - 1, 0)];
             if (r < nre) {
-                if (re[q] > start) yb[r] = acc ? (X)((A)yb[r] + sum) : (X)sum;
-                else if (!acc) yb[r] = X(0);
+                X *yr = y + (rowid ? rowid[i0 + r] : i0 + r);
+                if (re[q] > start) *yr = acc ? (X)((A)*yr + sum) : (X)sum;
+                else if (!acc) *yr = X(0);
             }
         }
     }
@@ -768,8 +771,11 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
                                            int32_t n_cols = 0,
                                            const uint16_t *__restrict__ wdict = nullptr,
                                            const int32_t *__restrict__ wlen = nullptr,
-                                           bool acc = false) {
+                                           bool acc = false,
+                                           const int32_t *__restrict__ rowid = nullptr) {
     static_assert((IDX != IDX_W8 && IDX != IDX_R8) || ALN, "window codes need row-aligned tiles");
+    // row lists (`rowid`) only on tiles that are not row-aligned
+    if constexpr (ALN) (void)rowid;
     if constexpr (IDX == IDX_R8) {
         // `wlen` holds the tiles' run records
         (void)carry;
@@ -812,7 +818,7 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
         merge_issue<S, IPT, NT, IDX>(t, rp, cols, val, tile_i, tile_j, tile_base, R);
         typename St<S>::X xs[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC];
         merge_gather<S, IPT, X32, IDX>(R, x, n_cols, xs);
-        merge_finish<S, IPT, LDS, IDX>(t, R, xs, y, carry, n_rows, lds, acc);
+        merge_finish<S, IPT, LDS, IDX>(t, R, xs, y, carry, n_rows, lds, acc, rowid);
     }
 }
 
@@ -825,7 +831,8 @@ __device__ __forceinline__ void merge_fixup_tile(int64_t t, const int32_t *__res
                                                  const int32_t *__restrict__ tile_j,
                                                  const typename St<S>::A *__restrict__ carry,
                                                  typename St<S>::X *__restrict__ y,
-                                                 int32_t n_rows) {
+                                                 int32_t n_rows,
+                                                 const int32_t *__restrict__ rowid = nullptr) {
     using X = typename St<S>::X;
     using A = typename St<S>::A;
     if (t < 1) return;
@@ -835,7 +842,8 @@ __device__ __forceinline__ void merge_fixup_tile(int64_t t, const int32_t *__res
     while (ta > 0 && tile_i[ta] == r) --ta;  // tile ta ended inside row r, so did ta+1..t-1
     A sum = A(0);
     for (int64_t q = ta; q < t; ++q) sum += carry[q];
-    y[r] = (X)(sum + (A)y[r]);
+    X *yr = y + (rowid ? rowid[r] : r);
+    *yr = (X)(sum + (A)*yr);
 }
 
 }  // namespace csr

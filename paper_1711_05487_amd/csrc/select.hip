@@ -72,6 +72,13 @@ double plan_bytes(const csr_matrix_s *A, const Plan &P) {
                  xb2 * A->n_rows * (2.0 * B - 2.0);
             if (A->tiles_fixup)  // every pass's carries, not the single pass's
                 b += 2.0 * ab * ((double)A->cb_tile_off[P.cblocks] - B - T);
+            if (A->cb_split) {
+                // passes after the first: row pointers, row list and y of
+                // their rows only
+                b -= 4.0 * (A->n_rows + 1) * (B - 1.0) + xb2 * A->n_rows * (2.0 * B - 2.0);
+                for (int q = 1; q < P.cblocks; ++q)
+                    b += 4.0 * (2.0 * (double)A->cb_rows[q] + 1.0) + 2.0 * xb2 * (double)A->cb_rows[q];
+            }
         }
     }
     if (P.long_rows && A->n_long > 0) {
@@ -352,21 +359,61 @@ csr_status_t build_colblocks(csr_matrix_s *A, int B, int L, hipStream_t s) {
                                     A->cb_col.as<int32_t>(), A->cb_val.p, s));
     // each block's merge tiles (its rows are no longer than the matrix's, so
     // the matrix's slack keeps them row-aligned)
-    std::vector<int64_t> tiles((size_t)B), tile_off((size_t)B + 1, 0);
     const int64_t slack = merge_slack(A, L);
+    // tiles that are not row-aligned: blocks after the first walk only the
+    // rows with nonzeros in them (a row list; y is reached through it), so
+    // that a block does not pay a path step for every row of the matrix
+    const bool split = slack == 0;
+    std::vector<int64_t> rows((size_t)B, n), rid_off((size_t)B + 1, 0), rrp_off((size_t)B + 1, 0);
+    std::vector<int32_t> rid, rrp;
+    if (split) {
+        for (int b = 1; b < B; ++b) {
+            const int32_t *cnt_b = c.data() + (size_t)b * n;
+            rrp.push_back(0);
+            int64_t run = 0, k = 0;
+            for (int32_t i = 0; i < n; ++i) {
+                if (cnt_b[i] == 0) continue;
+                rid.push_back(i);
+                run += cnt_b[i];
+                rrp.push_back((int32_t)run);
+                ++k;
+            }
+            rows[b] = k;
+            rid_off[b + 1] = rid_off[b] + k;
+            rrp_off[b + 1] = rrp_off[b] + k + 1;
+        }
+        if ((st = A->cb_rid.alloc(sizeof(int32_t) * std::max<size_t>(rid.size(), 1))) != CSR_OK)
+            return st;
+        if ((st = A->cb_rrp.alloc(sizeof(int32_t) * std::max<size_t>(rrp.size(), 1))) != CSR_OK)
+            return st;
+        if (!rid.empty())
+            CSR_HIP(hipMemcpyAsync(A->cb_rid.p, rid.data(), sizeof(int32_t) * rid.size(),
+                                   hipMemcpyHostToDevice, s));
+        if (!rrp.empty())
+            CSR_HIP(hipMemcpyAsync(A->cb_rrp.p, rrp.data(), sizeof(int32_t) * rrp.size(),
+                                   hipMemcpyHostToDevice, s));
+    }
+    std::vector<int64_t> tiles((size_t)B), tile_off((size_t)B + 1, 0);
     for (int b = 0; b < B; ++b) {
-        const int64_t total = (int64_t)n + (nnz_off[b + 1] - nnz_off[b]);
+        const int64_t total = rows[b] + (nnz_off[b + 1] - nnz_off[b]);
         tiles[b] = (total + (L - slack) - 1) / (L - slack);
         tile_off[b + 1] = tile_off[b] + tiles[b] + 1;
     }
     if ((st = A->cb_tile_i.alloc(sizeof(int32_t) * (size_t)tile_off[B])) != CSR_OK) return st;
     if ((st = A->cb_tile_j.alloc(sizeof(int32_t) * (size_t)tile_off[B])) != CSR_OK) return st;
-    for (int b = 0; b < B; ++b)
-        CSR_HIP(launch_merge_partition(A->cb_rp.as<int32_t>() + (size_t)b * (n + 1), n,
-                                       nnz_off[b + 1] - nnz_off[b], L, slack, tiles[b],
-                                       A->cb_tile_i.as<int32_t>() + tile_off[b],
+    for (int b = 0; b < B; ++b) {
+        const int32_t *rpb_dev = split && b > 0
+                                     ? A->cb_rrp.as<int32_t>() + rrp_off[b]
+                                     : A->cb_rp.as<int32_t>() + (size_t)b * (n + 1);
+        CSR_HIP(launch_merge_partition(rpb_dev, (int32_t)rows[b], nnz_off[b + 1] - nnz_off[b], L,
+                                       slack, tiles[b], A->cb_tile_i.as<int32_t>() + tile_off[b],
                                        A->cb_tile_j.as<int32_t>() + tile_off[b], s));
+    }
     CSR_HIP(hipStreamSynchronize(s));
+    A->cb_split = split ? 1 : 0;
+    A->cb_rows = rows;
+    A->cb_rid_off = rid_off;
+    A->cb_rrp_off = rrp_off;
     A->cb_B = B;
     A->cb_width = width;
     A->cb_L = L;
@@ -522,10 +569,10 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
             // int32 columns (no codes asked for, or the matrix is not
             // eligible for them): the merge path keeps its gathers inside
             // the L2, with column blocks when x outgrows it and the rows'
-            // columns spread over it (on tiles that are not row-aligned,
-            // on request: every pass then carries its split rows through
-            // the fixup and walks every row end again, which pays only
-            // where the gathers miss)
+            // columns spread over it (on tiles that are not row-aligned
+            // as well, unless turned off: every pass then carries its split
+            // rows through the fixup, and the passes after the first walk
+            // only the rows with nonzeros in their block)
             if (!A->has_features && (st = inspect(A, s)) != CSR_OK) return st;
             const int B = column_blocks_for(A);
             if (B >= 2) {

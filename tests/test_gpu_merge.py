@@ -277,8 +277,8 @@ def test_column_blocks_with_split_rows(rmat21):
     n, m, rp, col, val = rmat21
     dv = _dyadic(val, 43)
     A = pkg.CsrMatrix(rp, col, dv, n_cols=m)
-    # off by default on tiles that are not row-aligned
-    assert A.select("forced", forced_opts=M, merge_items=512)["column_blocks"] == 0
+    # on tiles that are not row-aligned unless turned off
+    assert A.select("forced", forced_opts=M, merge_items=512, split_row_blocks=0)["column_blocks"] == 0
     for opts in (M, M | pkg.OPT_DELTA):  # no eligible codes: the same blocks
         info = A.select("forced", forced_opts=opts, merge_items=512, split_row_blocks=1)
         assert info["merge_slack"] == 0 and info["delta_bits"] == 32
@@ -289,6 +289,10 @@ def test_column_blocks_with_split_rows(rmat21):
     assert np.array_equal(A.debug_copy(pkg.DEBUG_CB_ROWPTR, np.int32), rpb.ravel())
     assert np.array_equal(A.debug_copy(pkg.DEBUG_CB_COL, np.int32), colb)
     assert np.array_equal(A.debug_copy(pkg.DEBUG_CB_VAL, np.float64), valb)
+    rows, ptr = oracle.column_block_rows(rpb)  # blocks after the first: row lists
+    assert rows.size < (B - 1) * n
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_CB_ROWS, np.int32), rows)
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_CB_ROWLIST_PTR, np.int32), ptr)
     x = synth.dyadic_vector(m, 44)
     y = run(A, x)
     assert np.array_equal(y, oracle.spmv(rp, col, dv, x))

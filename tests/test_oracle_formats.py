@@ -610,3 +610,39 @@ def test_column_blocks_sum_to_the_product():
             y = y + oracle.spmv(rpb[b], colb[off:off + k], valb[off:off + k], x)
             off += k
         assert np.array_equal(y, oracle.spmv(rp, col, val, x))
+
+
+def test_column_block_rows_by_brute_force():
+    """Row lists of blocks 1 .. B-1: the rows with a nonzero whose column lies
+    in the block (Python sets over the CSR itself), ascending, with row
+    pointers counting those nonzeros; and the block products through the
+    lists add up to the product (dyadic inputs, bit-exact)."""
+    n, m, rp, col, val = synth.tiny_random(300, 900, 0.01, 35, dyadic=True)
+    x = synth.dyadic_vector(m, 7)
+    for B in (2, 3, 8):
+        width = (m + B - 1) // B
+        rpb, colb, valb = oracle.column_blocks(rp, col, val, B, width)
+        rows, ptr = oracle.column_block_rows(rpb)
+        ro = po = 0
+        y = oracle.spmv(rpb[0], colb[:rpb[0][-1]], valb[:rpb[0][-1]], x)
+        off = int(rpb[0][-1])
+        for b in range(1, B):
+            want = sorted({i for i in range(n) for j in range(rp[i], rp[i + 1])
+                           if b * width <= col[j] < (b + 1) * width})
+            k = len(want)
+            assert list(rows[ro:ro + k]) == want
+            p = ptr[po:po + k + 1]
+            assert p[0] == 0
+            counts = [sum(1 for j in range(rp[i], rp[i + 1]) if b * width <= col[j] < (b + 1) * width)
+                      for i in want]
+            assert list(np.diff(p)) == counts
+            nb = int(p[-1])
+            part = oracle.spmv(p, colb[off:off + nb], valb[off:off + nb], x)
+            y[want] = y[want] + part
+            off += nb
+            ro += k
+            po += k + 1
+        assert ro == rows.size and po == ptr.size
+        if B == 8:  # rows without nonzeros in some blocks are left out
+            assert rows.size < (B - 1) * n
+        assert np.array_equal(y, oracle.spmv(rp, col, val, x))
