@@ -48,7 +48,7 @@ typedef enum {
     CSR_ERR_INVALID_MATRIX = 2,  /* the CSR arrays violate the format */
     CSR_ERR_OUT_OF_MEMORY = 3,   /* a device or host allocation failed */
     CSR_ERR_DEVICE = 4,          /* a HIP runtime call failed */
-    CSR_ERR_UNSUPPORTED = 5,     /* e.g. nnz >= 2^31, delta codes on unsorted rows */
+    CSR_ERR_UNSUPPORTED = 5,     /* e.g. nnz > 2^31 - 4096, delta codes on unsorted rows */
     CSR_ERR_NOT_READY = 6        /* e.g. learned selection without loaded weights */
 } csr_status_t;
 
@@ -205,7 +205,8 @@ void csr_config_default(csr_config_t *cfg);
  * Synchronizes `stream` before returning, so the caller may free its arrays.
  * The plan starts as CSR_SEL_PLAIN. Errors: CSR_ERR_INVALID_ARG (NULL out,
  * negative sizes, NULL arrays with nnz > 0), CSR_ERR_UNSUPPORTED
- * (nnz >= 2^31), CSR_ERR_INVALID_MATRIX (no handle is created),
+ * (nnz > 2^31 - 4096: indices are int32 and loop indices step past the last
+ * nonzero by up to a workgroup), CSR_ERR_INVALID_MATRIX (no handle is created),
  * CSR_ERR_OUT_OF_MEMORY, CSR_ERR_DEVICE. On error *out is NULL.
  */
 csr_status_t csr_create(csr_matrix_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz,
@@ -266,7 +267,7 @@ csr_status_t csr_spmv_batched(int32_t count, const csr_matrix_t *h_A,
  * fixed array (it holds two counters whatever the size). Calls that overlap
  * on one GPU (e.g. on two streams) share the array and race: order them.
  * Asynchronous on `stream`. Errors: CSR_ERR_INVALID_ARG (negative sizes,
- * NULL arrays, x and y overlapping), CSR_ERR_UNSUPPORTED (nnz >= 2^31),
+ * NULL arrays, x and y overlapping), CSR_ERR_UNSUPPORTED (nnz > 2^31 - 4096),
  * CSR_ERR_DEVICE.
  */
 csr_status_t csr_spmv_noalloc(int32_t n_rows, int32_t n_cols, int64_t nnz,

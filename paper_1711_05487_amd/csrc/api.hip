@@ -369,7 +369,7 @@ csr_status_t csr_create(csr_matrix_t *out, int32_t n_rows, int32_t n_cols, int64
     *out = nullptr;
     if (n_rows < 0 || n_cols < 0 || nnz < 0)
         return fail(CSR_ERR_INVALID_ARG, "negative size");
-    if (nnz >= (int64_t)INT32_MAX) return fail(CSR_ERR_UNSUPPORTED, "nnz >= 2^31 - 1");
+    if (nnz > kMaxNnz) return fail(CSR_ERR_UNSUPPORTED, "nnz > 2^31 - 4096");
     if (!d_row_ptr || (nnz > 0 && (!d_col_idx || !d_val)))
         return fail(CSR_ERR_INVALID_ARG, "NULL array");
     if (storage < CSR_VAL_F64 || storage > CSR_VAL_BF16)

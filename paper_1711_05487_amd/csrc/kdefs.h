@@ -24,6 +24,10 @@ constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies
 // the tile's values instead of after a dictionary load
 enum IdxMode { IDX_I32 = 0, IDX_D16 = 1, IDX_D8 = 2, IDX_W8 = 3, IDX_R8 = 4 };
 constexpr int kWindowMax = 256;  // window entries per tile (8-bit ranks)
+// Largest nonzero count: indices are int32, and a lane's loop index may step
+// up to one workgroup (256) past the last nonzero before it stops, so the
+// count keeps that much (and more) below 2^31.
+constexpr int64_t kMaxNnz = (int64_t)INT32_MAX - 4095;
 constexpr int kRunWords = 16;
 constexpr int kRunsMax = kRunWords - 2;
 

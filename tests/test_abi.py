@@ -45,6 +45,7 @@ def test_argument_errors_before_device_work():
     assert L.csr_create(ctypes.byref(h), -1, 1, 0, P(1), None, None, 0, None) == 1
     assert h.value is None
     assert L.csr_create(ctypes.byref(h), 2, 2, 1 << 31, P(1), P(1), P(1), 0, None) == 5
+    assert L.csr_create(ctypes.byref(h), 2, 2, (1 << 31) - 4095, P(1), P(1), P(1), 0, None) == 5
     assert L.csr_create(ctypes.byref(h), 2, 2, 3, P(1), None, P(1), 0, None) == 1
     assert L.csr_create(ctypes.byref(h), 2, 2, 3, P(1), P(1), P(1), 7, None) == 1
     assert L.csr_spmv(None, P(1), P(2), None) == 1

@@ -1,0 +1,87 @@
+"""The largest matrix the library takes: NNZ = 2^31 - 4096 (int32 indices;
+a lane's loop index may step a workgroup past the last nonzero). A
+65,536 x 32,768 matrix stored dense in CSR, the last row 4,096 nonzeros
+short, values a_ij = ((i + 3 j) mod 7) - 3 and a dyadic x: every partial sum
+is an exact multiple of 2^-10 below 2^17, so every plan must give the exact
+product, which a closed form gives row by row (y_i = sum over residues r of
+(((i + 3 r) mod 7) - 3) S_r, S_r the sum of x_j over j = r mod 7). Built on
+the GPU with PyTorch; about 60 GB of device memory."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1711_05487_amd as pkg
+import synth
+
+pytestmark = pytest.mark.gpu
+
+N_ROWS, N_COLS = 65_536, 32_768
+NNZ = N_ROWS * N_COLS - 4096
+assert NNZ == 2**31 - 4096
+
+
+def closed_form(x):
+    xs = np.asarray(x, dtype=np.float64)
+    i = np.arange(N_ROWS)
+    y = np.zeros(N_ROWS)
+    full = [xs[r::7].sum() for r in range(7)]            # exact: dyadic partial sums
+    last = [xs[:N_COLS - 4096][r::7].sum() for r in range(7)]
+    for r in range(7):
+        c = ((i + 3 * r) % 7) - 3
+        y[:-1] += c[:-1] * full[r]
+        y[-1] += c[-1] * last[r]
+    return y
+
+
+@pytest.fixture(scope="module")
+def big():
+    free, _ = torch.cuda.mem_get_info()
+    if free < 100 * 2**30:
+        pytest.skip("needs about 60 GB of free device memory")
+    from paper_1711_05487_amd import learn
+    learn.install()
+    dev = torch.device("cuda")
+    j = torch.arange(N_COLS, dtype=torch.int32, device=dev)
+    col = j.repeat(N_ROWS)[:NNZ]
+    ri = (torch.arange(N_ROWS, dtype=torch.int32, device=dev) % 7).to(torch.int16)
+    cj = ((3 * j) % 7).to(torch.int16)
+    val = ((ri[:, None] + cj[None, :]) % 7 - 3).reshape(-1)[:NNZ].to(torch.float64)
+    rp = torch.arange(N_ROWS + 1, dtype=torch.int64, device=dev) * N_COLS
+    rp[-1] = NNZ
+    A = pkg.CsrMatrix(rp.to(torch.int32), col, val, n_cols=N_COLS)
+    del col, val, ri, cj, j, rp
+    torch.cuda.empty_cache()
+    x = synth.dyadic_vector(N_COLS, 71)
+    yield A, x
+    A.close()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("opts", [None, 0, pkg.OPT_MERGE, pkg.OPT_MERGE | pkg.OPT_DELTA,
+                                  pkg.OPT_UNROLL, pkg.OPT_PREFETCH, pkg.OPT_DECOMP])
+def test_max_nnz_exact(big, opts):
+    A, x = big
+    if opts is None:
+        info = A.select("learned")
+    else:
+        info = A.select("forced", forced_opts=opts)
+    if opts is not None and opts & pkg.OPT_MERGE:
+        assert info["merge_slack"] == 0  # rows of 32,768: tiles split rows
+    if opts == pkg.OPT_MERGE | pkg.OPT_DELTA:
+        assert info["delta_bits"] == 16  # tile ranges fit 16 bits
+    xd = torch.from_numpy(x).cuda()
+    y = A.spmv(xd)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy(), closed_form(x)), info["opts"]
+
+
+def test_max_nnz_features_and_rejection(big):
+    A, x = big
+    f, isum, sorted_flag = A.inspect()
+    assert f[0] == N_ROWS and f[1] == N_COLS - 4096 and f[2] == N_COLS
+    assert f[3] == NNZ / N_ROWS
+    # one nonzero more than the maximum is refused before anything is read
+    import ctypes
+    h = ctypes.c_void_p()
+    P = ctypes.c_void_p
+    assert pkg.lib().csr_create(ctypes.byref(h), 2, 2, NNZ + 1, P(8), P(8), P(8), 0, None) == 5
