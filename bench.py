@@ -325,6 +325,7 @@ def main():
             "merge_items": info["merge_items"],
             "delta_bits": info["delta_bits"], "window_codes": bool(info["window_codes"]),
             "window_runs": info["window_codes"] == 2,
+            "window_rank_bits": 9 if info["window_codes"] == 3 else 8 if info["window_codes"] else 0,
             "pct_of_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
             "pct_of_triad": round(100 * gbs / triad, 2),
             "triad_gbs": round(triad, 1),
@@ -490,9 +491,11 @@ def suite(args):
                 mx, p99 = chk.rel_errors(ys)
                 fb = info["format_bytes"]
                 emit({"case": "C4", "config": tag, "storage": storage,
-                      "index": ("int32" if info["delta_bits"] == 32 else "window8"
-                                if info["window_codes"] else f"delta{info['delta_bits']}")
+                      "index": ("int32" if info["delta_bits"] == 32 else
+                                f"window{info['delta_bits']}" if info["window_codes"]
+                                else f"delta{info['delta_bits']}")
                       + (" runs" if info["window_codes"] == 2 else ""),
+                      "merge_items": info["merge_items"],
                       "opts": [nm for bit, nm in pkg.OPT_NAMES.items() if info["opts"] & bit],
                       "ms": round(t, 5), "kernel_ms": round(k_ms, 5), "format_bytes": fb,
                       "gbs": round(fb / (t * 1e-3) / 1e9, 1),

@@ -156,7 +156,10 @@ typedef struct {
                                 16-bit offsets from its smallest one, each nonzero the 8-bit
                                 rank of its column among them; 2: the same ranks, with each
                                 tile's distinct columns stored as at most 14 runs of
-                                consecutive columns (a 64-byte record per tile) */
+                                consecutive columns (a 64-byte record per tile); 3: 9-bit
+                                ranks (delta_bits 9) on tiles of 1,024 items, windows of up
+                                to 512 columns: the code is the rank's low byte, the ninth
+                                bits sit in a 132-byte record per tile */
     int32_t column_blocks;   /* > 1: the merge path runs once per column slab of at most
                                 2 MiB of x, each pass adding into y (merge plans without
                                 codes, when x outgrows one XCD's L2, rows are short and
@@ -315,8 +318,13 @@ csr_status_t csr_jit_compile(int32_t storage, int32_t merge_items, int32_t index
  *         column - smallest column of the nonzero's merge tile), 7 merge tile
  *         bases int32[T] (the smallest column of each tile), 8 window
  *         dictionaries uint16[T][256] (the tile's distinct columns, ascending,
- *         minus its base; zero past the window), 9 window lengths int32[T],
- *         10 window codes uint8[nnz] (rank of the column in its tile's window),
+ *         minus its base; zero past the window; [T][512] with 9-bit ranks),
+ *         9 window lengths int32[T] (9-bit ranks, on tiles of 1,024 items:
+ *         records int32[T][33], the length, then 64 uint16 masks: lane l's
+ *         bit it * v + e is the ninth rank bit of tile element
+ *         it * 64 v + l v + e, v = 2 for FP64 values and 4 otherwise),
+ *         10 window codes uint8[nnz] (rank of the column in its tile's window;
+ *         its low byte with 9-bit ranks),
  *         11 column-block row pointers int32[B][n_rows + 1] (each from 0),
  *         12 column-block columns int32[nnz] and 13 values (storage type,
  *         nnz): the blocks' nonzeros one block after the other, rows in

@@ -270,20 +270,45 @@ def window_codes(tj, col, maxw: int = 256):
     per tile t the ascending distinct columns u_0 < ... < u_{m-1}, stored as
     base_t = u_0 and dict[t, k] = u_k - u_0; per nonzero the rank of its
     column in the window. Returns (base, wlen, dict, codes) with dict of
-    shape (T, maxw), zero past wlen; None when some tile has more than maxw
-    distinct columns or a column range of 2^16 or more."""
+    shape (T, maxw), zero past wlen, and codes uint8 (maxw <= 256) or the
+    full uint16 ranks (windows of up to 512 entries); None when some tile
+    has more than maxw distinct columns or a column range of 2^16 or more."""
     tj = np.ascontiguousarray(tj, dtype=np.int32)
     col = np.ascontiguousarray(col, dtype=np.int32)
     T = tj.size - 1
     base = np.zeros(max(T, 1), dtype=np.int32)
     wlen = np.zeros(max(T, 1), dtype=np.int32)
     dct = np.zeros((max(T, 1), maxw), dtype=np.uint16)
-    codes = np.zeros(max(col.size, 1), dtype=np.uint8)
+    codes = np.zeros(max(col.size, 1), dtype=np.uint16)
     if not lib().or_window_codes(T, _p(tj), _p(col), maxw, _p(base), _p(wlen),
                                  dct.ctypes.data_as(ctypes.c_void_p),
                                  codes.ctypes.data_as(ctypes.c_void_p)):
         return None
-    return base[:T], wlen[:T], dct[:T], codes[:col.size]
+    codes = codes[:col.size]
+    return base[:T], wlen[:T], dct[:T], codes.astype(np.uint8) if maxw <= 256 else codes
+
+
+def window_rank_records(tj, ranks, wlen, vec: int, lanes: int = 64):
+    """Where 9-bit window ranks keep their ninth bit: per tile a record of
+    1 + lanes / 2 int32 words, [0] = the window length, then lanes 16-bit
+    masks (two per word, the lower lane in the low half). Lane l's mask has
+    bit it * vec + e set when the rank of tile element it * lanes * vec +
+    l * vec + e (the element that lane loads as entry e of its load block
+    it) is 256 or more."""
+    tj = np.asarray(tj, dtype=np.int64)
+    ranks = np.asarray(ranks, dtype=np.int64)
+    T = tj.size - 1
+    masks = np.zeros((max(T, 0), lanes), dtype=np.int64)
+    for t in range(T):
+        for p in range(int(tj[t + 1] - tj[t])):
+            if ranks[tj[t] + p] >= 256:
+                it, r = divmod(p, lanes * vec)
+                lane, e = divmod(r, vec)
+                masks[t, lane] |= 1 << (it * vec + e)
+    rec = np.zeros((max(T, 0), 1 + lanes // 2), dtype=np.int64)
+    rec[:, 0] = np.asarray(wlen, dtype=np.int64)[:T]
+    rec[:, 1:] = masks[:, 0::2] | (masks[:, 1::2] << 16)
+    return rec.astype(np.uint32).view(np.int32)
 
 
 def window_runs(tj, col, max_runs: int = 14):

@@ -307,8 +307,9 @@ int or_merge_codes(int64_t T, const int32_t *tj, const int32_t *col, int w,
 /* compression; x brought close before use, the counterpart of prefetching  */
 /* x). Tile t's distinct columns, ascending, u_0 < ... < u_{m-1}, form its  */
 /* window: base_t = u_0, dict[t][k] = u_k - u_0 (16 bits), and nonzero j    */
-/* of the tile stores the 8-bit rank k of col[j] in the window. Eligible    */
-/* iff every tile has m <= maxw (at most 256) and u_{m-1} - u_0 < 2^16.      */
+/* of the tile stores the rank k of col[j] in the window (8 bits for        */
+/* windows of up to 256 entries, 9 for up to 512). Eligible iff every tile  */
+/* has m <= maxw and u_{m-1} - u_0 < 2^16.                                   */
 /* dict is T rows of maxw entries, zero past wlen[t] = m. Returns 1 and     */
 /* fills the outputs when eligible, else 0.                                  */
 static int cmp_i32(const void *a, const void *b)
@@ -318,7 +319,7 @@ static int cmp_i32(const void *a, const void *b)
 }
 
 int or_window_codes(int64_t T, const int32_t *tj, const int32_t *col, int maxw,
-                    int32_t *base, int32_t *wlen, uint16_t *dict, uint8_t *codes)
+                    int32_t *base, int32_t *wlen, uint16_t *dict, uint16_t *codes)
 {
     int64_t cap = 0;
     for (int64_t t = 0; t < T; ++t)
@@ -346,7 +347,7 @@ int or_window_codes(int64_t T, const int32_t *tj, const int32_t *col, int maxw,
                 if (u[mid] < col[j]) lo = mid + 1;
                 else hi = mid;
             }
-            codes[j] = (uint8_t)lo;
+            codes[j] = (uint16_t)lo;
         }
     }
     free(u);

@@ -218,10 +218,10 @@ hipError_t launch_spmv(const csr_matrix_s *A, const Plan &P, const void *x, void
         auto ti = A->tile_i.as<int32_t>();
         auto tj = A->tile_j.as<int32_t>();
         const int32_t *tb = P.idx != IDX_I32 ? A->tile_base.as<int32_t>() : nullptr;
-        if (P.idx == IDX_W8) {
+        if (P.idx == IDX_W8 || P.idx == IDX_W9) {
             arr[2] = A->wcodes.p;
             arr[6] = A->wdict.p;
-            arr[7] = A->wlen.p;
+            arr[7] = A->wlen.p;  // lengths, or the 9-bit ranks' records
         } else if (P.idx == IDX_R8) {
             arr[2] = A->wcodes.p;
             arr[7] = A->wruns.p;  // the tiles' run records
@@ -554,13 +554,14 @@ csr_status_t csr_debug_copy(csr_matrix_t A, int32_t what, void *h_dst, size_t by
     case 8:  // window dictionaries
         if (A->wcode_state == 1) {
             src = A->wdict.p;
-            n = sizeof(uint16_t) * kWindowMax * (size_t)A->n_tiles;
+            n = sizeof(uint16_t) * (A->wcode_wide ? kWideWindowMax : kWindowMax) *
+                (size_t)A->n_tiles;
         }
         break;
-    case 9:  // window lengths
+    case 9:  // window lengths (9-bit ranks: the per-tile records)
         if (A->wcode_state == 1) {
             src = A->wlen.p;
-            n = sizeof(int32_t) * (size_t)A->n_tiles;
+            n = sizeof(int32_t) * (A->wcode_wide ? kWideWords : 1) * (size_t)A->n_tiles;
         }
         break;
     case 10:  // window codes

@@ -134,7 +134,7 @@ void plan_classes(BatchPlan &B, const csr_matrix_t *h_A, const void *const *x, v
             M.tile_i = A->tile_i.as<int32_t>();
             M.tile_j = A->tile_j.as<int32_t>();
             M.carry = A->carry.p;
-            if (P.idx == IDX_W8) {
+            if (P.idx == IDX_W8 || P.idx == IDX_W9) {
                 M.codes = A->wcodes.p;
                 M.wdict = A->wdict.as<uint16_t>();
                 M.wlen = A->wlen.as<int32_t>();

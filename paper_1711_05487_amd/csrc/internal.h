@@ -108,6 +108,8 @@ struct csr_matrix_s {
     csr::DevBuf wlen;              // window codes: window entries of each tile, T int32
     csr::DevBuf wcodes;            // window codes: per-nonzero rank in its tile's window (uint8)
     int32_t wcode_state = 0;       // 1 valid, -1 not eligible, 0 not built
+    int32_t wcode_wide = 0;        // 1: 9-bit ranks (IDX_W9): dictionaries of kWideWindowMax
+                                   // entries, wlen holds kWideWords-word records
     int32_t wcodes_L = 0;          // tile size the window codes were built for
     csr::DevBuf wruns;             // run windows: per tile kRunWords int32 (IDX_R8)
     int32_t wruns_state = 0;       // 1 valid, -1 not eligible, 0 not built
@@ -200,9 +202,12 @@ hipError_t launch_merge_encode(const int32_t *col, const int32_t *tile_j, int64_
 // (records of tiles over kRunsMax hold their first kRunsMax runs).
 hipError_t launch_window_runs(const uint16_t *dict, const int32_t *wlen, const int32_t *base,
                               int64_t n_tiles, int32_t *rec, int32_t *max_runs, hipStream_t s);
+// wide_vec > 0: 9-bit ranks (windows of up to kWideWindowMax entries; wlen
+// receives the per-tile records, masks laid out for `wide_vec` elements per
+// lane and load block)
 hipError_t launch_window_encode(const int32_t *col, const int32_t *tile_j, const int32_t *base,
                                 int64_t n_tiles, uint16_t *dict, int32_t *wlen, uint8_t *codes,
-                                int32_t *max_m, hipStream_t s);
+                                int32_t *max_m, hipStream_t s, int wide_vec = 0);
 // Column blocks: cnt[b * n_rows + i] = nonzeros of row i in column block b
 // (columns [b width, (b+1) width)); then every nonzero is copied to its
 // block, rows in order and storage order inside a row, at pos[b] = off[b] +

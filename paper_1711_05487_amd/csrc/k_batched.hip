@@ -115,6 +115,10 @@ hipError_t go_ipt(bool nt, bool x32, int idx, const BatchMat *mats, const int32_
     case IDX_R8:
         if constexpr (ALN) return go<IPT, true, false, IDX_R8, true>(mats, item_mat, n_items, n_cu, s);
         else return hipErrorInvalidValue;
+    case IDX_W9:
+        if constexpr (ALN && IPT == 16)
+            return go<IPT, true, false, IDX_W9, true>(mats, item_mat, n_items, n_cu, s);
+        else return hipErrorInvalidValue;
     default: break;
     }
     if (nt)

@@ -131,6 +131,9 @@ hipError_t go_ipt(bool nt, bool x32, int idx, const MergeArgs &a, hipStream_t s)
     case IDX_R8:
         if constexpr (ALN) return go<IPT, true, false, IDX_R8, true>(a, s);
         else return hipErrorInvalidValue;
+    case IDX_W9:  // 9-bit window ranks: tiles of 1,024 items only
+        if constexpr (ALN && IPT == 16) return go<IPT, true, false, IDX_W9, true>(a, s);
+        else return hipErrorInvalidValue;
     default: break;
     }
     if (nt)

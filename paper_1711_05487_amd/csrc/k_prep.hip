@@ -202,24 +202,31 @@ __global__ __launch_bounds__(kWave) void k_merge_encode(const int32_t *__restric
 
 // Window codes of row-aligned merge tiles (MB + ML remedies on the merge
 // path): tile t's distinct columns u_0 < ... < u_{m-1} are its x window,
-// stored as offsets from the tile base (dict, kWindowMax entries per tile,
-// zero past m), and each nonzero stores the rank of its column in the
-// window. One wave per tile (waves stride over the tiles): the columns mark
-// a bitmap of the tile's column range (< 2^16, checked beforehand) in LDS,
+// stored as offsets from the tile base (dict, WMAX entries per tile, zero
+// past m), and each nonzero stores the rank of its column in the window.
+// One wave per tile (waves stride over the tiles): the columns mark a
+// bitmap of the tile's column range (< 2^16, checked beforehand) in LDS,
 // per-word popcount prefixes give every column its rank, and the set bits,
 // in order, are the window. The largest m of every wave goes to *max_m
-// (one atomic per wave); a tile with m > kWindowMax writes nothing.
+// (one atomic per wave); a tile with m > WMAX writes nothing. With 9-bit
+// ranks (WMAX = kWideWindowMax) the code is the rank's low byte and `wrec`
+// holds per tile kWideWords words: m, then per lane a 16-bit mask of the
+// ranks' ninth bits for the lane's elements (element e of load block it
+// of lane l is tile element it * 64 vec + l vec + e; bit it * vec + e).
 constexpr int kWindowWords = 65536 / 32;
+template <int WMAX>
 __global__ __launch_bounds__(kWave) void k_window_encode(const int32_t *__restrict__ col,
                                                          const int32_t *__restrict__ tile_j,
                                                          const int32_t *__restrict__ base,
                                                          int64_t n_tiles,
                                                          uint16_t *__restrict__ dict,
-                                                         int32_t *__restrict__ wlen,
+                                                         int32_t *__restrict__ wrec,
                                                          uint8_t *__restrict__ codes,
-                                                         int32_t *__restrict__ max_m) {
+                                                         int32_t *__restrict__ max_m, int vec) {
+    constexpr bool WIDE = WMAX > kWindowMax;
     __shared__ uint32_t bm[kWindowWords];
     __shared__ uint16_t pre[kWindowWords];
+    __shared__ uint32_t hm[kWave];
     const int lane = threadIdx.x;
     int32_t most = 0;
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
@@ -234,6 +241,7 @@ __global__ __launch_bounds__(kWave) void k_window_encode(const int32_t *__restri
         }
         const int nw = (hi >> 5) + 1;
         for (int w = lane; w < nw; w += kWave) bm[w] = 0u;
+        if (WIDE) hm[lane] = 0u;
         __syncthreads();
         for (int32_t j = j0 + lane; j < j1; j += kWave) {
             const int32_t off = col[j] - b;
@@ -248,28 +256,37 @@ __global__ __launch_bounds__(kWave) void k_window_encode(const int32_t *__restri
         const int32_t incl = group_scan<kWave>(cnt, lane);
         const int32_t m = __shfl(incl, kWave - 1);
         most = max(most, m);
-        if (m <= kWindowMax) {
+        if (m <= WMAX) {
             int32_t run = incl - cnt;
             for (int w = w0; w < w1; ++w) {
                 pre[w] = (uint16_t)run;
                 uint32_t bits = bm[w];
                 while (bits) {
                     const int q = __ffs(bits) - 1;
-                    dict[t * kWindowMax + run] = (uint16_t)((w << 5) + q);
+                    dict[t * WMAX + run] = (uint16_t)((w << 5) + q);
                     bits &= bits - 1;
                     ++run;
                 }
             }
-            for (int k = m + lane; k < kWindowMax; k += kWave) dict[t * kWindowMax + k] = 0;
-            if (lane == 0) wlen[t] = m;
+            for (int k = m + lane; k < WMAX; k += kWave) dict[t * WMAX + k] = 0;
+            if (lane == 0) wrec[WIDE ? t * kWideWords : t] = m;
         }
         __syncthreads();
-        if (m <= kWindowMax) {
+        if (m <= WMAX) {
             for (int32_t j = j0 + lane; j < j1; j += kWave) {
                 const int32_t off = col[j] - b;
                 const int w = off >> 5;
                 const uint32_t below = bm[w] & ((1u << (off & 31)) - 1u);
-                codes[j] = (uint8_t)(pre[w] + __popc(below));
+                const int32_t r = pre[w] + __popc(below);
+                codes[j] = (uint8_t)r;
+                if (WIDE && r >= kWindowMax) {
+                    const int32_t p = j - j0, step = kWave * vec;
+                    atomicOr(&hm[(p % step) / vec], 1u << ((p / step) * vec + p % vec));
+                }
+            }
+            if (WIDE) {
+                __syncthreads();
+                reinterpret_cast<uint16_t *>(wrec + t * kWideWords + 1)[lane] = (uint16_t)hm[lane];
             }
         }
         __syncthreads();  // the bitmap is cleared for the next tile
@@ -442,12 +459,16 @@ hipError_t launch_merge_encode(const int32_t *col, const int32_t *tile_j, int64_
 
 hipError_t launch_window_encode(const int32_t *col, const int32_t *tile_j, const int32_t *base,
                                 int64_t n_tiles, uint16_t *dict, int32_t *wlen, uint8_t *codes,
-                                int32_t *max_m, hipStream_t s) {
+                                int32_t *max_m, hipStream_t s, int wide_vec) {
     if (n_tiles == 0) return hipSuccess;
     // 12 KiB of LDS per wave: about a dozen waves per CU
     const unsigned g = (unsigned)std::min<int64_t>(n_tiles, 256 * 12);
-    hipLaunchKernelGGL(k_window_encode, dim3(g), dim3(kWave), 0, s, col, tile_j, base, n_tiles,
-                       dict, wlen, codes, max_m);
+    if (wide_vec > 0)
+        hipLaunchKernelGGL(k_window_encode<kWideWindowMax>, dim3(g), dim3(kWave), 0, s, col,
+                           tile_j, base, n_tiles, dict, wlen, codes, max_m, wide_vec);
+    else
+        hipLaunchKernelGGL(k_window_encode<kWindowMax>, dim3(g), dim3(kWave), 0, s, col, tile_j,
+                           base, n_tiles, dict, wlen, codes, max_m, 1);
     return hipGetLastError();
 }
 

@@ -22,8 +22,15 @@ constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies
 // column minus [0] | its length << 16), which the tile reads with scalar
 // loads before any vector load, so its x window is loaded together with
 // the tile's values instead of after a dictionary load
-enum IdxMode { IDX_I32 = 0, IDX_D16 = 1, IDX_D8 = 2, IDX_W8 = 3, IDX_R8 = 4 };
+// IDX_W9: window codes with 9-bit ranks on tiles of 1,024 items (IPT 16):
+// windows of up to kWideWindowMax entries; the rank's low byte is the code,
+// its ninth bit sits in a per-tile record of kWideWords int32 words ([0] the
+// entry count, then one 16-bit mask per lane: bit it * VEC + e for the
+// lane's element e of load block it)
+enum IdxMode { IDX_I32 = 0, IDX_D16 = 1, IDX_D8 = 2, IDX_W8 = 3, IDX_R8 = 4, IDX_W9 = 5 };
 constexpr int kWindowMax = 256;  // window entries per tile (8-bit ranks)
+constexpr int kWideWindowMax = 512;
+constexpr int kWideWords = 1 + 64 / 2;
 // Largest nonzero count: indices are int32, and a lane's loop index may step
 // up to one workgroup (256) past the last nonzero before it stops, so the
 // count keeps that much (and more) below 2^31.

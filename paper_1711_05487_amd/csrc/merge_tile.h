@@ -134,6 +134,10 @@ template <> struct MergeCol<IDX_D16> { using type = uint16_t; };
 template <> struct MergeCol<IDX_D8> { using type = uint8_t; };
 template <> struct MergeCol<IDX_W8> { using type = uint8_t; };
 template <> struct MergeCol<IDX_R8> { using type = uint8_t; };
+template <> struct MergeCol<IDX_W9> { using type = uint8_t; };
+
+// Window entries each lane loads (entries lane + 64 k).
+template <int IDX> constexpr int window_per_lane() { return IDX == IDX_W9 ? 8 : 4; }
 
 // What a lane holds for one tile between issuing its loads and reducing it.
 template <int S, int IPT, int IDX = IDX_I32> struct MergeTileRegs {
@@ -151,7 +155,8 @@ template <int S, int IPT, int IDX = IDX_I32> struct MergeTileRegs {
     VV vv[NIT];              // values of the tile's window
     CV cv[NIT];              // columns (or codes) of the tile's window
     int32_t wl;              // window codes: entries of the tile's x window
-    uint16_t dv[4];          // window codes: entries lane + 64 k, k < 4
+    uint16_t dv[window_per_lane<IDX>()];  // window codes: entries lane + 64 k
+    uint32_t hi;             // 9-bit ranks: the lane's ninth-bit mask
     typename VecOf<typename St<S>::X, 4>::type wx;  // run windows: x at entries lane + 64 k
 };
 
@@ -194,7 +199,10 @@ __device__ __forceinline__ void merge_issue(int64_t t, const int32_t *__restrict
     // most BS rows (the common case), else IPT (zeros past the tile's rows)
     const uint32_t nre = (uint32_t)(R.i1 - R.i0);
     const auto rr = buffer_range(rp + R.i0 + 1, nre * (uint32_t)sizeof(int32_t));
-    if (nre <= (uint32_t)BS) {
+    // 9-bit ranks: only the first 64 row ends are held from here (the row
+    // sums read the others when a tile ends more than 64 rows), which keeps
+    // the kernel's registers, and so its occupancy, down
+    if (IDX == IDX_W9 || nre <= (uint32_t)BS) {
         R.re[0] = buffer_load<int32_t, false>(rr, tid * 4u, 0u);
 #pragma unroll
         for (int q = 1; q < IPT; ++q) R.re[q] = 0;
@@ -203,13 +211,22 @@ __device__ __forceinline__ void merge_issue(int64_t t, const int32_t *__restrict
         for (int q = 0; q < IPT; ++q)
             R.re[q] = buffer_load<int32_t, false>(rr, tid * 4u, (uint32_t)(q * BS * 4));
     }
-    if constexpr (IDX == IDX_W8) {
+    if constexpr (IDX == IDX_W8 || IDX == IDX_W9) {
         // the window's dictionary entries lane + 64 k: each load reads 64
-        // consecutive entries (entries past the window read zero)
-        R.wl = wlen[t];
-        const auto rd = buffer_range(wdict + t * kWindowMax, (uint32_t)R.wl * 2u);
+        // consecutive entries (entries past the window read zero); 9-bit
+        // ranks: `wlen` holds the per-tile records (count, then the lanes'
+        // ninth-bit masks)
+        constexpr int NDV = window_per_lane<IDX>();
+        constexpr int WM = IDX == IDX_W9 ? kWideWindowMax : kWindowMax;
+        if constexpr (IDX == IDX_W9) {
+            R.wl = wlen[t * kWideWords];
+            R.hi = reinterpret_cast<const uint16_t *>(wlen + t * kWideWords + 1)[tid];
+        } else {
+            R.wl = wlen[t];
+        }
+        const auto rd = buffer_range(wdict + t * WM, (uint32_t)R.wl * 2u);
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < NDV; ++k)
             R.dv[k] = buffer_load<uint16_t, NT>(rd, tid * 2u, (uint32_t)(k * kMergeBlock * 2));
     }
     const auto rc = buffer_range(static_cast<const C *>(cols) + R.j0, nwin * (uint32_t)sizeof(C));
@@ -391,18 +408,20 @@ __device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT, ID
 // in LDS, and every nonzero reads its x there by its rank. The window
 // occupies the front of the product buffer, which is overwritten only after
 // the last rank has been read.
-template <int S, int IPT>
-__device__ __forceinline__ typename VecOf<typename St<S>::X, 4>::type merge_window_load(
-    const MergeTileRegs<S, IPT, IDX_W8> &R, const typename St<S>::X *__restrict__ x,
-    int32_t n_cols) {
+template <int S, int IPT, int IDX = IDX_W8>
+__device__ __forceinline__ typename VecOf<typename St<S>::X, window_per_lane<IDX>()>::type
+merge_window_load(const MergeTileRegs<S, IPT, IDX> &R, const typename St<S>::X *__restrict__ x,
+                  int32_t n_cols) {
     using X = typename St<S>::X;
-    static_assert(kWindowMax == 4 * kMergeBlock, "four window entries per lane");
+    constexpr int NDV = window_per_lane<IDX>();
+    static_assert(kWindowMax == 4 * kMergeBlock && kWideWindowMax == 8 * kMergeBlock,
+                  "four (eight) window entries per lane");
     // an entry is below 2^16: the range never needs more than 2^16 elements
     const uint32_t nx = (uint32_t)min(n_cols - R.base, 1 << 16);
     const auto rx = buffer_range(x + R.base, nx * (uint32_t)sizeof(X));
-    typename VecOf<X, 4>::type w;
+    typename VecOf<X, NDV>::type w;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < NDV; ++k) {
         // entries past the window read nothing (an offset past the range)
         const bool in = (int)threadIdx.x + k * kMergeBlock < R.wl;
         w[k] = buffer_load<X, false>(rx, in ? (uint32_t)R.dv[k] * (uint32_t)sizeof(X) : 0x80000000u, 0u);
@@ -412,31 +431,38 @@ __device__ __forceinline__ typename VecOf<typename St<S>::X, 4>::type merge_wind
 
 template <int S, int IPT, class LDS, int IDX = IDX_W8>
 __device__ __forceinline__ void merge_window_stage(
-    const MergeTileRegs<S, IPT, IDX> &R, const typename VecOf<typename St<S>::X, 4>::type &w,
-    LDS &lds,
+    const MergeTileRegs<S, IPT, IDX> &R,
+    const typename VecOf<typename St<S>::X, window_per_lane<IDX>()>::type &w, LDS &lds,
     typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC]) {
     using X = typename St<S>::X;
     constexpr int VEC = MergeTileRegs<S, IPT, IDX>::VEC, NIT = MergeTileRegs<S, IPT, IDX>::NIT;
-    static_assert(kWindowMax * sizeof(X) <= sizeof(lds.prod), "the window fits the product buffer");
+    constexpr int NDV = window_per_lane<IDX>();
+    static_assert(NDV * kMergeBlock * sizeof(X) <= sizeof(lds.prod),
+                  "the window fits the product buffer");
+    static_assert(IDX != IDX_W9 || NIT * VEC == 16, "9-bit ranks: 16 elements per lane");
     X *s_win = reinterpret_cast<X *>(lds.prod);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) s_win[threadIdx.x + k * kMergeBlock] = w[k];
+    for (int k = 0; k < NDV; ++k) s_win[threadIdx.x + k * kMergeBlock] = w[k];
     wave_lds_sync();
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) xs[it][e] = s_win[R.cv[it][e]];
+        for (int e = 0; e < VEC; ++e) {
+            uint32_t r = R.cv[it][e];
+            if constexpr (IDX == IDX_W9) r |= ((R.hi >> (it * VEC + e)) & 1u) << 8;
+            xs[it][e] = s_win[r];
+        }
     }
     wave_lds_sync();
 }
 
-template <int S, int IPT, class LDS>
-__device__ __forceinline__ void merge_gather_window(const MergeTileRegs<S, IPT, IDX_W8> &R,
+template <int S, int IPT, class LDS, int IDX = IDX_W8>
+__device__ __forceinline__ void merge_gather_window(const MergeTileRegs<S, IPT, IDX> &R,
                                                     const typename St<S>::X *__restrict__ x,
                                                     int32_t n_cols, LDS &lds,
-                                                    typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX_W8>::NIT]
-                                                                          [MergeTileRegs<S, IPT, IDX_W8>::VEC]) {
-    merge_window_stage<S, IPT>(R, merge_window_load<S, IPT>(R, x, n_cols), lds, xs);
+                                                    typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX>::NIT]
+                                                                          [MergeTileRegs<S, IPT, IDX>::VEC]) {
+    merge_window_stage<S, IPT, LDS, IDX>(R, merge_window_load<S, IPT, IDX>(R, x, n_cols), lds, xs);
 }
 
 // Run windows (row-aligned tiles, IDX_R8): the tile's record (its smallest
@@ -657,27 +683,34 @@ __device__ __forceinline__ void merge_gather_rows(const MergeRowRegs<S, IPT, IDX
 // largest g with g * rows <= 64): lane `sub` of the group sums the sub-th
 // contiguous chunk of the row in index order, and the group adds its chunks
 // pairwise. With more rows than lanes, lane l sums rows l, l + 64, ...
-// alone. `re` holds the row ends as MergeTileRegs does. With `acc` the row
-// sums are added to y (a column block after the first).
-template <int IPT, class A, class X>
+// alone. `re` holds the row ends as MergeTileRegs does (LAZY: only re[0];
+// the others are read from `rp` here). With `acc` the row sums are added to
+// y (a column block after the first).
+template <int IPT, bool LAZY = false, class A, class X>
 __device__ __forceinline__ void merge_row_sums(int32_t i0, int32_t i1, int32_t j0,
                                                const int32_t (&re)[IPT], const A *s_prod,
-                                               X *__restrict__ y, bool acc) {
+                                               X *__restrict__ y, bool acc,
+                                               const int32_t *__restrict__ rp = nullptr) {
     constexpr int BS = kMergeBlock;
     const int tid = threadIdx.x;
     const int nre = i1 - i0;  // rows of the tile
     X *yb = y + i0;
     if (nre > BS) {
+        int32_t rq_prev = 0;  // this lane's row end of the previous round
 #pragma unroll
         for (int q = 0; q < IPT; ++q) {
             if (q * BS < nre) {
                 const int r = tid + q * BS;
-                const int32_t end = re[q] - j0;
+                int32_t rq = re[q];
+                if constexpr (LAZY)
+                    if (q > 0) rq = r < nre ? rp[i0 + 1 + r] : 0;
+                const int32_t end = rq - j0;
                 int32_t prev = dpp_move<kDppWaveShr1, 0xF>(end);  // end of row r - 1
                 if (q > 0) {
-                    const int32_t wrap = __builtin_amdgcn_readlane(re[q - 1], BS - 1) - j0;
+                    const int32_t wrap = __builtin_amdgcn_readlane(rq_prev, BS - 1) - j0;
                     if (tid == 0) prev = wrap;
                 }
+                rq_prev = rq;
                 const int32_t start = r == 0 ? 0 : prev;
                 if (r < nre) {
                     const A v = lds_run_sum(s_prod, start, end);
@@ -706,7 +739,8 @@ __device__ __forceinline__ void merge_finish_rows(const MergeTileRegs<S, IPT, ID
                                                   const typename St<S>::X (&xs)[MergeTileRegs<S, IPT, IDX>::NIT]
                                                                                [MergeTileRegs<S, IPT, IDX>::VEC],
                                                   typename St<S>::X *__restrict__ y, LDS &lds,
-                                                  bool acc = false) {
+                                                  bool acc = false,
+                                                  const int32_t *__restrict__ rp = nullptr) {
     using A = typename St<S>::A;
     constexpr int VEC = MergeTileRegs<S, IPT, IDX>::VEC, NIT = MergeTileRegs<S, IPT, IDX>::NIT;
     using AV = typename VecOf<A, VEC>::type;
@@ -720,7 +754,7 @@ __device__ __forceinline__ void merge_finish_rows(const MergeTileRegs<S, IPT, ID
         *reinterpret_cast<AV *>(lds.prod + it * STEP + tid * VEC) = pv;
     }
     wave_lds_sync();
-    merge_row_sums<IPT>(R.i0, R.i1, R.j0, R.re, lds.prod, y, acc);
+    merge_row_sums<IPT, IDX == IDX_W9>(R.i0, R.i1, R.j0, R.re, lds.prod, y, acc, rp);
 }
 
 // Products of a row-aligned tile whose x was gathered in window order
@@ -773,7 +807,9 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
                                            const int32_t *__restrict__ wlen = nullptr,
                                            bool acc = false,
                                            const int32_t *__restrict__ rowid = nullptr) {
-    static_assert((IDX != IDX_W8 && IDX != IDX_R8) || ALN, "window codes need row-aligned tiles");
+    static_assert((IDX != IDX_W8 && IDX != IDX_R8 && IDX != IDX_W9) || ALN,
+                  "window codes need row-aligned tiles");
+    static_assert(IDX != IDX_W9 || IPT == 16, "9-bit window ranks on tiles of 1,024 items");
     // row lists (`rowid`) only on tiles that are not row-aligned
     if constexpr (ALN) (void)rowid;
     if constexpr (IDX == IDX_R8) {
@@ -788,14 +824,14 @@ __device__ __forceinline__ void merge_tile(int64_t t, const int32_t *__restrict_
         typename St<S>::X xs[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC];
         merge_window_stage<S, IPT, LDS, IDX>(R, R.wx, lds, xs);
         merge_finish_rows<S, IPT, LDS, IDX>(R, xs, y, lds, acc);
-    } else if constexpr (IDX == IDX_W8) {
+    } else if constexpr (IDX == IDX_W8 || IDX == IDX_W9) {
         (void)carry;
         (void)n_rows;
         MergeTileRegs<S, IPT, IDX> R;
         merge_issue<S, IPT, NT, IDX>(t, rp, cols, val, tile_i, tile_j, tile_base, R, wdict, wlen);
         typename St<S>::X xs[MergeTileRegs<S, IPT, IDX>::NIT][MergeTileRegs<S, IPT, IDX>::VEC];
-        merge_gather_window<S, IPT>(R, x, n_cols, lds, xs);
-        merge_finish_rows<S, IPT, LDS, IDX>(R, xs, y, lds, acc);
+        merge_gather_window<S, IPT, LDS, IDX>(R, x, n_cols, lds, xs);
+        merge_finish_rows<S, IPT, LDS, IDX>(R, xs, y, lds, acc, rp);
     } else if constexpr (ALN && IDX != IDX_I32) {
         // codes: one wide load per lane, gathers in window order
         (void)carry;

@@ -46,8 +46,10 @@ double plan_bytes(const csr_matrix_s *A, const Plan &P) {
     const double vb = (double)storage_bytes(A->storage);
     const double xb = A->storage == CSR_VAL_F64 ? 8.0 : 4.0;
     const double ib = P.idx == IDX_D16                                        ? 2.0
-                      : (P.idx == IDX_D8 || P.idx == IDX_W8 || P.idx == IDX_R8) ? 1.0
-                                                                                : 4.0;
+                      : (P.idx == IDX_D8 || P.idx == IDX_W8 || P.idx == IDX_R8 ||
+                         P.idx == IDX_W9)
+                          ? 1.0
+                          : 4.0;
     double b = (double)A->nnz * (vb + ib) + 4.0 * (A->n_rows + 1) + xb * A->n_cols +
                xb * A->n_rows;
     if (P.opts & CSR_OPT_MERGE) {
@@ -60,6 +62,7 @@ double plan_bytes(const csr_matrix_s *A, const Plan &P) {
         // window codes: the dictionaries (window entries read) and lengths;
         // run windows: one record per tile
         if (P.idx == IDX_W8) b += 2.0 * (double)A->wdict_entries + 4.0 * T;
+        if (P.idx == IDX_W9) b += 2.0 * (double)A->wdict_entries + 4.0 * kWideWords * T;
         if (P.idx == IDX_R8) b += 4.0 * kRunWords * T;
         if (P.cblocks > 0) {
             // column blocks: every pass reads its row pointers and tile table
@@ -95,8 +98,9 @@ void fill_info(const csr_matrix_s *A, const Plan &P, csr_plan_info_t *info) {
     info->merge_slack = (P.opts & CSR_OPT_MERGE) ? (int32_t)A->tiles_slack : 0;
     info->delta_bits = P.idx == IDX_D16                                        ? 16
                        : (P.idx == IDX_D8 || P.idx == IDX_W8 || P.idx == IDX_R8) ? 8
+                       : P.idx == IDX_W9                                           ? 9
                                                                                  : 32;
-    info->window_codes = P.idx == IDX_W8 ? 1 : P.idx == IDX_R8 ? 2 : 0;
+    info->window_codes = P.idx == IDX_W8 ? 1 : P.idx == IDX_R8 ? 2 : P.idx == IDX_W9 ? 3 : 0;
     info->column_blocks = P.cblocks;
     info->dynamic_rows = P.dyn;
     info->jit = P.jit;
@@ -224,42 +228,49 @@ csr_status_t build_window_codes(csr_matrix_s *A, hipStream_t s) {
     if ((st = build_merge_codes(A, s, false)) != CSR_OK) return st;
     A->wcodes_L = 0;  // not valid until the end
     A->wcode_state = 0;
+    A->wcode_wide = 0;
     if (A->tiles_slack <= 0 || A->mcode_bits > 16) {
         A->wcodes_L = A->tiles_L;
         A->wcode_state = -1;
         return CSR_OK;
     }
+    // tiles of 1,024 items: 9-bit ranks (windows of up to 512 entries)
+    const bool wide = A->tiles_L == 16 * kMergeBlock;
+    const int wmax = wide ? kWideWindowMax : kWindowMax;
+    const int wrec = wide ? kWideWords : 1;
     const int64_t T = A->n_tiles;
-    if ((st = A->wdict.alloc(sizeof(uint16_t) * kWindowMax * (size_t)std::max<int64_t>(T, 1))) !=
-        CSR_OK)
+    if ((st = A->wdict.alloc(sizeof(uint16_t) * wmax * (size_t)std::max<int64_t>(T, 1))) != CSR_OK)
         return st;
-    if ((st = A->wlen.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(T, 1))) != CSR_OK) return st;
+    if ((st = A->wlen.alloc(sizeof(int32_t) * wrec * (size_t)std::max<int64_t>(T, 1))) != CSR_OK)
+        return st;
     if ((st = A->wcodes.alloc((size_t)A->nnz + kPadBytes)) != CSR_OK) return st;
     CSR_HIP(hipMemsetAsync(A->wcodes.as<char>() + A->nnz, 0, kPadBytes, s));
     DevBuf most;
     if ((st = most.alloc(sizeof(int32_t))) != CSR_OK) return st;
     CSR_HIP(hipMemsetAsync(most.p, 0, sizeof(int32_t), s));
+    const int vec = A->storage == CSR_VAL_F64 ? 2 : 4;  // the merge kernel's elements per load
     CSR_HIP(launch_window_encode(A->col.as<int32_t>(), A->tile_j.as<int32_t>(),
                                  A->tile_base.as<int32_t>(), T, A->wdict.as<uint16_t>(),
                                  A->wlen.as<int32_t>(), A->wcodes.as<uint8_t>(),
-                                 most.as<int32_t>(), s));
+                                 most.as<int32_t>(), s, wide ? vec : 0));
     int32_t m = 0;
     CSR_HIP(hipMemcpyAsync(&m, most.p, sizeof(m), hipMemcpyDeviceToHost, s));
     CSR_HIP(hipStreamSynchronize(s));
-    if (m > kWindowMax) {
+    if (m > wmax) {
         A->wcodes_L = A->tiles_L;
         A->wcode_state = -1;
         return CSR_OK;
     }
-    std::vector<int32_t> wl((size_t)T);
+    std::vector<int32_t> wl((size_t)T * wrec);
     if (T > 0)
-        CSR_HIP(hipMemcpyAsync(wl.data(), A->wlen.p, sizeof(int32_t) * (size_t)T,
+        CSR_HIP(hipMemcpyAsync(wl.data(), A->wlen.p, sizeof(int32_t) * wl.size(),
                                hipMemcpyDeviceToHost, s));
     CSR_HIP(hipStreamSynchronize(s));
     int64_t sum = 0;
-    for (int32_t v : wl) sum += v;
+    for (int64_t t = 0; t < T; ++t) sum += wl[(size_t)t * wrec];
     A->wdict_entries = sum;
     A->wcodes_L = A->tiles_L;
+    A->wcode_wide = wide ? 1 : 0;
     A->wcode_state = 1;
     return CSR_OK;
 }
@@ -273,7 +284,7 @@ csr_status_t build_window_runs(csr_matrix_s *A, hipStream_t s) {
     if ((st = build_window_codes(A, s)) != CSR_OK) return st;
     A->wruns_L = 0;  // not valid until the end
     A->wruns_state = 0;
-    if (A->wcode_state != 1) {
+    if (A->wcode_state != 1 || A->wcode_wide) {  // run records hold 8-bit ranks only
         A->wruns_L = A->tiles_L;
         A->wruns_state = -1;
         return CSR_OK;
@@ -479,7 +490,8 @@ bool plan_tables_ok(const csr_matrix_s *A, const Plan &P) {
     if (P.opts & CSR_OPT_MERGE) {
         if (P.cblocks > 0) return A->cb_B == P.cblocks && A->cb_L == P.L;
         if (A->tiles_L != P.L || A->n_tiles <= 0) return false;
-        if (P.idx == IDX_W8) return A->wcode_state == 1 && A->wcodes_L == P.L;
+        if (P.idx == IDX_W8) return A->wcode_state == 1 && A->wcodes_L == P.L && !A->wcode_wide;
+        if (P.idx == IDX_W9) return A->wcode_state == 1 && A->wcodes_L == P.L && A->wcode_wide;
         if (P.idx == IDX_R8)
             return A->wcode_state == 1 && A->wcodes_L == P.L && A->wruns_state == 1 &&
                    A->wruns_L == P.L;
@@ -532,7 +544,20 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
     if (opts & CSR_OPT_MERGE) {
         // IMB (GPU counterpart of the runtime-chosen schedule). With DECOMP
         // as well, the merge path already balances long rows.
-        const int L = cfg.merge_items > 0 ? cfg.merge_items : 512;
+        int L = cfg.merge_items > 0 ? cfg.merge_items : 512;
+        if (cfg.merge_items <= 0 && (opts & CSR_OPT_DELTA)) {
+            // default tile size with codes: 1,024-item tiles when every
+            // tile's window fits 9-bit ranks (fewer x-window cache lines per
+            // nonzero; measured faster in every value storage), else 512
+            if ((st = build_tiles(A, 16 * kMergeBlock, s)) != CSR_OK) return st;
+            if (A->tiles_slack > 0) {
+                if ((st = build_merge_codes(A, s, false)) != CSR_OK) return st;
+                if (A->mcode_bits == 16) {
+                    if ((st = build_window_codes(A, s)) != CSR_OK) return st;
+                    if (A->wcode_state == 1 && A->wcode_wide) L = 16 * kMergeBlock;
+                }
+            }
+        }
         if (!merge_items_supported(L))
             return fail(CSR_ERR_INVALID_ARG,
                         "merge_items must be a multiple of 256 from 256 to 2048");
@@ -543,7 +568,8 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
             // 16 bits (streamed, like the compressed arrays of the remedy);
             // on row-aligned tiles whose ranges need 16 bits, window codes
             // when every tile has at most kWindowMax distinct columns
-            // (codes only at tile sizes where a lane's codes form whole loads)
+            // (kWideWindowMax with 9-bit ranks on tiles of 1,024 items;
+            // codes only at tile sizes where a lane's codes form whole loads)
             if ((st = build_merge_codes(A, s, false)) != CSR_OK) return st;
             const bool w8_fits = merge_codes_fit(L, 1);
             if (A->mcode_bits == 16 && A->tiles_slack > 0 && w8_fits) {
@@ -555,8 +581,10 @@ csr_status_t realize(csr_matrix_s *A, int32_t opts, const csr_config_t &cfg, Pla
                     return st;
             }
             if (A->mcode_bits == 16 && A->wcode_state == 1 && w8_fits) {
-                P.idx = cfg.window_runs == 1 && A->wruns_state == 1 && A->wruns_L == L ? IDX_R8
-                                                                                        : IDX_W8;
+                P.idx = A->wcode_wide ? IDX_W9
+                        : cfg.window_runs == 1 && A->wruns_state == 1 && A->wruns_L == L
+                            ? IDX_R8
+                            : IDX_W8;
                 P.nt = 1;
             } else if ((A->mcode_bits == 8 || A->mcode_bits == 16) &&
                        merge_codes_fit(L, A->mcode_bits / 8)) {

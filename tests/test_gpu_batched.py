@@ -221,3 +221,23 @@ def test_batched_column_blocks_with_split_rows():
     torch.cuda.synchronize()
     for k, (n, *_ ) in enumerate(mats):
         assert torch.equal(ys[k][:n], first[k][:n]), k
+
+
+def test_batched_nine_bit_windows_bit_identical():
+    """9-bit window ranks (1,024-item tiles) beside 8-bit windows and other
+    plans in one batch: the same bits as each matrix's own csr_spmv."""
+    n0, m0, rp0, col0, val0 = synth.stencil27(24)
+    mats = [(n0, m0, rp0, col0, val0), synth.stencil27(20)]
+    mats += [synth.batch_matrix(i)[1] for i in range(6)]
+    hs = [pkg.CsrMatrix(rp, col, val, n_cols=m) for (n, m, rp, col, val) in mats]
+    for k, A in enumerate(hs):
+        info = A.select("forced", forced_opts=pkg.OPT_MERGE | pkg.OPT_DELTA,
+                        merge_items=1024 if k < 2 else 512)
+        if k < 2:
+            assert info["window_codes"] == 3
+    xs, ys = vectors(mats, 800)
+    pkg.spmv_batched(hs, xs, ys)
+    torch.cuda.synchronize()
+    same_as_single(mats, hs, xs, ys, "9-bit windows")
+    for k, (n, m, rp, col, val) in enumerate(mats):
+        check_f64(ys[k][:n].cpu().numpy(), rp, col, val, xs[k].cpu().numpy(), f"batch {k}")

@@ -115,7 +115,7 @@ def test_precision_sweep_against_oracle(name, storage, index):
     opts = pkg.OPT_MERGE | (pkg.OPT_PREFETCH if index == "int32" else pkg.OPT_DELTA)
     info = A.select("forced", forced_opts=opts)
     if index == "delta":
-        assert info["delta_bits"] in (8, 16)
+        assert info["delta_bits"] in (8, 9, 16)
     xin = x if storage == "f64" else oracle.to_f32(x)
     y = spmv(A, xin)
     A.close()
@@ -128,7 +128,7 @@ def test_precision_sweep_against_oracle(name, storage, index):
         rep = check_reduced(y, rp, col, val, x, storage, what)
     assert rep["zero_rows_exact"]
     SWEEP[what] = {"index": ("window8 runs" if info["window_codes"] == 2 else
-                             "window8" if info["window_codes"] else
+                             f"window{info['delta_bits']}" if info["window_codes"] else
                              "int32" if info["delta_bits"] == 32 else f"delta{info['delta_bits']}"),
                    "max_rel_err": rep["max"], "p99_rel_err": rep["p99"]}
     out = os.environ.get("CSRSPMV_REPORT_DIR")

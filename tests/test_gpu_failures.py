@@ -55,7 +55,7 @@ def test_create_fails_cleanly_at_every_allocation():
 
 
 @pytest.mark.parametrize("committed,attempt", [
-    ({"mode": "forced", "forced_opts": pkg.OPT_MERGE | pkg.OPT_DELTA},
+    ({"mode": "forced", "forced_opts": pkg.OPT_MERGE | pkg.OPT_DELTA, "merge_items": 512},
      {"mode": "forced", "forced_opts": pkg.OPT_MERGE | pkg.OPT_PREFETCH, "merge_items": 1024}),
     ({"mode": "forced", "forced_opts": pkg.OPT_MERGE | pkg.OPT_PREFETCH, "merge_items": 256},
      {"mode": "exhaustive", "timing_calls": 2}),

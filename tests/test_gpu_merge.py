@@ -69,10 +69,11 @@ def test_dyadic_bit_exact(opts, L):
 @pytest.mark.parametrize("L", [256, 512, 1024])
 def test_merge_codes_bit_exact(L):
     """MERGE|DELTA: on row-aligned tiles whose column ranges need 16 bits and
-    whose windows hold at most 256 distinct columns, window codes (tile
-    bases, dictionaries, lengths and ranks equal to the oracle's); otherwise
-    tile bases and per-nonzero offsets at the narrowest width that holds
-    every tile's column range; int32 columns when no width fits."""
+    whose windows hold at most 256 distinct columns (512 with 9-bit ranks on
+    1,024-item tiles), window codes (tile bases, dictionaries, lengths or
+    ninth-bit records, and ranks equal to the oracle's); otherwise tile
+    bases and per-nonzero offsets at the narrowest width that holds every
+    tile's column range; int32 columns when no width fits."""
     seen = set()
     for name in ("lap100", "st27_24", "rmat14", "unif14", "unif17"):
         n, m, rp, col, val = matrix(name)
@@ -84,18 +85,21 @@ def test_merge_codes_bit_exact(L):
             if oracle.merge_codes(tj, col, w) is not None:
                 want = w
                 break
-        win = (oracle.window_codes(tj, col)
+        wide = L == 1024
+        win = (oracle.window_codes(tj, col, 512 if wide else 256)
                if want == 16 and info["merge_slack"] > 0 else None)
-        assert info["window_codes"] == (win is not None), (name, L)
+        assert info["window_codes"] == (0 if win is None else 3 if wide else 1), (name, L)
         if win is not None:
-            seen.add("window")
-            assert info["delta_bits"] == 8
+            seen.add("window9" if wide else "window")
+            assert info["delta_bits"] == (9 if wide else 8)
             base, wlen, dct, codes = win
             assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_BASE, np.int32), base)
-            assert np.array_equal(A.debug_copy(pkg.DEBUG_WINDOW_LEN, np.int32), wlen), (name, L)
+            rec = oracle.window_rank_records(tj, codes, wlen, vec=2).ravel() if wide else wlen
+            assert np.array_equal(A.debug_copy(pkg.DEBUG_WINDOW_LEN, np.int32), rec), (name, L)
             got = A.debug_copy(pkg.DEBUG_WINDOW_DICT, np.uint16).reshape(dct.shape)
             assert np.array_equal(got, dct), (name, L)
-            assert np.array_equal(A.debug_copy(pkg.DEBUG_WINDOW_CODES, np.uint8), codes), (name, L)
+            assert np.array_equal(A.debug_copy(pkg.DEBUG_WINDOW_CODES, np.uint8),
+                                  (codes & 255).astype(np.uint8)), (name, L)
             continue
         assert info["delta_bits"] == want, (name, L)
         if want == 32:
@@ -106,8 +110,8 @@ def test_merge_codes_bit_exact(L):
         assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_BASE, np.int32), base)
         got = A.debug_copy(pkg.DEBUG_MERGE_CODES, np.uint16 if want == 16 else np.uint8)
         assert np.array_equal(got, codes), (name, L)
-    if L == 1024:  # windows outgrow 256 entries: the 16-bit offsets take over
-        assert "delta16" in seen
+    if L == 1024:  # windows outgrow 256 entries: 9-bit ranks
+        assert "window9" in seen
     else:
         assert "window" in seen
 
@@ -121,7 +125,7 @@ def test_merge_codes_same_bits_as_int32_columns():
         A = pkg.CsrMatrix(rp, col, val)
         for L in (256, 512, 1024):
             info = A.select("forced", forced_opts=M | pkg.OPT_DELTA, merge_items=L)
-            assert info["delta_bits"] in (8, 16)
+            assert info["delta_bits"] in (8, 9, 16)
             y_codes = run(A, x)
             y_i32 = run(A, x, M | pkg.OPT_PREFETCH, L)
             assert np.array_equal(y_codes.view(np.uint64), y_i32.view(np.uint64)), (name, L)
@@ -431,3 +435,67 @@ def test_window_runs_parity_with_empty_rows(storage):
         y = A.spmv(torch.from_numpy(oracle.to_f32(x)).cuda())
         torch.cuda.synchronize()
         check_reduced(y.cpu().numpy(), rp2, col2, val2, x, storage, f"run windows {storage}")
+
+
+def tridiagonal(n, seed):
+    """a_i,i-1, a_ii, a_i,i+1 with dyadic values: about 256 rows and 258
+    distinct columns per 1,024-item tile (more rows than lanes, ranks past
+    255)."""
+    i = np.arange(n)
+    rows = np.concatenate([i[1:], i, i[:-1]])
+    cols = np.concatenate([i[1:] - 1, i, i[:-1] + 1])
+    vals = _dyadic(np.zeros(rows.size), seed)
+    return synth.from_coo(rows, cols, vals, n, n)
+
+
+def _stencil_dyadic():
+    n, m, rp, col, val = synth.stencil27(24)
+    return n, m, rp, col, _dyadic(val, 61)
+
+
+@pytest.mark.parametrize("name", ["st27_24", "tridiag"])
+def test_window_codes_nine_bit_bit_exact(name):
+    """9-bit window ranks on 1,024-item tiles (windows of up to 512 columns):
+    tile table, bases, dictionaries, codes and ninth-bit records bit-exact
+    against the oracle; y bit-exact on dyadic inputs and the same bits as
+    int32 columns on the same tiles; the tridiagonal's tiles end about 256
+    rows (row ends past the first 64 are read in the row-sum phase)."""
+    n, m, rp, col, val = _stencil_dyadic() if name == "st27_24" else tridiagonal(300_001, 62)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    info = A.select("forced", forced_opts=M | pkg.OPT_DELTA, merge_items=1024)
+    assert info["window_codes"] == 3 and info["delta_bits"] == 9
+    ti, tj = oracle.merge_tiles(rp, 1024, info["merge_slack"])
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_I, np.int32), ti)
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_J, np.int32), tj)
+    base, wlen, dct, ranks = oracle.window_codes(tj, col, 512)
+    assert ranks.max() >= 256
+    if name == "tridiag":
+        assert (np.diff(ti) > 64).mean() > 0.9
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_TILE_BASE, np.int32), base)
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_WINDOW_DICT, np.uint16), dct.ravel())
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_WINDOW_CODES, np.uint8), (ranks & 255).astype(np.uint8))
+    rec = oracle.window_rank_records(tj, ranks, wlen, vec=2)
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_WINDOW_LEN, np.int32), rec.ravel())
+    x = synth.dyadic_vector(m, 63)
+    y = run(A, x)
+    assert np.array_equal(y, oracle.spmv(rp, col, val, x))
+    assert np.array_equal(run(A, x, M, 1024), y)  # int32 columns, same tiles
+    A.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_window_codes_nine_bit_reduced_precision(storage):
+    n, m, rp, col, val = synth.stencil27(24)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m, storage=storage)
+    info = A.select("forced", forced_opts=M | pkg.OPT_DELTA, merge_items=1024)
+    assert info["window_codes"] == 3
+    ti, tj = oracle.merge_tiles(rp, 1024, info["merge_slack"])
+    base, wlen, dct, ranks = oracle.window_codes(tj, col, 512)
+    rec = oracle.window_rank_records(tj, ranks, wlen, vec=4)
+    assert np.array_equal(A.debug_copy(pkg.DEBUG_WINDOW_LEN, np.int32), rec.ravel())
+    x = synth.vector(m, 64)
+    xs = torch.from_numpy(oracle.to_f32(x)).cuda()
+    y = A.spmv(xs)
+    torch.cuda.synchronize()
+    check_reduced(y.cpu().numpy(), rp, col, val, x, storage, f"9-bit windows {storage}")
+    A.close()

@@ -646,3 +646,45 @@ def test_column_block_rows_by_brute_force():
         if B == 8:  # rows without nonzeros in some blocks are left out
             assert rows.size < (B - 1) * n
         assert np.array_equal(y, oracle.spmv(rp, col, val, x))
+
+
+def test_window_codes_nine_bit_ranks_by_brute_force():
+    """Windows of up to 512 entries (9-bit ranks on tiles of 1,024 items):
+    the ranks are the positions in the sorted set of the tile's columns
+    (Python sets), 512 distinct columns fit and 513 do not, and the
+    ninth-bit records put rank >= 256 at the lane and bit that load the
+    element (walking the lanes' load order element by element)."""
+    n = 3000
+    # tridiagonal-like rows: about 256 rows and 258 distinct columns per tile
+    rows = np.repeat(np.arange(n), 3)
+    cols = np.clip(rows + np.tile([-1, 0, 1], n), 0, n - 1)
+    keep = np.ones(rows.size, bool)
+    keep[[0, rows.size - 1]] = False  # row 0 and row n-1 have two entries
+    rows, cols = rows[keep], cols[keep]
+    rp = np.searchsorted(rows, np.arange(n + 1)).astype(np.int32)
+    col = cols.astype(np.int32)
+    ti, tj = _aligned_tiles(rp, 1024)
+    base, wlen, dct, ranks = oracle.window_codes(tj, col, 512)
+    assert ranks.dtype == np.uint16 and ranks.max() >= 256
+    for t in range(len(tj) - 1):
+        c = col[tj[t]:tj[t + 1]]
+        u = sorted(set(int(v) for v in c))
+        assert wlen[t] == len(u) and (not u or base[t] == u[0])
+        assert [int(v) for v in ranks[tj[t]:tj[t + 1]]] == [u.index(int(v)) for v in c]
+        assert [int(v) for v in dct[t, :len(u)]] == [v - u[0] for v in u]
+    assert oracle.window_codes(tj, col, 256) is None  # more than 256 distinct in a tile
+    for vec in (2, 4):
+        rec = oracle.window_rank_records(tj, ranks, wlen, vec)
+        masks = rec[:, 1:].view(np.uint16).reshape(len(tj) - 1, 64)
+        assert np.array_equal(rec[:, 0], wlen)
+        for t in range(len(tj) - 1):
+            for lane in range(64):
+                for it in range(1024 // (64 * vec)):
+                    for e in range(vec):
+                        p = it * 64 * vec + lane * vec + e
+                        bit = (int(masks[t, lane]) >> (it * vec + e)) & 1
+                        want = p < tj[t + 1] - tj[t] and ranks[tj[t] + p] >= 256
+                        assert bit == int(want), (t, lane, it, e)
+    # 512 distinct columns fit, 513 do not
+    one = lambda k: oracle.window_codes(np.array([0, k], np.int32), np.arange(k, dtype=np.int32) * 3, 512)
+    assert one(512) is not None and one(513) is None
