@@ -11,9 +11,12 @@ the paper does, by the Exact Match Ratio (predicted set equal to the label
 set) and the Partial Match Ratio (at least one class in common), under
 k-fold cross-validation.
 
-    python -m paper_1711_05487_amd.tree train --labels labels.jsonl --out tree.json
+    python -m paper_1711_05487_amd.tree train --labels bounds.jsonl --key classes
 
-The labels are the `profile_classes` recorded by `learn label`.
+The labels are the class masks the profile rule assigned when the records
+were taken: `classes` of the bounds records (`learn bounds`, the rule with
+the library's thresholds) or `profile_classes` of the timing labels
+(`learn label`).
 """
 from __future__ import annotations
 
@@ -181,17 +184,26 @@ def main():
     t = sub.add_parser("train")
     t.add_argument("--labels", required=True)
     t.add_argument("--out", default=TREE)
-    t.add_argument("--max-depth", type=int, default=10)
+    t.add_argument("--key", default="classes", help="record field holding the class mask")
+    t.add_argument("--max-depth", type=int, default=0,
+                   help="0: the depth of best cross-validated exact match, 2 .. 10")
     t.add_argument("--folds", type=int, default=10)
     a = ap.parse_args()
     from paper_1711_05487_amd import learn
     recs = learn.read_labels(a.labels)
     X = np.array([r["features"] for r in recs])
-    y = np.array([r["profile_classes"] for r in recs], dtype=np.int64)
-    exact, partial = cross_validate(X, y, folds=a.folds, max_depth=a.max_depth)
-    tree = fit(X, y, max_depth=a.max_depth)
+    y = np.array([r[a.key] for r in recs], dtype=np.int64)
+    depth, by_depth = a.max_depth, {}
+    if depth <= 0:
+        for d in range(2, 11):
+            by_depth[d] = cross_validate(X, y, folds=a.folds, max_depth=d)
+        depth = max(by_depth, key=lambda d: (by_depth[d][0], -d))
+    exact, partial = by_depth.get(depth) or cross_validate(X, y, folds=a.folds, max_depth=depth)
+    tree = fit(X, y, max_depth=depth)
     train_exact, train_partial = match_ratios(predict(tree, X), y)
-    meta = {"samples": len(recs), "folds": a.folds, "max_depth": a.max_depth,
+    meta = {"samples": len(recs), "labels": os.path.basename(a.labels), "key": a.key,
+            "folds": a.folds, "max_depth": depth,
+            "cv_exact_match_by_depth": {str(d): v[0] for d, v in by_depth.items()},
             "cv_exact_match": exact, "cv_partial_match": partial,
             "train_exact_match": train_exact, "train_partial_match": train_partial,
             "nodes": len(tree["feature"]),

@@ -76,9 +76,9 @@ def test_match_ratios_by_hand():
 
 def test_committed_tree_reproduces_its_training_record():
     d = json.load(open(tree.TREE))
-    recs = learn.read_labels(os.path.join(os.path.dirname(tree.TREE), "labels_mi355x.jsonl"))
+    recs = learn.read_labels(os.path.join(os.path.dirname(tree.TREE), d["meta"]["labels"]))
     X = np.array([r["features"] for r in recs])
-    y = np.array([r["profile_classes"] for r in recs])
+    y = np.array([r[d["meta"]["key"]] for r in recs])
     t = tree.load()
     assert tree.match_ratios(tree.predict(t, X), y)[0] == pytest.approx(d["meta"]["train_exact_match"])
     assert tree.fit(X, y, max_depth=d["meta"]["max_depth"]) == t
