@@ -208,6 +208,8 @@ def main():
     ap.add_argument("--irregular", action="store_true",
                     help="run the irregular configurations' plans (R-MAT 22, uniform 2^20 x 16) "
                          "a few times each, for counter runs")
+    ap.add_argument("--batch", action="store_true",
+                    help="the 512-matrix batched launch alone (C5-batch; one JSON line)")
     ap.add_argument("--partitions", action="store_true",
                     help="partition-aware ML study: localized irregular stretches and a suite "
                          "sample under the profile rule with and without partitions")
@@ -225,6 +227,8 @@ def main():
         return irregular(args)
     if args.partitions:
         return partitions(args)
+    if args.batch:
+        return batch_only()
 
     import torch
     import paper_1711_05487_amd as pkg
@@ -503,15 +507,20 @@ def suite(args):
             A.close()
         del chk
 
-    # C5-batch: 512 matrices, one graph-captured persistent launch against
-    # 512 separate launches, each matrix with its own selected plan
+    c5_batch(pkg, synth, torch)
+
+
+def c5_batch(pkg, synth, torch):
+    """C5-batch: 512 matrices, one graph-captured persistent launch against
+    512 separate launches, each matrix with its own selected plan."""
     log("C5-batch: generating 512 matrices")
     mats = [synth.batch_matrix(i) for i in range(512)]
-    hs, xs, ys, fbytes, rows = [], [], [], 0, 0
+    hs, xs, ys, fbytes, rows, nnz = [], [], [], 0, 0, 0
     for k, (_, (n, m, rp, col, val)) in enumerate(mats):
         A = pkg.CsrMatrix(rp, col, val, n_cols=m)
         fbytes += A.select("learned")["format_bytes"]
         rows += n
+        nnz += len(col)
         hs.append(A)
         xs.append(torch.from_numpy(synth.vector(m, 602 + k)).cuda())
         ys.append(torch.empty(max(n, 1), dtype=torch.float64, device="cuda"))
@@ -538,14 +547,25 @@ def suite(args):
             A.spmv(x, y)
 
     t_sep = timed(separate)
-    emit({"case": "C5-batch", "matrices": len(hs), "rows": rows, "format_bytes": fbytes,
-          "batched_ms": round(t_batch, 4), "separate_ms": round(t_sep, 4),
+    emit({"case": "C5-batch", "matrices": len(hs), "rows": rows, "nnz": nnz,
+          "format_bytes": fbytes, "batched_ms": round(t_batch, 4), "separate_ms": round(t_sep, 4),
+          "batched_gnnz_s": round(nnz / (t_batch * 1e-3) / 1e9, 1),
           "batched_gbs": round(fbytes / (t_batch * 1e-3) / 1e9, 1),
           "separate_gbs": round(fbytes / (t_sep * 1e-3) / 1e9, 1),
           "speedup": round(t_sep / t_batch, 3), "replay_identical": batch_ok})
     for A in hs:
         A.close()
 
+
+def batch_only():
+    import torch
+    import paper_1711_05487_amd as pkg
+    import synth
+    from paper_1711_05487_amd import learn
+
+    torch.cuda.set_device(0)
+    learn.install()
+    c5_batch(pkg, synth, torch)
 
 
 # ---------------------------------------------------------------------------
