@@ -293,7 +293,8 @@ csr_status_t csr_query(csr_matrix_t A, int32_t *n_rows, int32_t *n_cols, int64_t
  * Sec. IV-D): compiles the merge-path kernel for value storage `storage`,
  * tile size `merge_items` (a multiple of 256 from 256 to 2048), index mode
  * `index_mode` (0 int32 columns, 1 16-bit and 2 8-bit merge codes, 3 window
- * codes, 4 window codes with run records), non-temporal loads (`streaming`, int32 columns only) and row-aligned
+ * codes, 4 window codes with run records; 9-bit window ranks exist only on the
+ * prebuilt 1,024-item tiles and are refused here), non-temporal loads (`streaming`, int32 columns only) and row-aligned
  * tiles (`row_aligned`; required by window codes) with hipRTC for gfx950, from
  * the kernel sources built into the library, and copies the code object (an
  * AMDGPU ELF) to host memory `code` of `bytes` bytes (*needed receives its

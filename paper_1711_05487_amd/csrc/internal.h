@@ -104,9 +104,11 @@ struct csr_matrix_s {
     int32_t mcode_bits = 0;        // 8 / 16 when mcodes is valid, 32 = not eligible, 0 = not built
     int32_t mcodes_L = 0;          // tile size the merge codes were built for
     int32_t mcodes_encoded = 0;    // mcodes holds the codes (not only the bases and width)
-    csr::DevBuf wdict;             // window codes: per tile kWindowMax uint16 column offsets
+    csr::DevBuf wdict;             // window codes: per tile kWindowMax (9-bit ranks:
+                                   // kWideWindowMax) uint16 column offsets
     csr::DevBuf wlen;              // window codes: window entries of each tile, T int32
-    csr::DevBuf wcodes;            // window codes: per-nonzero rank in its tile's window (uint8)
+    csr::DevBuf wcodes;            // window codes: per-nonzero rank in its tile's window
+                                   // (uint8; 9-bit ranks: the low byte)
     int32_t wcode_state = 0;       // 1 valid, -1 not eligible, 0 not built
     int32_t wcode_wide = 0;        // 1: 9-bit ranks (IDX_W9): dictionaries of kWideWindowMax
                                    // entries, wlen holds kWideWords-word records

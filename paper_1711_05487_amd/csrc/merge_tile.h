@@ -402,7 +402,8 @@ __device__ __forceinline__ void merge_finish(int64_t t, MergeTileRegs<S, IPT, ID
 }
 
 // Window codes (row-aligned tiles): the tile's x window (its distinct
-// columns, at most kWindowMax) is read with four loads per lane (lane l:
+// columns, at most kWindowMax, or kWideWindowMax with 9-bit ranks) is read
+// with four (eight) loads per lane (lane l:
 // entries l + 64 k, so that one load covers 64 consecutive entries, which
 // are consecutive columns on banded rows and share few cache lines), staged
 // in LDS, and every nonzero reads its x there by its rank. The window
