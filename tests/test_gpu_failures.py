@@ -62,6 +62,11 @@ def test_create_fails_cleanly_at_every_allocation():
     ({"mode": "forced", "forced_opts": pkg.OPT_DELTA},
      {"mode": "forced", "forced_opts": pkg.OPT_DECOMP | pkg.OPT_UNROLL, "long_row_floor": 16,
       "long_row_factor": 1.0, "dynamic_rows": 1}),
+    # to and from 9-bit window ranks on 1,024-item tiles
+    ({"mode": "forced", "forced_opts": pkg.OPT_MERGE, "merge_items": 512},
+     {"mode": "forced", "forced_opts": pkg.OPT_MERGE | pkg.OPT_DELTA}),
+    ({"mode": "forced", "forced_opts": pkg.OPT_MERGE | pkg.OPT_DELTA},
+     {"mode": "forced", "forced_opts": pkg.OPT_MERGE | pkg.OPT_DELTA, "merge_items": 512}),
 ])
 def test_failed_select_keeps_a_working_plan(committed, attempt):
     """A fresh handle per failing allocation (tables a selection built once
@@ -75,6 +80,8 @@ def test_failed_select_keeps_a_working_plan(committed, attempt):
         return A, A.select(**committed)
 
     A, info0 = committed_handle()
+    if committed.get("forced_opts") == pkg.OPT_MERGE | pkg.OPT_DELTA and "merge_items" not in committed:
+        assert info0["window_codes"] == 3, info0  # the 9-bit ranks are what is kept
     check_f64(y_of(A, x), rp, col, val, x, "committed plan")
     k_max, _ = attempts_of(lambda: A.select(**attempt))
     A.close()
@@ -90,6 +97,7 @@ def test_failed_select_keeps_a_working_plan(committed, attempt):
         check_f64(y_of(A, x), rp, col, val, x, f"after failing allocation {k}")
         A.select(**committed)
         assert A.info["opts"] == info0["opts"]
+        assert A.info["window_codes"] == info0["window_codes"]
         check_f64(y_of(A, x), rp, col, val, x, f"committed again after {k}")
         A.close()
         assert pkg.debug_alloc()[:2] == live0, f"leak after failing allocation {k}"
