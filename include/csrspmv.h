@@ -231,6 +231,8 @@ csr_status_t csr_inspect(csr_matrix_t A, csr_features_t *out, void *stream);
  * plan (delta codes, merge-path tiles, long-row list). cfg may be NULL for
  * the defaults; out may be NULL. Synchronizes `stream`. PROFILE and
  * EXHAUSTIVE launch SpMV kernels that write into internal scratch vectors.
+ * A matrix without rows keeps the plain plan whatever the mode (nothing is
+ * inspected, timed or built).
  */
 csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg,
                         csr_plan_info_t *out, void *stream);

@@ -1346,6 +1346,14 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
     csr_status_t st = CSR_OK;
     double t_prep = 0.0;
     int32_t sel = mode;
+    if (A->n_rows == 0 && sel >= CSR_SEL_PLAIN && sel <= CSR_SEL_TREE) {
+        // a matrix without rows: every plan computes nothing, so the plain
+        // one is kept without inspecting, timing or preprocessing anything
+        if (sel == CSR_SEL_FORCED && !opts_realizable(cfg.forced_opts))
+            return fail(CSR_ERR_INVALID_ARG, "unknown optimization bits");
+        st = realize(A, 0, cfg, &P, s);
+        sel = -1;
+    }
     if (sel == CSR_SEL_TREE) {
         // features -> decision tree -> bottleneck classes -> Table II
         // remedies with default parameters (nothing timed); no tree -> the
