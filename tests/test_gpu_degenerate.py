@@ -1,13 +1,13 @@
 """Degenerate and boundary shapes through every path: all rows empty, a 1 x 1
-matrix, one dense row, one column, only the last row filled, rows of 62-65
-and 60-63 nonzeros (either side of the row-aligned tiles' limit), N + NNZ
-exactly one tile and one item past it, and banded rows whose windows need
-9-bit ranks or fit neither window width. Every catalogue variant at every
-prebuilt tile size, the selectors, the batched launch and the
-allocation-free entry point. Values are small integers and x is dyadic, so
-FP64 results must equal the oracle's bit for bit (Sec. II, Fig. 2);
-FP32/BF16 storage is held to its a-priori bound. Rows without nonzeros must
-give +0.0."""
+matrix, one dense row, one column, only the last row filled, unsorted rows
+with repeated columns, rows of 62-65 and 60-63 nonzeros (either side of the
+row-aligned tiles' limit), N + NNZ exactly one tile and one item past it,
+and banded rows whose windows need 9-bit ranks or fit neither window width.
+Every catalogue variant at every prebuilt tile size, the selectors, the
+batched launch and the allocation-free entry point. Values are small
+integers and x is dyadic, so FP64 results must equal the oracle's bit for
+bit (Sec. II, Fig. 2); FP32/BF16 storage is held to its a-priori bound.
+Rows without nonzeros must give +0.0."""
 import numpy as np
 import pytest
 import torch
@@ -65,6 +65,12 @@ def shapes():
     out["one tile exactly"] = (8, 300) + from_lengths(lens, 300, 33)
     lens = [127] * 7 + [128]
     out["one item past a tile"] = (8, 300) + from_lengths(lens, 300, 34)
+    # unsorted rows with repeated columns (summed in storage order; delta
+    # codes need sorted rows and must not be built)
+    lens = synth.uindex(39, 0, np.arange(300, dtype=np.uint64), 41)
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    col = synth.uindex(39, 1, np.arange(rp[-1], dtype=np.uint64), 60).astype(np.int32)
+    out["unsorted, repeated columns"] = (300, 60, rp, col)
     for bw in (200, 700):  # windows of 9-bit ranks / of neither width
         n, m, rp, col, _ = synth.banded_random(4000, bw, 16, 35)
         out[f"band {bw}"] = (n, m, rp, col)
@@ -126,6 +132,14 @@ def test_every_variant(name, storage):
             check(run(A, xin), rp, col, val, x, storage, what)
     finally:
         A.close()
+
+
+def test_unsorted_rows_get_no_delta_codes():
+    n, m, rp, col = SHAPES["unsorted, repeated columns"]
+    assert not oracle.rows_sorted(rp, col)
+    A = pkg.CsrMatrix(rp, col, dyadic_values(col.size, 36), n_cols=m)
+    assert A.select("forced", forced_opts=pkg.OPT_DELTA)["delta_bits"] == 32
+    A.close()
 
 
 def test_nine_bit_and_fallback_windows_chosen():
