@@ -875,8 +875,16 @@ __device__ __forceinline__ void merge_fixup_tile(int64_t t, const int32_t *__res
     if (t < 1) return;
     const int32_t r = tile_i[t];
     if (r >= n_rows || tile_i[t + 1] == r || rp[r] >= tile_j[t]) return;
-    int64_t ta = t - 1;
-    while (ta > 0 && tile_i[ta] == r) --ta;  // tile ta ended inside row r, so did ta+1..t-1
+    // tiles ta..t-1 ended inside row r: ta is the last tile that starts
+    // before row r (or 0), found by bisection over the non-decreasing tile
+    // rows (a row of a skewed matrix can span hundreds of tiles)
+    int64_t lo = 0, hi = t;  // first k in [0, t) with tile_i[k] >= r
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (tile_i[mid] < r) lo = mid + 1;
+        else hi = mid;
+    }
+    const int64_t ta = lo > 0 ? lo - 1 : 0;
     A sum = A(0);
     for (int64_t q = ta; q < t; ++q) sum += carry[q];
     X *yr = y + (rowid ? rowid[r] : r);
