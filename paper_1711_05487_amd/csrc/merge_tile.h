@@ -885,8 +885,17 @@ __device__ __forceinline__ void merge_fixup_tile(int64_t t, const int32_t *__res
         else hi = mid;
     }
     const int64_t ta = lo > 0 ? lo - 1 : 0;
+    // the carries in tile order; eight loads are issued before their adds
     A sum = A(0);
-    for (int64_t q = ta; q < t; ++q) sum += carry[q];
+    int64_t q = ta;
+    for (; q + 8 <= t; q += 8) {
+        A c[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] = carry[q + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sum += c[k];
+    }
+    for (; q < t; ++q) sum += carry[q];
     X *yr = y + (rowid ? rowid[r] : r);
     *yr = (X)(sum + (A)*yr);
 }
