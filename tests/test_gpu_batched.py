@@ -180,6 +180,34 @@ def test_batched_learned_plans_bit_identical():
     same_as_single(mats, hs, xs, ys, "learned")
 
 
+def test_batched_full_512_matrix_set_matches_oracle():
+    """The benchmark's 512-matrix batch (1,024-65,536 rows, every suite
+    family), each matrix with its learned plan: every y within the FP64 bar
+    against the oracle and bit-identical to the matrix's own csr_spmv, and a
+    second call with the same vectors replays the same bits."""
+    from paper_1711_05487_amd import learn
+    learn.install()
+    mats = [synth.batch_matrix(i)[1] for i in range(512)]
+    hs = [pkg.CsrMatrix(rp, col, val, n_cols=m) for (n, m, rp, col, val) in mats]
+    try:
+        for A in hs:
+            A.select("learned")
+        xs, ys = vectors(mats, 602)
+        pkg.spmv_batched(hs, xs, ys)
+        torch.cuda.synchronize()
+        first = [y.clone() for y in ys]
+        for k, (n, m, rp, col, val) in enumerate(mats):
+            check_f64(ys[k][:n].cpu().numpy(), rp, col, val, xs[k].cpu().numpy(), f"C5 matrix {k}")
+        same_as_single(mats, hs, xs, ys, "C5 learned")
+        pkg.spmv_batched(hs, xs, ys)
+        torch.cuda.synchronize()
+        for k, (n, *_ ) in enumerate(mats):
+            assert torch.equal(ys[k][:n], first[k][:n]), f"C5 replay {k}"
+    finally:
+        for A in hs:
+            A.close()
+
+
 def test_batched_back_to_back_moving_vectors():
     """Calls issued without waiting, each with new vectors: the descriptor
     refresh of one call must not change what the previous call reads."""
