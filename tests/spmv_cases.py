@@ -28,6 +28,8 @@ def matrix(name: str):
         return synth.stencil27(24)
     if name == "rmat22":
         return synth.rmat(22)
+    if name == "rmat22perm":
+        return permuted(*matrix("rmat22"), seed=304)
     if name == "rmat14":
         return synth.rmat(14, 16)
     if name == "unif20":
@@ -41,7 +43,23 @@ def matrix(name: str):
     raise KeyError(name)
 
 
-X_SEED = {"lap100": 101, "st27_128": 203, "rmat22": 303, "unif20": 403}
+def permuted(n, m, rp, col, val, seed):
+    """Symmetric permutation P A P^T with the seeded Fisher-Yates permutation p
+    (row i moves to p[i], column j to p[j]), rows sorted by column."""
+    p = synth.permutation(n, seed).astype(np.int64)
+    inv = np.empty_like(p)
+    inv[p] = np.arange(n)
+    lens = np.diff(rp).astype(np.int64)[inv]           # new row r is old row inv[r]
+    nrp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(lens, out=nrp[1:])
+    src = np.repeat(rp[:-1].astype(np.int64)[inv] - nrp[:-1], lens) + np.arange(nrp[-1])
+    rows = np.repeat(np.arange(n, dtype=np.int64), lens)
+    cols = p[col[src]]
+    order = np.argsort(rows * m + cols, kind="stable")
+    return n, m, nrp.astype(np.int32), cols[order].astype(np.int32), val[src][order]
+
+
+X_SEED = {"lap100": 101, "st27_128": 203, "rmat22": 303, "rmat22perm": 303, "unif20": 403}
 
 
 def xvec(name: str, n: int):

@@ -3,7 +3,8 @@ configurations the benchmark times:
 
   C1  2-D 5-point Laplacian 100^2 (cache-resident, launch bound)
   C2  27-point stencil on 128^3 (HBM bound, the headline workload)
-  C3a R-MAT scale 22, edge factor 16 (skewed rows: merge path, long rows)
+  C3a R-MAT scale 22, edge factor 16 (skewed rows: merge path, long rows),
+      and its seeded symmetric permutation (column blocks over row lists)
   C3b uniform random 2^20 x 16 (gather bound)
   C4  FP32 / BF16 value storage of C1 and C2
 
@@ -24,7 +25,7 @@ from spmv_cases import check_f64, check_reduced, matrix, xvec
 
 pytestmark = pytest.mark.gpu
 
-CONFIGS = ["lap100", "st27_128", "rmat22", "unif20"]
+CONFIGS = ["lap100", "st27_128", "rmat22", "rmat22perm", "unif20"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -71,6 +72,23 @@ def test_column_blocks_uniform_full_size():
     info = A.select("forced", forced_opts=pkg.OPT_MERGE | pkg.OPT_PREFETCH)
     assert info["column_blocks"] == 4
     check_f64(spmv(A, x), rp, col, val, x, "unif20 column blocks")
+    A.close()
+
+
+@pytest.mark.parametrize("name", ["rmat22", "rmat22perm"])
+def test_rmat_merge_plans_full_size(name):
+    """R-MAT 22 and its permutation under the merge plans the irregular
+    benchmark times: one pass (plain and streaming loads, split rows
+    carried through the fixup) and column blocks over row lists."""
+    n, m, rp, col, val = matrix(name)
+    x = xvec(name, m)
+    A = pkg.CsrMatrix(rp, col, val, n_cols=m)
+    for opts, over in ((pkg.OPT_MERGE, {"split_row_blocks": 0}),
+                       (pkg.OPT_MERGE | pkg.OPT_PREFETCH, {"split_row_blocks": 0}),
+                       (pkg.OPT_MERGE, {})):
+        info = A.select("forced", forced_opts=opts, **over)
+        assert info["column_blocks"] == (0 if over else 8), info
+        check_f64(spmv(A, x), rp, col, val, x, f"{name} opts={opts} {over}")
     A.close()
 
 
