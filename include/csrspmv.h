@@ -136,6 +136,12 @@ typedef struct {
                                 the fixup, and the blocks after the first walk only the rows
                                 with nonzeros in them; 0 = only on row-aligned tiles. The
                                 autotuner times both where they apply */
+    double ood_z;            /* LEARNED: a matrix whose standardized features (log2(1 + f)
+                                - mu) / sigma, with the loaded model's mu and sigma, reach
+                                beyond ood_z in absolute value lies outside what the model
+                                was trained on, and selection falls back to PROFILE (default
+                                4.0: the 2,000 training-suite matrices stay below 3; 0 turns
+                                the test off) */
 } csr_config_t;
 
 /* What csr_select decided and what it cost. */
@@ -175,6 +181,8 @@ typedef struct {
     double t_prep_ms;        /* format conversion for the chosen plan */
     double format_bytes;     /* algorithmic bytes of one SpMV with this plan */
     double ml_part_max;      /* largest partition ratio of the partition-aware ML test */
+    double feature_z_max;    /* LEARNED: the largest |standardized feature| the model saw
+                                (compared with ood_z); 0 for the other modes */
 } csr_plan_info_t;
 
 /* The 16 features of Sec. III-D, Table I (plus two project-defined ones):
@@ -192,7 +200,7 @@ typedef struct {
 
 /* Fill *cfg with the defaults (t_ml 1.0, t_imb 1.0, t_mb 0.5, remedy_map 1, split_row_blocks 1,
  * long_row_factor 32, long_row_floor 4096, autotune 1, timing_calls 32,
- * ml_partitions 0, t_ml_part 1.5, jit_tiles 0). */
+ * ml_partitions 0, t_ml_part 1.5, jit_tiles 0, ood_z 4.0). */
 void csr_config_default(csr_config_t *cfg);
 
 /*

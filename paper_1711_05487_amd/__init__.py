@@ -61,7 +61,8 @@ class Config(ctypes.Structure):
                 ("exhaustive_set", ctypes.c_int32), ("dynamic_rows", ctypes.c_int32),
                 ("ml_partitions", ctypes.c_int32), ("t_ml_part", ctypes.c_double),
                 ("jit_tiles", ctypes.c_int32), ("window_runs", ctypes.c_int32),
-                ("remedy_map", ctypes.c_int32), ("split_row_blocks", ctypes.c_int32)]
+                ("remedy_map", ctypes.c_int32), ("split_row_blocks", ctypes.c_int32),
+                ("ood_z", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -77,7 +78,8 @@ class PlanInfo(ctypes.Structure):
                 ("p_imb", ctypes.c_double), ("p_cmp", ctypes.c_double),
                 ("p_peak", ctypes.c_double), ("b_max", ctypes.c_double),
                 ("t_select_ms", ctypes.c_double), ("t_prep_ms", ctypes.c_double),
-                ("format_bytes", ctypes.c_double), ("ml_part_max", ctypes.c_double)]
+                ("format_bytes", ctypes.c_double), ("ml_part_max", ctypes.c_double),
+                ("feature_z_max", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -336,6 +336,7 @@ void csr_config_default(csr_config_t *cfg) {
     cfg->t_mb = 0.5;
     cfg->remedy_map = 1;
     cfg->split_row_blocks = 1;
+    cfg->ood_z = 4.0;
     cfg->long_row_factor = 32.0;
     cfg->long_row_floor = 4096;
     cfg->forced_opts = 0;

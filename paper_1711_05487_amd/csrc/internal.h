@@ -346,7 +346,8 @@ hipError_t launch_mlp_normalize(const double *f, const double *mu, const double 
                                 int64_t n, float *out, hipStream_t s);
 hipError_t launch_mlp_select(const float *p, int K, const double *f, const double *mu,
                              const double *sigma, int32_t *out, hipStream_t s);
-csr_status_t learned_pick(csr_matrix_s *A, hipStream_t s, int32_t *variant);
+csr_status_t learned_pick(csr_matrix_s *A, hipStream_t s, double ood_z, int32_t *variant,
+                          double *z_max);
 
 // Plans and selection (select.hip) -----------------------------------------------
 double plan_bytes(const csr_matrix_s *A, const Plan &P);

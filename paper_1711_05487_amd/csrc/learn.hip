@@ -1,6 +1,7 @@
 // C ABI of the learned selector: MLP training and inference kernels exposed
 // for the training driver and the parity tests, and the per-device model used
 // by CSR_SEL_LEARNED.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -14,6 +15,7 @@ namespace {
 struct Model {
     DevBuf params, mu, sigma, feat, pick;
     HostBuf io;  // pinned staging: 16 features in, the pick out
+    double h_mu[16] = {}, h_sigma[16] = {};  // the normalization, for the range test
     int K = 0;
     bool ready = false;
 };
@@ -31,14 +33,26 @@ csr_status_t check_model_args(int K) {
 }  // namespace
 
 // Runs the loaded model on the handle's features; *variant = argmax.
-// CSR_ERR_NOT_READY when no model is loaded on the device.
-csr_status_t learned_pick(csr_matrix_s *A, hipStream_t s, int32_t *variant) {
+// *z_max = the largest |standardized feature| (the model's input). Returns
+// CSR_ERR_NOT_READY, so that selection falls back to the profile-guided
+// rule, when no model is loaded on the device, when a feature is not
+// finite, or when z_max exceeds ood_z > 0 (a matrix outside the range the
+// model was trained on).
+csr_status_t learned_pick(csr_matrix_s *A, hipStream_t s, double ood_z, int32_t *variant,
+                          double *z_max) {
     std::lock_guard<std::mutex> lk(g_model_mu);
+    *z_max = 0.0;
     if (A->device < 0 || A->device >= 64 || !g_models[A->device].ready)
         return fail(CSR_ERR_NOT_READY, "no model loaded");
     Model &M = g_models[A->device];
     for (int i = 0; i < 16; ++i)
         if (!std::isfinite(A->feat.f[i])) return fail(CSR_ERR_NOT_READY, "non-finite feature");
+    double zm = 0.0;
+    for (int i = 0; i < 16; ++i)
+        zm = std::max(zm, std::fabs((std::log2(1.0 + A->feat.f[i]) - M.h_mu[i]) / M.h_sigma[i]));
+    *z_max = zm;
+    if (ood_z > 0.0 && !(zm <= ood_z))
+        return fail(CSR_ERR_NOT_READY, "features outside the model's training range");
     double *const hf = static_cast<double *>(M.io.p);
     int32_t *const hp = reinterpret_cast<int32_t *>(hf + 16);
     std::memcpy(hf, A->feat.f, sizeof(double) * 16);
@@ -84,6 +98,8 @@ csr_status_t csr_mlp_load(const float *h_params, int32_t K, const double *h_mu,
     CSR_HIP(hipMemcpy(M.params.p, h_params, sizeof(float) * n, hipMemcpyHostToDevice));
     CSR_HIP(hipMemcpy(M.mu.p, h_mu, sizeof(double) * 16, hipMemcpyHostToDevice));
     CSR_HIP(hipMemcpy(M.sigma.p, h_sigma, sizeof(double) * 16, hipMemcpyHostToDevice));
+    std::memcpy(M.h_mu, h_mu, sizeof(M.h_mu));
+    std::memcpy(M.h_sigma, h_sigma, sizeof(M.h_sigma));
     M.K = K;
     M.ready = true;
     return CSR_OK;

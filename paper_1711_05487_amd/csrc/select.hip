@@ -1325,6 +1325,8 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
         return fail(CSR_ERR_INVALID_ARG, "remedy_map must be 0 or 1");
     if (cfg.split_row_blocks != 0 && cfg.split_row_blocks != 1)
         return fail(CSR_ERR_INVALID_ARG, "split_row_blocks must be 0 or 1");
+    if (!(cfg.ood_z >= 0.0) || !std::isfinite(cfg.ood_z))
+        return fail(CSR_ERR_INVALID_ARG, "ood_z must be finite and >= 0");
     if (cfg.ml_partitions < 0 || cfg.ml_partitions > 4096 ||
         (cfg.ml_partitions > 0 && !(cfg.t_ml_part > 0.0)))
         return fail(CSR_ERR_INVALID_ARG, "ml_partitions must be in 0..4096 with t_ml_part > 0");
@@ -1408,10 +1410,11 @@ csr_status_t csr_select(csr_matrix_t A, int32_t mode, const csr_config_t *cfg_in
     }
     case CSR_SEL_LEARNED: {
         // features -> MLP -> catalogue variant with default parameters; no
-        // model (or non-finite features) -> the profile-guided path
+        // model, non-finite features, or features outside the model's
+        // training range -> the profile-guided path
         if ((st = inspect(A, s)) != CSR_OK) break;
         int32_t v = -1;
-        st = learned_pick(A, s, &v);
+        st = learned_pick(A, s, cfg.ood_z, &v, &info.feature_z_max);
         if (st == CSR_OK && v >= 0 && v < 16) {
             const auto tp = Clock::now();
             st = realize(A, kCatalogue[v], cfg, &P, s);

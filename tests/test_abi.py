@@ -34,6 +34,7 @@ def test_status_strings_and_defaults():
         assert L.csr_status_str(k).decode() == name
     c = pkg.default_config()
     assert (c.t_ml, c.t_imb, c.t_mb, c.remedy_map, c.split_row_blocks) == (1.0, 1.0, 0.5, 1, 1)
+    assert c.ood_z == 4.0
     assert c.long_row_factor == 32.0 and c.long_row_floor == 4096 and c.timing_calls == 32
 
 

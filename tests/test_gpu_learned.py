@@ -122,3 +122,42 @@ def test_regret_same_session_on_held_out_sample():
     gm = float(np.exp(np.mean(np.log(ratios))))
     print("same-session t_learned / t_best:", gm, "p90", float(np.percentile(ratios, 90)), len(ratios))
     assert gm <= 1.10
+
+
+def test_features_outside_the_training_range_fall_back_to_profile():
+    """The learned path's range test: the largest |standardized feature| is
+    reported, equal to the oracle's normalization of the same features with
+    the model's mu and sigma; past ood_z the profile-guided rule decides;
+    ood_z = 0 turns the test off; a 1 x 1 matrix lies outside the range of
+    the training suite at the default bound; invalid bounds are refused."""
+    import oracle
+    learn.install()
+    _, mu, sd, _ = learn.load_weights()
+    n, m, rp, col, val = matrix("st27_24")
+    x = xvec("st27_24", m)
+    A = pkg.CsrMatrix(rp, col, val)
+    f, _, _ = A.inspect()
+    z = float(np.abs(oracle.normalize(f, np.asarray(mu), np.asarray(sd))).max())
+    assert 0.0 < z < 4.0
+    info = A.select("learned")
+    assert info["fallback"] == 0 and info["feature_z_max"] == pytest.approx(z, rel=1e-12)
+    info = A.select("learned", ood_z=0.5 * z)
+    assert info["fallback"] == 1 and info["classes"] >= 0  # the profile rule ran
+    assert info["feature_z_max"] == pytest.approx(z, rel=1e-12)
+    y = A.spmv(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    check_f64(y.cpu().numpy(), rp, col, val, x, "out-of-range fallback plan")
+    assert A.select("learned", ood_z=0.0)["fallback"] == 0
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(pkg.CsrError):
+            A.select("learned", ood_z=bad)
+    assert A.select("profile")["feature_z_max"] == 0.0
+    A.close()
+    T = pkg.CsrMatrix(np.array([0, 1], dtype=np.int32), np.array([0], dtype=np.int32),
+                      np.array([2.0]), n_cols=1)
+    info = T.select("learned")
+    assert info["fallback"] == 1 and info["feature_z_max"] > 4.0
+    y = T.spmv(torch.tensor([0.5], dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    assert y.item() == 1.0
+    T.close()

@@ -62,7 +62,10 @@ def big():
 def test_max_nnz_exact(big, opts):
     A, x = big
     if opts is None:
-        info = A.select("learned")
+        # rows of 32,768 nonzeros lie far outside the selector's training
+        # range; the range test is turned off so that the model's own pick
+        # runs at this size
+        info = A.select("learned", ood_z=0.0)
     else:
         info = A.select("forced", forced_opts=opts)
     if opts is not None and opts & pkg.OPT_MERGE:

@@ -146,7 +146,8 @@ def test_learned_selection_uses_loaded_model():
         p = np.zeros(6288, dtype=np.float32)
         p[-16 + target] = 10.0  # output bias: a decisive, input-independent choice
         pkg.mlp_load(p, K, mu, sd)
-        info = A.select("learned")
+        # mu = 0, sigma = 1 is no training range: the range test is off
+        info = A.select("learned", ood_z=0.0)
         assert info["variant_id"] == target and info["fallback"] == 0
         assert info["opts"] == oracle.catalogue()[target]
         x = synth.vector(m, 2)
