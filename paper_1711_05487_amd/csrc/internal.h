@@ -164,6 +164,7 @@ struct csr_matrix_s {
     std::vector<double> mlp_ratios;
     csr::DevBuf dyn_ctr;           // the row-split dynamic schedule's two counters (zeroed once)
     csr::DevBuf feat_parts, feat_reuse, feat_long;  // feature-extraction partials, long rows
+    csr::DevBuf feat_bits;         // one bit per row: the rows the sweep left to the long pass
     csr::HostBuf feat_host;        // pinned copy of feat_reuse (the sweep's results)
     double t_inspect_ms = 0.0;
 };
@@ -306,16 +307,19 @@ constexpr size_t kFeatHeader = 128;
 static_assert(sizeof(FeatPart) + sizeof(int32_t) <= kFeatHeader, "feature header");
 // The sweep, its fold and the x-reuse samples, enqueued on s; `out` receives
 // the results laid out as above (the long rows are not in the fold yet).
-// parts: n_parts + long capacity entries; long_list: long capacity + 1 ints.
+// parts: n_parts + long capacity entries; long_list: long capacity + 1 ints
+// ([0] the long-row count); long_bits: ceil(n_rows / 32) words, one bit per
+// row the sweep leaves to the long pass.
 hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int G,
-                           FeatPart *parts, int32_t n_parts, int32_t *long_list, void *out,
-                           hipStream_t s);
-// With n_long > 0 long rows (the count launch_features left): their
-// partials, sorted by row, and the fold over all partials into `out`.
-// Synchronizes the stream (the long rows are sorted on the host).
-hipError_t features_long_rows(const int32_t *rp, const int32_t *col, int64_t nnz, int G,
-                              FeatPart *parts, int32_t n_parts, int32_t *long_list,
-                              int32_t n_long, void *out, hipStream_t s);
+                           FeatPart *parts, int32_t n_parts, int32_t *long_list,
+                           uint32_t *long_bits, void *out, hipStream_t s);
+// With n_long > 0 long rows (the count launch_features left): the long rows
+// listed in row order from their bits (on the device), their partials, and
+// the fold over all partials into `out`; enqueued on s.
+hipError_t features_long_rows(const int32_t *rp, const int32_t *col, int32_t n_rows, int64_t nnz,
+                              int G, FeatPart *parts, int32_t n_parts, int32_t *long_list,
+                              const uint32_t *long_bits, int32_t n_long, void *out,
+                              hipStream_t s);
 
 hipError_t launch_long_s0(const int32_t *col, const void *val, const void *x, void *y,
                           const int32_t *chunk_beg, void *part, int64_t n_chunks,

@@ -8,14 +8,14 @@
 //
 // G lanes share a row, each taking a contiguous segment (the entry before a
 // segment gives its first gap). Rows longer than 64 G entries are left out
-// of the sweep and listed; each is then reduced by a whole workgroup, in row
-// order, so one long row does not serialize a lane group. Integer totals are
+// of the sweep and marked in a bitmap, listed in row order from it on the
+// device, and each reduced by a whole workgroup, so one long row does not
+// serialize a lane group. Integer totals are
 // exact int64 sums; the scatter mean and variance use Welford updates per
 // thread merged with Chan's pairwise formula in a fixed tree, so the result
 // is deterministic. A second small kernel samples row pairs for the x-reuse
 // estimate, and a one-block kernel folds the per-block partials in order.
 #include <algorithm>
-#include <vector>
 
 #include "device.h"
 #include "internal.h"
@@ -132,7 +132,8 @@ template <int G>
 __global__ __launch_bounds__(kBlock) void k_features(const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ col,
                                                      int32_t n_rows, FeatPart *__restrict__ out,
-                                                     int32_t *__restrict__ long_list) {
+                                                     int32_t *__restrict__ long_list,
+                                                     uint32_t *__restrict__ long_bits) {
     __shared__ FeatPart s_part[kBlock / G];
     constexpr int NG = kBlock / G;
     const int lane = threadIdx.x % G;
@@ -152,7 +153,10 @@ __global__ __launch_bounds__(kBlock) void k_features(const int32_t *__restrict__
         }
         const int32_t k = e - b;
         if (k > 64 * G) {  // reduced by its own workgroup later
-            if (lane == 0) long_list[1 + atomicAdd(long_list, 1)] = (int32_t)r;
+            if (lane == 0) {
+                atomicAdd(long_list, 1);
+                atomicOr(long_bits + (r >> 5), 1u << (r & 31));
+            }
             continue;
         }
         // lane takes the contiguous segment [s0, s1) of the row
@@ -274,10 +278,45 @@ __global__ __launch_bounds__(kWave) void k_xreuse(const int32_t *__restrict__ rp
 
 template <int G>
 hipError_t go(const int32_t *rp, const int32_t *col, int32_t n_rows, FeatPart *parts,
-              int32_t n_parts, int32_t *long_list, hipStream_t s) {
+              int32_t n_parts, int32_t *long_list, uint32_t *long_bits, hipStream_t s) {
     hipLaunchKernelGGL(k_features<G>, dim3(n_parts), dim3(kBlock), 0, s, rp, col, n_rows, parts,
-                       long_list);
+                       long_list, long_bits);
     return hipGetLastError();
+}
+
+// The long rows in row order, from their bits: thread t counts the set bits
+// of its contiguous run of words, the counts are scanned, and each thread
+// writes its rows at its offset (list[1 + k] = k-th long row), so the long
+// pass folds them in row order without a host sort.
+__global__ __launch_bounds__(kBlock) void k_long_order(const uint32_t *__restrict__ bits,
+                                                       int64_t n_words,
+                                                       int32_t *__restrict__ list) {
+    __shared__ int32_t s_off[kBlock];
+    const int64_t chunk = (n_words + kBlock - 1) / kBlock;
+    const int64_t w0 = min((int64_t)threadIdx.x * chunk, n_words);
+    const int64_t w1 = min(w0 + chunk, n_words);
+    int32_t c = 0;
+    for (int64_t w = w0; w < w1; ++w) c += __popc(bits[w]);
+    s_off[threadIdx.x] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {  // exclusive scan of the counts, in order
+        int32_t run = 0;
+        for (int q = 0; q < kBlock; ++q) {
+            const int32_t v = s_off[q];
+            s_off[q] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int32_t k = 1 + s_off[threadIdx.x];
+    for (int64_t w = w0; w < w1; ++w) {
+        uint32_t m = bits[w];
+        while (m) {
+            const int b = __ffs(m) - 1;
+            list[k++] = (int32_t)(w * 32 + b);
+            m &= m - 1;
+        }
+    }
 }
 
 }  // namespace
@@ -297,20 +336,23 @@ int64_t features_long_capacity(int64_t nnz, int G) {
 }
 
 hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows, int G,
-                           FeatPart *parts, int32_t n_parts, int32_t *long_list, void *out,
-                           hipStream_t s) {
+                           FeatPart *parts, int32_t n_parts, int32_t *long_list,
+                           uint32_t *long_bits, void *out, hipStream_t s) {
     char *const out_b = static_cast<char *>(out);
     int32_t *const reuse_out = reinterpret_cast<int32_t *>(out_b + kFeatHeader);
     hipError_t e;
     if ((e = hipMemsetAsync(long_list, 0, sizeof(int32_t), s)) != hipSuccess) return e;
+    const size_t n_words = ((size_t)n_rows + 31) / 32;
+    if ((e = hipMemsetAsync(long_bits, 0, sizeof(uint32_t) * n_words, s)) != hipSuccess) return e;
+    uint32_t *const lb = long_bits;
     switch (G) {
-    case 1: e = go<1>(rp, col, n_rows, parts, n_parts, long_list, s); break;
-    case 2: e = go<2>(rp, col, n_rows, parts, n_parts, long_list, s); break;
-    case 4: e = go<4>(rp, col, n_rows, parts, n_parts, long_list, s); break;
-    case 8: e = go<8>(rp, col, n_rows, parts, n_parts, long_list, s); break;
-    case 16: e = go<16>(rp, col, n_rows, parts, n_parts, long_list, s); break;
-    case 32: e = go<32>(rp, col, n_rows, parts, n_parts, long_list, s); break;
-    default: e = go<64>(rp, col, n_rows, parts, n_parts, long_list, s); break;
+    case 1: e = go<1>(rp, col, n_rows, parts, n_parts, long_list, lb, s); break;
+    case 2: e = go<2>(rp, col, n_rows, parts, n_parts, long_list, lb, s); break;
+    case 4: e = go<4>(rp, col, n_rows, parts, n_parts, long_list, lb, s); break;
+    case 8: e = go<8>(rp, col, n_rows, parts, n_parts, long_list, lb, s); break;
+    case 16: e = go<16>(rp, col, n_rows, parts, n_parts, long_list, lb, s); break;
+    case 32: e = go<32>(rp, col, n_rows, parts, n_parts, long_list, lb, s); break;
+    default: e = go<64>(rp, col, n_rows, parts, n_parts, long_list, lb, s); break;
     }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_features_fold, dim3(1), dim3(kBlock), 0, s, parts, n_parts,
@@ -324,31 +366,24 @@ hipError_t launch_features(const int32_t *rp, const int32_t *col, int32_t n_rows
     return e;
 }
 
-hipError_t features_long_rows(const int32_t *rp, const int32_t *col, int64_t nnz, int G,
-                              FeatPart *parts, int32_t n_parts, int32_t *long_list,
-                              int32_t n_long, void *out, hipStream_t s) {
+hipError_t features_long_rows(const int32_t *rp, const int32_t *col, int32_t n_rows, int64_t nnz,
+                              int G, FeatPart *parts, int32_t n_parts, int32_t *long_list,
+                              const uint32_t *long_bits, int32_t n_long, void *out,
+                              hipStream_t s) {
     if (n_long < 0 || n_long > features_long_capacity(nnz, G)) return hipErrorInvalidValue;
     if (n_long == 0) return hipSuccess;
-    // listed in whatever order the sweep met them; sorted here so that their
-    // partials are folded in row order (deterministic features)
+    // listed in row order, so that their partials are folded in row order
+    // (deterministic features)
+    const int64_t n_words = ((int64_t)n_rows + 31) / 32;
+    hipLaunchKernelGGL(k_long_order, dim3(1), dim3(kBlock), 0, s, long_bits, n_words, long_list);
     hipError_t e;
-    std::vector<int32_t> rows((size_t)n_long);
-    if ((e = hipMemcpyAsync(rows.data(), long_list + 1, sizeof(int32_t) * rows.size(),
-                            hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return e;
-    std::sort(rows.begin(), rows.end());
-    if ((e = hipMemcpyAsync(long_list + 1, rows.data(), sizeof(int32_t) * rows.size(),
-                            hipMemcpyHostToDevice, s)) != hipSuccess)
-        return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_features_long, dim3((unsigned)n_long), dim3(kBlock), 0, s, rp, col,
                        long_list, parts + n_parts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_features_fold, dim3(1), dim3(kBlock), 0, s, parts, n_parts + n_long,
                        (const int32_t *)long_list, static_cast<char *>(out));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // rows lives until the copy has been consumed
-    return hipStreamSynchronize(s);
+    return hipGetLastError();
 }
 
 }  // namespace csr

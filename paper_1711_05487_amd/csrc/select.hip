@@ -788,6 +788,8 @@ csr_status_t feature_buffers(csr_matrix_s *A) {
     if (A->feat_long.bytes < sizeof(int32_t) * n_long &&
         (st = A->feat_long.alloc(sizeof(int32_t) * n_long)) != CSR_OK)
         return st;
+    const size_t n_bits = sizeof(uint32_t) * (((size_t)A->n_rows + 31) / 32);
+    if (A->feat_bits.bytes < n_bits && (st = A->feat_bits.alloc(n_bits)) != CSR_OK) return st;
     if (A->feat_reuse.bytes < n_out && (st = A->feat_reuse.alloc(n_out)) != CSR_OK) return st;
     if (A->feat_host.bytes < n_out && (st = A->feat_host.alloc(n_out)) != CSR_OK) return st;
     return CSR_OK;
@@ -808,7 +810,7 @@ csr_status_t inspect(csr_matrix_s *A, hipStream_t s) {
         if ((st = feature_buffers(A)) != CSR_OK) return st;  // allocated by csr_create
         CSR_HIP(launch_features(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->n_rows, G,
                                 A->feat_parts.as<FeatPart>(), n_parts, A->feat_long.as<int32_t>(),
-                                A->feat_reuse.p, s));
+                                A->feat_bits.as<uint32_t>(), A->feat_reuse.p, s));
         // one round trip when no row was long: the fold, the long-row count
         // and the x-reuse samples in one copy to pinned memory
         const size_t out_bytes = kFeatHeader + sizeof(int32_t) * 2 * (size_t)n_samp;
@@ -822,9 +824,10 @@ csr_status_t inspect(csr_matrix_s *A, hipStream_t s) {
         std::vector<int32_t> reuse(2 * (size_t)n_samp);
         if (n_samp > 0) std::memcpy(reuse.data(), h + kFeatHeader, sizeof(int32_t) * reuse.size());
         if (n_long != 0) {
-            CSR_HIP(features_long_rows(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->nnz, G,
-                                       A->feat_parts.as<FeatPart>(), n_parts,
-                                       A->feat_long.as<int32_t>(), n_long, A->feat_reuse.p, s));
+            CSR_HIP(features_long_rows(A->rp.as<int32_t>(), A->col.as<int32_t>(), A->n_rows,
+                                       A->nnz, G, A->feat_parts.as<FeatPart>(), n_parts,
+                                       A->feat_long.as<int32_t>(), A->feat_bits.as<uint32_t>(),
+                                       n_long, A->feat_reuse.p, s));
             CSR_HIP(hipMemcpyAsync(A->feat_host.p, A->feat_reuse.p, sizeof(p),
                                    hipMemcpyDeviceToHost, s));
             CSR_HIP(hipStreamSynchronize(s));
