@@ -79,10 +79,11 @@ struct SegStats {
     int32_t mn, mx, miss, grps;
 };
 // The segment is read U entries at a time, all U loads issued before any is
-// used (a segment is short, so one round usually covers it).
+// used (one round covers a segment of up to 16 entries; the 64-entry
+// segments of a skewed matrix's rows take four).
 __device__ __forceinline__ SegStats seg_stats(const int32_t *__restrict__ col, int32_t b,
                                               int32_t e, int32_t s0, int32_t s1) {
-    constexpr int U = 4;
+    constexpr int U = 16;
     SegStats g{INT32_MAX, INT32_MIN, 0, 0};
     int32_t prev = s0 > b && s0 < e ? col[s0 - 1] : 0;
     for (int32_t j0 = s0; j0 < s1; j0 += U) {
